@@ -1,0 +1,134 @@
+/*
+ * sie_triples.h -- C ABI of the MI355X (gfx950) per-fragment (T) library.
+ *
+ * What it computes: the closed-shell in-situ perturbative-triples energy E_x of
+ * one embedded SIE cluster (the paper's section "The In-situ Form of
+ * Perturbative (T) in SIE", equation E_corr_CCSD_T with the W, V, D, P and R
+ * definitions printed after it), and the sum E = sum_x E_x over clusters
+ * (equation C_f of the same section), from
+ *   orbital energies e_i, e_a           (canonical cluster orbitals),
+ *   CCSD amplitudes t_i^a, t_ij^ab,
+ *   ERI blocks (ia|bc), (jl|ia), (ia|jb) in chemists' notation.
+ * Readings of the printed equations: the two dummy indices of the W bracket
+ * are swapped back to  X = sum_d (ia|bd) t_kj^cd - sum_l (ia|jl) t_lk^bc,
+ * and the second term of R is read as the cyclic permutation X_kij.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Layouts are row-major and contiguous, indices i,j,k,l occupied (n_occ),
+ * a,b,c,d virtual (n_vir):
+ *   eps_occ [n_occ]                      e_i      HOST memory, float64
+ *   eps_vir [n_vir]                      e_a      HOST memory, float64
+ *   t1      [n_occ][n_vir]               t_i^a    device
+ *   t2      [n_occ][n_occ][n_vir][n_vir] t_ij^ab  device, must satisfy t_ij^ab = t_ji^ba
+ *   ovvv    [n_occ][n_vir][n_vir][n_vir] (ia|bc)  device, symmetric in b <-> c
+ *   ooov    [n_occ][n_occ][n_occ][n_vir] (jl|ia)  device, symmetric in j <-> l
+ *   ovov    [n_occ][n_vir][n_occ][n_vir] (ia|jb)  device, symmetric in (ia) <-> (jb)
+ * The library reads whichever twin of a symmetric pair suits its access
+ * pattern, so inputs that break these symmetries give implementation-defined
+ * results.
+ * Element type of t1, t2 and the ERI blocks: float64 for SIE_FP64, float32 for
+ * SIE_SPLIT_BF16.  Energies are always float64.
+ *
+ * Ownership: the caller owns every buffer (inputs, outputs, workspace); the
+ * library keeps no device memory between calls and allocates none.  The host
+ * arrays (eps_*, the descriptor structs) may be released when the call returns.
+ * Streams: `stream` is a hipStream_t (NULL = the default stream); all device
+ * work is enqueued on it and the call returns without waiting for it.
+ * Errors: every entry point returns a sie_status; nothing is thrown across
+ * the ABI and nothing aborts.  All argument checks run on the host before any
+ * HIP call, so a bad argument is reported without touching the device.
+ * sie_last_error() gives a message for the last failing call on the calling
+ * thread.  On an error no device work has been enqueued unless the status is
+ * SIE_ERR_HIP (a launch or copy failed part way; outputs are then undefined).
+ */
+#ifndef SIE_TRIPLES_H
+#define SIE_TRIPLES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIE_ABI_VERSION 1
+
+typedef enum {
+  SIE_OK = 0,
+  SIE_ERR_INVALID_ARG = 1,   /* bad pointer, size, alignment or orbital energies */
+  SIE_ERR_UNSUPPORTED = 2,   /* valid request that this build does not implement */
+  SIE_ERR_WORKSPACE = 3,     /* workspace missing or smaller than required        */
+  SIE_ERR_HIP = 5            /* a HIP runtime call failed; see sie_last_error()   */
+} sie_status;
+
+typedef enum {
+  SIE_FP64 = 0,        /* float64 inputs, float64 contractions and sums          */
+  SIE_SPLIT_BF16 = 1   /* float32 inputs split into bf16 hi + lo, three bf16
+                          products per contraction with float32 accumulation;
+                          denominators and energy sums in float64                */
+} sie_precision;
+
+/* One fragment (embedded cluster).  Pointers as described above. */
+typedef struct {
+  int32_t n_occ;             /* 1 <= n_occ <= SIE_MAX_OCC                      */
+  int32_t n_vir;             /* 1 <= n_vir <= SIE_MAX_VIR                      */
+  const double* eps_occ;     /* host [n_occ]                                   */
+  const double* eps_vir;     /* host [n_vir]                                   */
+  const void* t1;            /* device, see layouts                            */
+  const void* t2;
+  const void* ovvv;
+  const void* ooov;
+  const void* ovov;
+  const double* frag_proj;   /* C^f_ii' [n_occ][n_occ] of the same section, or
+                                NULL for the identity; non-NULL is rejected with
+                                SIE_ERR_UNSUPPORTED by this build               */
+} sie_fragment;
+
+#define SIE_MAX_OCC 256
+#define SIE_MAX_VIR 2048
+
+/* Number of unordered occupied triples i >= j >= k of a fragment:
+ * n_occ (n_occ + 1) (n_occ + 2) / 6.  Per-triple outputs are indexed by
+ * u = i (i+1) (i+2) / 6 + j (j+1) / 2 + k. */
+int64_t sie_occupied_triples(int32_t n_occ);
+
+/* Workspace bytes the energy entry points need for `n` fragments at
+ * precision `p`, given at most `max_bytes` may be used (0 = the library's
+ * default cap of 2 GiB).  Larger workspaces let more occupied triples run per
+ * launch.  Returns 0 if the arguments are invalid (see sie_last_error()). */
+size_t sie_triples_workspace_size(const sie_fragment* frags, int32_t n,
+                                  sie_precision p, size_t max_bytes);
+
+/* E_x of one fragment (equation E_corr_CCSD_T).
+ *   frag     host pointer to one descriptor
+ *   e_out    device float64 [1]: receives E_x
+ *   e_triples  device float64 [sie_occupied_triples(n_occ)] or NULL: receives
+ *            the contribution of each unordered occupied triple {i, j, k}
+ *            (their sum is E_x)
+ *   ws       device workspace of ws_bytes >= the size reported for this
+ *            fragment and precision; its contents on entry are ignored
+ * Deterministic: the same inputs give bitwise the same outputs. */
+sie_status sie_triples_energy(const sie_fragment* frag, sie_precision p,
+                              double* e_out, double* e_triples,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* Kernel timing (diagnostics).  While enabled on the calling thread, every
+ * launch made by the entry points above is bracketed by two HIP events on the
+ * launch stream.  sie_profile_collect waits for those events, writes the
+ * summed elapsed milliseconds and the launch count per kernel class into
+ * ms[SIE_PROF_CLASSES] and launches[SIE_PROF_CLASSES] (host arrays), and
+ * clears the record.  Classes: 0 = Wt build, 1 = R/D epilogue,
+ * 2 = reductions.  Enabling or disabling also clears the record. */
+#define SIE_PROF_CLASSES 3
+void sie_profile_enable(int on);
+sie_status sie_profile_collect(double* ms, int64_t* launches);
+
+const char* sie_last_error(void);
+int sie_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIE_TRIPLES_H */

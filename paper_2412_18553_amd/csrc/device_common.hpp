@@ -1,0 +1,40 @@
+// Device helpers shared by the (T) kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sie {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// D(16x16, f64) += A(16x4) * B(4x16) on the matrix cores.
+// Operand layout (one f64 per lane): A[row = lane % 16][k = lane / 16],
+// B[k = lane / 16][col = lane % 16]; result lane l, element v holds
+// D[4 * v + l / 16][l % 16] (measured on gfx950).
+__device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__host__ __device__ __forceinline__ int64_t tetra(int64_t n) {   // n(n+1)(n+2)/6
+  return n * (n + 1) * (n + 2) / 6;
+}
+__host__ __device__ __forceinline__ int64_t tri(int64_t n) {     // n(n+1)/2
+  return n * (n + 1) / 2;
+}
+
+// Linear index u of a sorted triple p >= q >= r (lexicographic in (p, q, r))
+// back to (p, q, r).  `bound` is an upper bound on p.
+__device__ __forceinline__ void decode_sorted_triple(int64_t u, int bound,
+                                                     int& p, int& q, int& r) {
+  int pp = 0;
+  while (pp + 1 < bound && tetra(pp + 1) <= u) ++pp;
+  int64_t rem = u - tetra(pp);
+  int qq = 0;
+  while (qq + 1 <= pp && tri(qq + 1) <= rem) ++qq;
+  p = pp;
+  q = qq;
+  r = (int)(rem - tri(qq));
+}
+
+}  // namespace sie

@@ -1,0 +1,133 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and every argument error is reported by the host checks
+(no HIP call is made on these paths, so fake device pointers are never read).
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2412_18553_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sie_triples.h")
+
+FAKE = 0x100000          # 1 MiB: non-NULL, aligned, never dereferenced
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sie_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def frag(o=4, v=10, eps_occ=None, eps_vir=None, keep=None, **ptrs):
+    eo = np.linspace(-1.0, -0.5, o) if eps_occ is None else np.asarray(eps_occ, np.float64)
+    ev = np.linspace(0.2, 1.0, v) if eps_vir is None else np.asarray(eps_vir, np.float64)
+    if keep is not None:
+        keep.extend([eo, ev])
+    p = dict(t1=FAKE, t2=FAKE, ovvv=FAKE, ooov=FAKE, ovov=FAKE, frag_proj=None)
+    p.update(ptrs)
+    return _lib.SieFragment(o, v, eo.ctypes.data, ev.ctypes.data, p["t1"], p["t2"],
+                            p["ovvv"], p["ooov"], p["ovov"], p["frag_proj"])
+
+
+def test_every_declared_symbol_exported(lib):
+    names = declared_functions()
+    assert set(names) == set(_lib.EXPORTED)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_and_counts(lib):
+    assert lib.sie_abi_version() == 1
+    assert lib.sie_occupied_triples(24) == 2600
+    assert lib.sie_occupied_triples(1) == 1
+
+
+def energy(lib, f, prec=_lib.SIE_FP64, e_out=FAKE, e_tri=None, ws=FAKE, ws_bytes=1 << 30):
+    return lib.sie_triples_energy(ctypes.byref(f) if f is not None else None, prec, e_out,
+                                  e_tri, ws, ws_bytes, None)
+
+
+def test_valid_workspace_query(lib):
+    keep = []
+    f = frag(keep=keep)
+    n = lib.sie_triples_workspace_size(ctypes.byref(f), 1, _lib.SIE_FP64, 0)
+    assert n >= 10 ** 3 * 8
+    # a cap forces fewer units per launch but never below one cube
+    small = lib.sie_triples_workspace_size(ctypes.byref(f), 1, _lib.SIE_FP64, 20000)
+    assert 0 < small <= 20000
+    assert lib.sie_triples_workspace_size(ctypes.byref(f), 1, _lib.SIE_FP64, 100) == 0
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(o=0), _lib.SIE_ERR_INVALID_ARG),
+    (dict(v=0), _lib.SIE_ERR_INVALID_ARG),
+    (dict(o=300), _lib.SIE_ERR_INVALID_ARG),
+    (dict(t2=None), _lib.SIE_ERR_INVALID_ARG),
+    (dict(ovvv=FAKE + 4), _lib.SIE_ERR_INVALID_ARG),            # misaligned float64
+    (dict(eps_occ=[-1.0, 0.5], eps_vir=[0.4, 1.0], o=2, v=2), _lib.SIE_ERR_INVALID_ARG),
+    (dict(eps_occ=[-1.0, float("nan")], o=2), _lib.SIE_ERR_INVALID_ARG),
+    (dict(frag_proj=FAKE), _lib.SIE_ERR_UNSUPPORTED),
+])
+def test_argument_errors(lib, kw, code):
+    keep = []
+    o = kw.pop("o", 4)
+    v = kw.pop("v", 10)
+    eo = kw.pop("eps_occ", None)
+    ev = kw.pop("eps_vir", None)
+    f = frag(max(o, 1) if o > 0 else o, v, eps_occ=eo if eo is not None else
+             (np.linspace(-1.0, -0.5, max(o, 1)) if o <= 256 else np.linspace(-1, -0.5, o)),
+             eps_vir=ev, keep=keep, **kw)
+    assert energy(lib, f) == code
+    assert len(_lib.last_error()) > 0
+
+
+def test_null_descriptor_and_outputs(lib):
+    assert energy(lib, None) == _lib.SIE_ERR_INVALID_ARG
+    keep = []
+    f = frag(keep=keep)
+    assert energy(lib, f, e_out=None) == _lib.SIE_ERR_INVALID_ARG
+    assert energy(lib, f, e_out=FAKE + 4) == _lib.SIE_ERR_INVALID_ARG
+    assert energy(lib, f, prec=7) == _lib.SIE_ERR_INVALID_ARG
+
+
+def test_workspace_errors(lib):
+    keep = []
+    f = frag(keep=keep)
+    assert energy(lib, f, ws=None) == _lib.SIE_ERR_WORKSPACE
+    assert energy(lib, f, ws=FAKE + 8) == _lib.SIE_ERR_WORKSPACE
+    assert energy(lib, f, ws_bytes=64) == _lib.SIE_ERR_WORKSPACE
+
+
+def test_split_precision_not_yet(lib):
+    keep = []
+    f = frag(keep=keep)
+    assert energy(lib, f, prec=_lib.SIE_SPLIT_BF16) == _lib.SIE_ERR_UNSUPPORTED
+
+
+def test_profile_collect_empty(lib):
+    lib.sie_profile_enable(1)
+    ms = (ctypes.c_double * 3)()
+    cnt = (ctypes.c_int64 * 3)()
+    assert lib.sie_profile_collect(ms, cnt) == _lib.SIE_OK
+    assert list(cnt) == [0, 0, 0]
+    lib.sie_profile_enable(0)
+    assert lib.sie_profile_collect(None, None) == _lib.SIE_ERR_INVALID_ARG
+
+
+def test_python_binding_rejects_bad_shapes():
+    torch = pytest.importorskip("torch")
+    import paper_2412_18553_amd as sie
+    with pytest.raises(TypeError):
+        sie.Fragment(np.zeros(2), np.ones(3), torch.zeros(2, 3, dtype=torch.float64),
+                     None, None, None, None)

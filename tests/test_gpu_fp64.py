@@ -1,0 +1,112 @@
+"""float64 (T) on the GPU against the CPU oracle, element by element.
+
+Tolerance: 1e-10 relative for the fragment energy; each per-occupied-triple
+contribution within 1e-10 of the largest contribution's magnitude.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.triples as T
+from synth import make_fragment, workload_fragment
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+RTOL = 1e-10
+
+
+def _dev(f):
+    import torch
+    cast = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda", torch.float64)  # noqa: E731
+    return (f.eps_occ, f.eps_vir, cast(f.t1), cast(f.t2), cast(f.ovvv), cast(f.ooov),
+            cast(f.ovov))
+
+
+def run_gpu(f):
+    import paper_2412_18553_amd as sie
+    e, tri = sie.triples_energy(*_dev(f), return_triples=True)
+    return float(e.item()), tri.cpu().numpy()
+
+
+def check_triples(tri, f, sample=None):
+    trip = oracle.occupied_triples(f.n_occ)
+    idx = range(len(trip)) if sample is None else sample
+    ref = np.array([oracle.occupied_triple_energy(*trip[u], *f.arrays()) for u in idx])
+    got = tri[list(idx)]
+    scale = max(np.max(np.abs(ref)), 1e-300)
+    assert np.max(np.abs(got - ref)) <= RTOL * scale, (got, ref)
+
+
+@pytest.mark.parametrize("o,v,aux,seed", [
+    (2, 3, 8, 2), (3, 17, 20, 3), (4, 16, 24, 4), (5, 33, 40, 5),
+    (7, 24, 30, 7), (6, 50, 60, 6), (9, 41, 50, 9)])
+def test_small_ragged_vs_oracle(o, v, aux, seed):
+    """Sizes that are not multiples of the 16- and 8-wide tiles or of the
+    4-deep occupied k-steps, so every ragged edge is exercised."""
+    print(f"case o={o} v={v} seed={seed}", flush=True)
+    f = make_fragment(o, v, aux, (7, seed))
+    e_gpu, tri = run_gpu(f)
+    e_ref = T.energy_literal_vectorized(*f.arrays())
+    assert abs(e_gpu - e_ref) <= RTOL * abs(e_ref), (e_gpu, e_ref)
+    check_triples(tri, f)
+    assert abs(tri.sum() - e_gpu) <= 1e-13 * abs(e_gpu)
+
+
+def test_one_occupied_is_zero():
+    f = make_fragment(1, 20, 30, (7, 1))
+    e_gpu, tri = run_gpu(f)
+    assert e_gpu == 0.0 and tri.tolist() == [0.0]
+
+
+def test_zero_t2_is_zero():
+    f = make_fragment(4, 20, 30, (7, 11))
+    f = f.replace(t2=np.zeros_like(f.t2))
+    e_gpu, _ = run_gpu(f)
+    assert e_gpu == 0.0
+
+
+def test_small_workload_golden_and_all_triples():
+    with open(os.path.join(GOLDEN, "o8v40.json")) as fh:
+        g = json.load(fh)
+    f = workload_fragment("o8v40")
+    e_gpu, tri = run_gpu(f)
+    assert abs(e_gpu - g["energy"]) <= RTOL * abs(g["energy"])
+    check_triples(tri, f)
+
+
+def test_deterministic():
+    f = make_fragment(6, 37, 40, (7, 21))
+    e1, t1 = run_gpu(f)
+    e2, t2 = run_gpu(f)
+    assert e1 == e2
+    assert np.array_equal(t1, t2)
+
+
+def _golden(name):
+    p = os.path.join(GOLDEN, name)
+    if not os.path.exists(p):
+        pytest.skip(f"{name} not generated")
+    with open(p) as fh:
+        return json.load(fh)
+
+
+def test_o24v200_full_size():
+    """Full 24/200 fragment in the benchmark's launch configuration: the
+    energy against the stored oracle value and sampled occupied triples
+    against the oracle."""
+    g = _golden("o24v200.json")
+    f = workload_fragment("o24v200")
+    e_gpu, tri = run_gpu(f)
+    print(f"o24v200 gpu={e_gpu!r} oracle={g['energy']!r}", flush=True)
+    assert abs(e_gpu - g["energy"]) <= RTOL * abs(g["energy"])
+    gu = _golden("o24v200_units.json")
+    trip = oracle.occupied_triples(f.n_occ)
+    pos = {t: u for u, t in enumerate(trip)}
+    for rec in gu["units"]:
+        u = pos[tuple(rec["ijk"])]
+        assert abs(tri[u] - rec["energy"]) <= RTOL * abs(rec["energy"]), rec
