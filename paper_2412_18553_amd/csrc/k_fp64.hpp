@@ -44,95 +44,214 @@ struct FragDev {
 constexpr int kTile = 16;     // virtual tile edge of the build kernel
 constexpr int kOrb = 8;       // virtual block edge of the epilogue orbits
 
-// acc[beta] += sum_{d < nv} A_beta[row][d] * B_beta[d][col], beta < nblk.
-// One operand is per block (row pointer + beta * blk_stride), the other is
-// shared by all blocks.  `pa`/`pb` point at the lane's contiguous d-row (the
-// row of A for lane % 16, the column of B for lane % 16); a_ok/b_ok mark lanes
-// whose row/column lies inside the virtual range (their pointer is clamped to
-// a valid row).  In each 16-wide chunk, k-step s of lane group g reads
-// d = d0 + 4 g + s, so each lane reads four consecutive doubles per row.
-template <bool A_PER_BLOCK>
-__device__ __forceinline__ void vv_term(d4 (&acc)[kTile], int nblk, int nv, int g,
-                                        const double* __restrict__ pa, bool a_ok,
-                                        const double* __restrict__ pb, bool b_ok,
-                                        int64_t blk_stride) {
-  const double* psh = A_PER_BLOCK ? pb : pa;
-  const double* pbl = A_PER_BLOCK ? pa : pb;
-  const bool sh_ok = A_PER_BLOCK ? b_ok : a_ok;
-  const bool bl_ok = A_PER_BLOCK ? a_ok : b_ok;
-  const int last = nblk - 1;
-  for (int d0 = 0; d0 < nv; d0 += 16) {
-    const int dl = d0 + 4 * g;
-    double sh[4];
-    bool dok[4];
-    int dc[4];
+#ifndef SIE_BUILD_BLOCKS_PER_CU
+#define SIE_BUILD_BLOCKS_PER_CU 2   // occupancy target of the build kernel
+#endif
+
+// One contraction term of the build kernel for one wave:
+//   acc[beta] += sum_{k < nK} A_beta[row][k] * B_beta[k][col],  beta < kBlk,
+// where one operand ("per-block") depends on the block index beta and the
+// other ("shared") does not.  For the lane's row (A) or column (B):
+//   per-block element (beta, k) = bl[beta * bstride + k * bl_k]
+//   shared element k            = scale * sh[k * sh_k]
+// K runs in chunks of kChunk = 8: in chunk c, k-step s (0, 1) of lane group g
+// covers k = 8 c + 2 g + s, so a lane reads two consecutive k per row.
+// Rows of lanes outside the virtual range, and blocks past the range, are
+// clamped to valid rows: they only feed output entries that are never
+// stored.  K past nK is zeroed on the shared operand.
+constexpr int kChunk = 8;
+constexpr int kBlk = 8;       // blocks per wave (two waves per layout)
+
+struct Term {
+  const double* bl;
+  const double* sh;
+  int64_t bstride, bl_k, sh_k;
+  int nK;
+  double scale;
+};
+
+struct Chunk {
+  double bl[kBlk][2];
+  double sh[2];
+};
+
+template <bool VEC>
+__device__ __forceinline__ void load_chunk(const Term& t, int c, int last, int g, Chunk& x) {
+  const int k0 = kChunk * c + 2 * g;
+  if (VEC && kChunk * c + kChunk <= t.nK) {
+    // contiguous 16-byte aligned rows (even row length, aligned bases)
+    const double2 s0 = *reinterpret_cast<const double2*>(t.sh + k0);
+    x.sh[0] = s0.x;
+    x.sh[1] = s0.y;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      dok[s] = dl + s < nv;
-      dc[s] = dok[s] ? dl + s : nv - 1;
-      const double v = psh[dc[s]];
-      sh[s] = (sh_ok && dok[s]) ? v : 0.0;
+    for (int beta = 0; beta < kBlk; ++beta) {
+      const double2 u = *reinterpret_cast<const double2*>(
+          t.bl + (int64_t)(beta < last ? beta : last) * t.bstride + k0);
+      x.bl[beta][0] = u.x;
+      x.bl[beta][1] = u.y;
+    }
+  } else {
+    int kc[2];
+    double m[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int k = k0 + s;
+      kc[s] = k < t.nK ? k : t.nK - 1;
+      m[s] = k < t.nK ? t.scale : 0.0;
     }
 #pragma unroll
-    for (int beta = 0; beta < kTile; ++beta) {
-      const double* p = pbl + (int64_t)(beta < last ? beta : last) * blk_stride;
-      double x[4];
+    for (int s = 0; s < 2; ++s) x.sh[s] = m[s] * t.sh[(int64_t)kc[s] * t.sh_k];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const double v = p[dc[s]];
-        x[s] = (bl_ok && dok[s]) ? v : 0.0;
-      }
-      if (beta < nblk) {
+    for (int beta = 0; beta < kBlk; ++beta) {
+      const double* p = t.bl + (int64_t)(beta < last ? beta : last) * t.bstride;
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-          acc[beta] = A_PER_BLOCK ? mfma16x16x4(x[s], sh[s], acc[beta])
-                                  : mfma16x16x4(sh[s], x[s], acc[beta]);
-      }
+      for (int s = 0; s < 2; ++s) x.bl[beta][s] = p[(int64_t)kc[s] * t.bl_k];
     }
   }
 }
 
-// acc[beta] += sum_{l < no} A_beta[row][l] * B_beta[l][col], beta < nblk.
-// Element (lane, l, beta) of A is pa[l * a_ls + beta * a_bs] (B likewise);
-// `a_scale` multiplies A (it carries the minus sign of the occupied term).
-__device__ __forceinline__ void oo_term(d4 (&acc)[kTile], int nblk, int no, int g,
-                                        const double* __restrict__ pa, bool a_ok,
-                                        int64_t a_ls, int64_t a_bs, double a_scale,
-                                        const double* __restrict__ pb, bool b_ok,
-                                        int64_t b_ls, int64_t b_bs) {
-  const int last = nblk - 1;
-  for (int l0 = 0; l0 < no; l0 += 4) {
-    const int l = l0 + g;
-    const bool lok = l < no;
-    const int lc = lok ? l : no - 1;
+template <bool A_IS_BL>
+__device__ __forceinline__ void mma_chunk(const Chunk& x, d4 (&acc)[kBlk]) {
 #pragma unroll
-    for (int beta = 0; beta < kTile; ++beta) {
-      const int bc = beta < last ? beta : last;
-      const double va = pa[(int64_t)lc * a_ls + (int64_t)bc * a_bs];
-      const double vb = pb[(int64_t)lc * b_ls + (int64_t)bc * b_bs];
-      const double xa = (a_ok && lok) ? a_scale * va : 0.0;
-      const double xb = (b_ok && lok) ? vb : 0.0;
-      if (beta < nblk) acc[beta] = mfma16x16x4(xa, xb, acc[beta]);
-    }
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int beta = 0; beta < kBlk; ++beta)
+      acc[beta] = A_IS_BL ? mfma16x16x4(x.bl[beta][s], x.sh[s], acc[beta])
+                          : mfma16x16x4(x.sh[s], x.bl[beta][s], acc[beta]);
+}
+
+// One term as a three-stage register pipeline: the loads of chunks c+1 and
+// c+2 are in flight while the 8 x 2 MFMAs of chunk c run.  Loads of chunks
+// past the end read clamped, zero-masked data and are never consumed.
+// `last` is the last block index (relative to this wave's first block) that
+// lies inside the virtual range.
+template <bool A_IS_BL, bool VEC>
+__device__ __forceinline__ void run_term(const Term& t, int last, int g, d4 (&acc)[kBlk]) {
+  const int nch = (t.nK + kChunk - 1) / kChunk;
+  Chunk b0, b1, b2;
+  load_chunk<VEC>(t, 0, last, g, b0);
+  load_chunk<VEC>(t, 1, last, g, b1);
+  for (int c = 0;; c += 3) {
+    load_chunk<VEC>(t, c + 2, last, g, b2);
+    mma_chunk<A_IS_BL>(b0, acc);
+    if (c + 1 >= nch) break;
+    load_chunk<VEC>(t, c + 3, last, g, b0);
+    mma_chunk<A_IS_BL>(b1, acc);
+    if (c + 2 >= nch) break;
+    load_chunk<VEC>(t, c + 4, last, g, b1);
+    mma_chunk<A_IS_BL>(b2, acc);
+    if (c + 3 >= nch) break;
   }
+}
+
+// Wt for one 16^3 virtual tile (a0.., b0.., c0..) of one unit (i, j, k) is
+// the sum of the six permuted copies (the P operator) of
+//   X^{abc}_{ijk} = sum_d (ia|bd) t_kj^cd - sum_l (ia|jl) t_lk^bc,
+// each split into its d-sum (K = n_v) and its l-sum (K = n_occ); (ia|jl) is
+// read as ooov[j][l][i][a] and t_ij^ab as t2[i][j][a][b] or its twin
+// t2[j][i][b][a].  Twelve terms, six per layout:
+//   L2 (block b, rows a, cols c): X^{bca}_{jki}, X^{cba}_{kji}, X^{bac}_{jik}
+//       d-sums and X^{abc}_{ijk}, X^{acb}_{ikj}, X^{cab}_{kij} l-sums;
+//   L1 (block a, rows b, cols c): X^{abc}_{ijk}, X^{acb}_{ikj}, X^{cab}_{kij}
+//       d-sums and X^{bca}_{jki}, X^{cba}_{kji}, X^{bac}_{jik} l-sums.
+// A wave owns blocks blk0 .. blk0 + 7 of its layout's block index.
+template <bool VEC>
+__device__ __forceinline__ void build_tile(const double* __restrict__ t2,
+                                           const double* __restrict__ ovvv,
+                                           const double* __restrict__ ooov, int i, int j, int k,
+                                           int no_, int nv_, int a0, int b0, int c0, bool l1,
+                                           int blk0, int r, int g, d4 (&acc)[kBlk]) {
+  const int64_t nv = nv_, no = no_, nv2 = nv * nv, nonv = no * nv;
+  const int64_t arc = min(a0 + r, nv_ - 1), brc = min(b0 + r, nv_ - 1),
+                crc = min(c0 + r, nv_ - 1);
+  Term t;
+  if (!l1) {
+    const int bb = b0 + blk0;                     // first block (b) of this wave
+    const int last = min(kBlk, nv_ - bb) - 1;
+    // X^{bca}_{jki}: sum_d t2[i][k][a][d] * ovvv[j][b][c][d]
+    t = Term{ovvv + ((j * nv + bb) * nv + crc) * nv, t2 + ((i * no + k) * nv + arc) * nv,
+             nv2, 1, 1, nv_, 1.0};
+    run_term<false, VEC>(t, last, g, acc);
+    // X^{cba}_{kji}: sum_d t2[i][j][a][d] * ovvv[k][c][b][d]
+    t = Term{ovvv + ((k * nv + crc) * nv + bb) * nv, t2 + ((i * no + j) * nv + arc) * nv,
+             nv, 1, 1, nv_, 1.0};
+    run_term<false, VEC>(t, last, g, acc);
+    // X^{bac}_{jik}: sum_d ovvv[j][b][a][d] * t2[k][i][c][d]
+    t = Term{ovvv + ((j * nv + bb) * nv + arc) * nv, t2 + ((k * no + i) * nv + crc) * nv,
+             nv2, 1, 1, nv_, 1.0};
+    run_term<true, VEC>(t, last, g, acc);
+    // X^{abc}_{ijk}: -sum_l ooov[j][l][i][a] * t2[l][k][b][c]
+    t = Term{t2 + (k * nv + bb) * nv + crc, ooov + (j * no * no + i) * nv + arc,
+             nv, nonv * nv, nonv, no_, -1.0};
+    run_term<false, false>(t, last, g, acc);
+    // X^{acb}_{ikj}: -sum_l ooov[k][l][i][a] * t2[j][l][b][c]
+    t = Term{t2 + (j * no * nv + bb) * nv + crc, ooov + (k * no * no + i) * nv + arc,
+             nv, nv2, nonv, no_, -1.0};
+    run_term<false, false>(t, last, g, acc);
+    // X^{cab}_{kij}: -sum_l t2[l][j][a][b] * ooov[i][l][k][c]
+    t = Term{t2 + (j * nv + arc) * nv + bb, ooov + (i * no * no + k) * nv + crc,
+             1, nonv * nv, nonv, no_, -1.0};
+    run_term<true, false>(t, last, g, acc);
+  } else {
+    const int aa = a0 + blk0;                     // first block (a) of this wave
+    const int last = min(kBlk, nv_ - aa) - 1;
+    // X^{abc}_{ijk}: sum_d ovvv[i][a][b][d] * t2[k][j][c][d]
+    t = Term{ovvv + ((i * nv + aa) * nv + brc) * nv, t2 + ((k * no + j) * nv + crc) * nv,
+             nv2, 1, 1, nv_, 1.0};
+    run_term<true, VEC>(t, last, g, acc);
+    // X^{acb}_{ikj}: sum_d t2[j][k][b][d] * ovvv[i][a][c][d]
+    t = Term{ovvv + ((i * nv + aa) * nv + crc) * nv, t2 + ((j * no + k) * nv + brc) * nv,
+             nv2, 1, 1, nv_, 1.0};
+    run_term<false, VEC>(t, last, g, acc);
+    // X^{cab}_{kij}: sum_d t2[j][i][b][d] * ovvv[k][c][a][d]
+    t = Term{ovvv + ((k * nv + crc) * nv + aa) * nv, t2 + ((j * no + i) * nv + brc) * nv,
+             nv, 1, 1, nv_, 1.0};
+    run_term<false, VEC>(t, last, g, acc);
+    // X^{bca}_{jki}: -sum_l ooov[k][l][j][b] * t2[i][l][a][c]
+    t = Term{t2 + (i * no * nv + aa) * nv + crc, ooov + (k * no * no + j) * nv + brc,
+             nv, nv2, nonv, no_, -1.0};
+    run_term<false, false>(t, last, g, acc);
+    // X^{cba}_{kji}: -sum_l t2[i][l][a][b] * ooov[j][l][k][c]
+    t = Term{t2 + (i * no * nv + aa) * nv + brc, ooov + (j * no * no + k) * nv + crc,
+             nv, nv2, nonv, no_, -1.0};
+    run_term<true, false>(t, last, g, acc);
+    // X^{bac}_{jik}: -sum_l ooov[i][l][j][b] * t2[l][k][a][c]
+    t = Term{t2 + (k * nv + aa) * nv + crc, ooov + (i * no * no + j) * nv + brc,
+             nv, nonv * nv, nonv, no_, -1.0};
+    run_term<false, false>(t, last, g, acc);
+  }
+}
+
+// Map a linear block index to a tile so that the blocks the hardware places
+// on one XCD (block index mod 8) cover a contiguous range of tiles and share
+// their operand rows in that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int bid, int n) {
+  constexpr int kXcd = 8;
+  const int q = n / kXcd, r = n % kXcd;
+  const int xcd = bid % kXcd, local = bid / kXcd;
+  return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
 // Wt for one 16^3 virtual tile of one unit, written to the unit's cube
 // cube[a][b][c] (n_v^3 doubles, row-major).  Grid: x = tile (ta, tb, tc),
-// y = unit within the launch.  Block: 128 threads (wave 0: layout L2,
-// wave 1: layout L1).
-__global__ __launch_bounds__(128) void k_build_w_f64(FragDev f, int64_t u0,
-                                                     int64_t n_units,
-                                                     double* __restrict__ cube,
-                                                     int64_t cube_stride) {
+// y = unit within the launch.  Block: 256 threads; waves 0-1 build layout
+// L2 (blocks b 0-7 / 8-15), waves 2-3 layout L1 (blocks a 0-7 / 8-15).  The
+// L2 half goes through LDS and is added by the L1 waves, which store the
+// tile.  VEC: n_v is even and every input base is 16-byte aligned, so
+// d-rows can be read 16 bytes at a time.
+template <bool VEC>
+__global__ __launch_bounds__(256, SIE_BUILD_BLOCKS_PER_CU) void k_build_w_f64(FragDev f, int64_t u0,
+                                                        int64_t n_units,
+                                                        double* __restrict__ cube,
+                                                        int64_t cube_stride) {
   const int64_t u = u0 + blockIdx.y;
   if (u >= n_units) return;
   int i, j, k;
   decode_sorted_triple(u, f.no, i, j, k);
   if (i == k) return;
-  const int no = f.no, nv = f.nv;
+  const int nv = f.nv;
   const int nbk = (nv + kTile - 1) / kTile;
-  int t = blockIdx.x;
+  int t = xcd_tile(blockIdx.x, nbk * nbk * nbk);
   const int ta = t / (nbk * nbk);
   t -= ta * nbk * nbk;
   const int tb = t / nbk;
@@ -140,96 +259,38 @@ __global__ __launch_bounds__(128) void k_build_w_f64(FragDev f, int64_t u0,
   const int a0 = ta * kTile, b0 = tb * kTile, c0 = tc * kTile;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, g = lane >> 4;
-  const int64_t nv2 = (int64_t)nv * nv;
-  const int64_t nonv = (int64_t)no * nv;
+  const bool l1 = wave >= 2;
+  const int blk0 = (wave & 1) * kBlk;
 
   __shared__ double xbuf[kTile * kTile * kTile];
 
-  d4 acc[kTile];
+  d4 acc[kBlk];
 #pragma unroll
-  for (int q = 0; q < kTile; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < kBlk; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
 
-  const double* __restrict__ t2 = f.t2;
-  const double* __restrict__ ovvv = f.ovvv;
-  const double* __restrict__ ooov = f.ooov;
+  build_tile<VEC>(f.t2, f.ovvv, f.ooov, i, j, k, f.no, nv, a0, b0, c0, l1, blk0, r, g, acc);
 
-  // lane row/column indices (clamped into range, flagged when outside)
-  const int ar = a0 + r, br = b0 + r, cr = c0 + r;
-  const bool a_ok = ar < nv, b_ok = br < nv, c_ok = cr < nv;
-  const int arc = a_ok ? ar : nv - 1, brc = b_ok ? br : nv - 1, crc = c_ok ? cr : nv - 1;
-
-  if (wave == 0) {
-    // ---- layout L2: block b, rows a, cols c ----
-    const int nblk = min(kTile, nv - b0);
-    // T2 = X^{bca}_{jki}: sum_d t2[i][k][a][d] * ovvv[j][b][c][d]
-    vv_term<false>(acc, nblk, nv, g,
-                   t2 + (((int64_t)i * no + k) * nv + arc) * nv, a_ok,
-                   ovvv + (((int64_t)j * nv + b0) * nv + crc) * nv, c_ok, nv2);
-    // T5 = X^{cba}_{kji}: sum_d t2[i][j][a][d] * ovvv[k][c][b][d]
-    vv_term<false>(acc, nblk, nv, g,
-                   t2 + (((int64_t)i * no + j) * nv + arc) * nv, a_ok,
-                   ovvv + (((int64_t)k * nv + crc) * nv + b0) * nv, c_ok, nv);
-    // T6 = X^{bac}_{jik}: sum_d ovvv[j][b][a][d] * t2[k][i][c][d]
-    vv_term<true>(acc, nblk, nv, g,
-                  ovvv + (((int64_t)j * nv + b0) * nv + arc) * nv, a_ok,
-                  t2 + (((int64_t)k * no + i) * nv + crc) * nv, c_ok, nv2);
-    // O1 = X^{abc}_{ijk}: -sum_l ooov[j][l][i][a] * t2[l][k][b][c]
-    oo_term(acc, nblk, no, g,
-            ooov + ((int64_t)j * no * no + i) * nv + arc, a_ok, nonv, 0, -1.0,
-            t2 + ((int64_t)k * nv + b0) * nv + crc, c_ok, nonv * nv, nv);
-    // O4 = X^{acb}_{ikj}: -sum_l ooov[k][l][i][a] * t2[j][l][b][c]
-    oo_term(acc, nblk, no, g,
-            ooov + ((int64_t)k * no * no + i) * nv + arc, a_ok, nonv, 0, -1.0,
-            t2 + ((int64_t)j * no * nv + b0) * nv + crc, c_ok, nv2, nv);
-    // O3 = X^{cab}_{kij}: -sum_l t2[l][j][a][b] * ooov[i][l][k][c]
-    oo_term(acc, nblk, no, g,
-            t2 + ((int64_t)j * nv + arc) * nv + b0, a_ok, nonv * nv, 1, -1.0,
-            ooov + ((int64_t)i * no * no + k) * nv + crc, c_ok, nonv, 0);
-    // hand the tile to wave 1: xbuf[b][a][c]
+  if (!l1) {
+    // element v of lane (g, r) in block q holds Wt[a0 + 4v + g][b0 + blk0 + q][c0 + r]
 #pragma unroll
-    for (int q = 0; q < kTile; ++q)
+    for (int q = 0; q < kBlk; ++q)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        xbuf[(q * kTile + 4 * v + g) * kTile + r] = acc[q][v];
-  } else {
-    // ---- layout L1: block a, rows b, cols c ----
-    const int nblk = min(kTile, nv - a0);
-    // T1 = X^{abc}_{ijk}: sum_d ovvv[i][a][b][d] * t2[k][j][c][d]
-    vv_term<true>(acc, nblk, nv, g,
-                  ovvv + (((int64_t)i * nv + a0) * nv + brc) * nv, b_ok,
-                  t2 + (((int64_t)k * no + j) * nv + crc) * nv, c_ok, nv2);
-    // T4 = X^{acb}_{ikj}: sum_d t2[j][k][b][d] * ovvv[i][a][c][d]
-    vv_term<false>(acc, nblk, nv, g,
-                   t2 + (((int64_t)j * no + k) * nv + brc) * nv, b_ok,
-                   ovvv + (((int64_t)i * nv + a0) * nv + crc) * nv, c_ok, nv2);
-    // T3 = X^{cab}_{kij}: sum_d t2[j][i][b][d] * ovvv[k][c][a][d]
-    vv_term<false>(acc, nblk, nv, g,
-                   t2 + (((int64_t)j * no + i) * nv + brc) * nv, b_ok,
-                   ovvv + (((int64_t)k * nv + crc) * nv + a0) * nv, c_ok, nv);
-    // O2 = X^{bca}_{jki}: -sum_l ooov[k][l][j][b] * t2[i][l][a][c]
-    oo_term(acc, nblk, no, g,
-            ooov + ((int64_t)k * no * no + j) * nv + brc, b_ok, nonv, 0, -1.0,
-            t2 + ((int64_t)i * no * nv + a0) * nv + crc, c_ok, nv2, nv);
-    // O5 = X^{cba}_{kji}: -sum_l t2[i][l][a][b] * ooov[j][l][k][c]
-    oo_term(acc, nblk, no, g,
-            t2 + ((int64_t)i * no * nv + a0) * nv + brc, b_ok, nv2, nv, -1.0,
-            ooov + ((int64_t)j * no * no + k) * nv + crc, c_ok, nonv, 0);
-    // O6 = X^{bac}_{jik}: -sum_l ooov[i][l][j][b] * t2[l][k][a][c]
-    oo_term(acc, nblk, no, g,
-            ooov + ((int64_t)i * no * no + j) * nv + brc, b_ok, nonv, 0, -1.0,
-            t2 + ((int64_t)k * nv + a0) * nv + crc, c_ok, nonv * nv, nv);
+        xbuf[((blk0 + q) * kTile + 4 * v + g) * kTile + r] = acc[q][v];
   }
   __syncthreads();
-  if (wave == 1) {
+  if (l1) {
+    // element v of lane (g, r) in block q holds Wt[a0 + blk0 + q][b0 + 4v + g][c0 + r]
     double* __restrict__ out = cube + (int64_t)blockIdx.y * cube_stride;
     const int c = c0 + r;
 #pragma unroll
-    for (int q = 0; q < kTile; ++q) {
-      const int a = a0 + q;
+    for (int q = 0; q < kBlk; ++q) {
+      const int a = a0 + blk0 + q;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int b = b0 + 4 * v + g;
-        const double w = acc[q][v] + xbuf[(b - b0) * kTile * kTile + q * kTile + r];
+        const int bl = 4 * v + g;
+        const int b = b0 + bl;
+        const double w = acc[q][v] + xbuf[(bl * kTile + blk0 + q) * kTile + r];
         if (a < nv && b < nv && c < nv) out[((int64_t)a * nv + b) * nv + c] = w;
       }
     }

@@ -257,12 +257,18 @@ sie_status sie_triples_energy(const sie_fragment* f, sie_precision p, double* e_
   const int nbk = (nv + sie::kTile - 1) / sie::kTile;
   const unsigned n_tiles = unsigned(nbk) * unsigned(nbk) * unsigned(nbk);
   const int64_t cube_stride = int64_t(pl.cube_bytes / sizeof(double));
+  // 16-byte row reads need an even row length and 16-byte aligned bases
+  const bool vec = (nv % 2 == 0) && aligned(f->t2, 16) && aligned(f->ovvv, 16);
   for (int64_t u0 = 0; u0 < pl.n_units; u0 += chunk) {
     const int64_t cnt = (pl.n_units - u0) < chunk ? (pl.n_units - u0) : chunk;
     {
       ProfScope ps(s, 0);
-      hipLaunchKernelGGL(sie::k_build_w_f64, dim3(n_tiles, unsigned(cnt)), dim3(128), 0, s, fd,
-                         u0, pl.n_units, d_cube, cube_stride);
+      if (vec)
+        hipLaunchKernelGGL(sie::k_build_w_f64<true>, dim3(n_tiles, unsigned(cnt)), dim3(256), 0,
+                           s, fd, u0, pl.n_units, d_cube, cube_stride);
+      else
+        hipLaunchKernelGGL(sie::k_build_w_f64<false>, dim3(n_tiles, unsigned(cnt)), dim3(256), 0,
+                           s, fd, u0, pl.n_units, d_cube, cube_stride);
     }
     {
       ProfScope ps(s, 1);
