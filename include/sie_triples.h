@@ -88,15 +88,31 @@ typedef struct {
 #define SIE_MAX_OCC 256
 #define SIE_MAX_VIR 2048
 
+/* Gradient outputs of one fragment for sie_triples_backward: device float64
+ * arrays with the shapes of the inputs of the same name, or NULL to skip that
+ * input's gradient. */
+typedef struct {
+  double* t1;
+  double* t2;
+  double* ovvv;
+  double* ooov;
+  double* ovov;
+} sie_fragment_grad;
+
 /* Number of unordered occupied triples i >= j >= k of a fragment:
  * n_occ (n_occ + 1) (n_occ + 2) / 6.  Per-triple outputs are indexed by
  * u = i (i+1) (i+2) / 6 + j (j+1) / 2 + k. */
 int64_t sie_occupied_triples(int32_t n_occ);
 
-/* Workspace bytes the energy entry points need for `n` fragments at
- * precision `p`, given at most `max_bytes` may be used (0 = the library's
- * default cap of 2 GiB).  Larger workspaces let more occupied triples run per
- * launch.  Returns 0 if the arguments are invalid (see sie_last_error()). */
+/* Workspace bytes the energy entry points need for the `n` fragments
+ * frags[0..n-1] (host array) at precision `p`, given that at most `max_bytes`
+ * may be used (0 = the library's default cap of 2 GiB, or the value of the
+ * environment variable SIE_MAX_WORKSPACE_BYTES).  Beyond a fixed part (tables,
+ * per-triple partial sums and, for SIE_SPLIT_BF16, the bf16 hi/lo copies of
+ * the float32 inputs) the workspace holds the W-tilde cubes of as many
+ * occupied triples as fit; a larger workspace means fewer launches.  Returns 0
+ * if the arguments are invalid or the minimum exceeds the cap (see
+ * sie_last_error()). */
 size_t sie_triples_workspace_size(const sie_fragment* frags, int32_t n,
                                   sie_precision p, size_t max_bytes);
 
@@ -106,12 +122,63 @@ size_t sie_triples_workspace_size(const sie_fragment* frags, int32_t n,
  *   e_triples  device float64 [sie_occupied_triples(n_occ)] or NULL: receives
  *            the contribution of each unordered occupied triple {i, j, k}
  *            (their sum is E_x)
- *   ws       device workspace of ws_bytes >= the size reported for this
- *            fragment and precision; its contents on entry are ignored
- * Deterministic: the same inputs give bitwise the same outputs. */
+ *   ws       device workspace of ws_bytes >= sie_triples_workspace_size(frag,
+ *            1, p, cap) for some cap; its contents on entry are ignored
+ * Deterministic: the same inputs give bitwise the same outputs.  The call
+ * waits for work already queued on `stream` while it uploads its small tables
+ * (fragment descriptors, orbital energies, work list), then returns before
+ * its own kernels finish. */
 sie_status sie_triples_energy(const sie_fragment* frag, sie_precision p,
                               double* e_out, double* e_triples,
                               void* ws, size_t ws_bytes, void* stream);
+
+/* E_x of each of n fragments and E = sum_x E_x (equation C_f), in one
+ * evaluation: the occupied triples of all fragments form one work list,
+ * ordered longest first, run in as few launches as the workspace allows.
+ *   frags    host array of n >= 1 descriptors, same rules as above
+ *   e_frag   device float64 [n]: E_x per fragment
+ *   e_total  device float64 [1] or NULL: the sum over fragments
+ *   ws       >= sie_triples_workspace_size(frags, n, p, cap) bytes
+ * E_x equals what sie_triples_energy gives for the fragment alone (bitwise:
+ * the per-fragment reductions run in the same fixed order).  Deterministic;
+ * same stream behaviour as sie_triples_energy. */
+sie_status sie_triples_energy_batched(const sie_fragment* frags, int32_t n,
+                                      sie_precision p, double* e_frag,
+                                      double* e_total, void* ws, size_t ws_bytes,
+                                      void* stream);
+
+/* Workspace bytes sie_triples_backward needs for the n fragments frags[0..n-1]
+ * (host array), with the same cap rule as sie_triples_workspace_size; the
+ * backward workspace also holds its contraction lists.  Returns 0 if the
+ * arguments are invalid or the minimum exceeds the cap. */
+size_t sie_triples_backward_workspace_size(const sie_fragment* frags, int32_t n,
+                                           sie_precision p, size_t max_bytes);
+
+/* Gradient of E_x (same equation and readings as sie_triples_energy, C^f =
+ * identity) with respect to t1, t2, ovvv, ooov and ovov of each of n
+ * fragments.  The energy is not printed as differentiated in the paper; the
+ * gradient is the exact adjoint of the energy as computed here: with
+ * G = w (R'[Wt] + R'[Wt + Vt]) / D and H = w R'[Wt] / D per occupied triple
+ * (w = 2 A_ijk, R' the virtual-index form of R), every contraction that builds
+ * Wt is transposed against G and every V-tilde product against H.  Wt is
+ * recomputed, not stored.
+ *   frags    host array of n >= 1 descriptors (as for the energy); p must be
+ *            SIE_FP64 (SIE_SPLIT_BF16 returns SIE_ERR_UNSUPPORTED)
+ *   grad_e   device float64 [n], the upstream derivative dL/dE_x, or NULL
+ *            for all ones
+ *   grads    host array [n]; each non-NULL pointer is OVERWRITTEN with
+ *            grad_e[x] * dE_x / d(input), symmetrized over the input's
+ *            index-symmetry orbit (the mean over t_ij^ab and t_ji^ba, over
+ *            (ia|bc) and (ia|cb), over (jl|ia) and (lj|ia), over (ia|jb) and
+ *            (jb|ia)), so the result does not depend on which twin the
+ *            kernels read.  Gradient arrays must not overlap the inputs.
+ *   e_frag   device float64 [n] or NULL: receives E_x
+ *   ws       >= sie_triples_backward_workspace_size(frags, n, p, cap) bytes
+ * Deterministic (fixed summation order, no atomics); same stream behaviour as
+ * sie_triples_energy.  Cost about three times the energy's. */
+sie_status sie_triples_backward(const sie_fragment* frags, int32_t n, sie_precision p,
+                                const double* grad_e, const sie_fragment_grad* grads,
+                                double* e_frag, void* ws, size_t ws_bytes, void* stream);
 
 /* Kernel timing (diagnostics).  While enabled on the calling thread, every
  * launch made by the entry points above is bracketed by two HIP events on the
@@ -119,8 +186,10 @@ sie_status sie_triples_energy(const sie_fragment* frag, sie_precision p,
  * summed elapsed milliseconds and the launch count per kernel class into
  * ms[SIE_PROF_CLASSES] and launches[SIE_PROF_CLASSES] (host arrays), and
  * clears the record.  Classes: 0 = Wt build, 1 = R/D epilogue,
- * 2 = reductions.  Enabling or disabling also clears the record. */
-#define SIE_PROF_CLASSES 3
+ * 2 = reductions, 3 = split staging (SIE_SPLIT_BF16 only), 4 = gradient
+ * contractions (sie_triples_backward; its G/H kernel counts as class 1).
+ * Enabling or disabling also clears the record. */
+#define SIE_PROF_CLASSES 5
 void sie_profile_enable(int on);
 sie_status sie_profile_collect(double* ms, int64_t* launches);
 

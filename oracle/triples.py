@@ -151,16 +151,23 @@ def energy_literal(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov,
 
 
 def energy_literal_vectorized(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov,
-                              a_values=None, return_parts=False):
+                              a_values=None, return_parts=False, x_terms=None):
     """Same sum as `energy_literal` (C = I), with the innermost c loop done as
     one batched contraction per (a, b) pair.
 
     a_values restricts the outer loop (for splitting the work over processes;
     the full energy is the fsum of the parts over a partition of range(n_v)).
     Returns the partial sum over the given a values.
+
+    x_terms, if given, is a list of (ovvv', ooov', t2') triples: X is then the
+    sum of the brackets of eq. W_in_CCSD_T evaluated with each triple (X is
+    bilinear in the integrals and t2, so this expresses products of split
+    operands).  t2, ovvv and ooov are then used only for their shapes.
     """
     eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov = _check(
         eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov)
+    terms = [(ovvv, ooov, t2)] if x_terms is None else [
+        tuple(np.asarray(x, np.float64) for x in tr) for tr in x_terms]
     o, v = eps_occ.shape[0], eps_vir.shape[0]
     e3 = (eps_occ[:, None, None] + eps_occ[None, :, None]
           + eps_occ[None, None, :])
@@ -168,11 +175,14 @@ def energy_literal_vectorized(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov,
 
     def x_gen(A, B, C):
         """X^{abc}_{ijk} for a in A, b in B, c in C (slices): array [a, b, c, i, j, k]."""
-        vv = np.einsum("iabd,kjcd->abcijk", ovvv[:, A, B, :], t2[:, :, C, :],
-                       optimize=True)
-        oo = np.einsum("jlia,lkbc->abcijk", ooov[:, :, :, A], t2[:, :, B, C],
-                       optimize=True)
-        return vv - oo
+        out = 0.0
+        for (vvvi, oooi, tt) in terms:
+            vv = np.einsum("iabd,kjcd->abcijk", vvvi[:, A, B, :], tt[:, :, C, :],
+                           optimize=True)
+            oo = np.einsum("jlia,lkbc->abcijk", oooi[:, :, :, A], tt[:, :, B, C],
+                           optimize=True)
+            out = out + (vv - oo)
+        return out
 
     def u_gen(A, B, C):
         """U^{abc}_{ijk} = (ia|jb) t_k^c for slices A, B, C: array [a, b, c, i, j, k]."""

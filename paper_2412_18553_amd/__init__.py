@@ -19,7 +19,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import SieError, SieFragment  # noqa: F401
+from ._lib import SieError, SieFragment, SieFragmentGrad  # noqa: F401
 
 PRECISIONS = {"fp64": _lib.SIE_FP64, "split_bf16": _lib.SIE_SPLIT_BF16}
 INPUT_DTYPE = {"fp64": torch.float64, "split_bf16": torch.float32}
@@ -84,10 +84,25 @@ class Fragment:
         return occupied_triples(self.n_occ)
 
 
-def workspace_size(frag: Fragment, max_bytes: int = 0) -> int:
+def _desc_array(frags):
+    frags = [frags] if isinstance(frags, Fragment) else list(frags)
+    if not frags:
+        raise ValueError("need at least one fragment")
+    prec = {f.precision for f in frags}
+    if len(prec) != 1:
+        raise ValueError("all fragments of one evaluation must share the precision")
+    dev = {f.device for f in frags}
+    if len(dev) != 1:
+        raise ValueError("all fragments of one evaluation must be on one GPU")
+    arr = (SieFragment * len(frags))(*[f.desc for f in frags])
+    return frags, arr, PRECISIONS[frags[0].precision]
+
+
+def workspace_size(frags, max_bytes: int = 0) -> int:
+    """Workspace bytes for one fragment or a list of fragments (see the C header)."""
     lib = _lib.load()
-    n = lib.sie_triples_workspace_size(ctypes.byref(frag.desc), 1,
-                                       PRECISIONS[frag.precision], max_bytes)
+    frags, arr, prec = _desc_array(frags)
+    n = lib.sie_triples_workspace_size(arr, len(frags), prec, max_bytes)
     if n == 0:
         raise SieError(_lib.SIE_ERR_INVALID_ARG, _lib.last_error())
     return int(n)
@@ -118,6 +133,124 @@ def energy(frag: Fragment, *, workspace: torch.Tensor | None = None,
                                 workspace.data_ptr(), workspace.numel(), stream)
     _lib.check(st)
     return out
+
+
+def energy_batched(frags, *, workspace: torch.Tensor | None = None,
+                   out: torch.Tensor | None = None, total: torch.Tensor | None = None,
+                   max_workspace_bytes: int = 0):
+    """Enqueue E_x for every fragment of `frags` (one evaluation, one work
+    list) on the current stream; returns (e_frag [n], e_total [1]) float64
+    device tensors."""
+    lib = _lib.load()
+    frags, arr, prec = _desc_array(frags)
+    device = frags[0].device
+    if workspace is None:
+        workspace = torch.empty(workspace_size(frags, max_workspace_bytes), dtype=torch.uint8,
+                                device=device)
+    if workspace.dtype != torch.uint8 or not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous uint8 CUDA tensor")
+    if out is None:
+        out = torch.empty(len(frags), dtype=torch.float64, device=device)
+    if total is None:
+        total = torch.empty(1, dtype=torch.float64, device=device)
+    if out.numel() != len(frags) or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor with one entry per fragment")
+    stream = torch.cuda.current_stream(device).cuda_stream
+    st = lib.sie_triples_energy_batched(arr, len(frags), prec, out.data_ptr(), total.data_ptr(),
+                                        workspace.data_ptr(), workspace.numel(), stream)
+    _lib.check(st)
+    return out, total
+
+
+GRAD_NAMES = ("t1", "t2", "ovvv", "ooov", "ovov")
+
+
+def backward_workspace_size(frags, max_bytes: int = 0) -> int:
+    """Workspace bytes of `backward` for one fragment or a list (see the C header)."""
+    lib = _lib.load()
+    frags, arr, prec = _desc_array(frags)
+    n = lib.sie_triples_backward_workspace_size(arr, len(frags), prec, max_bytes)
+    if n == 0:
+        raise SieError(_lib.SIE_ERR_INVALID_ARG, _lib.last_error())
+    return int(n)
+
+
+def backward(frags, *, grad_e: torch.Tensor | None = None, grads=None,
+             e_frag: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+             max_workspace_bytes: int = 0, want=GRAD_NAMES):
+    """Enqueue the gradient of E_x for each fragment on the current stream.
+
+    Returns a list (one dict per fragment) of float64 device tensors
+    {name: grad_e[x] * dE_x/d name} for the names in `want`, symmetrized over
+    each input's index-symmetry orbit.  `grads`, if given, is such a list of
+    preallocated tensors to overwrite.  `grad_e`: float64 device tensor [n]
+    or None (ones).  `e_frag`: optional float64 [n] receiving E_x."""
+    lib = _lib.load()
+    single = isinstance(frags, Fragment)
+    frags, arr, prec = _desc_array(frags)
+    device = frags[0].device
+    if grads is None:
+        grads = [{name: torch.empty_like(getattr(f, name), dtype=torch.float64)
+                  for name in want} for f in frags]
+    if len(grads) != len(frags):
+        raise ValueError("grads needs one dict per fragment")
+    garr = (SieFragmentGrad * len(frags))()
+    for x, (f, g) in enumerate(zip(frags, grads)):
+        for name in GRAD_NAMES:
+            t = g.get(name)
+            if t is None:
+                continue
+            ref = getattr(f, name)
+            if (not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or
+                    t.shape != ref.shape or not t.is_contiguous() or t.device != device):
+                raise ValueError(f"grads[{x}][{name!r}] must be a contiguous float64 tensor "
+                                 f"of shape {tuple(ref.shape)} on {device}")
+            setattr(garr[x], name, t.data_ptr())
+    if grad_e is not None:
+        if (grad_e.dtype != torch.float64 or grad_e.numel() != len(frags) or
+                not grad_e.is_contiguous() or grad_e.device != device):
+            raise ValueError("grad_e must be a contiguous float64 tensor with one entry per fragment")
+    if e_frag is not None:
+        if (e_frag.dtype != torch.float64 or e_frag.numel() != len(frags) or
+                not e_frag.is_contiguous() or e_frag.device != device):
+            raise ValueError("e_frag must be a contiguous float64 tensor with one entry per fragment")
+    if workspace is None:
+        workspace = torch.empty(backward_workspace_size(frags, max_workspace_bytes),
+                                dtype=torch.uint8, device=device)
+    if workspace.dtype != torch.uint8 or not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous uint8 CUDA tensor")
+    stream = torch.cuda.current_stream(device).cuda_stream
+    st = lib.sie_triples_backward(arr, len(frags), prec,
+                                  None if grad_e is None else grad_e.data_ptr(), garr,
+                                  None if e_frag is None else e_frag.data_ptr(),
+                                  workspace.data_ptr(), workspace.numel(), stream)
+    _lib.check(st)
+    return grads[0] if single else grads
+
+
+class SieTriples(torch.autograd.Function):
+    """E_x as a differentiable function of (t1, t2, ovvv, ooov, ovov).
+
+    SieTriples.apply(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov) returns a 0-d
+    float64 tensor; backward calls the library's adjoint (float64 only) and
+    returns symmetrized gradients cast to each input's dtype."""
+
+    @staticmethod
+    def forward(ctx, eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov):
+        frag = Fragment(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, "fp64")
+        ctx.frag = frag
+        return energy(frag)[0].clone()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        frag = ctx.frag
+        want = [name for name, need in zip(GRAD_NAMES, ctx.needs_input_grad[2:]) if need]
+        if not want:
+            return (None,) * 7
+        ge = grad_out.detach().reshape(1).to(device=frag.device, dtype=torch.float64).contiguous()
+        g = backward(frag, grad_e=ge, want=want)
+        return (None, None) + tuple(
+            g[name].to(getattr(frag, name).dtype) if name in g else None for name in GRAD_NAMES)
 
 
 def triples_energy(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, *, precision="fp64",

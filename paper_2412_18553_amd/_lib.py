@@ -26,9 +26,10 @@ STATUS_NAMES = {0: "SIE_OK", 1: "SIE_ERR_INVALID_ARG", 2: "SIE_ERR_UNSUPPORTED",
 
 # every symbol include/sie_triples.h declares
 EXPORTED = ["sie_abi_version", "sie_last_error", "sie_occupied_triples",
-            "sie_triples_workspace_size", "sie_triples_energy",
+            "sie_triples_workspace_size", "sie_triples_energy", "sie_triples_energy_batched",
+            "sie_triples_backward_workspace_size", "sie_triples_backward",
             "sie_profile_enable", "sie_profile_collect"]
-PROF_CLASSES = ("w_build", "epilogue", "reduce")
+PROF_CLASSES = ("w_build", "epilogue", "reduce", "split", "grad")
 
 
 class SieFragment(ctypes.Structure):
@@ -44,6 +45,10 @@ class SieFragment(ctypes.Structure):
         ("ovov", ctypes.c_void_p),
         ("frag_proj", ctypes.c_void_p),
     ]
+
+
+class SieFragmentGrad(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in ("t1", "t2", "ovvv", "ooov", "ovov")]
 
 
 class SieError(RuntimeError):
@@ -77,6 +82,19 @@ def load() -> ctypes.CDLL:
     lib.sie_triples_energy.argtypes = [ctypes.POINTER(SieFragment), ctypes.c_int,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_size_t, ctypes.c_void_p]
+    lib.sie_triples_energy_batched.restype = ctypes.c_int
+    lib.sie_triples_energy_batched.argtypes = [ctypes.POINTER(SieFragment), ctypes.c_int32,
+                                               ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.sie_triples_backward_workspace_size.restype = ctypes.c_size_t
+    lib.sie_triples_backward_workspace_size.argtypes = [ctypes.POINTER(SieFragment),
+                                                        ctypes.c_int32, ctypes.c_int,
+                                                        ctypes.c_size_t]
+    lib.sie_triples_backward.restype = ctypes.c_int
+    lib.sie_triples_backward.argtypes = [ctypes.POINTER(SieFragment), ctypes.c_int32,
+                                         ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.POINTER(SieFragmentGrad), ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.sie_profile_enable.restype = None
     lib.sie_profile_enable.argtypes = [ctypes.c_int]
     lib.sie_profile_collect.restype = ctypes.c_int

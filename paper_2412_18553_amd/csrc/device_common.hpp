@@ -7,6 +7,21 @@
 namespace sie {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));   // 8 bf16 or 16 bytes
+
+// Global-address-space views of generic pointers: loads through them are
+// global (vmcnt only), not flat (which also counts against the LDS counter
+// and would make every LDS wait also wait for in-flight prefetches).
+#define SIE_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const SIE_GLOBAL T* gptr(const T* p) {
+  return (const SIE_GLOBAL T*)(p);
+}
+template <typename T>
+__device__ __forceinline__ SIE_GLOBAL T* gptr_w(T* p) {
+  return (SIE_GLOBAL T*)(p);
+}
 
 // D(16x16, f64) += A(16x4) * B(4x16) on the matrix cores.
 // Operand layout (one f64 per lane): A[row = lane % 16][k = lane / 16],

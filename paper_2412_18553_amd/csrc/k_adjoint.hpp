@@ -1,0 +1,748 @@
+// Adjoint (gradient) kernels of the float64 (T) energy.
+//
+// With the energy written per unordered occupied triple ("unit") u = (i, j, k),
+//   E = sum_u w_u sum_abc Wt R'[Wt + Vt] / D,      w_u = 2 A_ijk,
+// and R' symmetric under the abc inner product (its cyclic terms are each
+// other's transposes, its transpositions their own) with D symmetric in abc,
+//   dE = sum_u sum_abc G dWt + H dVt,
+//   G = w_u (R'[Wt] + R'[Wt + Vt]) / D,     H = w_u R'[Wt] / D.
+// Wt of a unit is the sum of the twelve contractions the forward build
+// evaluates (six over d, six over l; see k_fp64.hpp); the gradient with
+// respect to each contraction's two operands is a contraction of G with the
+// other operand.  Vt = (ia|jb) t_k^c + (ia|kc) t_j^b + (jb|kc) t_i^a gives
+// the t1 and ovov parts from H.
+//
+// Per round of units (cubes resident in the workspace arena):
+//   k_hat            Wt partial cubes -> G, H in place (and the unit energies)
+//   k_adj_contract   the 24 G contractions, grouped by output slice
+//   k_adj_ovov/t1    the H contractions
+// Every launch owns each output element it writes (the host groups all of a
+// round's contributions to one output slice into one list, summed in a fixed
+// order by the work-groups that own the slice's tiles), so the gradient is a
+// plain read-modify-write sum without atomics and bitwise reproducible.
+#pragma once
+
+#include "device_common.hpp"
+#include "k_fp64.hpp"
+#include "work.hpp"
+
+namespace sie {
+
+// ---------------------------------------------------------------------------
+// G and H, in place of the two partial cubes of each unit.
+// ---------------------------------------------------------------------------
+
+// Same orbit traversal as k_epilogue (float64 partial cubes, Wt[a][b][c] =
+// P1[a][b][c] + P2[b][a][c]): the work-group that reads an orbit's blocks of
+// both cubes writes G[a][b][c] over the first and H[a][b][c] over the second
+// at exactly those blocks.  Also
+// writes the unit's energy partials (as k_epilogue).  grad_e[frag] (or 1)
+// scales G and H.
+__global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
+                                             const Item* __restrict__ items, int n_items,
+                                             double* __restrict__ arena,
+                                             double* __restrict__ partials, int pstride,
+                                             const double* __restrict__ grad_e) {
+  const int r = find_item<false>(items, n_items, blockIdx.x);
+  const int64_t start = r ? items[r - 1].part_end : 0;
+  const Item it = items[r];
+  const FragDesc fd = descs[it.frag];
+  const int slot = int(int64_t(blockIdx.x) - start);
+  int i, j, k;
+  decode_sorted_triple(it.unit, fd.no, i, j, k);
+  __shared__ double sw[6][kOrb * kOrb * kOrb];
+  __shared__ double sz[6][kOrb * kOrb * kOrb];
+  __shared__ double red[4];
+  double* out = partials + (fd.unit_base + it.unit) * pstride + slot;
+  if (i == k) {
+    if (threadIdx.x == 0) *out = 0.0;
+    return;
+  }
+  const double* __restrict__ t1 = static_cast<const double*>(fd.t1);
+  const double* __restrict__ ovov = static_cast<const double*>(fd.ovov);
+  const double* __restrict__ eps = fd.eps;
+  const int no = fd.no, nv = fd.nv;
+  const int nb = (nv + kOrb - 1) / kOrb;
+  const int64_t n_orb = tetra(nb);
+  const double* __restrict__ ev = eps + no;
+  const double eijk = gptr(eps)[i] + gptr(eps)[j] + gptr(eps)[k];
+  const double scale = ((i == j || j == k) ? 1.0 : 2.0) * (grad_e ? gptr(grad_e)[it.frag] : 1.0);
+  double* __restrict__ w1 = arena + it.cube_off;
+  double* __restrict__ w2 = w1 + fd.half;
+  const int64_t nonv = (int64_t)no * nv;
+  const double* ov_ij = ovov + (int64_t)i * nv * nonv + (int64_t)j * nv;
+  const double* ov_ik = ovov + (int64_t)i * nv * nonv + (int64_t)k * nv;
+  const double* ov_jk = ovov + (int64_t)j * nv * nonv + (int64_t)k * nv;
+  const double* t1i = t1 + (int64_t)i * nv;
+  const double* t1j = t1 + (int64_t)j * nv;
+  const double* t1k = t1 + (int64_t)k * nv;
+  constexpr int E = kOrb * kOrb * kOrb;
+
+  double acc = 0.0;
+  for (int64_t o = slot; o < n_orb; o += fd.n_part) {
+    int t0, t1b, t2b;
+    decode_sorted_triple(o, nb, t0, t1b, t2b);
+    for (int idx = threadIdx.x; idx < 6 * E; idx += 256) {
+      const int s = idx / E, e = idx - s * E;
+      int p0, p1, p2;
+      slot_perm(s, p0, p1, p2);
+      const int a = kOrb * pick3(p0, t0, t1b, t2b) + (e >> 6);
+      const int b = kOrb * pick3(p1, t0, t1b, t2b) + ((e >> 3) & 7);
+      const int c = kOrb * pick3(p2, t0, t1b, t2b) + (e & 7);
+      double w = 0.0, z = 0.0;
+      if (a < nv && b < nv && c < nv) {
+        w = gptr(w1)[((int64_t)a * nv + b) * nv + c] + gptr(w2)[((int64_t)b * nv + a) * nv + c];
+        const double vt = gptr(ov_ij)[(int64_t)a * nonv + b] * gptr(t1k)[c] +
+                          gptr(ov_ik)[(int64_t)a * nonv + c] * gptr(t1j)[b] +
+                          gptr(ov_jk)[(int64_t)b * nonv + c] * gptr(t1i)[a];
+        z = w + vt;
+      }
+      sw[s][e] = w;
+      sz[s][e] = z;
+    }
+    __syncthreads();
+    unsigned primary = 0;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      int p0, p1, p2;
+      slot_perm(s, p0, p1, p2);
+      bool dup = false;
+#pragma unroll
+      for (int s2 = 0; s2 < s; ++s2) {
+        int q0, q1, q2;
+        slot_perm(s2, q0, q1, q2);
+        dup |= pick3(p0, t0, t1b, t2b) == pick3(q0, t0, t1b, t2b) &&
+               pick3(p1, t0, t1b, t2b) == pick3(q1, t0, t1b, t2b) &&
+               pick3(p2, t0, t1b, t2b) == pick3(q2, t0, t1b, t2b);
+      }
+      if (!dup) primary |= 1u << s;
+    }
+    for (int idx = threadIdx.x; idx < 6 * E; idx += 256) {
+      const int s = idx / E, e = idx - s * E;
+      if (!((primary >> s) & 1u)) continue;
+      int p0, p1, p2;
+      slot_perm(s, p0, p1, p2);
+      const int x = e >> 6, y = (e >> 3) & 7, zz = e & 7;
+      const int a = kOrb * pick3(p0, t0, t1b, t2b) + x;
+      const int b = kOrb * pick3(p1, t0, t1b, t2b) + y;
+      const int c = kOrb * pick3(p2, t0, t1b, t2b) + zz;
+      if (a >= nv || b >= nv || c >= nv) continue;
+      const int e_cab = (zz << 6) | (x << 3) | y, s_cab = orbit_slot(p2, p0, p1);
+      const int e_bca = (y << 6) | (zz << 3) | x, s_bca = orbit_slot(p1, p2, p0);
+      const int e_cba = (zz << 6) | (y << 3) | x, s_cba = orbit_slot(p2, p1, p0);
+      const int e_acb = (x << 6) | (zz << 3) | y, s_acb = orbit_slot(p0, p2, p1);
+      const int e_bac = (y << 6) | (x << 3) | zz, s_bac = orbit_slot(p1, p0, p2);
+      const double rz = 4.0 * sz[s][e] + sz[s_cab][e_cab] + sz[s_bca][e_bca] -
+                        2.0 * (sz[s_cba][e_cba] + sz[s_acb][e_acb] + sz[s_bac][e_bac]);
+      const double rw = 4.0 * sw[s][e] + sw[s_cab][e_cab] + sw[s_bca][e_bca] -
+                        2.0 * (sw[s_cba][e_cba] + sw[s_acb][e_acb] + sw[s_bac][e_bac]);
+      const double d = eijk - gptr(ev)[a] - gptr(ev)[b] - gptr(ev)[c];
+      acc += sw[s][e] * rz / d;
+      const int64_t pos = ((int64_t)a * nv + b) * nv + c;
+      gptr_w(w1)[pos] = scale * (rw + rz) / d;
+      gptr_w(w2)[pos] = scale * rw / d;
+    }
+    __syncthreads();
+  }
+  const double s = block_sum_256(acc, red);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// ---------------------------------------------------------------------------
+// Contractions of G: output-stationary grouped products on the FP64 matrix
+// cores.
+// ---------------------------------------------------------------------------
+
+enum AdjClass {
+  kAdjOvvv = 0,   // dE/d ovvv[x]       per-block tiles (block, row, col)
+  kAdjT2oo = 1,   // dE/d t2[p][*] from the l-sums, per-block tiles
+  kAdjT2vv = 2,   // dE/d t2[s1][s2] from the d-sums, summed-block tiles
+  kAdjOoov = 3,   // dE/d ooov[m][*][n][*], summed-block tiles
+  kAdjOvov = 4,   // dE/d ovov[p][*][q][*] from H
+  kAdjT1 = 5,     // dE/d t1[p] from H
+  kAdjClasses = 6
+};
+
+// Output slice (a0, a1) that term `kind` of class `cls` writes for the unit
+// (i, j, k); a1 = 0 for classes with a single slice index.
+template <typename T>
+__host__ __device__ __forceinline__ T pick6(int q, T v0, T v1, T v2, T v3, T v4, T v5) {
+  return q == 0 ? v0 : q == 1 ? v1 : q == 2 ? v2 : q == 3 ? v3 : q == 4 ? v4 : v5;
+}
+
+__host__ __device__ inline void adj_slice(int cls, int kind, int i, int j, int k, int& a0,
+                                          int& a1) {
+  a1 = 0;
+  switch (cls) {
+    case kAdjOvvv: a0 = pick6(kind, i, i, k, j, k, j); break;
+    case kAdjT2oo: a0 = pick6(kind, i, i, k, k, j, j); break;
+    case kAdjT2vv:
+      a0 = pick6(kind, k, j, j, i, i, k);
+      a1 = pick6(kind, j, k, i, k, j, i);
+      break;
+    case kAdjOoov:
+      a0 = pick6(kind, k, j, i, j, k, i);
+      a1 = pick6(kind, j, k, j, i, i, k);
+      break;
+    case kAdjOvov:
+      a0 = pick6(kind, i, i, j, 0, 0, 0);
+      a1 = pick6(kind, j, k, k, 0, 0, 0);
+      break;
+    default: a0 = pick6(kind, k, j, i, 0, 0, 0); break;   // kAdjT1
+  }
+}
+
+__host__ __device__ inline int adj_kinds(int cls) { return cls >= kAdjOvov ? 3 : 6; }
+// Summed-block classes split the first summed virtual index into groups of kABB.
+__host__ __device__ inline bool adj_reduce(int cls) { return cls == kAdjT2vv || cls == kAdjOoov; }
+
+struct AdjGroup {
+  int frag;
+  int a0, a1;          // output slice
+  int rec_begin, rec_end;
+  int pad;
+  int64_t wg_end;      // inclusive prefix sum of work-groups over the launch
+};
+
+struct AdjRec {
+  int item;            // index into the round's items
+  int kind;            // term of the class
+  int g;               // block group (summed-block classes), else 0
+  int pad;
+};
+
+constexpr int kABB = 8;        // blocks per work-group
+constexpr int kAR = 64;        // MFMA rows per work-group
+constexpr int kAC = 32;        // MFMA cols per work-group
+constexpr int kAKc = 8;        // K chunk
+constexpr int kAPlanes = kAKc / 2;
+constexpr int kAThreads = 64 * (kAR / 16) * (kAC / 16);
+constexpr int kALdsB = kABB * kAR;                 // first LDS row of the B side
+constexpr int kALdsRows = kABB * kAR + kABB * kAC;
+static_assert(kAPlanes == 4, "one k-pair plane per MFMA lane group");
+
+// Element (beta, x, k) of the A side (rows, always G) is a[beta*a_b + x*a_x + k*a_k];
+// of the B side (cols) b[beta*b_b + x*b_x + k*b_k] with b_b = 0 when the B side
+// is shared by all blocks.
+struct ATerm {
+  const double* a;
+  int64_t a_b, a_x, a_k;
+  const double* b;
+  int64_t b_b, b_x, b_k;
+  double scale;        // applied to the B side
+  int nblk;            // valid blocks (summed-block classes); per-block: the tile's
+};
+
+template <int CLS>
+__device__ __forceinline__ ATerm make_adj(int kind, int g, int i, int j, int k, int no_, int nv_,
+                                          const double* G, const double* t2, const double* ovvv,
+                                          const double* ooov, int blk0, int row0, int col0) {
+  const int64_t nv = nv_, no = no_, nv2 = nv * nv;
+  const int64_t sA = nv2, sB = nv, sC = 1;
+  ATerm t;
+  t.scale = 1.0;
+  t.nblk = kABB;
+  if (CLS == kAdjOvvv) {
+    // dovvv[x][p][q][d] += sum_r Gperm[p][q][r] t2[s1][s2][r][d]
+    const int64_t Sb = pick6(kind, sA, sA, sC, sB, sC, sB);
+    const int64_t Sx = pick6(kind, sB, sC, sA, sC, sB, sA);
+    const int64_t Sk = pick6(kind, sC, sB, sB, sA, sA, sC);
+    const int64_t s1 = pick6(kind, k, j, j, i, i, k), s2 = pick6(kind, j, k, i, k, j, i);
+    t.a = G + blk0 * Sb + row0 * Sx;
+    t.a_b = Sb; t.a_x = Sx; t.a_k = Sk;
+    t.b = t2 + (s1 * no + s2) * nv2 + col0;
+    t.b_b = 0; t.b_x = 1; t.b_k = nv;
+  } else if (CLS == kAdjT2oo) {
+    // dt2[p][l][y][z] += -sum_K Gperm[y][z][K] ooov[m][l][n][K]
+    const int64_t Sy = pick6(kind, sA, sA, sC, sC, sB, sB);
+    const int64_t Sz = pick6(kind, sC, sB, sA, sB, sC, sA);
+    const int64_t SK = pick6(kind, sB, sC, sB, sA, sA, sC);
+    const int64_t m = pick6(kind, k, j, i, j, k, i), n = pick6(kind, j, k, j, i, i, k);
+    t.a = G + blk0 * Sy + row0 * Sz;
+    t.a_b = Sy; t.a_x = Sz; t.a_k = SK;
+    t.b = ooov + ((m * no + col0) * no + n) * nv;
+    t.b_b = 0; t.b_x = no * nv; t.b_k = 1;
+    t.scale = -1.0;
+  } else if (CLS == kAdjT2vv) {
+    // dt2[s1][s2][r][d] += sum_{k1, k2} Gperm[k1][r][k2] ovvv[x][..k1..k2..][d]
+    const int64_t Ab = pick6(kind, sA, sA, sA, sB, sB, sA);
+    const int64_t Ax = pick6(kind, sC, sB, sB, sA, sA, sC);
+    const int64_t Ak = pick6(kind, sB, sC, sC, sC, sC, sB);
+    const int64_t Bb = pick6(kind, nv2, nv2, nv, nv2, nv, nv);
+    const int64_t Bk = pick6(kind, nv, nv, nv2, nv, nv2, nv2);
+    const int64_t x = pick6(kind, i, i, k, j, k, j);
+    const int64_t k10 = int64_t(g) * kABB;
+    t.a = G + k10 * Ab + row0 * Ax;
+    t.a_b = Ab; t.a_x = Ax; t.a_k = Ak;
+    t.b = ovvv + x * nv2 * nv + k10 * Bb + col0;
+    t.b_b = Bb; t.b_x = 1; t.b_k = Bk;
+    t.nblk = nv_ - int(k10) < kABB ? nv_ - int(k10) : kABB;
+  } else {   // kAdjOoov
+    // dooov[m][l][n][x] += -sum_{k1, k2} Gperm[k1][x][k2] t2[..l..][k1][k2]
+    const int64_t Ab = pick6(kind, sA, sA, sA, sB, sB, sA);
+    const int64_t Ax = pick6(kind, sB, sC, sB, sA, sA, sC);
+    const int64_t Ak = pick6(kind, sC, sB, sC, sC, sC, sB);
+    const int64_t base = pick6(kind, i * no * nv2, i * no * nv2, k * nv2, k * nv2, j * no * nv2,
+                               j * nv2);
+    const int64_t Bl = pick6(kind, nv2, nv2, no * nv2, no * nv2, nv2, no * nv2);
+    const int64_t k10 = int64_t(g) * kABB;
+    t.a = G + k10 * Ab + row0 * Ax;
+    t.a_b = Ab; t.a_x = Ax; t.a_k = Ak;
+    t.b = t2 + base + col0 * Bl + k10 * nv;
+    t.b_b = nv; t.b_x = Bl; t.b_k = 1;
+    t.scale = -1.0;
+    t.nblk = nv_ - int(k10) < kABB ? nv_ - int(k10) : kABB;
+  }
+  return t;
+}
+
+// Staging order of an operand's (beta, x, k-pair) units: the dimension with
+// unit stride walks fastest so that consecutive threads read consecutive
+// addresses.
+enum { kFastK = 0, kFastX = 1, kFastB = 2 };
+
+__device__ __forceinline__ int fast_dim(int64_t sb, int64_t sx, int64_t sk) {
+  return sk == 1 ? kFastK : (sx == 1 ? kFastX : (sb == 1 ? kFastB : kFastX));
+}
+
+template <int X>
+__device__ __forceinline__ void unit_coords(int mode, int u, int& beta, int& x, int& kp) {
+  constexpr int lx = X == 64 ? 6 : (X == 32 ? 5 : 4);
+  if (mode == kFastK) {
+    kp = u & (kAPlanes - 1);
+    const int rr = u >> 2;
+    x = rr & (X - 1);
+    beta = rr >> lx;
+  } else if (mode == kFastX) {
+    x = u & (X - 1);
+    const int rest = u >> lx;
+    beta = rest & (kABB - 1);
+    kp = rest >> 3;
+  } else {
+    beta = u & (kABB - 1);
+    x = (u >> 3) & (X - 1);
+    kp = u >> (3 + lx);
+  }
+}
+
+// k-pair (k, k+1) of one row; entries past nK read in bounds and count zero.
+__device__ __forceinline__ double2 pair_at(const double* row, int64_t ks, int k, int nK, double s) {
+  const SIE_GLOBAL double* g = gptr(row);
+  const int k0 = k < nK ? k : nK - 1;
+  const int k1 = k + 1 < nK ? k + 1 : nK - 1;
+  double2 v;
+  v.x = (k < nK ? s : 0.0) * g[(int64_t)k0 * ks];
+  v.y = (k + 1 < nK ? s : 0.0) * g[(int64_t)k1 * ks];
+  return v;
+}
+
+constexpr int kAUnitsA = kABB * kAR * kAPlanes / kAThreads;   // 4
+constexpr int kAUnitsB = kABB * kAC * kAPlanes / kAThreads;   // 2
+
+struct AStage {
+  double2 a[kAUnitsA];
+  double2 b[kAUnitsB];
+};
+
+// Global loads of chunk c of term t.  `nrow`, `ncol`: valid rows / cols of
+// the tile; `nblk`: valid blocks (rows of blocks past it read block 0 and,
+// for summed blocks, count zero).
+__device__ __forceinline__ void adj_load(const ATerm& t, bool reduce, int c, int nK, int nrow,
+                                         int ncol, int nblk, int tid, AStage& st) {
+  const int k0 = c * kAKc;
+  const int ma = fast_dim(t.a_b, t.a_x, t.a_k);
+#pragma unroll
+  for (int m = 0; m < kAUnitsA; ++m) {
+    int beta, x, kp;
+    unit_coords<kAR>(ma, tid + m * kAThreads, beta, x, kp);
+    const bool bok = beta < nblk;
+    const int bb = bok ? beta : 0;
+    const int xx = x < nrow ? x : nrow - 1;
+    const double s = (reduce && !bok) ? 0.0 : 1.0;
+    st.a[m] = pair_at(t.a + bb * t.a_b + xx * t.a_x, t.a_k, k0 + 2 * kp, nK, s);
+  }
+  const int mb = fast_dim(t.b_b == 0 ? 2 : t.b_b, t.b_x, t.b_k);
+#pragma unroll
+  for (int m = 0; m < kAUnitsB; ++m) {
+    const int u = tid + m * kAThreads;
+    int beta, x, kp;
+    unit_coords<kAC>(mb, u, beta, x, kp);
+    const int bb = beta < nblk ? beta : 0;
+    const int xx = x < ncol ? x : ncol - 1;
+    st.b[m] = pair_at(t.b + bb * t.b_b + xx * t.b_x, t.b_k, k0 + 2 * kp, nK, t.scale);
+  }
+}
+
+__device__ __forceinline__ void adj_store(const ATerm& t, int tid, const AStage& st,
+                                          double2* buf) {
+  const int ma = fast_dim(t.a_b, t.a_x, t.a_k);
+#pragma unroll
+  for (int m = 0; m < kAUnitsA; ++m) {
+    int beta, x, kp;
+    unit_coords<kAR>(ma, tid + m * kAThreads, beta, x, kp);
+    buf[kp * kALdsRows + beta * kAR + x] = st.a[m];
+  }
+  const int mb = fast_dim(t.b_b == 0 ? 2 : t.b_b, t.b_x, t.b_k);
+#pragma unroll
+  for (int m = 0; m < kAUnitsB; ++m) {
+    int beta, x, kp;
+    unit_coords<kAC>(mb, tid + m * kAThreads, beta, x, kp);
+    buf[kp * kALdsRows + kALdsB + beta * kAC + x] = st.b[m];
+  }
+}
+
+// One chunk of MFMAs; lane group g holds k-pair plane g.  A shared B side
+// (b_b = 0) was staged identically in every block, so block beta always
+// reads its own rows.
+__device__ __forceinline__ void adj_mma(const double2* buf, int g, int rrow, int rcol,
+                                        d4 (&acc)[kABB]) {
+  const double2* pl = buf + g * kALdsRows;
+  double2 a[kABB], b[kABB];
+#pragma unroll
+  for (int beta = 0; beta < kABB; ++beta) {
+    a[beta] = pl[beta * kAR + rrow];
+    b[beta] = pl[kALdsB + beta * kAC + rcol];
+  }
+#pragma unroll
+  for (int beta = 0; beta < kABB; ++beta) acc[beta] = mfma16x16x4(a[beta].x, b[beta].x, acc[beta]);
+#pragma unroll
+  for (int beta = 0; beta < kABB; ++beta) acc[beta] = mfma16x16x4(a[beta].y, b[beta].y, acc[beta]);
+}
+
+struct AdjOut {
+  double* out;
+  int64_t ob, orow, ocol;
+  int nb, nr, nc;        // output extent: blocks, rows, cols
+};
+
+template <int CLS>
+__device__ __forceinline__ AdjOut adj_out(const FragDesc& fd, const AdjGroup& gr) {
+  const int64_t nv = fd.nv, no = fd.no, nv2 = nv * nv;
+  AdjOut o;
+  if (CLS == kAdjOvvv) {
+    o.out = fd.g_ovvv + gr.a0 * nv2 * nv;
+    o.ob = nv2; o.orow = nv; o.ocol = 1;
+    o.nb = fd.nv; o.nr = fd.nv; o.nc = fd.nv;
+  } else if (CLS == kAdjT2oo) {
+    o.out = fd.g_t2 + gr.a0 * no * nv2;
+    o.ob = nv; o.orow = 1; o.ocol = nv2;
+    o.nb = fd.nv; o.nr = fd.nv; o.nc = fd.no;
+  } else if (CLS == kAdjT2vv) {
+    o.out = fd.g_t2 + (gr.a0 * no + gr.a1) * nv2;
+    o.ob = 0; o.orow = nv; o.ocol = 1;
+    o.nb = 1; o.nr = fd.nv; o.nc = fd.nv;
+  } else {
+    o.out = fd.g_ooov + (gr.a0 * no * no + gr.a1) * nv;
+    o.ob = 0; o.orow = 1; o.ocol = no * nv;
+    o.nb = 1; o.nr = fd.nv; o.nc = fd.no;
+  }
+  return o;
+}
+
+// Work-groups per output slice of a class for a fragment.
+__host__ __device__ inline int64_t adj_tiles(int cls, int no, int nv) {
+  const int64_t nrt = (nv + kAR - 1) / kAR;
+  const int64_t nbt = (nv + kABB - 1) / kABB;
+  switch (cls) {
+    case kAdjOvvv: return nbt * nrt * ((nv + kAC - 1) / kAC);
+    case kAdjT2oo: return nbt * nrt * ((no + kAC - 1) / kAC);
+    case kAdjT2vv: return nrt * ((nv + kAC - 1) / kAC);
+    case kAdjOoov: return nrt * ((no + kAC - 1) / kAC);
+    case kAdjOvov: return (int64_t(nv) * nv + 255) / 256;
+    default: return (nv + 63) / 64;
+  }
+}
+
+__device__ __forceinline__ int find_group(const AdjGroup* __restrict__ gs, int n, int64_t x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (gs[mid].wg_end > x) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+// Grid: the concatenated tiles of the launch's groups.  Block: kAThreads.
+template <int CLS>
+__global__ __launch_bounds__(kAThreads, 1) void k_adj_contract(
+    const FragDesc* __restrict__ descs, const Item* __restrict__ items,
+    const AdjGroup* __restrict__ groups, int n_groups, const AdjRec* __restrict__ recs,
+    const double* __restrict__ arena) {
+  constexpr bool kReduce = CLS == kAdjT2vv || CLS == kAdjOoov;
+  const int gi = find_group(groups, n_groups, blockIdx.x);
+  const AdjGroup gr = groups[gi];
+  const int64_t start = gi ? groups[gi - 1].wg_end : 0;
+  const FragDesc fd = descs[gr.frag];
+  const int no = fd.no, nv = fd.nv;
+  const AdjOut o = adj_out<CLS>(fd, gr);
+
+  // tile of the slice
+  const int nrt = (o.nr + kAR - 1) / kAR, nct = (o.nc + kAC - 1) / kAC;
+  const int ntile = int(adj_tiles(CLS, no, nv));
+  int t = xcd_tile(int(int64_t(blockIdx.x) - start), ntile);
+  const int tb = t / (nrt * nct);
+  t -= tb * nrt * nct;
+  const int tr = t / nct, tc = t - tr * nct;
+  const int blk0 = tb * kABB, row0 = tr * kAR, col0 = tc * kAC;
+  const int nrow = min(kAR, o.nr - row0), ncol = min(kAC, o.nc - col0);
+  const int nblk_tile = kReduce ? kABB : min(kABB, o.nb - blk0);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int rq = wave % (kAR / 16), ch = wave / (kAR / 16);
+  const int rrow = rq * 16 + r, rcol = ch * 16 + r;
+
+  __shared__ double2 lds[2][kAPlanes * kALdsRows];
+  d4 acc[kABB];
+#pragma unroll
+  for (int q = 0; q < kABB; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const double* t2p = static_cast<const double*>(fd.t2);
+  const double* ovvvp = static_cast<const double*>(fd.ovvv);
+  const double* ooovp = static_cast<const double*>(fd.ooov);
+  const int nchunk = (nv + kAKc - 1) / kAKc;
+
+  auto term_of = [&](int rec) {
+    const AdjRec rr = recs[rec];
+    const Item it = items[rr.item];
+    int i, j, k;
+    decode_sorted_triple(it.unit, no, i, j, k);
+    return make_adj<CLS>(rr.kind, rr.g, i, j, k, no, nv, arena + it.cube_off, t2p, ovvvp,
+                         ooovp, blk0, row0, col0);
+  };
+
+  int rec = gr.rec_begin, c = 0;
+  ATerm tcur = term_of(rec);
+  AStage st;
+  adj_load(tcur, kReduce, 0, nv, nrow, ncol, kReduce ? tcur.nblk : nblk_tile, tid, st);
+  adj_store(tcur, tid, st, lds[0]);
+  __syncthreads();
+  int buf = 0;
+  while (true) {
+    int recn = rec, cn = c + 1;
+    ATerm tn = tcur;
+    bool more = true;
+    if (cn >= nchunk) {
+      if (rec + 1 >= gr.rec_end) {
+        more = false;
+      } else {
+        recn = rec + 1;
+        cn = 0;
+        tn = term_of(recn);
+      }
+    }
+    if (more) adj_load(tn, kReduce, cn, nv, nrow, ncol, kReduce ? tn.nblk : nblk_tile, tid, st);
+    adj_mma(lds[buf], g, rrow, rcol, acc);
+    if (!more) break;
+    adj_store(tn, tid, st, lds[buf ^ 1]);
+    __syncthreads();
+    buf ^= 1;
+    rec = recn;
+    c = cn;
+    tcur = tn;
+  }
+
+  // acc[beta][v] = out[blk0 + beta][row0 + rq*16 + 4v + g][col0 + rcol]
+  const int col = col0 + rcol;
+  if (kReduce) {
+    d4 s = acc[0];
+#pragma unroll
+    for (int beta = 1; beta < kABB; ++beta) s += acc[beta];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = row0 + rq * 16 + 4 * v + g;
+      if (row < o.nr && col < o.nc) {
+        SIE_GLOBAL double* p = gptr_w(o.out) + row * o.orow + col * o.ocol;
+        *p = *p + s[v];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int beta = 0; beta < kABB; ++beta) {
+      const int blk = blk0 + beta;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = row0 + rq * 16 + 4 * v + g;
+        if (blk < o.nb && row < o.nr && col < o.nc) {
+          SIE_GLOBAL double* p = gptr_w(o.out) + blk * o.ob + row * o.orow + col * o.ocol;
+          *p = *p + acc[beta][v];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Contractions of H (memory-bound; one output element per thread or per
+// fixed-order block reduction).
+// ---------------------------------------------------------------------------
+
+// dovov[p][y][q][z] += sum over the third virtual of H t1.  Block: 256
+// threads, one (y, z) element each.
+__global__ __launch_bounds__(256) void k_adj_ovov(const FragDesc* __restrict__ descs,
+                                                  const Item* __restrict__ items,
+                                                  const AdjGroup* __restrict__ groups,
+                                                  int n_groups, const AdjRec* __restrict__ recs,
+                                                  const double* __restrict__ arena) {
+  const int gi = find_group(groups, n_groups, blockIdx.x);
+  const AdjGroup gr = groups[gi];
+  const int64_t start = gi ? groups[gi - 1].wg_end : 0;
+  const FragDesc fd = descs[gr.frag];
+  const int no = fd.no, nv = fd.nv;
+  const int64_t e = (int64_t(blockIdx.x) - start) * 256 + threadIdx.x;
+  if (e >= int64_t(nv) * nv) return;
+  const int y = int(e / nv), z = int(e - int64_t(y) * nv);
+  const double* t1 = static_cast<const double*>(fd.t1);
+  const int64_t nv2 = int64_t(nv) * nv;
+  double s = 0.0;
+  for (int q = gr.rec_begin; q < gr.rec_end; ++q) {
+    const AdjRec rr = recs[q];
+    const Item it = items[rr.item];
+    int i, j, k;
+    decode_sorted_triple(it.unit, no, i, j, k);
+    const double* H = arena + it.cube_off + fd.half;
+    if (rr.kind == 0) {          // (y, z) = (a, b): sum_c H[a][b][c] t1[k][c]
+      const SIE_GLOBAL double* h = gptr(H) + y * nv2 + int64_t(z) * nv;
+      const SIE_GLOBAL double* tv = gptr(t1) + int64_t(k) * nv;
+      for (int c = 0; c < nv; ++c) s += h[c] * tv[c];
+    } else if (rr.kind == 1) {   // (y, z) = (a, c): sum_b H[a][b][c] t1[j][b]
+      const SIE_GLOBAL double* h = gptr(H) + y * nv2 + z;
+      const SIE_GLOBAL double* tv = gptr(t1) + int64_t(j) * nv;
+      for (int b = 0; b < nv; ++b) s += h[int64_t(b) * nv] * tv[b];
+    } else {                     // (y, z) = (b, c): sum_a H[a][b][c] t1[i][a]
+      const SIE_GLOBAL double* h = gptr(H) + int64_t(y) * nv + z;
+      const SIE_GLOBAL double* tv = gptr(t1) + int64_t(i) * nv;
+      for (int a = 0; a < nv; ++a) s += h[a * nv2] * tv[a];
+    }
+  }
+  SIE_GLOBAL double* p = gptr_w(fd.g_ovov) + ((int64_t(gr.a0) * nv + y) * no + gr.a1) * nv + z;
+  *p = *p + s;
+}
+
+__device__ __forceinline__ double block_sum_fixed256(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  const double s = ((red[0] + red[1]) + red[2]) + red[3];
+  __syncthreads();
+  return s;
+}
+
+// dt1[p][y] for y in a 64-wide tile.  Block: 256 threads.
+__global__ __launch_bounds__(256) void k_adj_t1(const FragDesc* __restrict__ descs,
+                                                const Item* __restrict__ items,
+                                                const AdjGroup* __restrict__ groups,
+                                                int n_groups, const AdjRec* __restrict__ recs,
+                                                const double* __restrict__ arena) {
+  __shared__ double red[4];
+  __shared__ double part[4][64];
+  const int gi = find_group(groups, n_groups, blockIdx.x);
+  const AdjGroup gr = groups[gi];
+  const int64_t start = gi ? groups[gi - 1].wg_end : 0;
+  const FragDesc fd = descs[gr.frag];
+  const int no = fd.no, nv = fd.nv;
+  const int y0 = int(int64_t(blockIdx.x) - start) * 64;
+  const int ny = min(64, nv - y0);
+  const double* ovov = static_cast<const double*>(fd.ovov);
+  const int64_t nv2 = int64_t(nv) * nv, onv = int64_t(no) * nv;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double mine = 0.0;   // thread y0 + threadIdx.x's sum (threads < ny)
+  for (int q = gr.rec_begin; q < gr.rec_end; ++q) {
+    const AdjRec rr = recs[q];
+    const Item it = items[rr.item];
+    int i, j, k;
+    decode_sorted_triple(it.unit, no, i, j, k);
+    const SIE_GLOBAL double* H = gptr(arena + it.cube_off + fd.half);
+    if (rr.kind == 0) {
+      // y = c: sum_{a,b} H[a][b][c] ovov[i][a][j][b]; lanes over c, waves over (a, b)
+      double s = 0.0;
+      if (lane < ny) {
+        const int c = y0 + lane;
+        for (int64_t ab = wave; ab < nv2; ab += 4) {
+          const int a = int(ab / nv), b = int(ab - int64_t(a) * nv);
+          s += H[ab * nv + c] * gptr(ovov)[(int64_t(i) * nv + a) * onv + int64_t(j) * nv + b];
+        }
+      }
+      part[wave][lane] = s;
+      __syncthreads();
+      if (threadIdx.x < 64) mine += ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+      __syncthreads();
+    } else {
+      // kind 1: y = b, sum_{a,c} H[a][b][c] ovov[i][a][k][c]
+      // kind 2: y = a, sum_{b,c} H[a][b][c] ovov[j][b][k][c]
+      for (int yy = 0; yy < ny; ++yy) {
+        const int y = y0 + yy;
+        double s = 0.0;
+        for (int64_t e = threadIdx.x; e < nv2; e += 256) {
+          const int u = int(e / nv), c = int(e - int64_t(u) * nv);
+          if (rr.kind == 1)
+            s += H[(int64_t(u) * nv + y) * nv + c] *
+                 gptr(ovov)[(int64_t(i) * nv + u) * onv + int64_t(k) * nv + c];
+          else
+            s += H[(int64_t(y) * nv + u) * nv + c] *
+                 gptr(ovov)[(int64_t(j) * nv + u) * onv + int64_t(k) * nv + c];
+        }
+        const double tot = block_sum_fixed256(s, red);
+        if (threadIdx.x == yy) mine += tot;
+      }
+    }
+  }
+  if (threadIdx.x < ny) {
+    SIE_GLOBAL double* p = gptr_w(fd.g_t1) + int64_t(gr.a0) * nv + y0 + threadIdx.x;
+    *p = *p + mine;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fill and symmetrize.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_fill_zero(double* __restrict__ p, int64_t n) {
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < n;
+       e += int64_t(gridDim.x) * 256)
+    gptr_w(p)[e] = 0.0;
+}
+
+enum SymKind { kSymT2 = 0, kSymOvvv = 1, kSymOoov = 2, kSymOvov = 3 };
+
+// Index of the twin of flat element e (same value for symmetric inputs):
+//   t2[i][j][a][b] ~ t2[j][i][b][a], ovvv[i][a][b][d] ~ ovvv[i][a][d][b],
+//   ooov[j][l][i][a] ~ ooov[l][j][i][a], ovov[i][a][j][b] ~ ovov[j][b][i][a].
+__host__ __device__ inline int64_t twin_index(int kind, int64_t e, int64_t no, int64_t nv) {
+  switch (kind) {
+    case kSymT2: {
+      const int64_t b = e % nv, a = (e / nv) % nv, j = (e / (nv * nv)) % no, i = e / (nv * nv * no);
+      return ((j * no + i) * nv + b) * nv + a;
+    }
+    case kSymOvvv: {
+      const int64_t d = e % nv, b = (e / nv) % nv, rest = e / (nv * nv);
+      return (rest * nv + d) * nv + b;
+    }
+    case kSymOoov: {
+      const int64_t a = e % nv, i = (e / nv) % no, l = (e / (nv * no)) % no, j = e / (nv * no * no);
+      return ((l * no + j) * no + i) * nv + a;
+    }
+    default: {
+      const int64_t b = e % nv, j = (e / nv) % no, a = (e / (nv * no)) % nv, i = e / (nv * no * nv);
+      return ((j * nv + b) * no + i) * nv + a;
+    }
+  }
+}
+
+// g[e] = g[twin(e)] = (g[e] + g[twin(e)]) / 2; the thread of the smaller
+// index of each pair does both writes.
+__global__ __launch_bounds__(256) void k_symmetrize(double* __restrict__ g, int kind, int no,
+                                                    int nv, int64_t n) {
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < n;
+       e += int64_t(gridDim.x) * 256) {
+    const int64_t t = twin_index(kind, e, no, nv);
+    if (t <= e) continue;
+    const double m = 0.5 * (gptr(g)[e] + gptr(g)[t]);
+    gptr_w(g)[e] = m;
+    gptr_w(g)[t] = m;
+  }
+}
+
+}  // namespace sie

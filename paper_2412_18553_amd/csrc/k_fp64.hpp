@@ -14,81 +14,183 @@
 // Per unit, Wt over the n_v^3 virtual cube is the sum of six permuted copies
 // (the P operator) of
 //   X^{abc}_{ijk} = sum_d (ia|bd) t_kj^cd - sum_l (ia|jl) t_lk^bc,
-// i.e. 6 contractions over d (K = n_v) and 6 over l (K = n_occ).  The build
-// kernel evaluates them for one 16 x 16 x 16 tile of (a, b, c) with two
-// waves: each wave owns a register tile in one of two MFMA layouts
+// i.e. 6 contractions over d (K = n_v) and 6 over l (K = n_occ).  A
+// contraction maps onto 16x16xK matrix products only in a register layout
+// whose block index is one of the indices its (ov|vv)-side operand carries;
+// two layouts cover all twelve:
 //   L1: block index a, MFMA rows b, MFMA cols c
 //   L2: block index b, MFMA rows a, MFMA cols c
-// (a term can be evaluated as a 16x16xK matrix product only in a layout whose
-// block index is one of the indices its (ov|vv)-side operand carries).  The L2
-// tile is passed through LDS, added to the L1 tile and written to the
-// workspace cube.  The epilogue kernel then reads the cube by symmetric
-// orbits of 8 x 8 x 8 virtual blocks, so that every permuted element R' needs
-// is in LDS, forms Vt and D on the fly and reduces in a fixed order.
+// The float64 build evaluates both layouts of a 16^3 tile in one work-group
+// (the L2 half is added through LDS) and writes Wt[a][b][c] to the unit's
+// cube.  The split build (k_bf16.hpp) evaluates each layout in its own
+// work-groups over larger tiles and writes two partial cubes,
+// Wt[a][b][c] = P1[a][b][c] + P2[b][a][c].  The epilogue kernel reads the
+// cube(s) by symmetric orbits of 8 x 8 x 8 virtual blocks, so that every
+// permuted element R' needs is in LDS, forms Vt and D on the fly and reduces
+// in a fixed order.
 #pragma once
 
 #include "device_common.hpp"
+#include "work.hpp"
 
 namespace sie {
 
-struct FragDev {
-  const double* t1;     // [no][nv]
-  const double* t2;     // [no][no][nv][nv]
-  const double* ovvv;   // [no][nv][nv][nv]
-  const double* ooov;   // [no][no][no][nv]
-  const double* ovov;   // [no][nv][no][nv]
-  const double* eps;    // [no + nv]: eps_occ then eps_vir (workspace copy)
-  int no, nv;
-};
-
-constexpr int kTile = 16;     // virtual tile edge of the build kernel
 constexpr int kOrb = 8;       // virtual block edge of the epilogue orbits
 
 #ifndef SIE_BUILD_BLOCKS_PER_CU
-#define SIE_BUILD_BLOCKS_PER_CU 2   // occupancy target of the build kernel
+#define SIE_BUILD_BLOCKS_PER_CU 2   // occupancy target of the float64 build kernel
 #endif
 
-// One contraction term of the build kernel for one wave:
-//   acc[beta] += sum_{k < nK} A_beta[row][k] * B_beta[k][col],  beta < kBlk,
-// where one operand ("per-block") depends on the block index beta and the
-// other ("shared") does not.  For the lane's row (A) or column (B):
-//   per-block element (beta, k) = bl[beta * bstride + k * bl_k]
-//   shared element k            = scale * sh[k * sh_k]
-// K runs in chunks of kChunk = 8: in chunk c, k-step s (0, 1) of lane group g
-// covers k = 8 c + 2 g + s, so a lane reads two consecutive k per row.
-// Rows of lanes outside the virtual range, and blocks past the range, are
-// clamped to valid rows: they only feed output entries that are never
-// stored.  K past nK is zeroed on the shared operand.
-constexpr int kChunk = 8;
-constexpr int kBlk = 8;       // blocks per wave (two waves per layout)
+// ---------------------------------------------------------------------------
+// float64 W-tilde build.  A work-group of 4 waves computes, for one unit and
+// one register layout, the layout's six terms over 16 blocks x 32 rows x 32
+// cols; wave w owns blocks 4w .. 4w + 3 and all 32 x 32 rows x cols, i.e. 16
+// MFMA accumulators (4 blocks x 2 row tiles x 2 col tiles).  Each k-pair a
+// lane loads feeds 8 MFMAs (per-block operand: 2 tiles of its side; shared
+// operand: 4 blocks x 2 tiles), so a wave reads 160 bytes per lane per 32
+// MFMAs.  Operands go straight from global memory (L1/L2) into registers in
+// K-chunks of 8, two chunks in flight.  Each layout writes its own partial
+// cube, Wt[a][b][c] = P1[a][b][c] + P2[b][a][c].
+//   L1 (block a, rows b, cols c): d-sums of X^{abc}_{ijk}, X^{acb}_{ikj},
+//       X^{cab}_{kij} and l-sums of X^{bca}_{jki}, X^{cba}_{kji}, X^{bac}_{jik}
+//   L2 (block b, rows a, cols c): d-sums of X^{bca}_{jki}, X^{cba}_{kji},
+//       X^{bac}_{jik} and l-sums of X^{abc}_{ijk}, X^{acb}_{ikj}, X^{cab}_{kij}
+// with X^{abc}_{ijk} = sum_d (ia|bd) t_kj^cd - sum_l (ia|jl) t_lk^bc, (ia|jl)
+// read as ooov[j][l][i][a] and t_ij^ab as t2[i][j][a][b] or its twin.
+// ---------------------------------------------------------------------------
+constexpr int kWBlk = 4;                 // blocks per wave
+constexpr int kWWaves = 4;               // waves per work-group
+constexpr int kWBB = kWBlk * kWWaves;    // blocks per work-group
+constexpr int kWT = 2;                   // 16-wide MFMA tiles per wave along rows and cols
+constexpr int kWEdge = 16 * kWT;         // rows (= cols) per work-group
+constexpr int kWChunk = 8;               // K chunk (a k-pair per lane group)
 
-struct Term {
+// Element (beta, x, k) of the per-block operand is bl[beta*bl_b + x*bl_x + k*bl_k];
+// element (x, k) of the shared operand is scale * sh[x*sh_x + k*sh_k]; x is
+// relative to the tile origin of the operand's MFMA side.
+struct WTerm {
   const double* bl;
+  int64_t bl_b, bl_x, bl_k;
   const double* sh;
-  int64_t bstride, bl_k, sh_k;
+  int64_t sh_x, sh_k;
   int nK;
   double scale;
 };
 
-struct Chunk {
-  double bl[kBlk][2];
-  double sh[2];
+// Term q (0..5) of layout L2 (or L1) for unit (i, j, k) and tile origin
+// (blk0, row0, col0) in that layout's (block, row, col) naming; A_IS_BL
+// tells which MFMA side the per-block operand is on (see wterm_a_is_bl).
+template <bool L2, int Q>
+__device__ __forceinline__ WTerm make_wterm(const double* __restrict__ t2,
+                                            const double* __restrict__ ovvv,
+                                            const double* __restrict__ ooov, int i, int j, int k,
+                                            int no_, int nv_, int blk0, int row0, int col0) {
+  const int64_t nv = nv_, no = no_, nv2 = nv * nv, nonv = no * nv;
+  WTerm t;
+  t.nK = nv_;
+  t.scale = 1.0;
+  if (!L2) {  // block a = blk0 + beta, row b = row0 + x, col c = col0 + x
+    if (Q == 0) {         // X^{abc}_{ijk} d-sum: ovvv[i][a][b][d] * t2[k][j][c][d]
+      t.bl = ovvv + ((i * nv + blk0) * nv + row0) * nv; t.bl_b = nv2; t.bl_x = nv; t.bl_k = 1;
+      t.sh = t2 + ((k * no + j) * nv + col0) * nv; t.sh_x = nv; t.sh_k = 1;
+    } else if (Q == 1) {  // X^{acb}_{ikj} d-sum: t2[j][k][b][d] * ovvv[i][a][c][d]
+      t.sh = t2 + ((j * no + k) * nv + row0) * nv; t.sh_x = nv; t.sh_k = 1;
+      t.bl = ovvv + ((i * nv + blk0) * nv + col0) * nv; t.bl_b = nv2; t.bl_x = nv; t.bl_k = 1;
+    } else if (Q == 2) {  // X^{cab}_{kij} d-sum: t2[j][i][b][d] * ovvv[k][c][a][d]
+      t.sh = t2 + ((j * no + i) * nv + row0) * nv; t.sh_x = nv; t.sh_k = 1;
+      t.bl = ovvv + ((k * nv + col0) * nv + blk0) * nv; t.bl_b = nv; t.bl_x = nv2; t.bl_k = 1;
+    } else if (Q == 3) {  // X^{bca}_{jki} l-sum: -ooov[k][l][j][b] * t2[i][l][a][c]
+      t.sh = ooov + (k * no * no + j) * nv + row0; t.sh_x = 1; t.sh_k = nonv; t.scale = -1.0;
+      t.bl = t2 + (i * no * nv + blk0) * nv + col0; t.bl_b = nv; t.bl_x = 1; t.bl_k = nv2;
+      t.nK = no_;
+    } else if (Q == 4) {  // X^{cba}_{kji} l-sum: t2[i][l][a][b] * -ooov[j][l][k][c]
+      t.bl = t2 + (i * no * nv + blk0) * nv + row0; t.bl_b = nv; t.bl_x = 1; t.bl_k = nv2;
+      t.sh = ooov + (j * no * no + k) * nv + col0; t.sh_x = 1; t.sh_k = nonv; t.scale = -1.0;
+      t.nK = no_;
+    } else {              // X^{bac}_{jik} l-sum: -ooov[i][l][j][b] * t2[l][k][a][c]
+      t.sh = ooov + (i * no * no + j) * nv + row0; t.sh_x = 1; t.sh_k = nonv; t.scale = -1.0;
+      t.bl = t2 + (k * nv + blk0) * nv + col0; t.bl_b = nv; t.bl_x = 1; t.bl_k = nonv * nv;
+      t.nK = no_;
+    }
+  } else {    // block b = blk0 + beta, row a = row0 + x, col c = col0 + x
+    if (Q == 0) {         // X^{bca}_{jki} d-sum: t2[i][k][a][d] * ovvv[j][b][c][d]
+      t.sh = t2 + ((i * no + k) * nv + row0) * nv; t.sh_x = nv; t.sh_k = 1;
+      t.bl = ovvv + ((j * nv + blk0) * nv + col0) * nv; t.bl_b = nv2; t.bl_x = nv; t.bl_k = 1;
+    } else if (Q == 1) {  // X^{cba}_{kji} d-sum: t2[i][j][a][d] * ovvv[k][c][b][d]
+      t.sh = t2 + ((i * no + j) * nv + row0) * nv; t.sh_x = nv; t.sh_k = 1;
+      t.bl = ovvv + ((k * nv + col0) * nv + blk0) * nv; t.bl_b = nv; t.bl_x = nv2; t.bl_k = 1;
+    } else if (Q == 2) {  // X^{bac}_{jik} d-sum: ovvv[j][b][a][d] * t2[k][i][c][d]
+      t.bl = ovvv + ((j * nv + blk0) * nv + row0) * nv; t.bl_b = nv2; t.bl_x = nv; t.bl_k = 1;
+      t.sh = t2 + ((k * no + i) * nv + col0) * nv; t.sh_x = nv; t.sh_k = 1;
+    } else if (Q == 3) {  // X^{abc}_{ijk} l-sum: -ooov[j][l][i][a] * t2[l][k][b][c]
+      t.sh = ooov + (j * no * no + i) * nv + row0; t.sh_x = 1; t.sh_k = nonv; t.scale = -1.0;
+      t.bl = t2 + (k * nv + blk0) * nv + col0; t.bl_b = nv; t.bl_x = 1; t.bl_k = nonv * nv;
+      t.nK = no_;
+    } else if (Q == 4) {  // X^{acb}_{ikj} l-sum: -ooov[k][l][i][a] * t2[j][l][b][c]
+      t.sh = ooov + (k * no * no + i) * nv + row0; t.sh_x = 1; t.sh_k = nonv; t.scale = -1.0;
+      t.bl = t2 + (j * no * nv + blk0) * nv + col0; t.bl_b = nv; t.bl_x = 1; t.bl_k = nv2;
+      t.nK = no_;
+    } else {              // X^{cab}_{kij} l-sum: t2[l][j][a][b] * -ooov[i][l][k][c]
+      t.bl = t2 + (j * nv + row0) * nv + blk0; t.bl_b = 1; t.bl_x = nv; t.bl_k = nonv * nv;
+      t.sh = ooov + (i * no * no + k) * nv + col0; t.sh_x = 1; t.sh_k = nonv; t.scale = -1.0;
+      t.nK = no_;
+    }
+  }
+  return t;
+}
+
+// Per-block operand on the MFMA A side (rows)?  The d-sums read K contiguous
+// (Q < 3); the l-sums read K with a stride.
+template <bool L2, int Q>
+__device__ __forceinline__ constexpr bool wterm_a_is_bl() {
+  return L2 ? (Q == 2 || Q == 5) : (Q == 0 || Q == 4);
+}
+
+struct WChunk {
+  double bl[kWBlk][kWT][2];   // [block][tile of the per-block side][k of the pair]
+  double sh[kWT][2];          // [tile of the shared side][k of the pair]
 };
 
-template <bool VEC>
-__device__ __forceinline__ void load_chunk(const Term& t, int c, int last, int g, Chunk& x) {
-  const int k0 = kChunk * c + 2 * g;
-  if (VEC && kChunk * c + kChunk <= t.nK) {
-    // contiguous 16-byte aligned rows (even row length, aligned bases)
-    const double2 s0 = *reinterpret_cast<const double2*>(t.sh + k0);
-    x.sh[0] = s0.x;
-    x.sh[1] = s0.y;
+// Lane pointers of one term: per-block rows (block 0) and shared rows for the
+// lane's two tiles, clamped into the valid range; blocks past `last` read
+// block `last`.
+struct WLane {
+  const double* bl[kWT];
+  const double* sh[kWT];
+};
+
+template <bool A_IS_BL>
+__device__ __forceinline__ WLane wlane(const WTerm& t, int r, int nrow, int ncol) {
+  WLane p;
+  const int nb = A_IS_BL ? nrow : ncol;   // valid extent of the per-block side
+  const int ns = A_IS_BL ? ncol : nrow;
 #pragma unroll
-    for (int beta = 0; beta < kBlk; ++beta) {
-      const double2 u = *reinterpret_cast<const double2*>(
-          t.bl + (int64_t)(beta < last ? beta : last) * t.bstride + k0);
-      x.bl[beta][0] = u.x;
-      x.bl[beta][1] = u.y;
+  for (int q = 0; q < kWT; ++q) {
+    const int xb = min(16 * q + r, nb - 1), xs = min(16 * q + r, ns - 1);
+    p.bl[q] = t.bl + xb * t.bl_x;
+    p.sh[q] = t.sh + xs * t.sh_x;
+  }
+  return p;
+}
+
+template <bool VEC>
+__device__ __forceinline__ void load_wchunk(const WTerm& t, const WLane& p, int c, int last, int g,
+                                            WChunk& x) {
+  const int k0 = kWChunk * c + 2 * g;
+  if (VEC && kWChunk * c + kWChunk <= t.nK) {
+    // K contiguous, 16-byte aligned rows of even length
+#pragma unroll
+    for (int q = 0; q < kWT; ++q) {
+      const d2v s0 = *(const SIE_GLOBAL d2v*)(gptr(p.sh[q]) + k0);
+      x.sh[q][0] = s0.x;
+      x.sh[q][1] = s0.y;
+#pragma unroll
+      for (int beta = 0; beta < kWBlk; ++beta) {
+        const d2v u = *(const SIE_GLOBAL d2v*)(gptr(p.bl[q]) +
+                                                 (int64_t)(beta < last ? beta : last) * t.bl_b + k0);
+        x.bl[beta][q][0] = u.x;
+        x.bl[beta][q][1] = u.y;
+      }
     }
   } else {
     int kc[2];
@@ -100,126 +202,77 @@ __device__ __forceinline__ void load_chunk(const Term& t, int c, int last, int g
       m[s] = k < t.nK ? t.scale : 0.0;
     }
 #pragma unroll
-    for (int s = 0; s < 2; ++s) x.sh[s] = m[s] * t.sh[(int64_t)kc[s] * t.sh_k];
+    for (int q = 0; q < kWT; ++q) {
 #pragma unroll
-    for (int beta = 0; beta < kBlk; ++beta) {
-      const double* p = t.bl + (int64_t)(beta < last ? beta : last) * t.bstride;
+      for (int s = 0; s < 2; ++s) x.sh[q][s] = m[s] * gptr(p.sh[q])[(int64_t)kc[s] * t.sh_k];
 #pragma unroll
-      for (int s = 0; s < 2; ++s) x.bl[beta][s] = p[(int64_t)kc[s] * t.bl_k];
+      for (int beta = 0; beta < kWBlk; ++beta) {
+        const SIE_GLOBAL double* b = gptr(p.bl[q]) + (int64_t)(beta < last ? beta : last) * t.bl_b;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) x.bl[beta][q][s] = b[(int64_t)kc[s] * t.bl_k];
+      }
     }
   }
 }
 
+// acc[beta][rt][ct]: rows 16 rt .., cols 16 ct .. of block beta.  Sub-tiles
+// that lie wholly outside the virtual range (rt_ok / ct_ok false, uniform)
+// are skipped.
 template <bool A_IS_BL>
-__device__ __forceinline__ void mma_chunk(const Chunk& x, d4 (&acc)[kBlk]) {
+__device__ __forceinline__ void mma_wchunk(const WChunk& x, bool r1_ok, bool c1_ok,
+                                           d4 (&acc)[kWBlk][kWT][kWT]) {
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
-    for (int beta = 0; beta < kBlk; ++beta)
-      acc[beta] = A_IS_BL ? mfma16x16x4(x.bl[beta][s], x.sh[s], acc[beta])
-                          : mfma16x16x4(x.sh[s], x.bl[beta][s], acc[beta]);
+    for (int rt = 0; rt < kWT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < kWT; ++ct) {
+        if ((rt == 1 && !r1_ok) || (ct == 1 && !c1_ok)) continue;
+#pragma unroll
+        for (int beta = 0; beta < kWBlk; ++beta)
+          acc[beta][rt][ct] = A_IS_BL
+              ? mfma16x16x4(x.bl[beta][rt][s], x.sh[ct][s], acc[beta][rt][ct])
+              : mfma16x16x4(x.sh[rt][s], x.bl[beta][ct][s], acc[beta][rt][ct]);
+      }
 }
 
-// One term as a three-stage register pipeline: the loads of chunks c+1 and
-// c+2 are in flight while the 8 x 2 MFMAs of chunk c run.  Loads of chunks
-// past the end read clamped, zero-masked data and are never consumed.
-// `last` is the last block index (relative to this wave's first block) that
-// lies inside the virtual range.
-template <bool A_IS_BL, bool VEC>
-__device__ __forceinline__ void run_term(const Term& t, int last, int g, d4 (&acc)[kBlk]) {
-  const int nch = (t.nK + kChunk - 1) / kChunk;
-  Chunk b0, b1, b2;
-  load_chunk<VEC>(t, 0, last, g, b0);
-  load_chunk<VEC>(t, 1, last, g, b1);
-  for (int c = 0;; c += 3) {
-    load_chunk<VEC>(t, c + 2, last, g, b2);
-    mma_chunk<A_IS_BL>(b0, acc);
+// One term: two chunks in flight (loads of chunk c + 1 issued before the
+// MFMAs of chunk c); loads past the end are clamped, masked and unused.
+template <bool L2, int Q, bool VEC>
+__device__ __forceinline__ void run_wterm(const double* t2, const double* ovvv,
+                                          const double* ooov, int i, int j, int k, int no, int nv,
+                                          int blk0, int row0, int col0, int nrow, int ncol,
+                                          int last, int r, int g, d4 (&acc)[kWBlk][kWT][kWT]) {
+  constexpr bool A = wterm_a_is_bl<L2, Q>();
+  constexpr bool V = VEC && Q < 3;
+  const WTerm t = make_wterm<L2, Q>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0);
+  const WLane p = wlane<A>(t, r, nrow, ncol);
+  const bool r1_ok = nrow > 16, c1_ok = ncol > 16;
+  const int nch = (t.nK + kWChunk - 1) / kWChunk;
+  WChunk b0, b1;
+  load_wchunk<V>(t, p, 0, last, g, b0);
+  for (int c = 0;; c += 2) {
+    load_wchunk<V>(t, p, c + 1, last, g, b1);
+    mma_wchunk<A>(b0, r1_ok, c1_ok, acc);
     if (c + 1 >= nch) break;
-    load_chunk<VEC>(t, c + 3, last, g, b0);
-    mma_chunk<A_IS_BL>(b1, acc);
+    load_wchunk<V>(t, p, c + 2, last, g, b0);
+    mma_wchunk<A>(b1, r1_ok, c1_ok, acc);
     if (c + 2 >= nch) break;
-    load_chunk<VEC>(t, c + 4, last, g, b1);
-    mma_chunk<A_IS_BL>(b2, acc);
-    if (c + 3 >= nch) break;
   }
 }
 
-// Wt for one 16^3 virtual tile (a0.., b0.., c0..) of one unit (i, j, k) is
-// the sum of the six permuted copies (the P operator) of
-//   X^{abc}_{ijk} = sum_d (ia|bd) t_kj^cd - sum_l (ia|jl) t_lk^bc,
-// each split into its d-sum (K = n_v) and its l-sum (K = n_occ); (ia|jl) is
-// read as ooov[j][l][i][a] and t_ij^ab as t2[i][j][a][b] or its twin
-// t2[j][i][b][a].  Twelve terms, six per layout:
-//   L2 (block b, rows a, cols c): X^{bca}_{jki}, X^{cba}_{kji}, X^{bac}_{jik}
-//       d-sums and X^{abc}_{ijk}, X^{acb}_{ikj}, X^{cab}_{kij} l-sums;
-//   L1 (block a, rows b, cols c): X^{abc}_{ijk}, X^{acb}_{ikj}, X^{cab}_{kij}
-//       d-sums and X^{bca}_{jki}, X^{cba}_{kji}, X^{bac}_{jik} l-sums.
-// A wave owns blocks blk0 .. blk0 + 7 of its layout's block index.
-template <bool VEC>
-__device__ __forceinline__ void build_tile(const double* __restrict__ t2,
-                                           const double* __restrict__ ovvv,
-                                           const double* __restrict__ ooov, int i, int j, int k,
-                                           int no_, int nv_, int a0, int b0, int c0, bool l1,
-                                           int blk0, int r, int g, d4 (&acc)[kBlk]) {
-  const int64_t nv = nv_, no = no_, nv2 = nv * nv, nonv = no * nv;
-  const int64_t arc = min(a0 + r, nv_ - 1), brc = min(b0 + r, nv_ - 1),
-                crc = min(c0 + r, nv_ - 1);
-  Term t;
-  if (!l1) {
-    const int bb = b0 + blk0;                     // first block (b) of this wave
-    const int last = min(kBlk, nv_ - bb) - 1;
-    // X^{bca}_{jki}: sum_d t2[i][k][a][d] * ovvv[j][b][c][d]
-    t = Term{ovvv + ((j * nv + bb) * nv + crc) * nv, t2 + ((i * no + k) * nv + arc) * nv,
-             nv2, 1, 1, nv_, 1.0};
-    run_term<false, VEC>(t, last, g, acc);
-    // X^{cba}_{kji}: sum_d t2[i][j][a][d] * ovvv[k][c][b][d]
-    t = Term{ovvv + ((k * nv + crc) * nv + bb) * nv, t2 + ((i * no + j) * nv + arc) * nv,
-             nv, 1, 1, nv_, 1.0};
-    run_term<false, VEC>(t, last, g, acc);
-    // X^{bac}_{jik}: sum_d ovvv[j][b][a][d] * t2[k][i][c][d]
-    t = Term{ovvv + ((j * nv + bb) * nv + arc) * nv, t2 + ((k * no + i) * nv + crc) * nv,
-             nv2, 1, 1, nv_, 1.0};
-    run_term<true, VEC>(t, last, g, acc);
-    // X^{abc}_{ijk}: -sum_l ooov[j][l][i][a] * t2[l][k][b][c]
-    t = Term{t2 + (k * nv + bb) * nv + crc, ooov + (j * no * no + i) * nv + arc,
-             nv, nonv * nv, nonv, no_, -1.0};
-    run_term<false, false>(t, last, g, acc);
-    // X^{acb}_{ikj}: -sum_l ooov[k][l][i][a] * t2[j][l][b][c]
-    t = Term{t2 + (j * no * nv + bb) * nv + crc, ooov + (k * no * no + i) * nv + arc,
-             nv, nv2, nonv, no_, -1.0};
-    run_term<false, false>(t, last, g, acc);
-    // X^{cab}_{kij}: -sum_l t2[l][j][a][b] * ooov[i][l][k][c]
-    t = Term{t2 + (j * nv + arc) * nv + bb, ooov + (i * no * no + k) * nv + crc,
-             1, nonv * nv, nonv, no_, -1.0};
-    run_term<true, false>(t, last, g, acc);
-  } else {
-    const int aa = a0 + blk0;                     // first block (a) of this wave
-    const int last = min(kBlk, nv_ - aa) - 1;
-    // X^{abc}_{ijk}: sum_d ovvv[i][a][b][d] * t2[k][j][c][d]
-    t = Term{ovvv + ((i * nv + aa) * nv + brc) * nv, t2 + ((k * no + j) * nv + crc) * nv,
-             nv2, 1, 1, nv_, 1.0};
-    run_term<true, VEC>(t, last, g, acc);
-    // X^{acb}_{ikj}: sum_d t2[j][k][b][d] * ovvv[i][a][c][d]
-    t = Term{ovvv + ((i * nv + aa) * nv + crc) * nv, t2 + ((j * no + k) * nv + brc) * nv,
-             nv2, 1, 1, nv_, 1.0};
-    run_term<false, VEC>(t, last, g, acc);
-    // X^{cab}_{kij}: sum_d t2[j][i][b][d] * ovvv[k][c][a][d]
-    t = Term{ovvv + ((k * nv + crc) * nv + aa) * nv, t2 + ((j * no + i) * nv + brc) * nv,
-             nv, 1, 1, nv_, 1.0};
-    run_term<false, VEC>(t, last, g, acc);
-    // X^{bca}_{jki}: -sum_l ooov[k][l][j][b] * t2[i][l][a][c]
-    t = Term{t2 + (i * no * nv + aa) * nv + crc, ooov + (k * no * no + j) * nv + brc,
-             nv, nv2, nonv, no_, -1.0};
-    run_term<false, false>(t, last, g, acc);
-    // X^{cba}_{kji}: -sum_l t2[i][l][a][b] * ooov[j][l][k][c]
-    t = Term{t2 + (i * no * nv + aa) * nv + brc, ooov + (j * no * no + k) * nv + crc,
-             nv, nv2, nonv, no_, -1.0};
-    run_term<true, false>(t, last, g, acc);
-    // X^{bac}_{jik}: -sum_l ooov[i][l][j][b] * t2[l][k][a][c]
-    t = Term{t2 + (k * nv + aa) * nv + crc, ooov + (i * no * no + j) * nv + brc,
-             nv, nonv * nv, nonv, no_, -1.0};
-    run_term<false, false>(t, last, g, acc);
-  }
+template <bool L2, bool VEC>
+__device__ __forceinline__ void build_wtile(const double* t2, const double* ovvv,
+                                            const double* ooov, int i, int j, int k, int no,
+                                            int nv, int blk0, int row0, int col0, int nrow,
+                                            int ncol, int last, int r, int g,
+                                            d4 (&acc)[kWBlk][kWT][kWT]) {
+  run_wterm<L2, 0, VEC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
+  run_wterm<L2, 1, VEC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
+  run_wterm<L2, 2, VEC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
+  run_wterm<L2, 3, VEC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
+  run_wterm<L2, 4, VEC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
+  run_wterm<L2, 5, VEC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
 }
 
 // Map a linear block index to a tile so that the blocks the hardware places
@@ -232,69 +285,141 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
   return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
-// Wt for one 16^3 virtual tile of one unit, written to the unit's cube
-// cube[a][b][c] (n_v^3 doubles, row-major).  Grid: x = tile (ta, tb, tc),
-// y = unit within the launch.  Block: 256 threads; waves 0-1 build layout
-// L2 (blocks b 0-7 / 8-15), waves 2-3 layout L1 (blocks a 0-7 / 8-15).  The
-// L2 half goes through LDS and is added by the L1 waves, which store the
-// tile.  VEC: n_v is even and every input base is 16-byte aligned, so
-// d-rows can be read 16 bytes at a time.
-template <bool VEC>
-__global__ __launch_bounds__(256, SIE_BUILD_BLOCKS_PER_CU) void k_build_w_f64(FragDev f, int64_t u0,
-                                                        int64_t n_units,
-                                                        double* __restrict__ cube,
-                                                        int64_t cube_stride) {
-  const int64_t u = u0 + blockIdx.y;
-  if (u >= n_units) return;
+// Build work-groups of one unit for a fragment of n_v virtuals: two layouts
+// x 16-block x 32-row x 32-col tiles.
+__host__ __device__ __forceinline__ int64_t wbuild_tiles(int nv) {
+  const int64_t nb = (nv + kWBB - 1) / kWBB, ne = (nv + kWEdge - 1) / kWEdge;
+  return 2 * nb * ne * ne;
+}
+
+// Partial cube of one layout over one 16 x 32 x 32 tile of one unit, written
+// to the unit's first (L1) or second (L2) cube in (block, row, col) order.
+// Grid: the concatenated build work-groups of the round's items.  Block: 256
+// threads.  VEC (FragDesc::vec): n_v is even and the t2 / ovvv bases are
+// 16-byte aligned, so d-rows are read 16 bytes at a time.
+__global__ __launch_bounds__(256, SIE_BUILD_BLOCKS_PER_CU) void k_build_w_f64(
+    const FragDesc* __restrict__ descs, const Item* __restrict__ items, int n_items,
+    double* __restrict__ arena) {
+  const int ri = find_item<true>(items, n_items, blockIdx.x);
+  const int64_t start = ri ? items[ri - 1].blk_end : 0;
+  const Item it = items[ri];
+  const FragDesc fd = descs[it.frag];
   int i, j, k;
-  decode_sorted_triple(u, f.no, i, j, k);
+  decode_sorted_triple(it.unit, fd.no, i, j, k);
   if (i == k) return;
-  const int nv = f.nv;
-  const int nbk = (nv + kTile - 1) / kTile;
-  int t = xcd_tile(blockIdx.x, nbk * nbk * nbk);
-  const int ta = t / (nbk * nbk);
-  t -= ta * nbk * nbk;
-  const int tb = t / nbk;
-  const int tc = t - tb * nbk;
-  const int a0 = ta * kTile, b0 = tb * kTile, c0 = tc * kTile;
+  const int nv = fd.nv;
+  const int nbt = (nv + kWBB - 1) / kWBB, net = (nv + kWEdge - 1) / kWEdge;
+  const int per = nbt * net * net;
+  int t = xcd_tile(int(int64_t(blockIdx.x) - start), 2 * per);
+  const bool l2 = t >= per;
+  if (l2) t -= per;
+  const int tb = t / (net * net);
+  t -= tb * net * net;
+  const int tr = t / net, tc = t - tr * net;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, g = lane >> 4;
-  const bool l1 = wave >= 2;
-  const int blk0 = (wave & 1) * kBlk;
+  const int blk0 = tb * kWBB + wave * kWBlk;
+  const int row0 = tr * kWEdge, col0 = tc * kWEdge;
+  if (blk0 >= nv) return;                       // no barrier follows: waves may leave
+  const int nrow = min(kWEdge, nv - row0), ncol = min(kWEdge, nv - col0);
+  const int last = min(kWBlk, nv - blk0) - 1;
+  const double* t2 = static_cast<const double*>(fd.t2);
+  const double* ovvv = static_cast<const double*>(fd.ovvv);
+  const double* ooov = static_cast<const double*>(fd.ooov);
 
-  __shared__ double xbuf[kTile * kTile * kTile];
-
-  d4 acc[kBlk];
+  d4 acc[kWBlk][kWT][kWT];
 #pragma unroll
-  for (int q = 0; q < kBlk; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-
-  build_tile<VEC>(f.t2, f.ovvv, f.ooov, i, j, k, f.no, nv, a0, b0, c0, l1, blk0, r, g, acc);
-
-  if (!l1) {
-    // element v of lane (g, r) in block q holds Wt[a0 + 4v + g][b0 + blk0 + q][c0 + r]
+  for (int b = 0; b < kWBlk; ++b)
 #pragma unroll
-    for (int q = 0; q < kBlk; ++q)
+    for (int p = 0; p < kWT; ++p)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        xbuf[((blk0 + q) * kTile + 4 * v + g) * kTile + r] = acc[q][v];
+      for (int q = 0; q < kWT; ++q) acc[b][p][q] = d4{0.0, 0.0, 0.0, 0.0};
+
+  if (l2) {
+    if (fd.vec) build_wtile<true, true>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
+    else build_wtile<true, false>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
+  } else {
+    if (fd.vec) build_wtile<false, true>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
+    else build_wtile<false, false>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
   }
-  __syncthreads();
-  if (l1) {
-    // element v of lane (g, r) in block q holds Wt[a0 + blk0 + q][b0 + 4v + g][c0 + r]
-    double* __restrict__ out = cube + (int64_t)blockIdx.y * cube_stride;
-    const int c = c0 + r;
+
+  // element v of lane (g, r) in acc[beta][rt][ct] holds
+  // P[blk0 + beta][row0 + 16 rt + 4 v + g][col0 + 16 ct + r]
+  double* __restrict__ out = arena + it.cube_off + (l2 ? fd.half : 0);
 #pragma unroll
-    for (int q = 0; q < kBlk; ++q) {
-      const int a = a0 + blk0 + q;
+  for (int beta = 0; beta < kWBlk; ++beta) {
+    const int blk = blk0 + beta;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int bl = 4 * v + g;
-        const int b = b0 + bl;
-        const double w = acc[q][v] + xbuf[(bl * kTile + blk0 + q) * kTile + r];
-        if (a < nv && b < nv && c < nv) out[((int64_t)a * nv + b) * nv + c] = w;
+    for (int rt = 0; rt < kWT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < kWT; ++ct) {
+        const int col = col0 + 16 * ct + r;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = row0 + 16 * rt + 4 * v + g;
+          if (blk < nv && row < nv && col < nv)
+            gptr_w(out)[((int64_t)blk * nv + row) * nv + col] = acc[beta][rt][ct][v];
+        }
       }
-    }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Tile geometry of the LDS-staged split build (k_bf16.hpp): each work-group
+// computes, for one unit and one of the two register layouts, that layout's
+// six terms over kBB blocks x kRows rows x kCols cols, 8 waves, wave (rq, ch)
+// owning rows 16 rq .. 16 rq + 15 and cols 16 ch .. 16 ch + 15 of every block.
+// ---------------------------------------------------------------------------
+constexpr int kBB = 8;                          // blocks per work-group
+constexpr int kRows = 64;                       // MFMA rows per work-group (A side)
+constexpr int kCols = 32;                       // MFMA cols per work-group (B side)
+constexpr int kThreads = 64 * (kRows / 16) * (kCols / 16);
+constexpr int kLdsRows = kBB * kRows + kRows;   // per-block region + shared region
+constexpr int kShBase = kBB * kRows;            // first LDS row of the shared operand
+
+#ifndef SIE_BUILD_BLOCKS_PER_CU
+#define SIE_BUILD_BLOCKS_PER_CU 2   // occupancy target of the build kernel
+#endif
+
+// Lane's row/col clamps for one tile: blocks, rows and cols inside [0, n_v).
+struct TileDims {
+  int nblk;       // valid blocks in the tile (>= 1)
+  int nrow;       // valid rows (>= 1)
+  int ncol;       // valid cols (>= 1)
+};
+
+// Build tiles of one layout for a fragment of n_v virtuals.
+__host__ __device__ __forceinline__ int64_t build_tiles(int nv) {
+  return int64_t((nv + kBB - 1) / kBB) * ((nv + kRows - 1) / kRows) * ((nv + kCols - 1) / kCols);
+}
+
+// Block -> (item, layout, tile) of a round.  Within an item, blocks that the
+// hardware places on one XCD (same index mod 8) get a contiguous range of
+// tiles, so they share operand rows in that XCD's L2.
+struct BlockWork {
+  Item it;
+  int l2;
+  int blk0, row0, col0;
+};
+
+__device__ __forceinline__ BlockWork block_work(const FragDesc& fd, const Item* items, int r,
+                                                int64_t local) {
+  BlockWork w;
+  w.it = items[r];
+  const int64_t T = fd.tiles;
+  int64_t t = xcd_tile(int(local), int(2 * T));
+  w.l2 = t >= T;
+  if (w.l2) t -= T;
+  const int nv = fd.nv;
+  const int nrt = (nv + kRows - 1) / kRows, nct = (nv + kCols - 1) / kCols;
+  const int tb = int(t / (nrt * nct));
+  t -= int64_t(tb) * nrt * nct;
+  const int tr = int(t / nct);
+  const int tcol = int(t - int64_t(tr) * nct);
+  w.blk0 = tb * kBB;
+  w.row0 = tr * kRows;
+  w.col0 = tcol * kCols;
+  return w;
 }
 
 // Orbit slots enumerate the position permutations (0,1,2) (0,2,1) (1,0,2)
@@ -326,45 +451,54 @@ __device__ __forceinline__ double block_sum_256(double v, double* red) {
 
 // Per-unit partial sums of Wt R'[Wt + Vt] / D over symmetric orbits of
 // 8 x 8 x 8 virtual blocks (A >= B >= C and their permuted images).
-// Grid: x = partial slot (strides over orbits), y = unit within the launch.
-__global__ __launch_bounds__(256) void k_epilogue_f64(FragDev f, int64_t u0,
-                                                      int64_t n_units,
-                                                      const double* __restrict__ cube,
-                                                      int64_t cube_stride,
-                                                      double* __restrict__ partials,
-                                                      int n_part) {
-  const int64_t u = u0 + blockIdx.y;
-  if (u >= n_units) return;
+// Wt[a][b][c] = cube1[a][b][c] (+ cube2[b][a][c] with TWO, the split build's
+// partial cubes), float64 or float32 cubes; V-tilde from t1 and ovov (float64
+// or float32 inputs), all arithmetic in float64.  Grid: the concatenated
+// epilogue blocks of the round's items (n_part per item; block p of an item
+// takes orbits p, p + n_part, ...).
+template <typename CubeT, typename InT, bool TWO>
+__global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ descs,
+                                                  const Item* __restrict__ items, int n_items,
+                                                  const CubeT* __restrict__ arena,
+                                                  double* __restrict__ partials, int pstride) {
+  const int r = find_item<false>(items, n_items, blockIdx.x);
+  const int64_t start = r ? items[r - 1].part_end : 0;
+  const Item it = items[r];
+  const FragDesc fd = descs[it.frag];
+  const int slot = int(int64_t(blockIdx.x) - start);
   int i, j, k;
-  decode_sorted_triple(u, f.no, i, j, k);
+  decode_sorted_triple(it.unit, fd.no, i, j, k);
   __shared__ double sw[6][kOrb * kOrb * kOrb];
   __shared__ double sz[6][kOrb * kOrb * kOrb];
   __shared__ double red[4];
-  double* out = partials + u * n_part + blockIdx.x;
+  double* out = partials + (fd.unit_base + it.unit) * pstride + slot;
   if (i == k) {
     if (threadIdx.x == 0) *out = 0.0;
     return;
   }
-  const int no = f.no, nv = f.nv;
+  const InT* __restrict__ t1 = static_cast<const InT*>(fd.t1);
+  const InT* __restrict__ ovov = static_cast<const InT*>(fd.ovov);
+  const double* __restrict__ eps = fd.eps;
+  const int no_ = fd.no, nv_ = fd.nv;
+  const int no = no_, nv = nv_;
   const int nb = (nv + kOrb - 1) / kOrb;
   const int64_t n_orb = tetra(nb);
-  const double* __restrict__ ev = f.eps + no;
-  const double eijk = f.eps[i] + f.eps[j] + f.eps[k];
-  const double* __restrict__ w3 = cube + (int64_t)blockIdx.y * cube_stride;
-  const double* __restrict__ ovov = f.ovov;
-  const double* __restrict__ t1 = f.t1;
+  const double* __restrict__ ev = eps + no;
+  const double eijk = gptr(eps)[i] + gptr(eps)[j] + gptr(eps)[k];
+  const CubeT* __restrict__ w1 = arena + it.cube_off;
+  const CubeT* __restrict__ w2 = w1 + fd.half;
   const int64_t nonv = (int64_t)no * nv;
-  const double* ov_ij = ovov + (int64_t)i * nv * nonv + (int64_t)j * nv;   // (ia|jb) = ov_ij[a*nonv + b]
-  const double* ov_ik = ovov + (int64_t)i * nv * nonv + (int64_t)k * nv;
-  const double* ov_jk = ovov + (int64_t)j * nv * nonv + (int64_t)k * nv;
-  const double* t1i = t1 + (int64_t)i * nv;
-  const double* t1j = t1 + (int64_t)j * nv;
-  const double* t1k = t1 + (int64_t)k * nv;
+  const InT* ov_ij = ovov + (int64_t)i * nv * nonv + (int64_t)j * nv;   // (ia|jb) = ov_ij[a*nonv + b]
+  const InT* ov_ik = ovov + (int64_t)i * nv * nonv + (int64_t)k * nv;
+  const InT* ov_jk = ovov + (int64_t)j * nv * nonv + (int64_t)k * nv;
+  const InT* t1i = t1 + (int64_t)i * nv;
+  const InT* t1j = t1 + (int64_t)j * nv;
+  const InT* t1k = t1 + (int64_t)k * nv;
 
   constexpr int E = kOrb * kOrb * kOrb;
 
   double acc = 0.0;
-  for (int64_t o = blockIdx.x; o < n_orb; o += gridDim.x) {
+  for (int64_t o = slot; o < n_orb; o += fd.n_part) {
     int t0, t1b, t2b;
     decode_sorted_triple(o, nb, t0, t1b, t2b);
     for (int idx = threadIdx.x; idx < 6 * E; idx += 256) {
@@ -376,10 +510,11 @@ __global__ __launch_bounds__(256) void k_epilogue_f64(FragDev f, int64_t u0,
       const int c = kOrb * pick3(p2, t0, t1b, t2b) + (e & 7);
       double w = 0.0, z = 0.0;
       if (a < nv && b < nv && c < nv) {
-        w = w3[((int64_t)a * nv + b) * nv + c];
-        const double vt = ov_ij[(int64_t)a * nonv + b] * t1k[c] +
-                          ov_ik[(int64_t)a * nonv + c] * t1j[b] +
-                          ov_jk[(int64_t)b * nonv + c] * t1i[a];
+        w = (double)gptr(w1)[((int64_t)a * nv + b) * nv + c];
+        if (TWO) w += (double)gptr(w2)[((int64_t)b * nv + a) * nv + c];
+        const double vt = (double)gptr(ov_ij)[(int64_t)a * nonv + b] * (double)gptr(t1k)[c] +
+                          (double)gptr(ov_ik)[(int64_t)a * nonv + c] * (double)gptr(t1j)[b] +
+                          (double)gptr(ov_jk)[(int64_t)b * nonv + c] * (double)gptr(t1i)[a];
         z = w + vt;
       }
       sw[s][e] = w;
@@ -422,7 +557,7 @@ __global__ __launch_bounds__(256) void k_epilogue_f64(FragDev f, int64_t u0,
       const double zacb = sz[orbit_slot(p0, p2, p1)][(x << 6) | (zz << 3) | y];
       const double zbac = sz[orbit_slot(p1, p0, p2)][(y << 6) | (x << 3) | zz];
       const double rz = 4.0 * zabc + zcab + zbca - 2.0 * (zcba + zacb + zbac);
-      const double d = eijk - ev[a] - ev[b] - ev[c];
+      const double d = eijk - gptr(ev)[a] - gptr(ev)[b] - gptr(ev)[c];
       acc += sw[s][e] * rz / d;
     }
     __syncthreads();

@@ -3,28 +3,56 @@
 #pragma once
 
 #include "device_common.hpp"
+#include "work.hpp"
 
 namespace sie {
 
-// e_units[u] = 2 A_ijk * sum_{p < n_part} partials[u][p]  (u in [0, n_units)),
-// A_ijk the equal-index weight of the unordered occupied triple (i, j, k).
-__global__ __launch_bounds__(256) void k_unit_energy(int no, int64_t n_units,
+// e_units[unit_base + u] = 2 A_ijk * sum_{p < n_part} partials[(unit_base + u) * pstride + p]
+// for every unit u of fragment blockIdx.y, A_ijk the equal-index weight of
+// the unordered occupied triple (i, j, k); units with i = j = k are 0.
+__global__ __launch_bounds__(256) void k_unit_energy(const FragDesc* __restrict__ descs,
                                                      const double* __restrict__ partials,
-                                                     int n_part,
-                                                     double* __restrict__ e_units) {
+                                                     int pstride, double* __restrict__ e_units) {
+  const FragDesc fd = descs[blockIdx.y];
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= n_units) return;
+  if (u >= tetra(fd.no)) return;
   int i, j, k;
-  decode_sorted_triple(u, no, i, j, k);
+  decode_sorted_triple(u, fd.no, i, j, k);
+  double* out = e_units + fd.unit_base + u;
   if (i == k) {
-    e_units[u] = 0.0;
+    *out = 0.0;
     return;
   }
-  const double* p = partials + u * n_part;
+  const double* p = partials + (fd.unit_base + u) * pstride;
   double s = 0.0;
-  for (int q = 0; q < n_part; ++q) s += p[q];
+  for (int q = 0; q < fd.n_part; ++q) s += p[q];
   const double weight = (i == j || j == k) ? 1.0 : 2.0;   // 2 A_ijk
-  e_units[u] = weight * s;
+  *out = weight * s;
+}
+
+__device__ __forceinline__ double block_sum_fixed(double s, double* buf) {
+  buf[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
+    __syncthreads();
+  }
+  return buf[0];
+}
+
+// e_frag[f] = sum of fragment f's per-unit energies, in a fixed order
+// (one block of 256 threads per fragment).
+__global__ __launch_bounds__(256) void k_frag_energy(const FragDesc* __restrict__ descs,
+                                                     const double* __restrict__ e_units,
+                                                     double* __restrict__ e_frag) {
+  __shared__ double buf[256];
+  const FragDesc fd = descs[blockIdx.x];
+  const int64_t n = tetra(fd.no);
+  const double* x = e_units + fd.unit_base;
+  double s = 0.0;
+  for (int64_t q = threadIdx.x; q < n; q += 256) s += x[q];
+  const double t = block_sum_fixed(s, buf);
+  if (threadIdx.x == 0) e_frag[blockIdx.x] = t;
 }
 
 // out[0] = sum_{q < n} x[q] in a fixed order (one block of 256 threads:

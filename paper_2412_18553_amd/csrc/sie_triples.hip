@@ -7,9 +7,14 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
+#include <array>
 #include <string>
+#include <utility>
 #include <vector>
 
+#include "k_adjoint.hpp"
+#include "k_bf16.hpp"
 #include "k_fp64.hpp"
 #include "k_reduce.hpp"
 
@@ -37,35 +42,102 @@ size_t default_cap() {
   return kDefaultCap;
 }
 
-// Workspace layout of one energy evaluation:
-//   [eps copy (no + nv)] [unit energies] [partials units x n_part] [cube x chunk]
-struct Plan {
+size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
+
+// Per-fragment sizes.
+struct FragPlan {
   int no = 0, nv = 0;
-  int64_t n_units = 0;
+  int Kv = 0, Ko = 0;
+  int64_t n_units = 0;       // all i >= j >= k (per-unit arrays)
+  int64_t work_units = 0;    // units that are not i = j = k
   int n_part = 0;
-  size_t off_eps = 0, off_units = 0, off_part = 0, off_cube = 0;
-  size_t cube_bytes = 0;     // one unit's Wt cube
-  size_t fixed_bytes = 0;    // everything but the cubes
+  size_t split_bytes = 0;    // vS + tS + tT + oT
+  size_t half_bytes = 0;     // one partial cube (aligned)
+  double unit_cost = 0.0;    // flops per unit (ordering key)
 };
 
-Plan make_plan(int no, int nv) {
-  Plan p;
+FragPlan frag_plan(int no, int nv, bool split) {
+  FragPlan p;
   p.no = no;
   p.nv = nv;
   p.n_units = sie::tetra(no);
+  p.work_units = p.n_units - no;
   const int64_t nb = (nv + sie::kOrb - 1) / sie::kOrb;
   const int64_t n_orb = sie::tetra(nb);
   p.n_part = int(n_orb < kMaxPartials ? n_orb : kMaxPartials);
+  const size_t o = size_t(no), v = size_t(nv);
+  if (split) {
+    p.Kv = int(round_up(v, sie::kKs));
+    p.Ko = int(round_up(o, sie::kKs));
+    // 4 bytes (bf16 hi + lo) per padded element
+    p.split_bytes = align_up(4 * o * v * v * size_t(p.Kv), 256) +
+                    align_up(4 * o * o * v * size_t(p.Kv), 256) +
+                    align_up(4 * o * v * v * size_t(p.Ko), 256) +
+                    align_up(4 * o * o * v * size_t(p.Ko), 256);
+  }
+  p.half_bytes = align_up((split ? sizeof(float) : sizeof(double)) * v * v * v, 256);
+  p.unit_cost = 12.0 * double(v) * v * v * v + 12.0 * double(o) * v * v * v;
+  return p;
+}
+
+// Workspace layout of one evaluation of n fragments:
+//   [descriptors] [eps copies] [per-unit energies] [per-unit partials]
+//   [fragment energies] [items] [split copies] [cube arena]
+struct Plan {
+  bool split = false;
+  std::vector<FragPlan> frags;
+  int64_t total_units = 0, total_work = 0;
+  int pstride = 0;
+  size_t off_desc = 0, off_eps = 0, off_units = 0, off_part = 0, off_efrag = 0, off_items = 0;
+  size_t off_split = 0, off_adj = 0, off_arena = 0;
+  size_t adj_recs = 0;       // bound on the adjoint records (= groups) of all rounds
+  size_t fixed_bytes = 0;    // everything before the arena
+  size_t min_arena = 0;      // the largest cube pair of any fragment
+  size_t all_arena = 0;      // every unit's cube pair at once
+};
+
+// Records per unit of the backward pass: 6 + 6 per-block terms, 6 + 6 summed
+// terms per block group of kABB virtuals, 3 + 3 H terms.
+size_t adj_recs_per_unit(int nv) {
+  return size_t(18) + size_t(12) * size_t((nv + sie::kABB - 1) / sie::kABB);
+}
+
+Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad = false) {
+  Plan p;
+  p.split = prec == SIE_SPLIT_BF16;
+  size_t eps_n = 0, split_bytes = 0;
+  for (int x = 0; x < n; ++x) {
+    FragPlan fp = frag_plan(frags[x].n_occ, frags[x].n_vir, p.split);
+    p.total_units += fp.n_units;
+    p.total_work += fp.work_units;
+    p.pstride = fp.n_part > p.pstride ? fp.n_part : p.pstride;
+    eps_n += size_t(fp.no + fp.nv);
+    split_bytes += fp.split_bytes;
+    const size_t pair = 2 * fp.half_bytes;
+    p.min_arena = fp.work_units > 0 && pair > p.min_arena ? pair : p.min_arena;
+    p.all_arena += pair * size_t(fp.work_units);
+    if (grad) p.adj_recs += size_t(fp.work_units) * adj_recs_per_unit(fp.nv);
+    p.frags.push_back(fp);
+  }
   size_t off = 0;
+  p.off_desc = off;
+  off = align_up(off + sizeof(sie::FragDesc) * size_t(n), 256);
   p.off_eps = off;
-  off = align_up(off + sizeof(double) * size_t(no + nv), 256);
+  off = align_up(off + sizeof(double) * eps_n, 256);
   p.off_units = off;
-  off = align_up(off + sizeof(double) * size_t(p.n_units), 256);
+  off = align_up(off + sizeof(double) * size_t(p.total_units), 256);
   p.off_part = off;
-  off = align_up(off + sizeof(double) * size_t(p.n_units) * size_t(p.n_part), 256);
-  p.off_cube = off;
+  off = align_up(off + sizeof(double) * size_t(p.total_units) * size_t(p.pstride), 256);
+  p.off_efrag = off;
+  off = align_up(off + sizeof(double) * size_t(n), 256);
+  p.off_items = off;
+  off = align_up(off + sizeof(sie::Item) * size_t(p.total_work), 256);
+  p.off_split = off;
+  off = align_up(off + split_bytes, 256);
+  p.off_adj = off;
+  off = align_up(off + (sizeof(sie::AdjRec) + sizeof(sie::AdjGroup)) * p.adj_recs + 256, 256);
+  p.off_arena = off;
   p.fixed_bytes = off;
-  p.cube_bytes = align_up(sizeof(double) * size_t(nv) * size_t(nv) * size_t(nv), 256);
   return p;
 }
 
@@ -104,8 +176,6 @@ sie_status check_fragment(const sie_fragment* f, sie_precision prec, const char*
                 w + ": max(eps_occ) >= min(eps_vir): a triples denominator would not be negative");
   if (f->frag_proj)
     return fail(SIE_ERR_UNSUPPORTED, w + ": fragment projector C^f is not supported by this build");
-  if (prec == SIE_SPLIT_BF16)
-    return fail(SIE_ERR_UNSUPPORTED, w + ": SIE_SPLIT_BF16 is not supported by this build");
   return SIE_OK;
 }
 
@@ -186,107 +256,565 @@ int64_t sie_occupied_triples(int32_t n_occ) {
   return n_occ < 0 ? 0 : sie::tetra(n_occ);
 }
 
-size_t sie_triples_workspace_size(const sie_fragment* frags, int32_t n, sie_precision p,
-                                  size_t max_bytes) {
+}  // extern "C"
+
+namespace {
+
+size_t workspace_size(const sie_fragment* frags, int32_t n, sie_precision p, size_t max_bytes,
+                      bool grad, const char* who) {
+  const std::string w(who);
   if (!frags || n < 1) {
-    fail(SIE_ERR_INVALID_ARG, "sie_triples_workspace_size: need at least one fragment");
+    fail(SIE_ERR_INVALID_ARG, w + ": need at least one fragment");
     return 0;
   }
+  for (int32_t x = 0; x < n; ++x)
+    if (check_fragment(&frags[x], p, who) != SIE_OK) return 0;
   const size_t cap = max_bytes ? max_bytes : default_cap();
-  size_t need = 0;
-  for (int32_t x = 0; x < n; ++x) {
-    if (check_fragment(&frags[x], p, "sie_triples_workspace_size") != SIE_OK) return 0;
-    const Plan pl = make_plan(frags[x].n_occ, frags[x].n_vir);
-    const size_t one = pl.fixed_bytes + pl.cube_bytes;
-    if (one > cap) {
-      fail(SIE_ERR_WORKSPACE, "sie_triples_workspace_size: cap below the minimum for one fragment");
-      return 0;
-    }
-    int64_t chunk = int64_t((cap - pl.fixed_bytes) / pl.cube_bytes);
-    if (chunk > pl.n_units) chunk = pl.n_units;
-    const size_t bytes = pl.fixed_bytes + size_t(chunk) * pl.cube_bytes;
-    need = bytes > need ? bytes : need;
+  const Plan pl = make_plan(frags, n, p, grad);
+  const size_t need_min = pl.fixed_bytes + pl.min_arena;
+  if (need_min > cap) {
+    fail(SIE_ERR_WORKSPACE, w + ": cap below the minimum workspace");
+    return 0;
   }
-  return need;
+  size_t arena = cap - pl.fixed_bytes;
+  if (arena > pl.all_arena) arena = pl.all_arena;
+  if (arena < pl.min_arena) arena = pl.min_arena;
+  return pl.fixed_bytes + arena;
 }
 
-sie_status sie_triples_energy(const sie_fragment* f, sie_precision p, double* e_out,
-                              double* e_triples, void* ws, size_t ws_bytes, void* stream) {
-  sie_status st = check_fragment(f, p, "sie_triples_energy");
-  if (st != SIE_OK) return st;
-  if (!e_out || !aligned(e_out, sizeof(double)))
-    return fail(SIE_ERR_INVALID_ARG, "sie_triples_energy: e_out is NULL or misaligned");
-  if (e_triples && !aligned(e_triples, sizeof(double)))
-    return fail(SIE_ERR_INVALID_ARG, "sie_triples_energy: e_triples is misaligned");
-  const Plan pl = make_plan(f->n_occ, f->n_vir);
+}  // namespace
+
+extern "C" {
+
+size_t sie_triples_workspace_size(const sie_fragment* frags, int32_t n, sie_precision p,
+                                  size_t max_bytes) {
+  return workspace_size(frags, n, p, max_bytes, false, "sie_triples_workspace_size");
+}
+
+size_t sie_triples_backward_workspace_size(const sie_fragment* frags, int32_t n,
+                                           sie_precision p, size_t max_bytes) {
+  return workspace_size(frags, n, p, max_bytes, true, "sie_triples_backward_workspace_size");
+}
+
+}  // extern "C"
+
+namespace {
+
+// Host tables of one evaluation: descriptors, orbital energies, and the
+// work items (units of all fragments, longest first) cut into rounds whose
+// cube pairs fit in the arena.
+struct Tables {
+  std::vector<sie::FragDesc> desc;
+  std::vector<double> eps;
+  std::vector<sie::Item> items;
+  std::vector<size_t> round_begin;   // item index of each round's start, then the end
+};
+
+void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
+                 size_t arena_bytes, const sie_fragment_grad* grads, Tables& T) {
+  auto dev = [&](size_t off) { return base + off; };
+  std::vector<sie::FragDesc>& desc = T.desc;
+  std::vector<double>& eps = T.eps;
+  desc.assign(static_cast<size_t>(n), sie::FragDesc{});
+  eps.clear();
+  int64_t unit_base = 0;
+  size_t split_off = pl.off_split;
+  for (int x = 0; x < n; ++x) {
+    const sie_fragment& f = frags[x];
+    const FragPlan& fp = pl.frags[size_t(x)];
+    sie::FragDesc& d = desc[size_t(x)];
+    d.t1 = f.t1; d.t2 = f.t2; d.ovvv = f.ovvv; d.ooov = f.ooov; d.ovov = f.ovov;
+    d.eps = reinterpret_cast<const double*>(dev(pl.off_eps)) + eps.size();
+    eps.insert(eps.end(), f.eps_occ, f.eps_occ + f.n_occ);
+    eps.insert(eps.end(), f.eps_vir, f.eps_vir + f.n_vir);
+    d.no = fp.no;
+    d.nv = fp.nv;
+    d.Kv = fp.Kv;
+    d.Ko = fp.Ko;
+    // 16-byte row reads need an even row length and 16-byte aligned bases
+    d.vec = (!pl.split && fp.nv % 2 == 0 && aligned(f.t2, 16) && aligned(f.ovvv, 16)) ? 1 : 0;
+    d.n_part = fp.n_part;
+    d.unit_base = unit_base;
+    d.half = int64_t(fp.half_bytes / (pl.split ? sizeof(float) : sizeof(double)));
+    // split: tiles per layout (two layouts); float64: work-groups per unit
+    d.tiles = pl.split ? sie::build_tiles(fp.nv) : sie::wbuild_tiles(fp.nv);
+    d.vS = d.tS = d.tT = d.oT = nullptr;
+    d.g_t1 = grads ? grads[x].t1 : nullptr;
+    d.g_t2 = grads ? grads[x].t2 : nullptr;
+    d.g_ovvv = grads ? grads[x].ovvv : nullptr;
+    d.g_ooov = grads ? grads[x].ooov : nullptr;
+    d.g_ovov = grads ? grads[x].ovov : nullptr;
+    if (pl.split) {
+      const size_t o = size_t(fp.no), v = size_t(fp.nv);
+      d.vS = reinterpret_cast<const sie::u4v*>(dev(split_off));
+      split_off += align_up(4 * o * v * v * size_t(fp.Kv), 256);
+      d.tS = reinterpret_cast<const sie::u4v*>(dev(split_off));
+      split_off += align_up(4 * o * o * v * size_t(fp.Kv), 256);
+      d.tT = reinterpret_cast<const sie::u4v*>(dev(split_off));
+      split_off += align_up(4 * o * v * v * size_t(fp.Ko), 256);
+      d.oT = reinterpret_cast<const sie::u4v*>(dev(split_off));
+      split_off += align_up(4 * o * o * v * size_t(fp.Ko), 256);
+    }
+    unit_base += fp.n_units;
+  }
+
+  // units that are not i = j = k, longest first (stable within a fragment)
+  std::vector<std::pair<int, int>> order;   // (fragment, unit)
+  order.reserve(size_t(pl.total_work));
+  for (int x = 0; x < n; ++x) {
+    const int no = pl.frags[size_t(x)].no;
+    int u = 0;
+    for (int i = 0; i < no; ++i)
+      for (int j = 0; j <= i; ++j)
+        for (int k = 0; k <= j; ++k, ++u)
+          if (i != k) order.emplace_back(x, u);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](const auto& a, const auto& b) {
+    return pl.frags[size_t(a.first)].unit_cost > pl.frags[size_t(b.first)].unit_cost;
+  });
+
+  // rounds: consecutive items whose cube pairs fit in the arena
+  std::vector<sie::Item>& items = T.items;
+  std::vector<size_t>& round_begin = T.round_begin;
+  items.assign(order.size(), sie::Item{});
+  round_begin.clear();
+  {
+    size_t used = 0;
+    int64_t blk = 0, part = 0;
+    const size_t elem = pl.split ? sizeof(float) : sizeof(double);
+    for (size_t r = 0; r < order.size(); ++r) {
+      const FragPlan& fp = pl.frags[size_t(order[r].first)];
+      const size_t pair = 2 * fp.half_bytes;
+      if (r == 0 || used + pair > arena_bytes) {
+        round_begin.push_back(r);
+        used = 0;
+        blk = 0;
+        part = 0;
+      }
+      sie::Item& it = items[r];
+      it.frag = order[r].first;
+      it.unit = order[r].second;
+      it.cube_off = int64_t(used / elem);
+      used += pair;
+      blk += (pl.split ? 2 : 1) * desc[size_t(it.frag)].tiles;
+      part += fp.n_part;
+      it.blk_end = blk;
+      it.part_end = part;
+    }
+    round_begin.push_back(order.size());
+  }
+
+}
+
+// One evaluation over n fragments (see work.hpp).
+sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag_out,
+               double* e_total, double* e_triples, void* ws, size_t ws_bytes, void* stream,
+               const char* who) {
+  const std::string w(who);
+  if (!frags || n < 1) return fail(SIE_ERR_INVALID_ARG, w + ": need at least one fragment");
+  for (int x = 0; x < n; ++x) {
+    sie_status st = check_fragment(&frags[x], p, who);
+    if (st != SIE_OK) return st;
+  }
+  const Plan pl = make_plan(frags, n, p);
   if (!ws || !aligned(ws, 256))
-    return fail(SIE_ERR_WORKSPACE, "sie_triples_energy: workspace is NULL or not 256-byte aligned");
-  if (ws_bytes < pl.fixed_bytes + pl.cube_bytes)
-    return fail(SIE_ERR_WORKSPACE, "sie_triples_energy: workspace smaller than required (see "
-                                   "sie_triples_workspace_size)");
-  int64_t chunk = int64_t((ws_bytes - pl.fixed_bytes) / pl.cube_bytes);
-  if (chunk > pl.n_units) chunk = pl.n_units;
-  if (chunk > 65535) chunk = 65535;
+    return fail(SIE_ERR_WORKSPACE, w + ": workspace is NULL or not 256-byte aligned");
+  if (ws_bytes < pl.fixed_bytes + pl.min_arena)
+    return fail(SIE_ERR_WORKSPACE,
+                w + ": workspace smaller than required (see sie_triples_workspace_size)");
+  const size_t arena_bytes = ws_bytes - pl.fixed_bytes;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
-  double* d_eps = reinterpret_cast<double*>(base + pl.off_eps);
-  double* d_units = e_triples ? e_triples : reinterpret_cast<double*>(base + pl.off_units);
-  double* d_part = reinterpret_cast<double*>(base + pl.off_part);
-  double* d_cube = reinterpret_cast<double*>(base + pl.off_cube);
+  auto dev = [&](size_t off) { return base + off; };
 
-  const int no = pl.no, nv = pl.nv;
-  st = hip_check(hipMemcpyAsync(d_eps, f->eps_occ, sizeof(double) * no, hipMemcpyHostToDevice, s),
-                 "copy eps_occ");
+  Tables T;
+  make_tables(frags, n, pl, base, arena_bytes, nullptr, T);
+  std::vector<sie::FragDesc>& desc = T.desc;
+  std::vector<double>& eps = T.eps;
+  std::vector<sie::Item>& items = T.items;
+  std::vector<size_t>& round_begin = T.round_begin;
+
+  // ---- uploads (host tables must outlive the copies: wait for them) ----
+  sie_status st = hip_check(hipMemcpyAsync(dev(pl.off_desc), desc.data(),
+                                           sizeof(sie::FragDesc) * desc.size(),
+                                           hipMemcpyHostToDevice, s), "upload descriptors");
+  if (st == SIE_OK)
+    st = hip_check(hipMemcpyAsync(dev(pl.off_eps), eps.data(), sizeof(double) * eps.size(),
+                                  hipMemcpyHostToDevice, s), "upload orbital energies");
+  if (st == SIE_OK && !items.empty())
+    st = hip_check(hipMemcpyAsync(dev(pl.off_items), items.data(),
+                                  sizeof(sie::Item) * items.size(), hipMemcpyHostToDevice, s),
+                   "upload work items");
+  if (st == SIE_OK) st = hip_check(hipStreamSynchronize(s), "upload tables");
   if (st != SIE_OK) return st;
-  st = hip_check(hipMemcpyAsync(d_eps + no, f->eps_vir, sizeof(double) * nv,
-                                hipMemcpyHostToDevice, s),
-                 "copy eps_vir");
-  if (st != SIE_OK) return st;
 
-  sie::FragDev fd;
-  fd.t1 = static_cast<const double*>(f->t1);
-  fd.t2 = static_cast<const double*>(f->t2);
-  fd.ovvv = static_cast<const double*>(f->ovvv);
-  fd.ooov = static_cast<const double*>(f->ooov);
-  fd.ovov = static_cast<const double*>(f->ovov);
-  fd.eps = d_eps;
-  fd.no = no;
-  fd.nv = nv;
+  const sie::FragDesc* d_desc = reinterpret_cast<const sie::FragDesc*>(dev(pl.off_desc));
+  const sie::Item* d_items = reinterpret_cast<const sie::Item*>(dev(pl.off_items));
+  double* d_units = (e_triples && n == 1) ? e_triples
+                                          : reinterpret_cast<double*>(dev(pl.off_units));
+  double* d_part = reinterpret_cast<double*>(dev(pl.off_part));
+  double* d_efrag = e_frag_out ? e_frag_out : reinterpret_cast<double*>(dev(pl.off_efrag));
 
-  const int nbk = (nv + sie::kTile - 1) / sie::kTile;
-  const unsigned n_tiles = unsigned(nbk) * unsigned(nbk) * unsigned(nbk);
-  const int64_t cube_stride = int64_t(pl.cube_bytes / sizeof(double));
-  // 16-byte row reads need an even row length and 16-byte aligned bases
-  const bool vec = (nv % 2 == 0) && aligned(f->t2, 16) && aligned(f->ovvv, 16);
-  for (int64_t u0 = 0; u0 < pl.n_units; u0 += chunk) {
-    const int64_t cnt = (pl.n_units - u0) < chunk ? (pl.n_units - u0) : chunk;
-    {
-      ProfScope ps(s, 0);
-      if (vec)
-        hipLaunchKernelGGL(sie::k_build_w_f64<true>, dim3(n_tiles, unsigned(cnt)), dim3(256), 0,
-                           s, fd, u0, pl.n_units, d_cube, cube_stride);
-      else
-        hipLaunchKernelGGL(sie::k_build_w_f64<false>, dim3(n_tiles, unsigned(cnt)), dim3(256), 0,
-                           s, fd, u0, pl.n_units, d_cube, cube_stride);
+  // ---- split staging (split precision) ----
+  if (pl.split) {
+    ProfScope ps(s, 3);
+    auto split = [&](const void* src, int P, int X, int Y, int64_t sp, int64_t sx, int64_t sy,
+                     int64_t sk, int K, int Kpad, bool kfast, const sie::u4v* dst) {
+      const int64_t total = int64_t(P) * X * Y * (Kpad / 8);
+      const int64_t nb = (total + 255) / 256;
+      const unsigned grid = unsigned(nb < 65536 ? nb : 65536);
+      hipLaunchKernelGGL(sie::k_split_bf16, dim3(grid), dim3(256), 0, s,
+                         static_cast<const float*>(src), P, X, Y, sp, sx, sy, sk, K, Kpad, kfast,
+                         const_cast<sie::u4v*>(dst));
+    };
+    for (int x = 0; x < n; ++x) {
+      const sie::FragDesc& d = desc[size_t(x)];
+      const int no = d.no, nv = d.nv;
+      const int64_t o = no, v = nv;
+      // vS[i][a][b][d] <- ovvv, tS[i][j][a][d] <- t2 (K = d contiguous)
+      split(d.ovvv, no, nv, nv, v * v * v, v * v, v, 1, nv, d.Kv, true, d.vS);
+      split(d.t2, no, no, nv, o * v * v, v * v, v, 1, nv, d.Kv, true, d.tS);
+      // tT[p][x][y][l] = t2[p][l][x][y], oT[x][y][v][l] = ooov[x][l][y][v] (K = l)
+      split(d.t2, no, nv, nv, o * v * v, v, 1, v * v, no, d.Ko, false, d.tT);
+      split(d.ooov, no, no, nv, o * o * v, v, 1, o * v, no, d.Ko, false, d.oT);
     }
-    {
-      ProfScope ps(s, 1);
-      hipLaunchKernelGGL(sie::k_epilogue_f64, dim3(unsigned(pl.n_part), unsigned(cnt)),
-                         dim3(256), 0, s, fd, u0, pl.n_units, d_cube, cube_stride, d_part,
-                         pl.n_part);
+    st = hip_check(hipGetLastError(), "launch split staging");
+    if (st != SIE_OK) return st;
+  }
+
+  // ---- rounds ----
+  for (size_t q = 0; q + 1 < round_begin.size(); ++q) {
+    const size_t r0 = round_begin[q], r1 = round_begin[q + 1];
+    if (r1 == r0) continue;
+    const int cnt = int(r1 - r0);
+    const unsigned n_blk = unsigned(items[r1 - 1].blk_end);
+    const unsigned n_epi = unsigned(items[r1 - 1].part_end);
+    const sie::Item* ri = d_items + r0;
+    if (!pl.split) {
+      double* arena = reinterpret_cast<double*>(dev(pl.off_arena));
+      {
+        ProfScope ps(s, 0);
+        hipLaunchKernelGGL(sie::k_build_w_f64, dim3(n_blk), dim3(256), 0, s, d_desc,
+                           ri, cnt, arena);
+      }
+      {
+        ProfScope ps(s, 1);
+        hipLaunchKernelGGL((sie::k_epilogue<double, double, true>), dim3(n_epi), dim3(256), 0, s,
+                           d_desc, ri, cnt, arena, d_part, pl.pstride);
+      }
+    } else {
+      float* arena = reinterpret_cast<float*>(dev(pl.off_arena));
+      {
+        ProfScope ps(s, 0);
+        hipLaunchKernelGGL(sie::k_build_w_bf16x3, dim3(n_blk), dim3(sie::kThreads), 0, s, d_desc,
+                           ri, cnt, arena);
+      }
+      {
+        ProfScope ps(s, 1);
+        hipLaunchKernelGGL((sie::k_epilogue<float, float, true>), dim3(n_epi), dim3(256), 0, s, d_desc,
+                           ri, cnt, arena, d_part, pl.pstride);
+      }
     }
     st = hip_check(hipGetLastError(), "launch (T) kernels");
     if (st != SIE_OK) return st;
   }
-  const unsigned ub = unsigned((pl.n_units + 255) / 256);
+
+  // ---- reductions ----
   {
     ProfScope ps(s, 2);
-    hipLaunchKernelGGL(sie::k_unit_energy, dim3(ub), dim3(256), 0, s, no, pl.n_units, d_part,
-                       pl.n_part, d_units);
-    hipLaunchKernelGGL(sie::k_sum_fixed, dim3(1), dim3(256), 0, s, d_units, pl.n_units, e_out);
+    int64_t max_units = 1;
+    for (const auto& fp : pl.frags) max_units = fp.n_units > max_units ? fp.n_units : max_units;
+    hipLaunchKernelGGL(sie::k_unit_energy, dim3(unsigned((max_units + 255) / 256), unsigned(n)),
+                       dim3(256), 0, s, d_desc, d_part, pl.pstride, d_units);
+    hipLaunchKernelGGL(sie::k_frag_energy, dim3(unsigned(n)), dim3(256), 0, s, d_desc, d_units,
+                       d_efrag);
+    if (e_total)
+      hipLaunchKernelGGL(sie::k_sum_fixed, dim3(1), dim3(256), 0, s, d_efrag, int64_t(n), e_total);
   }
   return hip_check(hipGetLastError(), "launch reductions");
+}
+
+
+// Backward contraction lists of one round: for every class, the output slices
+// the round's units touch (sorted), each with its records in item order.
+struct AdjLaunch {
+  size_t group_off = 0;   // first group in the uploaded group table
+  int n_groups = 0;
+  int64_t n_wg = 0;
+};
+
+void adj_round_lists(const Tables& T, size_t r0, size_t r1, std::vector<sie::AdjGroup>& groups,
+                     std::vector<sie::AdjRec>& recs, AdjLaunch (&launch)[sie::kAdjClasses]) {
+  for (int cls = 0; cls < sie::kAdjClasses; ++cls) {
+    struct Key {
+      int frag, a0, a1;
+      bool operator<(const Key& o) const {
+        return frag != o.frag ? frag < o.frag : (a0 != o.a0 ? a0 < o.a0 : a1 < o.a1);
+      }
+    };
+    std::vector<std::pair<Key, sie::AdjRec>> list;
+    for (size_t r = r0; r < r1; ++r) {
+      const sie::Item& it = T.items[r];
+      const sie::FragDesc& d = T.desc[size_t(it.frag)];
+      const bool want = cls == sie::kAdjOvvv ? d.g_ovvv != nullptr
+                        : cls == sie::kAdjOoov ? d.g_ooov != nullptr
+                        : cls == sie::kAdjOvov ? d.g_ovov != nullptr
+                        : cls == sie::kAdjT1   ? d.g_t1 != nullptr
+                                               : d.g_t2 != nullptr;
+      if (!want) continue;
+      // sorted triple of the unit index
+      int i = 0, j = 0, k = 0;
+      {
+        int64_t u = it.unit;
+        while (sie::tetra(i + 1) <= u) ++i;
+        u -= sie::tetra(i);
+        while (sie::tri(j + 1) <= u) ++j;
+        k = int(u - sie::tri(j));
+      }
+      const int ng = sie::adj_reduce(cls) ? (d.nv + sie::kABB - 1) / sie::kABB : 1;
+      for (int kind = 0; kind < sie::adj_kinds(cls); ++kind) {
+        Key key{it.frag, 0, 0};
+        sie::adj_slice(cls, kind, i, j, k, key.a0, key.a1);
+        for (int g = 0; g < ng; ++g) {
+          sie::AdjRec rec{int(r - r0), kind, g, 0};
+          list.emplace_back(key, rec);
+        }
+      }
+    }
+    std::stable_sort(list.begin(), list.end(),
+                     [](const auto& a, const auto& b) { return a.first < b.first; });
+    launch[cls].group_off = groups.size();
+    launch[cls].n_groups = 0;
+    int64_t wg = 0;
+    for (size_t q = 0; q < list.size();) {
+      size_t e = q;
+      while (e < list.size() && !(list[q].first < list[e].first) && !(list[e].first < list[q].first))
+        ++e;
+      const Key& key = list[q].first;
+      const sie::FragDesc& d = T.desc[size_t(key.frag)];
+      sie::AdjGroup gr{};
+      gr.frag = key.frag;
+      gr.a0 = key.a0;
+      gr.a1 = key.a1;
+      gr.rec_begin = int(recs.size());
+      for (size_t m = q; m < e; ++m) recs.push_back(list[m].second);
+      gr.rec_end = int(recs.size());
+      wg += sie::adj_tiles(cls, d.no, d.nv);
+      gr.wg_end = wg;
+      groups.push_back(gr);
+      ++launch[cls].n_groups;
+      q = e;
+    }
+    launch[cls].n_wg = wg;
+  }
+}
+
+sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const double* grad_e,
+                        const sie_fragment_grad* grads, double* e_frag_out, void* ws,
+                        size_t ws_bytes, void* stream) {
+  const char* who = "sie_triples_backward";
+  const std::string w(who);
+  if (!frags || n < 1) return fail(SIE_ERR_INVALID_ARG, w + ": need at least one fragment");
+  if (!grads) return fail(SIE_ERR_INVALID_ARG, w + ": gradient descriptor array is NULL");
+  for (int x = 0; x < n; ++x) {
+    sie_status st = check_fragment(&frags[x], p, who);
+    if (st != SIE_OK) return st;
+    const sie_fragment_grad& g = grads[x];
+    for (const double* q : {g.t1, g.t2, g.ovvv, g.ooov, g.ovov})
+      if (q && !aligned(q, sizeof(double)))
+        return fail(SIE_ERR_INVALID_ARG, w + ": a gradient array is misaligned");
+  }
+  if (p != SIE_FP64)
+    return fail(SIE_ERR_UNSUPPORTED, w + ": only SIE_FP64 has a backward pass in this build");
+  if (grad_e && !aligned(grad_e, sizeof(double)))
+    return fail(SIE_ERR_INVALID_ARG, w + ": grad_e is misaligned");
+  if (e_frag_out && !aligned(e_frag_out, sizeof(double)))
+    return fail(SIE_ERR_INVALID_ARG, w + ": e_frag is misaligned");
+  const Plan pl = make_plan(frags, n, p, true);
+  if (!ws || !aligned(ws, 256))
+    return fail(SIE_ERR_WORKSPACE, w + ": workspace is NULL or not 256-byte aligned");
+  if (ws_bytes < pl.fixed_bytes + pl.min_arena)
+    return fail(SIE_ERR_WORKSPACE,
+                w + ": workspace smaller than required (see sie_triples_backward_workspace_size)");
+  const size_t arena_bytes = ws_bytes - pl.fixed_bytes;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  auto dev = [&](size_t off) { return base + off; };
+
+  Tables T;
+  make_tables(frags, n, pl, base, arena_bytes, grads, T);
+  const size_t n_rounds = T.round_begin.size() - 1;
+  std::vector<sie::AdjGroup> groups;
+  std::vector<sie::AdjRec> recs;
+  std::vector<std::array<AdjLaunch, sie::kAdjClasses>> launches(n_rounds);
+  for (size_t q = 0; q < n_rounds; ++q) {
+    AdjLaunch l[sie::kAdjClasses];
+    adj_round_lists(T, T.round_begin[q], T.round_begin[q + 1], groups, recs, l);
+    for (int c = 0; c < sie::kAdjClasses; ++c) launches[q][size_t(c)] = l[c];
+  }
+  if (recs.size() > pl.adj_recs || groups.size() > pl.adj_recs)
+    return fail(SIE_ERR_HIP, w + ": internal error: contraction lists exceed their bound");
+  const size_t off_recs = pl.off_adj;
+  const size_t off_groups = align_up(off_recs + sizeof(sie::AdjRec) * pl.adj_recs, 256);
+
+  sie_status st = hip_check(hipMemcpyAsync(dev(pl.off_desc), T.desc.data(),
+                                           sizeof(sie::FragDesc) * T.desc.size(),
+                                           hipMemcpyHostToDevice, s), "upload descriptors");
+  if (st == SIE_OK)
+    st = hip_check(hipMemcpyAsync(dev(pl.off_eps), T.eps.data(), sizeof(double) * T.eps.size(),
+                                  hipMemcpyHostToDevice, s), "upload orbital energies");
+  if (st == SIE_OK && !T.items.empty())
+    st = hip_check(hipMemcpyAsync(dev(pl.off_items), T.items.data(),
+                                  sizeof(sie::Item) * T.items.size(), hipMemcpyHostToDevice, s),
+                   "upload work items");
+  if (st == SIE_OK && !recs.empty())
+    st = hip_check(hipMemcpyAsync(dev(off_recs), recs.data(), sizeof(sie::AdjRec) * recs.size(),
+                                  hipMemcpyHostToDevice, s), "upload contraction records");
+  if (st == SIE_OK && !groups.empty())
+    st = hip_check(hipMemcpyAsync(dev(off_groups), groups.data(),
+                                  sizeof(sie::AdjGroup) * groups.size(), hipMemcpyHostToDevice, s),
+                   "upload contraction groups");
+  if (st == SIE_OK) st = hip_check(hipStreamSynchronize(s), "upload tables");
+  if (st != SIE_OK) return st;
+
+  const sie::FragDesc* d_desc = reinterpret_cast<const sie::FragDesc*>(dev(pl.off_desc));
+  const sie::Item* d_items = reinterpret_cast<const sie::Item*>(dev(pl.off_items));
+  const sie::AdjRec* d_recs = reinterpret_cast<const sie::AdjRec*>(dev(off_recs));
+  const sie::AdjGroup* d_groups = reinterpret_cast<const sie::AdjGroup*>(dev(off_groups));
+  double* d_units = reinterpret_cast<double*>(dev(pl.off_units));
+  double* d_part = reinterpret_cast<double*>(dev(pl.off_part));
+  double* d_efrag = e_frag_out ? e_frag_out : reinterpret_cast<double*>(dev(pl.off_efrag));
+  double* arena = reinterpret_cast<double*>(dev(pl.off_arena));
+
+  auto fill = [&](double* ptr, int64_t count) {
+    if (!ptr || count <= 0) return;
+    const int64_t nb = (count + 255) / 256;
+    hipLaunchKernelGGL(sie::k_fill_zero, dim3(unsigned(nb < 65536 ? nb : 65536)), dim3(256), 0,
+                       s, ptr, count);
+  };
+  {
+    ProfScope ps(s, 4);
+    for (int x = 0; x < n; ++x) {
+      const int64_t o = frags[x].n_occ, v = frags[x].n_vir;
+      fill(grads[x].t1, o * v);
+      fill(grads[x].t2, o * o * v * v);
+      fill(grads[x].ovvv, o * v * v * v);
+      fill(grads[x].ooov, o * o * o * v);
+      fill(grads[x].ovov, o * v * o * v);
+    }
+  }
+  st = hip_check(hipGetLastError(), "launch gradient fill");
+  if (st != SIE_OK) return st;
+
+  for (size_t q = 0; q < n_rounds; ++q) {
+    const size_t r0 = T.round_begin[q], r1 = T.round_begin[q + 1];
+    if (r1 == r0) continue;
+    const int cnt = int(r1 - r0);
+    const sie::Item* ri = d_items + r0;
+    {
+      ProfScope ps(s, 0);
+      hipLaunchKernelGGL(sie::k_build_w_f64, dim3(unsigned(T.items[r1 - 1].blk_end)),
+                         dim3(256), 0, s, d_desc, ri, cnt, arena);
+    }
+    {
+      ProfScope ps(s, 1);
+      hipLaunchKernelGGL(sie::k_hat, dim3(unsigned(T.items[r1 - 1].part_end)), dim3(256), 0, s,
+                         d_desc, ri, cnt, arena, d_part, pl.pstride, grad_e);
+    }
+    {
+      ProfScope ps(s, 4);
+      const auto& L = launches[q];
+      const AdjLaunch& lo = L[sie::kAdjOvvv];
+      if (lo.n_wg)
+        hipLaunchKernelGGL(sie::k_adj_contract<sie::kAdjOvvv>, dim3(unsigned(lo.n_wg)),
+                           dim3(sie::kAThreads), 0, s, d_desc, ri, d_groups + lo.group_off,
+                           lo.n_groups, d_recs, arena);
+      const AdjLaunch& lv = L[sie::kAdjT2vv];
+      if (lv.n_wg)
+        hipLaunchKernelGGL(sie::k_adj_contract<sie::kAdjT2vv>, dim3(unsigned(lv.n_wg)),
+                           dim3(sie::kAThreads), 0, s, d_desc, ri, d_groups + lv.group_off,
+                           lv.n_groups, d_recs, arena);
+      const AdjLaunch& lt = L[sie::kAdjT2oo];
+      if (lt.n_wg)
+        hipLaunchKernelGGL(sie::k_adj_contract<sie::kAdjT2oo>, dim3(unsigned(lt.n_wg)),
+                           dim3(sie::kAThreads), 0, s, d_desc, ri, d_groups + lt.group_off,
+                           lt.n_groups, d_recs, arena);
+      const AdjLaunch& lr = L[sie::kAdjOoov];
+      if (lr.n_wg)
+        hipLaunchKernelGGL(sie::k_adj_contract<sie::kAdjOoov>, dim3(unsigned(lr.n_wg)),
+                           dim3(sie::kAThreads), 0, s, d_desc, ri, d_groups + lr.group_off,
+                           lr.n_groups, d_recs, arena);
+      const AdjLaunch& lp = L[sie::kAdjOvov];
+      if (lp.n_wg)
+        hipLaunchKernelGGL(sie::k_adj_ovov, dim3(unsigned(lp.n_wg)), dim3(256), 0, s, d_desc, ri,
+                           d_groups + lp.group_off, lp.n_groups, d_recs, arena);
+      const AdjLaunch& l1 = L[sie::kAdjT1];
+      if (l1.n_wg)
+        hipLaunchKernelGGL(sie::k_adj_t1, dim3(unsigned(l1.n_wg)), dim3(256), 0, s, d_desc, ri,
+                           d_groups + l1.group_off, l1.n_groups, d_recs, arena);
+    }
+    st = hip_check(hipGetLastError(), "launch backward kernels");
+    if (st != SIE_OK) return st;
+  }
+
+  {
+    ProfScope ps(s, 4);
+    auto sym = [&](double* ptr, int kind, int no, int nv, int64_t count) {
+      if (!ptr) return;
+      const int64_t nb = (count + 255) / 256;
+      hipLaunchKernelGGL(sie::k_symmetrize, dim3(unsigned(nb < 65536 ? nb : 65536)), dim3(256),
+                         0, s, ptr, kind, no, nv, count);
+    };
+    for (int x = 0; x < n; ++x) {
+      const int no = frags[x].n_occ, nv = frags[x].n_vir;
+      const int64_t o = no, v = nv;
+      sym(grads[x].t2, sie::kSymT2, no, nv, o * o * v * v);
+      sym(grads[x].ovvv, sie::kSymOvvv, no, nv, o * v * v * v);
+      sym(grads[x].ooov, sie::kSymOoov, no, nv, o * o * o * v);
+      sym(grads[x].ovov, sie::kSymOvov, no, nv, o * v * o * v);
+    }
+  }
+  {
+    ProfScope ps(s, 2);
+    int64_t max_units = 1;
+    for (const auto& fp : pl.frags) max_units = fp.n_units > max_units ? fp.n_units : max_units;
+    hipLaunchKernelGGL(sie::k_unit_energy, dim3(unsigned((max_units + 255) / 256), unsigned(n)),
+                       dim3(256), 0, s, d_desc, d_part, pl.pstride, d_units);
+    hipLaunchKernelGGL(sie::k_frag_energy, dim3(unsigned(n)), dim3(256), 0, s, d_desc, d_units,
+                       d_efrag);
+  }
+  return hip_check(hipGetLastError(), "launch gradient symmetrization and reductions");
+}
+
+}  // namespace
+
+extern "C" {
+
+sie_status sie_triples_energy(const sie_fragment* f, sie_precision p, double* e_out,
+                              double* e_triples, void* ws, size_t ws_bytes, void* stream) {
+  if (!e_out || !aligned(e_out, sizeof(double)))
+    return fail(SIE_ERR_INVALID_ARG, "sie_triples_energy: e_out is NULL or misaligned");
+  if (e_triples && !aligned(e_triples, sizeof(double)))
+    return fail(SIE_ERR_INVALID_ARG, "sie_triples_energy: e_triples is misaligned");
+  return run(f, 1, p, nullptr, e_out, e_triples, ws, ws_bytes, stream, "sie_triples_energy");
+}
+
+sie_status sie_triples_energy_batched(const sie_fragment* frags, int32_t n, sie_precision p,
+                                      double* e_frag, double* e_total, void* ws,
+                                      size_t ws_bytes, void* stream) {
+  if (!e_frag || !aligned(e_frag, sizeof(double)))
+    return fail(SIE_ERR_INVALID_ARG, "sie_triples_energy_batched: e_frag is NULL or misaligned");
+  if (e_total && !aligned(e_total, sizeof(double)))
+    return fail(SIE_ERR_INVALID_ARG, "sie_triples_energy_batched: e_total is misaligned");
+  return run(frags, n, p, e_frag, e_total, nullptr, ws, ws_bytes, stream,
+             "sie_triples_energy_batched");
+}
+
+sie_status sie_triples_backward(const sie_fragment* frags, int32_t n, sie_precision p,
+                                const double* grad_e, const sie_fragment_grad* grads,
+                                double* e_frag, void* ws, size_t ws_bytes, void* stream) {
+  return run_backward(frags, n, p, grad_e, grads, e_frag, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

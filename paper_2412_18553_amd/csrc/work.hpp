@@ -1,0 +1,64 @@
+// Work description shared by the host runtime and the kernels.
+//
+// An evaluation covers one or more fragments.  Their occupied triples
+// ("units", i >= j >= k, not all equal) are ordered longest-first by cost per
+// unit and cut into rounds whose W-tilde cubes fit in the workspace arena.
+// Each round is one build launch and one epilogue launch whose blocks are the
+// concatenation of every item's blocks (item = one unit of one fragment):
+// the hardware dispatcher hands blocks out in index order, so the round is a
+// longest-job-first work queue over all fragments.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace sie {
+
+struct FragDesc {
+  // caller inputs: float64 (SIE_FP64) or float32 (SIE_SPLIT_BF16)
+  const void* t1;
+  const void* t2;
+  const void* ovvv;
+  const void* ooov;
+  const void* ovov;
+  // split copies in the workspace (SIE_SPLIT_BF16 only), see k_bf16.hpp
+  const u4v* vS;
+  const u4v* tS;
+  const u4v* tT;
+  const u4v* oT;
+  const double* eps;      // [no + nv] workspace copy: eps_occ then eps_vir
+  int no, nv;
+  int Kv, Ko;             // padded contraction lengths of the split copies
+  int vec;                // float64: rows may be read 16 bytes at a time
+  int n_part;             // epilogue partial slots per unit
+  int64_t unit_base;      // first entry of this fragment in the per-unit arrays
+  int64_t half;           // elements per partial cube (aligned)
+  int64_t tiles;          // build tiles per layout
+  // gradient outputs (float64, input shapes; backward only)
+  double* g_t1;
+  double* g_t2;
+  double* g_ovvv;
+  double* g_ooov;
+  double* g_ovov;
+};
+
+struct Item {
+  int frag;               // fragment index
+  int unit;               // unit index u within the fragment (tetrahedral order)
+  int64_t cube_off;       // element offset of the item's two partial cubes
+  int64_t blk_end;        // inclusive end of the item's build blocks (prefix sum)
+  int64_t part_end;       // inclusive end of the item's epilogue blocks (prefix sum)
+};
+
+// First item r with key(r) > x, for prefix-sum keys (blk_end or part_end).
+template <bool BUILD>
+__device__ __forceinline__ int find_item(const Item* __restrict__ items, int n, int64_t x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const int64_t key = BUILD ? items[mid].blk_end : items[mid].part_end;
+    if (key > x) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+}  // namespace sie

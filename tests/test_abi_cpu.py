@@ -109,18 +109,23 @@ def test_workspace_errors(lib):
     assert energy(lib, f, ws_bytes=64) == _lib.SIE_ERR_WORKSPACE
 
 
-def test_split_precision_not_yet(lib):
+def test_split_precision_checks(lib):
     keep = []
-    f = frag(keep=keep)
-    assert energy(lib, f, prec=_lib.SIE_SPLIT_BF16) == _lib.SIE_ERR_UNSUPPORTED
+    f = frag(keep=keep, ovvv=FAKE + 4)            # float32 needs 4-byte alignment only
+    assert lib.sie_triples_workspace_size(ctypes.byref(f), 1, _lib.SIE_SPLIT_BF16, 0) > 0
+    f = frag(keep=keep, ovvv=FAKE + 2)
+    assert energy(lib, f, prec=_lib.SIE_SPLIT_BF16) == _lib.SIE_ERR_INVALID_ARG
 
 
 def test_profile_collect_empty(lib):
+    header = open(HEADER).read()
+    n = int(re.search(r"#define SIE_PROF_CLASSES (\d+)", header).group(1))
+    assert n == len(_lib.PROF_CLASSES)
     lib.sie_profile_enable(1)
-    ms = (ctypes.c_double * 3)()
-    cnt = (ctypes.c_int64 * 3)()
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
     assert lib.sie_profile_collect(ms, cnt) == _lib.SIE_OK
-    assert list(cnt) == [0, 0, 0]
+    assert list(cnt) == [0] * n
     lib.sie_profile_enable(0)
     assert lib.sie_profile_collect(None, None) == _lib.SIE_ERR_INVALID_ARG
 
@@ -131,3 +136,28 @@ def test_python_binding_rejects_bad_shapes():
     with pytest.raises(TypeError):
         sie.Fragment(np.zeros(2), np.ones(3), torch.zeros(2, 3, dtype=torch.float64),
                      None, None, None, None)
+
+
+def backward(lib, f, grads, prec=_lib.SIE_FP64, ws=FAKE, ws_bytes=1 << 30, grad_e=None):
+    return lib.sie_triples_backward(ctypes.byref(f), 1, prec, grad_e, grads, None, ws, ws_bytes,
+                                    None)
+
+
+def test_backward_workspace_and_errors(lib):
+    keep = []
+    f = frag(keep=keep)
+    fwd = lib.sie_triples_workspace_size(ctypes.byref(f), 1, _lib.SIE_FP64, 0)
+    bwd = lib.sie_triples_backward_workspace_size(ctypes.byref(f), 1, _lib.SIE_FP64, 0)
+    assert bwd > fwd > 0
+    g = _lib.SieFragmentGrad(FAKE, FAKE, FAKE, FAKE, FAKE)
+    assert lib.sie_triples_backward(ctypes.byref(f), 1, _lib.SIE_FP64, None, None, None, FAKE,
+                                    1 << 30, None) == _lib.SIE_ERR_INVALID_ARG
+    assert backward(lib, f, ctypes.byref(_lib.SieFragmentGrad(FAKE, FAKE + 4, None, None, None))
+                    ) == _lib.SIE_ERR_INVALID_ARG
+    assert backward(lib, f, ctypes.byref(g), grad_e=FAKE + 4) == _lib.SIE_ERR_INVALID_ARG
+    assert backward(lib, f, ctypes.byref(g), prec=_lib.SIE_SPLIT_BF16) == _lib.SIE_ERR_UNSUPPORTED
+    assert backward(lib, f, ctypes.byref(g), ws=None) == _lib.SIE_ERR_WORKSPACE
+    assert backward(lib, f, ctypes.byref(g), ws_bytes=4096) == _lib.SIE_ERR_WORKSPACE
+    fp = frag(keep=keep, frag_proj=FAKE)
+    assert backward(lib, fp, ctypes.byref(g)) == _lib.SIE_ERR_UNSUPPORTED
+    assert len(_lib.last_error()) > 0

@@ -1,0 +1,192 @@
+"""float64 gradient of the (T) energy on the GPU (sie_triples_backward).
+
+Small fragments: every entry of every gradient block against the oracle
+gradient (oracle/grad.py, itself pinned by finite differences of the
+textbook spin-orbital energy), within 1e-10 of the block's largest entry.
+
+The 16-occupied / 120-virtual fragment (too large for the dense oracle):
+properties that hold at any size, evaluated with the GPU energy path
+  * central differences along seeded symmetric directions, per block (the
+    energy is at most quadratic in each block, so the difference is exact
+    up to rounding), within 1e-8 relative;
+  * the Euler identities of the W/V split: sum t1 g_t1 = E_WV = sum ovov
+    g_ovov, sum t2 g_t2 = 2 E_WW + E_WV = sum ovvv g_ovvv + sum ooov g_ooov,
+    with E_WV = E - E(t1 = 0) and E_WW = E(t1 = 0) from the energy path.
+"""
+
+import numpy as np
+import pytest
+
+from oracle.grad import energy_gradient, symmetrize_direction
+from synth import make_fragment, workload_fragment
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ("t1", "t2", "ovvv", "ooov", "ovov")
+RTOL = 1e-10
+
+
+def _dev(f):
+    import torch
+    cast = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda", torch.float64)  # noqa: E731
+    return [f.eps_occ, f.eps_vir] + [cast(getattr(f, n)) for n in NAMES]
+
+
+def gpu_grad(f, grad_e=None, e_frag=None, max_workspace_bytes=0):
+    import torch
+    import paper_2412_18553_amd as sie
+    frag = sie.Fragment(*_dev(f))
+    ge = None if grad_e is None else torch.tensor([grad_e], dtype=torch.float64, device="cuda")
+    g = sie.backward(frag, grad_e=ge, e_frag=e_frag, max_workspace_bytes=max_workspace_bytes)
+    torch.cuda.synchronize()
+    return {n: g[n].cpu().numpy() for n in NAMES}
+
+
+def gpu_energy(args):
+    import paper_2412_18553_amd as sie
+    return float(sie.triples_energy(*args).item())
+
+
+@pytest.mark.parametrize("o,v,aux,seed", [
+    (2, 3, 8, 1), (3, 9, 24, 2), (4, 12, 30, 3), (5, 20, 60, 4), (3, 33, 40, 5),
+    (4, 70, 90, 6)])
+def test_gradient_vs_oracle(o, v, aux, seed):
+    """Ragged sizes: virtual counts off the 8-, 32- and 64-wide tiles, and
+    70 virtuals spanning two 64-row tiles and three 32-col tiles."""
+    print(f"case o={o} v={v} seed={seed}", flush=True)
+    f = make_fragment(o, v, aux, (11, seed))
+    _, _, _, ref = energy_gradient(*f.arrays())
+    got = gpu_grad(f)
+    for n in NAMES:
+        scale = max(np.abs(ref[n]).max(), 1e-300)
+        err = np.abs(got[n] - ref[n]).max() / scale
+        print(f"  {n}: max|err|/max|g| = {err:.2e}", flush=True)
+        assert err <= RTOL, (n, err)
+
+
+def test_one_occupied_gradient_is_zero():
+    f = make_fragment(1, 12, 20, (11, 9))
+    got = gpu_grad(f)
+    for n in NAMES:
+        assert np.all(got[n] == 0.0), n
+
+
+def test_energy_output_matches_forward_and_scaling():
+    import torch
+    import paper_2412_18553_amd as sie
+    f = make_fragment(4, 20, 40, (11, 10))
+    e_fwd = gpu_energy(_dev(f))
+    e_frag = torch.empty(1, dtype=torch.float64, device="cuda")
+    g1 = gpu_grad(f, e_frag=e_frag)
+    assert float(e_frag.item()) == e_fwd                   # same kernels, same order
+    g25 = gpu_grad(f, grad_e=2.5)
+    for n in NAMES:
+        assert np.allclose(g25[n], 2.5 * g1[n], rtol=1e-14, atol=0.0), n
+    g1b = gpu_grad(f)
+    for n in NAMES:
+        assert np.array_equal(g1b[n], g1[n]), n            # deterministic
+    del sie
+
+
+def test_small_workspace_many_rounds():
+    """A workspace cap that admits one occupied triple per round."""
+    import paper_2412_18553_amd as sie
+    f = make_fragment(5, 20, 60, (11, 4))
+    frag = sie.Fragment(*_dev(f))
+    full = sie.backward_workspace_size(frag)
+    pair = 2 * 20 ** 3 * 8                      # two float64 cubes of one triple
+    small = sie.backward_workspace_size(frag, max_bytes=full - 29 * pair)
+    assert small == full - 29 * pair
+    g_small = gpu_grad(f, max_workspace_bytes=small)
+    g_full = gpu_grad(f)
+    for n in NAMES:
+        scale = np.abs(g_full[n]).max()
+        assert np.abs(g_small[n] - g_full[n]).max() <= 1e-13 * scale, n
+
+
+def test_batched_backward_matches_single():
+    import torch
+    import paper_2412_18553_amd as sie
+    fs = [make_fragment(4, 20, 40, (11, 20)), make_fragment(3, 13, 30, (11, 21)),
+          make_fragment(5, 9, 20, (11, 22))]
+    frags = [sie.Fragment(*_dev(f)) for f in fs]
+    ge = torch.tensor([1.0, -0.5, 3.0], dtype=torch.float64, device="cuda")
+    e_frag = torch.empty(3, dtype=torch.float64, device="cuda")
+    gs = sie.backward(frags, grad_e=ge, e_frag=e_frag)
+    torch.cuda.synchronize()
+    for x, f in enumerate(fs):
+        single = gpu_grad(f, grad_e=float(ge[x].item()))
+        for n in NAMES:
+            got = gs[x][n].cpu().numpy()
+            scale = np.abs(single[n]).max()
+            assert np.abs(got - single[n]).max() <= 1e-13 * scale, (x, n)
+        assert float(e_frag[x].item()) == gpu_energy(_dev(f))
+
+
+def test_autograd_function():
+    import torch
+    import paper_2412_18553_amd as sie
+    f = make_fragment(3, 17, 30, (11, 30))
+    args = _dev(f)
+    leaves = [a.clone().requires_grad_(True) for a in args[2:]]
+    e = sie.SieTriples.apply(args[0], args[1], *leaves)
+    (3.0 * e).backward()
+    ref = gpu_grad(f, grad_e=3.0)
+    for n, leaf in zip(NAMES, leaves):
+        assert np.array_equal(leaf.grad.cpu().numpy(), ref[n]), n
+    _, _, _, oref = energy_gradient(*f.arrays())
+    for n, leaf in zip(NAMES, leaves):
+        g = leaf.grad.cpu().numpy()
+        assert np.abs(g - 3.0 * oref[n]).max() <= RTOL * 3.0 * np.abs(oref[n]).max(), n
+
+
+def test_split_backward_is_unsupported():
+    import torch
+    import paper_2412_18553_amd as sie
+    f = make_fragment(3, 9, 20, (11, 40))
+    cast = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda", torch.float32)  # noqa: E731
+    frag = sie.Fragment(f.eps_occ, f.eps_vir, *[cast(getattr(f, n)) for n in NAMES],
+                        precision="split_bf16")
+    with pytest.raises(sie.SieError, match="SIE_ERR_UNSUPPORTED"):
+        sie.backward(frag, workspace=torch.empty(1 << 20, dtype=torch.uint8, device="cuda"))
+
+
+# ------------------------------------------------------------- full size
+@pytest.fixture(scope="module")
+def o16v120():
+    f = workload_fragment("o16v120")
+    return f, _dev(f), gpu_grad(f)
+
+
+def test_o16v120_directional_differences(o16v120):
+    f, args, g = o16v120
+    rng = np.random.default_rng(16120)
+    for pos, n in enumerate(NAMES):
+        x = getattr(f, n)
+        v = symmetrize_direction(n, rng.normal(size=x.shape) * np.abs(x).mean())
+        h = 1e-2
+        plus, minus = list(args), list(args)
+        import torch
+        vd = torch.from_numpy(v).to("cuda", torch.float64)
+        plus[2 + pos] = args[2 + pos] + h * vd
+        minus[2 + pos] = args[2 + pos] - h * vd
+        fd = (gpu_energy(plus) - gpu_energy(minus)) / (2 * h)
+        an = float(np.sum(g[n] * v))
+        print(f"  {n}: analytic {an:.12e} differences {fd:.12e}", flush=True)
+        assert abs(an - fd) <= 1e-8 * abs(fd), (n, an, fd)
+
+
+def test_o16v120_euler_identities(o16v120):
+    import torch
+    f, args, g = o16v120
+    e = gpu_energy(args)
+    zero_t1 = list(args)
+    zero_t1[2] = torch.zeros_like(args[2])
+    e_ww = gpu_energy(zero_t1)
+    e_wv = e - e_ww
+    dot = {n: float(np.sum(getattr(f, n) * g[n])) for n in NAMES}
+    tol = 1e-10 * abs(e)
+    assert abs(dot["t1"] - e_wv) <= tol
+    assert abs(dot["ovov"] - e_wv) <= tol
+    assert abs(dot["t2"] - (2 * e_ww + e_wv)) <= tol
+    assert abs(dot["ovvv"] + dot["ooov"] - (2 * e_ww + e_wv)) <= tol
