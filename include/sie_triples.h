@@ -162,8 +162,10 @@ size_t sie_triples_backward_workspace_size(const sie_fragment* frags, int32_t n,
  * (w = 2 A_ijk, R' the virtual-index form of R), every contraction that builds
  * Wt is transposed against G and every V-tilde product against H.  Wt is
  * recomputed, not stored.
- *   frags    host array of n >= 1 descriptors (as for the energy); p must be
- *            SIE_FP64 (SIE_SPLIT_BF16 returns SIE_ERR_UNSUPPORTED)
+ *   frags    host array of n >= 1 descriptors (as for the energy).  With
+ *            SIE_SPLIT_BF16 Wt is rebuilt from the bf16 hi/lo products, G and
+ *            H are held in float32 and the transposed contractions run in
+ *            float64 on the float32 inputs; gradients are float64 either way
  *   grad_e   device float64 [n], the upstream derivative dL/dE_x, or NULL
  *            for all ones
  *   grads    host array [n]; each non-NULL pointer is OVERWRITTEN with
@@ -192,6 +194,20 @@ sie_status sie_triples_backward(const sie_fragment* frags, int32_t n, sie_precis
 #define SIE_PROF_CLASSES 5
 void sie_profile_enable(int on);
 sie_status sie_profile_collect(double* ms, int64_t* launches);
+
+/* Tile shapes of the float64 W-tilde build (autotuning).  The build kernel
+ * is compiled for sie_tile_variants() tile shapes; sie_tile_variant_shape
+ * writes variant v's shape into shape[4] (host): blocks per wave, 16-wide
+ * MFMA row tiles and col tiles per wave, work-groups per CU targeted.  A
+ * fragment's variant is the first table entry whose bound is >= its n_vir
+ * (variant 0 past the last).  sie_set_tile_table installs a table of n
+ * entries (host arrays: strictly ascending bounds >= 1, valid variants) for
+ * the whole process, or the built-in tuned table when n = 0.  Energies do not
+ * depend on the variant beyond rounding of the contraction order.  Not to be
+ * called while another thread runs an evaluation. */
+int32_t sie_tile_variants(void);
+sie_status sie_tile_variant_shape(int32_t variant, int32_t* shape);
+sie_status sie_set_tile_table(int32_t n, const int32_t* nv_max, const int32_t* variant);
 
 const char* sie_last_error(void);
 int sie_abi_version(void);

@@ -264,6 +264,28 @@ def triples_energy(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, *, precision="fp6
     return (e[0], tri) if return_triples else e[0]
 
 
+def tile_variants():
+    """Tile shapes of the float64 build: [(blocks/wave, row tiles, col tiles, WGs/CU)]."""
+    lib = _lib.load()
+    out = []
+    for v in range(lib.sie_tile_variants()):
+        shape = (ctypes.c_int32 * 4)()
+        _lib.check(lib.sie_tile_variant_shape(v, shape))
+        out.append(tuple(shape))
+    return out
+
+
+def set_tile_table(table=None) -> None:
+    """Install [(n_vir upper bound, variant), ...] (ascending) for the float64
+    build, or the built-in tuned table with None."""
+    lib = _lib.load()
+    table = list(table or [])
+    n = len(table)
+    nv = (ctypes.c_int32 * max(n, 1))(*[int(b) for b, _ in table])
+    var = (ctypes.c_int32 * max(n, 1))(*[int(v) for _, v in table])
+    _lib.check(lib.sie_set_tile_table(n, nv, var))
+
+
 def profile_enable(on: bool = True) -> None:
     """Time every library kernel launch on this thread with HIP events."""
     _lib.load().sie_profile_enable(1 if on else 0)

@@ -38,9 +38,10 @@ namespace sie {
 // at exactly those blocks.  Also
 // writes the unit's energy partials (as k_epilogue).  grad_e[frag] (or 1)
 // scales G and H.
+template <typename CubeT, typename InT>
 __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
                                              const Item* __restrict__ items, int n_items,
-                                             double* __restrict__ arena,
+                                             CubeT* __restrict__ arena,
                                              double* __restrict__ partials, int pstride,
                                              const double* __restrict__ grad_e) {
   const int r = find_item<false>(items, n_items, blockIdx.x);
@@ -50,16 +51,16 @@ __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
   const int slot = int(int64_t(blockIdx.x) - start);
   int i, j, k;
   decode_sorted_triple(it.unit, fd.no, i, j, k);
-  __shared__ double sw[6][kOrb * kOrb * kOrb];
-  __shared__ double sz[6][kOrb * kOrb * kOrb];
+  __shared__ double sw[6][kOrbSlot];
+  __shared__ double sz[6][kOrbSlot];
   __shared__ double red[4];
   double* out = partials + (fd.unit_base + it.unit) * pstride + slot;
   if (i == k) {
     if (threadIdx.x == 0) *out = 0.0;
     return;
   }
-  const double* __restrict__ t1 = static_cast<const double*>(fd.t1);
-  const double* __restrict__ ovov = static_cast<const double*>(fd.ovov);
+  const InT* __restrict__ t1 = static_cast<const InT*>(fd.t1);
+  const InT* __restrict__ ovov = static_cast<const InT*>(fd.ovov);
   const double* __restrict__ eps = fd.eps;
   const int no = fd.no, nv = fd.nv;
   const int nb = (nv + kOrb - 1) / kOrb;
@@ -67,15 +68,15 @@ __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
   const double* __restrict__ ev = eps + no;
   const double eijk = gptr(eps)[i] + gptr(eps)[j] + gptr(eps)[k];
   const double scale = ((i == j || j == k) ? 1.0 : 2.0) * (grad_e ? gptr(grad_e)[it.frag] : 1.0);
-  double* __restrict__ w1 = arena + it.cube_off;
-  double* __restrict__ w2 = w1 + fd.half;
+  CubeT* __restrict__ w1 = arena + it.cube_off;
+  CubeT* __restrict__ w2 = w1 + fd.half;
   const int64_t nonv = (int64_t)no * nv;
-  const double* ov_ij = ovov + (int64_t)i * nv * nonv + (int64_t)j * nv;
-  const double* ov_ik = ovov + (int64_t)i * nv * nonv + (int64_t)k * nv;
-  const double* ov_jk = ovov + (int64_t)j * nv * nonv + (int64_t)k * nv;
-  const double* t1i = t1 + (int64_t)i * nv;
-  const double* t1j = t1 + (int64_t)j * nv;
-  const double* t1k = t1 + (int64_t)k * nv;
+  const InT* ov_ij = ovov + (int64_t)i * nv * nonv + (int64_t)j * nv;
+  const InT* ov_ik = ovov + (int64_t)i * nv * nonv + (int64_t)k * nv;
+  const InT* ov_jk = ovov + (int64_t)j * nv * nonv + (int64_t)k * nv;
+  const InT* t1i = t1 + (int64_t)i * nv;
+  const InT* t1j = t1 + (int64_t)j * nv;
+  const InT* t1k = t1 + (int64_t)k * nv;
   constexpr int E = kOrb * kOrb * kOrb;
 
   double acc = 0.0;
@@ -91,14 +92,15 @@ __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
       const int c = kOrb * pick3(p2, t0, t1b, t2b) + (e & 7);
       double w = 0.0, z = 0.0;
       if (a < nv && b < nv && c < nv) {
-        w = gptr(w1)[((int64_t)a * nv + b) * nv + c] + gptr(w2)[((int64_t)b * nv + a) * nv + c];
-        const double vt = gptr(ov_ij)[(int64_t)a * nonv + b] * gptr(t1k)[c] +
-                          gptr(ov_ik)[(int64_t)a * nonv + c] * gptr(t1j)[b] +
-                          gptr(ov_jk)[(int64_t)b * nonv + c] * gptr(t1i)[a];
+        w = (double)gptr(w1)[((int64_t)a * nv + b) * nv + c] +
+            (double)gptr(w2)[((int64_t)b * nv + a) * nv + c];
+        const double vt = (double)gptr(ov_ij)[(int64_t)a * nonv + b] * (double)gptr(t1k)[c] +
+                          (double)gptr(ov_ik)[(int64_t)a * nonv + c] * (double)gptr(t1j)[b] +
+                          (double)gptr(ov_jk)[(int64_t)b * nonv + c] * (double)gptr(t1i)[a];
         z = w + vt;
       }
-      sw[s][e] = w;
-      sz[s][e] = z;
+      sw[s][orb_lds(e >> 6, (e >> 3) & 7, e & 7)] = w;
+      sz[s][orb_lds(e >> 6, (e >> 3) & 7, e & 7)] = z;
     }
     __syncthreads();
     unsigned primary = 0;
@@ -127,20 +129,21 @@ __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
       const int b = kOrb * pick3(p1, t0, t1b, t2b) + y;
       const int c = kOrb * pick3(p2, t0, t1b, t2b) + zz;
       if (a >= nv || b >= nv || c >= nv) continue;
-      const int e_cab = (zz << 6) | (x << 3) | y, s_cab = orbit_slot(p2, p0, p1);
-      const int e_bca = (y << 6) | (zz << 3) | x, s_bca = orbit_slot(p1, p2, p0);
-      const int e_cba = (zz << 6) | (y << 3) | x, s_cba = orbit_slot(p2, p1, p0);
-      const int e_acb = (x << 6) | (zz << 3) | y, s_acb = orbit_slot(p0, p2, p1);
-      const int e_bac = (y << 6) | (x << 3) | zz, s_bac = orbit_slot(p1, p0, p2);
-      const double rz = 4.0 * sz[s][e] + sz[s_cab][e_cab] + sz[s_bca][e_bca] -
+      const int e_abc = orb_lds(x, y, zz);
+      const int e_cab = orb_lds(zz, x, y), s_cab = orbit_slot(p2, p0, p1);
+      const int e_bca = orb_lds(y, zz, x), s_bca = orbit_slot(p1, p2, p0);
+      const int e_cba = orb_lds(zz, y, x), s_cba = orbit_slot(p2, p1, p0);
+      const int e_acb = orb_lds(x, zz, y), s_acb = orbit_slot(p0, p2, p1);
+      const int e_bac = orb_lds(y, x, zz), s_bac = orbit_slot(p1, p0, p2);
+      const double rz = 4.0 * sz[s][e_abc] + sz[s_cab][e_cab] + sz[s_bca][e_bca] -
                         2.0 * (sz[s_cba][e_cba] + sz[s_acb][e_acb] + sz[s_bac][e_bac]);
-      const double rw = 4.0 * sw[s][e] + sw[s_cab][e_cab] + sw[s_bca][e_bca] -
+      const double rw = 4.0 * sw[s][e_abc] + sw[s_cab][e_cab] + sw[s_bca][e_bca] -
                         2.0 * (sw[s_cba][e_cba] + sw[s_acb][e_acb] + sw[s_bac][e_bac]);
       const double d = eijk - gptr(ev)[a] - gptr(ev)[b] - gptr(ev)[c];
-      acc += sw[s][e] * rz / d;
+      acc += sw[s][e_abc] * rz / d;
       const int64_t pos = ((int64_t)a * nv + b) * nv + c;
-      gptr_w(w1)[pos] = scale * (rw + rz) / d;
-      gptr_w(w2)[pos] = scale * rw / d;
+      gptr_w(w1)[pos] = CubeT(scale * (rw + rz) / d);
+      gptr_w(w2)[pos] = CubeT(scale * rw / d);
     }
     __syncthreads();
   }
@@ -224,22 +227,24 @@ static_assert(kAPlanes == 4, "one k-pair plane per MFMA lane group");
 // Element (beta, x, k) of the A side (rows, always G) is a[beta*a_b + x*a_x + k*a_k];
 // of the B side (cols) b[beta*b_b + x*b_x + k*b_k] with b_b = 0 when the B side
 // is shared by all blocks.
+template <typename CubeT, typename InT>
 struct ATerm {
-  const double* a;
+  const CubeT* a;
   int64_t a_b, a_x, a_k;
-  const double* b;
+  const InT* b;
   int64_t b_b, b_x, b_k;
   double scale;        // applied to the B side
   int nblk;            // valid blocks (summed-block classes); per-block: the tile's
 };
 
-template <int CLS>
-__device__ __forceinline__ ATerm make_adj(int kind, int g, int i, int j, int k, int no_, int nv_,
-                                          const double* G, const double* t2, const double* ovvv,
-                                          const double* ooov, int blk0, int row0, int col0) {
+template <int CLS, typename CubeT, typename InT>
+__device__ __forceinline__ ATerm<CubeT, InT> make_adj(int kind, int g, int i, int j, int k, int no_,
+                                                      int nv_, const CubeT* G, const InT* t2,
+                                                      const InT* ovvv, const InT* ooov, int blk0,
+                                                      int row0, int col0) {
   const int64_t nv = nv_, no = no_, nv2 = nv * nv;
   const int64_t sA = nv2, sB = nv, sC = 1;
-  ATerm t;
+  ATerm<CubeT, InT> t;
   t.scale = 1.0;
   t.nblk = kABB;
   if (CLS == kAdjOvvv) {
@@ -326,13 +331,14 @@ __device__ __forceinline__ void unit_coords(int mode, int u, int& beta, int& x, 
 }
 
 // k-pair (k, k+1) of one row; entries past nK read in bounds and count zero.
-__device__ __forceinline__ double2 pair_at(const double* row, int64_t ks, int k, int nK, double s) {
-  const SIE_GLOBAL double* g = gptr(row);
+template <typename T>
+__device__ __forceinline__ double2 pair_at(const T* row, int64_t ks, int k, int nK, double s) {
+  const SIE_GLOBAL T* g = gptr(row);
   const int k0 = k < nK ? k : nK - 1;
   const int k1 = k + 1 < nK ? k + 1 : nK - 1;
   double2 v;
-  v.x = (k < nK ? s : 0.0) * g[(int64_t)k0 * ks];
-  v.y = (k + 1 < nK ? s : 0.0) * g[(int64_t)k1 * ks];
+  v.x = (k < nK ? s : 0.0) * (double)g[(int64_t)k0 * ks];
+  v.y = (k + 1 < nK ? s : 0.0) * (double)g[(int64_t)k1 * ks];
   return v;
 }
 
@@ -347,7 +353,8 @@ struct AStage {
 // Global loads of chunk c of term t.  `nrow`, `ncol`: valid rows / cols of
 // the tile; `nblk`: valid blocks (rows of blocks past it read block 0 and,
 // for summed blocks, count zero).
-__device__ __forceinline__ void adj_load(const ATerm& t, bool reduce, int c, int nK, int nrow,
+template <typename Term>
+__device__ __forceinline__ void adj_load(const Term& t, bool reduce, int c, int nK, int nrow,
                                          int ncol, int nblk, int tid, AStage& st) {
   const int k0 = c * kAKc;
   const int ma = fast_dim(t.a_b, t.a_x, t.a_k);
@@ -373,7 +380,8 @@ __device__ __forceinline__ void adj_load(const ATerm& t, bool reduce, int c, int
   }
 }
 
-__device__ __forceinline__ void adj_store(const ATerm& t, int tid, const AStage& st,
+template <typename Term>
+__device__ __forceinline__ void adj_store(const Term& t, int tid, const AStage& st,
                                           double2* buf) {
   const int ma = fast_dim(t.a_b, t.a_x, t.a_k);
 #pragma unroll
@@ -463,11 +471,11 @@ __device__ __forceinline__ int find_group(const AdjGroup* __restrict__ gs, int n
 }
 
 // Grid: the concatenated tiles of the launch's groups.  Block: kAThreads.
-template <int CLS>
+template <int CLS, typename CubeT, typename InT>
 __global__ __launch_bounds__(kAThreads, 1) void k_adj_contract(
     const FragDesc* __restrict__ descs, const Item* __restrict__ items,
     const AdjGroup* __restrict__ groups, int n_groups, const AdjRec* __restrict__ recs,
-    const double* __restrict__ arena) {
+    const CubeT* __restrict__ arena) {
   constexpr bool kReduce = CLS == kAdjT2vv || CLS == kAdjOoov;
   const int gi = find_group(groups, n_groups, blockIdx.x);
   const AdjGroup gr = groups[gi];
@@ -498,9 +506,9 @@ __global__ __launch_bounds__(kAThreads, 1) void k_adj_contract(
 #pragma unroll
   for (int q = 0; q < kABB; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
 
-  const double* t2p = static_cast<const double*>(fd.t2);
-  const double* ovvvp = static_cast<const double*>(fd.ovvv);
-  const double* ooovp = static_cast<const double*>(fd.ooov);
+  const InT* t2p = static_cast<const InT*>(fd.t2);
+  const InT* ovvvp = static_cast<const InT*>(fd.ovvv);
+  const InT* ooovp = static_cast<const InT*>(fd.ooov);
   const int nchunk = (nv + kAKc - 1) / kAKc;
 
   auto term_of = [&](int rec) {
@@ -508,12 +516,12 @@ __global__ __launch_bounds__(kAThreads, 1) void k_adj_contract(
     const Item it = items[rr.item];
     int i, j, k;
     decode_sorted_triple(it.unit, no, i, j, k);
-    return make_adj<CLS>(rr.kind, rr.g, i, j, k, no, nv, arena + it.cube_off, t2p, ovvvp,
+    return make_adj<CLS, CubeT, InT>(rr.kind, rr.g, i, j, k, no, nv, arena + it.cube_off, t2p, ovvvp,
                          ooovp, blk0, row0, col0);
   };
 
   int rec = gr.rec_begin, c = 0;
-  ATerm tcur = term_of(rec);
+  ATerm<CubeT, InT> tcur = term_of(rec);
   AStage st;
   adj_load(tcur, kReduce, 0, nv, nrow, ncol, kReduce ? tcur.nblk : nblk_tile, tid, st);
   adj_store(tcur, tid, st, lds[0]);
@@ -521,7 +529,7 @@ __global__ __launch_bounds__(kAThreads, 1) void k_adj_contract(
   int buf = 0;
   while (true) {
     int recn = rec, cn = c + 1;
-    ATerm tn = tcur;
+    ATerm<CubeT, InT> tn = tcur;
     bool more = true;
     if (cn >= nchunk) {
       if (rec + 1 >= gr.rec_end) {
@@ -580,11 +588,12 @@ __global__ __launch_bounds__(kAThreads, 1) void k_adj_contract(
 
 // dovov[p][y][q][z] += sum over the third virtual of H t1.  Block: 256
 // threads, one (y, z) element each.
+template <typename CubeT, typename InT>
 __global__ __launch_bounds__(256) void k_adj_ovov(const FragDesc* __restrict__ descs,
                                                   const Item* __restrict__ items,
                                                   const AdjGroup* __restrict__ groups,
                                                   int n_groups, const AdjRec* __restrict__ recs,
-                                                  const double* __restrict__ arena) {
+                                                  const CubeT* __restrict__ arena) {
   const int gi = find_group(groups, n_groups, blockIdx.x);
   const AdjGroup gr = groups[gi];
   const int64_t start = gi ? groups[gi - 1].wg_end : 0;
@@ -593,7 +602,7 @@ __global__ __launch_bounds__(256) void k_adj_ovov(const FragDesc* __restrict__ d
   const int64_t e = (int64_t(blockIdx.x) - start) * 256 + threadIdx.x;
   if (e >= int64_t(nv) * nv) return;
   const int y = int(e / nv), z = int(e - int64_t(y) * nv);
-  const double* t1 = static_cast<const double*>(fd.t1);
+  const InT* t1 = static_cast<const InT*>(fd.t1);
   const int64_t nv2 = int64_t(nv) * nv;
   double s = 0.0;
   for (int q = gr.rec_begin; q < gr.rec_end; ++q) {
@@ -601,19 +610,19 @@ __global__ __launch_bounds__(256) void k_adj_ovov(const FragDesc* __restrict__ d
     const Item it = items[rr.item];
     int i, j, k;
     decode_sorted_triple(it.unit, no, i, j, k);
-    const double* H = arena + it.cube_off + fd.half;
+    const CubeT* H = arena + it.cube_off + fd.half;
     if (rr.kind == 0) {          // (y, z) = (a, b): sum_c H[a][b][c] t1[k][c]
-      const SIE_GLOBAL double* h = gptr(H) + y * nv2 + int64_t(z) * nv;
-      const SIE_GLOBAL double* tv = gptr(t1) + int64_t(k) * nv;
-      for (int c = 0; c < nv; ++c) s += h[c] * tv[c];
+      const SIE_GLOBAL CubeT* h = gptr(H) + y * nv2 + int64_t(z) * nv;
+      const SIE_GLOBAL InT* tv = gptr(t1) + int64_t(k) * nv;
+      for (int c = 0; c < nv; ++c) s += (double)h[c] * (double)tv[c];
     } else if (rr.kind == 1) {   // (y, z) = (a, c): sum_b H[a][b][c] t1[j][b]
-      const SIE_GLOBAL double* h = gptr(H) + y * nv2 + z;
-      const SIE_GLOBAL double* tv = gptr(t1) + int64_t(j) * nv;
-      for (int b = 0; b < nv; ++b) s += h[int64_t(b) * nv] * tv[b];
+      const SIE_GLOBAL CubeT* h = gptr(H) + y * nv2 + z;
+      const SIE_GLOBAL InT* tv = gptr(t1) + int64_t(j) * nv;
+      for (int b = 0; b < nv; ++b) s += (double)h[int64_t(b) * nv] * (double)tv[b];
     } else {                     // (y, z) = (b, c): sum_a H[a][b][c] t1[i][a]
-      const SIE_GLOBAL double* h = gptr(H) + int64_t(y) * nv + z;
-      const SIE_GLOBAL double* tv = gptr(t1) + int64_t(i) * nv;
-      for (int a = 0; a < nv; ++a) s += h[a * nv2] * tv[a];
+      const SIE_GLOBAL CubeT* h = gptr(H) + int64_t(y) * nv + z;
+      const SIE_GLOBAL InT* tv = gptr(t1) + int64_t(i) * nv;
+      for (int a = 0; a < nv; ++a) s += (double)h[a * nv2] * (double)tv[a];
     }
   }
   SIE_GLOBAL double* p = gptr_w(fd.g_ovov) + ((int64_t(gr.a0) * nv + y) * no + gr.a1) * nv + z;
@@ -631,11 +640,12 @@ __device__ __forceinline__ double block_sum_fixed256(double v, double* red) {
 }
 
 // dt1[p][y] for y in a 64-wide tile.  Block: 256 threads.
+template <typename CubeT, typename InT>
 __global__ __launch_bounds__(256) void k_adj_t1(const FragDesc* __restrict__ descs,
                                                 const Item* __restrict__ items,
                                                 const AdjGroup* __restrict__ groups,
                                                 int n_groups, const AdjRec* __restrict__ recs,
-                                                const double* __restrict__ arena) {
+                                                const CubeT* __restrict__ arena) {
   __shared__ double red[4];
   __shared__ double part[4][64];
   const int gi = find_group(groups, n_groups, blockIdx.x);
@@ -645,7 +655,7 @@ __global__ __launch_bounds__(256) void k_adj_t1(const FragDesc* __restrict__ des
   const int no = fd.no, nv = fd.nv;
   const int y0 = int(int64_t(blockIdx.x) - start) * 64;
   const int ny = min(64, nv - y0);
-  const double* ovov = static_cast<const double*>(fd.ovov);
+  const InT* ovov = static_cast<const InT*>(fd.ovov);
   const int64_t nv2 = int64_t(nv) * nv, onv = int64_t(no) * nv;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double mine = 0.0;   // thread y0 + threadIdx.x's sum (threads < ny)
@@ -654,7 +664,7 @@ __global__ __launch_bounds__(256) void k_adj_t1(const FragDesc* __restrict__ des
     const Item it = items[rr.item];
     int i, j, k;
     decode_sorted_triple(it.unit, no, i, j, k);
-    const SIE_GLOBAL double* H = gptr(arena + it.cube_off + fd.half);
+    const SIE_GLOBAL CubeT* H = gptr(arena + it.cube_off + fd.half);
     if (rr.kind == 0) {
       // y = c: sum_{a,b} H[a][b][c] ovov[i][a][j][b]; lanes over c, waves over (a, b)
       double s = 0.0;
@@ -662,7 +672,8 @@ __global__ __launch_bounds__(256) void k_adj_t1(const FragDesc* __restrict__ des
         const int c = y0 + lane;
         for (int64_t ab = wave; ab < nv2; ab += 4) {
           const int a = int(ab / nv), b = int(ab - int64_t(a) * nv);
-          s += H[ab * nv + c] * gptr(ovov)[(int64_t(i) * nv + a) * onv + int64_t(j) * nv + b];
+          s += (double)H[ab * nv + c] *
+               (double)gptr(ovov)[(int64_t(i) * nv + a) * onv + int64_t(j) * nv + b];
         }
       }
       part[wave][lane] = s;
@@ -678,11 +689,11 @@ __global__ __launch_bounds__(256) void k_adj_t1(const FragDesc* __restrict__ des
         for (int64_t e = threadIdx.x; e < nv2; e += 256) {
           const int u = int(e / nv), c = int(e - int64_t(u) * nv);
           if (rr.kind == 1)
-            s += H[(int64_t(u) * nv + y) * nv + c] *
-                 gptr(ovov)[(int64_t(i) * nv + u) * onv + int64_t(k) * nv + c];
+            s += (double)H[(int64_t(u) * nv + y) * nv + c] *
+                 (double)gptr(ovov)[(int64_t(i) * nv + u) * onv + int64_t(k) * nv + c];
           else
-            s += H[(int64_t(y) * nv + u) * nv + c] *
-                 gptr(ovov)[(int64_t(j) * nv + u) * onv + int64_t(k) * nv + c];
+            s += (double)H[(int64_t(y) * nv + u) * nv + c] *
+                 (double)gptr(ovov)[(int64_t(j) * nv + u) * onv + int64_t(k) * nv + c];
         }
         const double tot = block_sum_fixed256(s, red);
         if (threadIdx.x == yy) mine += tot;

@@ -37,10 +37,6 @@ namespace sie {
 
 constexpr int kOrb = 8;       // virtual block edge of the epilogue orbits
 
-#ifndef SIE_BUILD_BLOCKS_PER_CU
-#define SIE_BUILD_BLOCKS_PER_CU 2   // occupancy target of the float64 build kernel
-#endif
-
 // ---------------------------------------------------------------------------
 // float64 W-tilde build.  A work-group of 4 waves computes, for one unit and
 // one register layout, the layout's six terms over 16 blocks x 32 rows x 32
@@ -58,11 +54,7 @@ constexpr int kOrb = 8;       // virtual block edge of the epilogue orbits
 // with X^{abc}_{ijk} = sum_d (ia|bd) t_kj^cd - sum_l (ia|jl) t_lk^bc, (ia|jl)
 // read as ooov[j][l][i][a] and t_ij^ab as t2[i][j][a][b] or its twin.
 // ---------------------------------------------------------------------------
-constexpr int kWBlk = 4;                 // blocks per wave
 constexpr int kWWaves = 4;               // waves per work-group
-constexpr int kWBB = kWBlk * kWWaves;    // blocks per work-group
-constexpr int kWT = 2;                   // 16-wide MFMA tiles per wave along rows and cols
-constexpr int kWEdge = 16 * kWT;         // rows (= cols) per work-group
 constexpr int kWChunk = 8;               // K chunk (a k-pair per lane group)
 
 // Element (beta, x, k) of the per-block operand is bl[beta*bl_b + x*bl_x + k*bl_k];
@@ -146,52 +138,56 @@ __device__ __forceinline__ constexpr bool wterm_a_is_bl() {
   return L2 ? (Q == 2 || Q == 5) : (Q == 0 || Q == 4);
 }
 
+// Registers of one K-chunk: the per-block operand for BLK blocks x NB tiles
+// of its MFMA side, the shared operand for NS tiles of the other side.
+template <int BLK, int NB, int NS>
 struct WChunk {
-  double bl[kWBlk][kWT][2];   // [block][tile of the per-block side][k of the pair]
-  double sh[kWT][2];          // [tile of the shared side][k of the pair]
+  double bl[BLK][NB][2];      // [block][tile][k of the pair]
+  double sh[NS][2];           // [tile][k of the pair]
 };
 
-// Lane pointers of one term: per-block rows (block 0) and shared rows for the
-// lane's two tiles, clamped into the valid range; blocks past `last` read
-// block `last`.
+// Lane pointers of one term: per-block rows (block 0) and shared rows of the
+// lane's tiles, clamped into the valid range.
+template <int NB, int NS>
 struct WLane {
-  const double* bl[kWT];
-  const double* sh[kWT];
+  const double* bl[NB];
+  const double* sh[NS];
 };
 
-template <bool A_IS_BL>
-__device__ __forceinline__ WLane wlane(const WTerm& t, int r, int nrow, int ncol) {
-  WLane p;
+template <bool A_IS_BL, int NB, int NS>
+__device__ __forceinline__ WLane<NB, NS> wlane(const WTerm& t, int r, int nrow, int ncol) {
+  WLane<NB, NS> p;
   const int nb = A_IS_BL ? nrow : ncol;   // valid extent of the per-block side
   const int ns = A_IS_BL ? ncol : nrow;
 #pragma unroll
-  for (int q = 0; q < kWT; ++q) {
-    const int xb = min(16 * q + r, nb - 1), xs = min(16 * q + r, ns - 1);
-    p.bl[q] = t.bl + xb * t.bl_x;
-    p.sh[q] = t.sh + xs * t.sh_x;
-  }
+  for (int q = 0; q < NB; ++q) p.bl[q] = t.bl + min(16 * q + r, nb - 1) * t.bl_x;
+#pragma unroll
+  for (int q = 0; q < NS; ++q) p.sh[q] = t.sh + min(16 * q + r, ns - 1) * t.sh_x;
   return p;
 }
 
-template <bool VEC>
-__device__ __forceinline__ void load_wchunk(const WTerm& t, const WLane& p, int c, int last, int g,
-                                            WChunk& x) {
+// Chunk c of a term; blocks past `last` read block `last`.
+template <bool VEC, int BLK, int NB, int NS>
+__device__ __forceinline__ void load_wchunk(const WTerm& t, const WLane<NB, NS>& p, int c,
+                                            int last, int g, WChunk<BLK, NB, NS>& x) {
   const int k0 = kWChunk * c + 2 * g;
   if (VEC && kWChunk * c + kWChunk <= t.nK) {
     // K contiguous, 16-byte aligned rows of even length
 #pragma unroll
-    for (int q = 0; q < kWT; ++q) {
+    for (int q = 0; q < NS; ++q) {
       const d2v s0 = *(const SIE_GLOBAL d2v*)(gptr(p.sh[q]) + k0);
       x.sh[q][0] = s0.x;
       x.sh[q][1] = s0.y;
+    }
 #pragma unroll
-      for (int beta = 0; beta < kWBlk; ++beta) {
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int beta = 0; beta < BLK; ++beta) {
         const d2v u = *(const SIE_GLOBAL d2v*)(gptr(p.bl[q]) +
                                                  (int64_t)(beta < last ? beta : last) * t.bl_b + k0);
         x.bl[beta][q][0] = u.x;
         x.bl[beta][q][1] = u.y;
       }
-    }
   } else {
     int kc[2];
     double m[2];
@@ -202,34 +198,35 @@ __device__ __forceinline__ void load_wchunk(const WTerm& t, const WLane& p, int 
       m[s] = k < t.nK ? t.scale : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < kWT; ++q) {
+    for (int q = 0; q < NS; ++q)
 #pragma unroll
       for (int s = 0; s < 2; ++s) x.sh[q][s] = m[s] * gptr(p.sh[q])[(int64_t)kc[s] * t.sh_k];
 #pragma unroll
-      for (int beta = 0; beta < kWBlk; ++beta) {
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int beta = 0; beta < BLK; ++beta) {
         const SIE_GLOBAL double* b = gptr(p.bl[q]) + (int64_t)(beta < last ? beta : last) * t.bl_b;
 #pragma unroll
         for (int s = 0; s < 2; ++s) x.bl[beta][q][s] = b[(int64_t)kc[s] * t.bl_k];
       }
-    }
   }
 }
 
-// acc[beta][rt][ct]: rows 16 rt .., cols 16 ct .. of block beta.  Sub-tiles
-// that lie wholly outside the virtual range (rt_ok / ct_ok false, uniform)
-// are skipped.
-template <bool A_IS_BL>
-__device__ __forceinline__ void mma_wchunk(const WChunk& x, bool r1_ok, bool c1_ok,
-                                           d4 (&acc)[kWBlk][kWT][kWT]) {
+// acc[beta][rt][ct]: rows 16 rt .., cols 16 ct .. of block beta.  Row / col
+// tiles wholly outside the virtual range (uniform) are skipped.
+template <bool A_IS_BL, int BLK, int TR, int TC>
+__device__ __forceinline__ void mma_wchunk(
+    const WChunk<BLK, (A_IS_BL ? TR : TC), (A_IS_BL ? TC : TR)>& x, int nrow, int ncol,
+    d4 (&acc)[BLK][TR][TC]) {
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
-    for (int rt = 0; rt < kWT; ++rt)
+    for (int rt = 0; rt < TR; ++rt)
 #pragma unroll
-      for (int ct = 0; ct < kWT; ++ct) {
-        if ((rt == 1 && !r1_ok) || (ct == 1 && !c1_ok)) continue;
+      for (int ct = 0; ct < TC; ++ct) {
+        if ((rt > 0 && 16 * rt >= nrow) || (ct > 0 && 16 * ct >= ncol)) continue;
 #pragma unroll
-        for (int beta = 0; beta < kWBlk; ++beta)
+        for (int beta = 0; beta < BLK; ++beta)
           acc[beta][rt][ct] = A_IS_BL
               ? mfma16x16x4(x.bl[beta][rt][s], x.sh[ct][s], acc[beta][rt][ct])
               : mfma16x16x4(x.sh[rt][s], x.bl[beta][ct][s], acc[beta][rt][ct]);
@@ -238,41 +235,45 @@ __device__ __forceinline__ void mma_wchunk(const WChunk& x, bool r1_ok, bool c1_
 
 // One term: two chunks in flight (loads of chunk c + 1 issued before the
 // MFMAs of chunk c); loads past the end are clamped, masked and unused.
-template <bool L2, int Q, bool VEC>
+template <bool L2, int Q, bool VEC, int BLK, int TR, int TC>
 __device__ __forceinline__ void run_wterm(const double* t2, const double* ovvv,
                                           const double* ooov, int i, int j, int k, int no, int nv,
                                           int blk0, int row0, int col0, int nrow, int ncol,
-                                          int last, int r, int g, d4 (&acc)[kWBlk][kWT][kWT]) {
+                                          int last, int r, int g, d4 (&acc)[BLK][TR][TC]) {
   constexpr bool A = wterm_a_is_bl<L2, Q>();
   constexpr bool V = VEC && Q < 3;
+  constexpr int NB = A ? TR : TC, NS = A ? TC : TR;
   const WTerm t = make_wterm<L2, Q>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0);
-  const WLane p = wlane<A>(t, r, nrow, ncol);
-  const bool r1_ok = nrow > 16, c1_ok = ncol > 16;
+  const WLane<NB, NS> p = wlane<A, NB, NS>(t, r, nrow, ncol);
   const int nch = (t.nK + kWChunk - 1) / kWChunk;
-  WChunk b0, b1;
+  WChunk<BLK, NB, NS> b0, b1;
   load_wchunk<V>(t, p, 0, last, g, b0);
   for (int c = 0;; c += 2) {
     load_wchunk<V>(t, p, c + 1, last, g, b1);
-    mma_wchunk<A>(b0, r1_ok, c1_ok, acc);
+    mma_wchunk<A, BLK, TR, TC>(b0, nrow, ncol, acc);
     if (c + 1 >= nch) break;
     load_wchunk<V>(t, p, c + 2, last, g, b0);
-    mma_wchunk<A>(b1, r1_ok, c1_ok, acc);
+    mma_wchunk<A, BLK, TR, TC>(b1, nrow, ncol, acc);
     if (c + 2 >= nch) break;
   }
 }
 
-template <bool L2, bool VEC>
+template <bool L2, bool VEC, int BLK, int TR, int TC>
 __device__ __forceinline__ void build_wtile(const double* t2, const double* ovvv,
                                             const double* ooov, int i, int j, int k, int no,
                                             int nv, int blk0, int row0, int col0, int nrow,
                                             int ncol, int last, int r, int g,
-                                            d4 (&acc)[kWBlk][kWT][kWT]) {
-  run_wterm<L2, 0, VEC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
-  run_wterm<L2, 1, VEC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
-  run_wterm<L2, 2, VEC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
-  run_wterm<L2, 3, VEC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
-  run_wterm<L2, 4, VEC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
-  run_wterm<L2, 5, VEC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
+                                            d4 (&acc)[BLK][TR][TC]) {
+#define SIE_WTERM(Q) \
+  run_wterm<L2, Q, VEC, BLK, TR, TC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, nrow, \
+                                     ncol, last, r, g, acc)
+  SIE_WTERM(0);
+  SIE_WTERM(1);
+  SIE_WTERM(2);
+  SIE_WTERM(3);
+  SIE_WTERM(4);
+  SIE_WTERM(5);
+#undef SIE_WTERM
 }
 
 // Map a linear block index to a tile so that the blocks the hardware places
@@ -285,21 +286,43 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
   return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
-// Build work-groups of one unit for a fragment of n_v virtuals: two layouts
-// x 16-block x 32-row x 32-col tiles.
-__host__ __device__ __forceinline__ int64_t wbuild_tiles(int nv) {
-  const int64_t nb = (nv + kWBB - 1) / kWBB, ne = (nv + kWEdge - 1) / kWEdge;
-  return 2 * nb * ne * ne;
+// Tile shapes of the float64 build: BLK blocks per wave (4 waves per
+// work-group), TR x TC 16-wide MFMA tiles per wave along rows x cols, and
+// the occupancy target BPC (work-groups per CU).  Variant 0 is the default;
+// a tile table (sie_set_tile_table) picks one per fragment by n_v.
+struct WShape {
+  int blk, tr, tc, bpc;
+};
+constexpr int kWVariants = 4;
+__host__ __device__ inline WShape wshape(int v) {
+  switch (v) {
+    case 1: return WShape{4, 2, 2, 1};
+    case 2: return WShape{2, 2, 2, 2};
+    case 3: return WShape{8, 1, 1, 2};
+    default: return WShape{4, 2, 2, 2};
+  }
 }
 
-// Partial cube of one layout over one 16 x 32 x 32 tile of one unit, written
-// to the unit's first (L1) or second (L2) cube in (block, row, col) order.
-// Grid: the concatenated build work-groups of the round's items.  Block: 256
-// threads.  VEC (FragDesc::vec): n_v is even and the t2 / ovvv bases are
-// 16-byte aligned, so d-rows are read 16 bytes at a time.
-__global__ __launch_bounds__(256, SIE_BUILD_BLOCKS_PER_CU) void k_build_w_f64(
-    const FragDesc* __restrict__ descs, const Item* __restrict__ items, int n_items,
-    double* __restrict__ arena) {
+// Build work-groups of one unit for a fragment of n_v virtuals: two layouts
+// x (4 BLK)-block x (16 TR)-row x (16 TC)-col tiles.
+__host__ __device__ inline int64_t wbuild_tiles(int nv, int variant) {
+  const WShape w = wshape(variant);
+  const int64_t bb = int64_t(kWWaves) * w.blk;
+  return 2 * ((nv + bb - 1) / bb) * ((nv + 16 * w.tr - 1) / (16 * w.tr)) *
+         ((nv + 16 * w.tc - 1) / (16 * w.tc));
+}
+
+// Partial cube of one layout over one tile of one unit, written to the
+// unit's first (L1) or second (L2) cube in (block, row, col) order.  Grid:
+// the concatenated build work-groups of the round's items (all of one tile
+// variant).  Block: 256 threads.  VEC (FragDesc::vec): n_v is even and the
+// t2 / ovvv bases are 16-byte aligned, so d-rows are read 16 bytes at a time.
+template <int BLK, int TR, int TC, int BPC>
+__global__ __launch_bounds__(256, BPC) void k_build_w_f64(const FragDesc* __restrict__ descs,
+                                                          const Item* __restrict__ items,
+                                                          int n_items,
+                                                          double* __restrict__ arena) {
+  constexpr int BB = kWWaves * BLK, ER = 16 * TR, EC = 16 * TC;
   const int ri = find_item<true>(items, n_items, blockIdx.x);
   const int64_t start = ri ? items[ri - 1].blk_end : 0;
   const Item it = items[ri];
@@ -308,51 +331,55 @@ __global__ __launch_bounds__(256, SIE_BUILD_BLOCKS_PER_CU) void k_build_w_f64(
   decode_sorted_triple(it.unit, fd.no, i, j, k);
   if (i == k) return;
   const int nv = fd.nv;
-  const int nbt = (nv + kWBB - 1) / kWBB, net = (nv + kWEdge - 1) / kWEdge;
-  const int per = nbt * net * net;
+  const int nbt = (nv + BB - 1) / BB, nrt = (nv + ER - 1) / ER, nct = (nv + EC - 1) / EC;
+  const int per = nbt * nrt * nct;
   int t = xcd_tile(int(int64_t(blockIdx.x) - start), 2 * per);
   const bool l2 = t >= per;
   if (l2) t -= per;
-  const int tb = t / (net * net);
-  t -= tb * net * net;
-  const int tr = t / net, tc = t - tr * net;
+  const int tb = t / (nrt * nct);
+  t -= tb * nrt * nct;
+  const int tr = t / nct, tc = t - tr * nct;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, g = lane >> 4;
-  const int blk0 = tb * kWBB + wave * kWBlk;
-  const int row0 = tr * kWEdge, col0 = tc * kWEdge;
+  const int blk0 = tb * BB + wave * BLK;
+  const int row0 = tr * ER, col0 = tc * EC;
   if (blk0 >= nv) return;                       // no barrier follows: waves may leave
-  const int nrow = min(kWEdge, nv - row0), ncol = min(kWEdge, nv - col0);
-  const int last = min(kWBlk, nv - blk0) - 1;
+  const int nrow = min(ER, nv - row0), ncol = min(EC, nv - col0);
+  const int last = min(BLK, nv - blk0) - 1;
   const double* t2 = static_cast<const double*>(fd.t2);
   const double* ovvv = static_cast<const double*>(fd.ovvv);
   const double* ooov = static_cast<const double*>(fd.ooov);
 
-  d4 acc[kWBlk][kWT][kWT];
+  d4 acc[BLK][TR][TC];
 #pragma unroll
-  for (int b = 0; b < kWBlk; ++b)
+  for (int b = 0; b < BLK; ++b)
 #pragma unroll
-    for (int p = 0; p < kWT; ++p)
+    for (int p = 0; p < TR; ++p)
 #pragma unroll
-      for (int q = 0; q < kWT; ++q) acc[b][p][q] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int q = 0; q < TC; ++q) acc[b][p][q] = d4{0.0, 0.0, 0.0, 0.0};
 
+#define SIE_WTILE(L, V) \
+  build_wtile<L, V, BLK, TR, TC>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, row0, col0, nrow, \
+                                 ncol, last, r, g, acc)
   if (l2) {
-    if (fd.vec) build_wtile<true, true>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
-    else build_wtile<true, false>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
+    if (fd.vec) SIE_WTILE(true, true);
+    else SIE_WTILE(true, false);
   } else {
-    if (fd.vec) build_wtile<false, true>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
-    else build_wtile<false, false>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, row0, col0, nrow, ncol, last, r, g, acc);
+    if (fd.vec) SIE_WTILE(false, true);
+    else SIE_WTILE(false, false);
   }
+#undef SIE_WTILE
 
   // element v of lane (g, r) in acc[beta][rt][ct] holds
   // P[blk0 + beta][row0 + 16 rt + 4 v + g][col0 + 16 ct + r]
   double* __restrict__ out = arena + it.cube_off + (l2 ? fd.half : 0);
 #pragma unroll
-  for (int beta = 0; beta < kWBlk; ++beta) {
+  for (int beta = 0; beta < BLK; ++beta) {
     const int blk = blk0 + beta;
 #pragma unroll
-    for (int rt = 0; rt < kWT; ++rt)
+    for (int rt = 0; rt < TR; ++rt)
 #pragma unroll
-      for (int ct = 0; ct < kWT; ++ct) {
+      for (int ct = 0; ct < TC; ++ct) {
         const int col = col0 + 16 * ct + r;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -376,10 +403,6 @@ constexpr int kCols = 32;                       // MFMA cols per work-group (B s
 constexpr int kThreads = 64 * (kRows / 16) * (kCols / 16);
 constexpr int kLdsRows = kBB * kRows + kRows;   // per-block region + shared region
 constexpr int kShBase = kBB * kRows;            // first LDS row of the shared operand
-
-#ifndef SIE_BUILD_BLOCKS_PER_CU
-#define SIE_BUILD_BLOCKS_PER_CU 2   // occupancy target of the build kernel
-#endif
 
 // Lane's row/col clamps for one tile: blocks, rows and cols inside [0, n_v).
 struct TileDims {
@@ -420,6 +443,16 @@ __device__ __forceinline__ BlockWork block_work(const FragDesc& fd, const Item* 
   w.row0 = tr * kRows;
   w.col0 = tcol * kCols;
   return w;
+}
+
+// LDS position of in-block offset (x, y, z) of an 8^3 orbit block, padded so
+// that the six permuted reads of a wave (x fixed, y and z over the lanes)
+// spread over the 16 double-wide banks (at most 5 lanes per bank instead of
+// up to 32 without padding).
+constexpr int kOrbPlane = 72, kOrbRow = 9;
+constexpr int kOrbSlot = kOrb * kOrbPlane;
+__device__ __forceinline__ int orb_lds(int x, int y, int z) {
+  return x * kOrbPlane + y * kOrbRow + z;
 }
 
 // Orbit slots enumerate the position permutations (0,1,2) (0,2,1) (1,0,2)
@@ -468,8 +501,7 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
   const int slot = int(int64_t(blockIdx.x) - start);
   int i, j, k;
   decode_sorted_triple(it.unit, fd.no, i, j, k);
-  __shared__ double sw[6][kOrb * kOrb * kOrb];
-  __shared__ double sz[6][kOrb * kOrb * kOrb];
+  __shared__ double sz[6][kOrbSlot];
   __shared__ double red[4];
   double* out = partials + (fd.unit_base + it.unit) * pstride + slot;
   if (i == k) {
@@ -496,12 +528,16 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
   const InT* t1k = t1 + (int64_t)k * nv;
 
   constexpr int E = kOrb * kOrb * kOrb;
+  constexpr int kPer = 6 * E / 256;       // elements of an orbit per thread
 
   double acc = 0.0;
   for (int64_t o = slot; o < n_orb; o += fd.n_part) {
     int t0, t1b, t2b;
     decode_sorted_triple(o, nb, t0, t1b, t2b);
-    for (int idx = threadIdx.x; idx < 6 * E; idx += 256) {
+    double wreg[kPer];   // Wt of this thread's elements (the same ones in both passes)
+#pragma unroll 2
+    for (int m = 0; m < kPer; ++m) {
+      const int idx = threadIdx.x + 256 * m;
       const int s = idx / E, e = idx - s * E;
       int p0, p1, p2;
       slot_perm(s, p0, p1, p2);
@@ -517,8 +553,8 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
                           (double)gptr(ov_jk)[(int64_t)b * nonv + c] * (double)gptr(t1i)[a];
         z = w + vt;
       }
-      sw[s][e] = w;
-      sz[s][e] = z;
+      wreg[m] = w;
+      sz[s][orb_lds(e >> 6, (e >> 3) & 7, e & 7)] = z;
     }
     __syncthreads();
     // a slot whose block triple repeats an earlier slot's is not summed twice
@@ -538,7 +574,9 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
       }
       if (!dup) primary |= 1u << s;
     }
-    for (int idx = threadIdx.x; idx < 6 * E; idx += 256) {
+#pragma unroll 2
+    for (int m = 0; m < kPer; ++m) {
+      const int idx = threadIdx.x + 256 * m;
       const int s = idx / E, e = idx - s * E;
       if (!((primary >> s) & 1u)) continue;
       int p0, p1, p2;
@@ -550,15 +588,15 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
       if (a >= nv || b >= nv || c >= nv) continue;
       // Z at the five permuted virtual triples, found in the slot holding
       // the permuted block triple at the permuted in-block offsets
-      const double zabc = sz[s][e];
-      const double zcab = sz[orbit_slot(p2, p0, p1)][(zz << 6) | (x << 3) | y];
-      const double zbca = sz[orbit_slot(p1, p2, p0)][(y << 6) | (zz << 3) | x];
-      const double zcba = sz[orbit_slot(p2, p1, p0)][(zz << 6) | (y << 3) | x];
-      const double zacb = sz[orbit_slot(p0, p2, p1)][(x << 6) | (zz << 3) | y];
-      const double zbac = sz[orbit_slot(p1, p0, p2)][(y << 6) | (x << 3) | zz];
+      const double zabc = sz[s][orb_lds(x, y, zz)];
+      const double zcab = sz[orbit_slot(p2, p0, p1)][orb_lds(zz, x, y)];
+      const double zbca = sz[orbit_slot(p1, p2, p0)][orb_lds(y, zz, x)];
+      const double zcba = sz[orbit_slot(p2, p1, p0)][orb_lds(zz, y, x)];
+      const double zacb = sz[orbit_slot(p0, p2, p1)][orb_lds(x, zz, y)];
+      const double zbac = sz[orbit_slot(p1, p0, p2)][orb_lds(y, x, zz)];
       const double rz = 4.0 * zabc + zcab + zbca - 2.0 * (zcba + zacb + zbac);
       const double d = eijk - gptr(ev)[a] - gptr(ev)[b] - gptr(ev)[c];
-      acc += sw[s][e] * rz / d;
+      acc += wreg[m] * rz / d;
     }
     __syncthreads();
   }

@@ -9,6 +9,8 @@
 #include <cstdlib>
 #include <algorithm>
 #include <array>
+#include <iterator>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -184,6 +186,25 @@ sie_status hip_check(hipError_t e, const char* what) {
   return fail(SIE_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// ---- float64 build tile table: (n_v upper bound, variant), ascending ----
+// The built-in table comes from the autotuner (tile_table.inc); callers may
+// install another with sie_set_tile_table.
+struct TileEntry {
+  int32_t nv_max, variant;
+};
+const TileEntry kBuiltinTiles[] = {
+#include "tile_table.inc"
+};
+std::mutex g_tiles_mu;
+std::vector<TileEntry> g_tiles(std::begin(kBuiltinTiles), std::end(kBuiltinTiles));
+
+int tile_variant(int nv) {
+  std::lock_guard<std::mutex> lock(g_tiles_mu);
+  for (const TileEntry& e : g_tiles)
+    if (nv <= e.nv_max) return e.variant;
+  return 0;
+}
+
 // ---- optional kernel timing ----
 struct ProfRec {
   hipEvent_t start, stop;
@@ -250,6 +271,36 @@ sie_status sie_profile_collect(double* ms, int64_t* launches) {
   return st;
 }
 
+int32_t sie_tile_variants(void) { return sie::kWVariants; }
+
+sie_status sie_tile_variant_shape(int32_t variant, int32_t* shape) {
+  if (variant < 0 || variant >= sie::kWVariants || !shape)
+    return fail(SIE_ERR_INVALID_ARG, "sie_tile_variant_shape: bad variant or NULL output");
+  const sie::WShape w = sie::wshape(variant);
+  shape[0] = w.blk;
+  shape[1] = w.tr;
+  shape[2] = w.tc;
+  shape[3] = w.bpc;
+  return SIE_OK;
+}
+
+sie_status sie_set_tile_table(int32_t n, const int32_t* nv_max, const int32_t* variant) {
+  std::vector<TileEntry> t;
+  if (n < 0 || (n > 0 && (!nv_max || !variant)))
+    return fail(SIE_ERR_INVALID_ARG, "sie_set_tile_table: bad count or NULL arrays");
+  for (int32_t q = 0; q < n; ++q) {
+    if (variant[q] < 0 || variant[q] >= sie::kWVariants)
+      return fail(SIE_ERR_INVALID_ARG, "sie_set_tile_table: unknown variant");
+    if (nv_max[q] < 1 || (q > 0 && nv_max[q] <= nv_max[q - 1]))
+      return fail(SIE_ERR_INVALID_ARG, "sie_set_tile_table: bounds must be positive and ascending");
+    t.push_back(TileEntry{nv_max[q], variant[q]});
+  }
+  if (n == 0) t.assign(std::begin(kBuiltinTiles), std::end(kBuiltinTiles));
+  std::lock_guard<std::mutex> lock(g_tiles_mu);
+  g_tiles.swap(t);
+  return SIE_OK;
+}
+
 const char* sie_last_error(void) { return g_err.c_str(); }
 
 int64_t sie_occupied_triples(int32_t n_occ) {
@@ -308,6 +359,11 @@ struct Tables {
   std::vector<double> eps;
   std::vector<sie::Item> items;
   std::vector<size_t> round_begin;   // item index of each round's start, then the end
+  struct Segment {
+    size_t round, r0, r1;            // items [r0, r1) of the round share a tile variant
+    int variant;
+  };
+  std::vector<Segment> segments;     // in round order
 };
 
 void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
@@ -337,7 +393,8 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
     d.unit_base = unit_base;
     d.half = int64_t(fp.half_bytes / (pl.split ? sizeof(float) : sizeof(double)));
     // split: tiles per layout (two layouts); float64: work-groups per unit
-    d.tiles = pl.split ? sie::build_tiles(fp.nv) : sie::wbuild_tiles(fp.nv);
+    d.variant = pl.split ? 0 : tile_variant(fp.nv);
+    d.tiles = pl.split ? sie::build_tiles(fp.nv) : sie::wbuild_tiles(fp.nv, d.variant);
     d.vS = d.tS = d.tT = d.oT = nullptr;
     d.g_t1 = grads ? grads[x].t1 : nullptr;
     d.g_t2 = grads ? grads[x].t2 : nullptr;
@@ -403,7 +460,91 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
     }
     round_begin.push_back(order.size());
   }
+  // float64: the build launches once per tile variant of a round, so group
+  // each round's items by variant (stable) and restart the block prefix sums
+  // at each variant's segment; the epilogue prefix sums run over the round.
+  T.segments.clear();
+  for (size_t q = 0; q + 1 < round_begin.size(); ++q) {
+    const size_t r0 = round_begin[q], r1 = round_begin[q + 1];
+    if (!pl.split)
+      std::stable_sort(items.begin() + r0, items.begin() + r1,
+                       [&](const sie::Item& a, const sie::Item& b) {
+                         return desc[size_t(a.frag)].variant < desc[size_t(b.frag)].variant;
+                       });
+    int64_t blk = 0, part = 0;
+    size_t seg0 = r0;
+    for (size_t r = r0; r < r1; ++r) {
+      sie::Item& it = items[r];
+      const int var = desc[size_t(it.frag)].variant;
+      if (r > r0 && var != desc[size_t(items[r - 1].frag)].variant) {
+        T.segments.push_back({q, seg0, r, desc[size_t(items[r - 1].frag)].variant});
+        seg0 = r;
+        blk = 0;
+      }
+      blk += (pl.split ? 2 : 1) * desc[size_t(it.frag)].tiles;
+      part += pl.frags[size_t(it.frag)].n_part;
+      it.blk_end = blk;
+      it.part_end = part;
+    }
+    if (r1 > r0) T.segments.push_back({q, seg0, r1, desc[size_t(items[r1 - 1].frag)].variant});
+  }
+}
 
+void launch_build_f64(int variant, unsigned grid, hipStream_t s, const sie::FragDesc* desc,
+                      const sie::Item* items, int n_items, double* arena) {
+  switch (variant) {
+    case 1:
+      hipLaunchKernelGGL((sie::k_build_w_f64<4, 2, 2, 1>), dim3(grid), dim3(256), 0, s, desc,
+                         items, n_items, arena);
+      break;
+    case 2:
+      hipLaunchKernelGGL((sie::k_build_w_f64<2, 2, 2, 2>), dim3(grid), dim3(256), 0, s, desc,
+                         items, n_items, arena);
+      break;
+    case 3:
+      hipLaunchKernelGGL((sie::k_build_w_f64<8, 1, 1, 2>), dim3(grid), dim3(256), 0, s, desc,
+                         items, n_items, arena);
+      break;
+    default:
+      hipLaunchKernelGGL((sie::k_build_w_f64<4, 2, 2, 2>), dim3(grid), dim3(256), 0, s, desc,
+                         items, n_items, arena);
+      break;
+  }
+}
+
+// float64 build launches of round q (one per tile variant present).
+void build_round_f64(const Tables& T, size_t q, hipStream_t s, const sie::FragDesc* desc,
+                     const sie::Item* d_items, double* arena) {
+  for (const auto& sg : T.segments) {
+    if (sg.round != q) continue;
+    launch_build_f64(sg.variant, unsigned(T.items[sg.r1 - 1].blk_end), s, desc,
+                     d_items + sg.r0, int(sg.r1 - sg.r0), arena);
+  }
+}
+
+// bf16 hi/lo copies of every fragment's float32 inputs (see k_bf16.hpp).
+sie_status stage_split(const std::vector<sie::FragDesc>& desc, hipStream_t s) {
+  ProfScope ps(s, 3);
+  auto split = [&](const void* src, int P, int X, int Y, int64_t sp, int64_t sx, int64_t sy,
+                   int64_t sk, int K, int Kpad, bool kfast, const sie::u4v* dst) {
+    const int64_t total = int64_t(P) * X * Y * (Kpad / 8);
+    const int64_t nb = (total + 255) / 256;
+    const unsigned grid = unsigned(nb < 65536 ? nb : 65536);
+    hipLaunchKernelGGL(sie::k_split_bf16, dim3(grid), dim3(256), 0, s,
+                       static_cast<const float*>(src), P, X, Y, sp, sx, sy, sk, K, Kpad, kfast,
+                       const_cast<sie::u4v*>(dst));
+  };
+  for (const sie::FragDesc& d : desc) {
+    const int no = d.no, nv = d.nv;
+    const int64_t o = no, v = nv;
+    // vS[i][a][b][d] <- ovvv, tS[i][j][a][d] <- t2 (K = d contiguous)
+    split(d.ovvv, no, nv, nv, v * v * v, v * v, v, 1, nv, d.Kv, true, d.vS);
+    split(d.t2, no, no, nv, o * v * v, v * v, v, 1, nv, d.Kv, true, d.tS);
+    // tT[p][x][y][l] = t2[p][l][x][y], oT[x][y][v][l] = ooov[x][l][y][v] (K = l)
+    split(d.t2, no, nv, nv, o * v * v, v, 1, v * v, no, d.Ko, false, d.tT);
+    split(d.ooov, no, no, nv, o * o * v, v, 1, o * v, no, d.Ko, false, d.oT);
+  }
+  return hip_check(hipGetLastError(), "launch split staging");
 }
 
 // One evaluation over n fragments (see work.hpp).
@@ -458,28 +599,7 @@ sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag
 
   // ---- split staging (split precision) ----
   if (pl.split) {
-    ProfScope ps(s, 3);
-    auto split = [&](const void* src, int P, int X, int Y, int64_t sp, int64_t sx, int64_t sy,
-                     int64_t sk, int K, int Kpad, bool kfast, const sie::u4v* dst) {
-      const int64_t total = int64_t(P) * X * Y * (Kpad / 8);
-      const int64_t nb = (total + 255) / 256;
-      const unsigned grid = unsigned(nb < 65536 ? nb : 65536);
-      hipLaunchKernelGGL(sie::k_split_bf16, dim3(grid), dim3(256), 0, s,
-                         static_cast<const float*>(src), P, X, Y, sp, sx, sy, sk, K, Kpad, kfast,
-                         const_cast<sie::u4v*>(dst));
-    };
-    for (int x = 0; x < n; ++x) {
-      const sie::FragDesc& d = desc[size_t(x)];
-      const int no = d.no, nv = d.nv;
-      const int64_t o = no, v = nv;
-      // vS[i][a][b][d] <- ovvv, tS[i][j][a][d] <- t2 (K = d contiguous)
-      split(d.ovvv, no, nv, nv, v * v * v, v * v, v, 1, nv, d.Kv, true, d.vS);
-      split(d.t2, no, no, nv, o * v * v, v * v, v, 1, nv, d.Kv, true, d.tS);
-      // tT[p][x][y][l] = t2[p][l][x][y], oT[x][y][v][l] = ooov[x][l][y][v] (K = l)
-      split(d.t2, no, nv, nv, o * v * v, v, 1, v * v, no, d.Ko, false, d.tT);
-      split(d.ooov, no, no, nv, o * o * v, v, 1, o * v, no, d.Ko, false, d.oT);
-    }
-    st = hip_check(hipGetLastError(), "launch split staging");
+    st = stage_split(desc, s);
     if (st != SIE_OK) return st;
   }
 
@@ -495,8 +615,7 @@ sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag
       double* arena = reinterpret_cast<double*>(dev(pl.off_arena));
       {
         ProfScope ps(s, 0);
-        hipLaunchKernelGGL(sie::k_build_w_f64, dim3(n_blk), dim3(256), 0, s, d_desc,
-                           ri, cnt, arena);
+        build_round_f64(T, q, s, d_desc, d_items, arena);
       }
       {
         ProfScope ps(s, 1);
@@ -610,6 +729,40 @@ void adj_round_lists(const Tables& T, size_t r0, size_t r1, std::vector<sie::Adj
   }
 }
 
+// G / H and the gradient contractions of one backward round.
+template <typename CubeT, typename InT>
+void backward_round(const std::array<AdjLaunch, sie::kAdjClasses>& L, hipStream_t s,
+                    const sie::FragDesc* d_desc, const sie::Item* ri, int cnt,
+                    const sie::AdjGroup* d_groups, const sie::AdjRec* d_recs, CubeT* arena,
+                    double* d_part, int pstride, const double* grad_e, unsigned n_epi) {
+  {
+    ProfScope ps(s, 1);
+    hipLaunchKernelGGL((sie::k_hat<CubeT, InT>), dim3(n_epi), dim3(256), 0, s, d_desc, ri, cnt,
+                       arena, d_part, pstride, grad_e);
+  }
+  ProfScope ps(s, 4);
+  auto contract = [&](auto kernel, const AdjLaunch& l) {
+    if (l.n_wg)
+      hipLaunchKernelGGL(kernel, dim3(unsigned(l.n_wg)), dim3(sie::kAThreads), 0, s, d_desc, ri,
+                         d_groups + l.group_off, l.n_groups, d_recs,
+                         static_cast<const CubeT*>(arena));
+  };
+  contract(sie::k_adj_contract<sie::kAdjOvvv, CubeT, InT>, L[sie::kAdjOvvv]);
+  contract(sie::k_adj_contract<sie::kAdjT2vv, CubeT, InT>, L[sie::kAdjT2vv]);
+  contract(sie::k_adj_contract<sie::kAdjT2oo, CubeT, InT>, L[sie::kAdjT2oo]);
+  contract(sie::k_adj_contract<sie::kAdjOoov, CubeT, InT>, L[sie::kAdjOoov]);
+  const AdjLaunch& lp = L[sie::kAdjOvov];
+  if (lp.n_wg)
+    hipLaunchKernelGGL((sie::k_adj_ovov<CubeT, InT>), dim3(unsigned(lp.n_wg)), dim3(256), 0, s,
+                       d_desc, ri, d_groups + lp.group_off, lp.n_groups, d_recs,
+                       static_cast<const CubeT*>(arena));
+  const AdjLaunch& l1 = L[sie::kAdjT1];
+  if (l1.n_wg)
+    hipLaunchKernelGGL((sie::k_adj_t1<CubeT, InT>), dim3(unsigned(l1.n_wg)), dim3(256), 0, s,
+                       d_desc, ri, d_groups + l1.group_off, l1.n_groups, d_recs,
+                       static_cast<const CubeT*>(arena));
+}
+
 sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const double* grad_e,
                         const sie_fragment_grad* grads, double* e_frag_out, void* ws,
                         size_t ws_bytes, void* stream) {
@@ -625,8 +778,6 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
       if (q && !aligned(q, sizeof(double)))
         return fail(SIE_ERR_INVALID_ARG, w + ": a gradient array is misaligned");
   }
-  if (p != SIE_FP64)
-    return fail(SIE_ERR_UNSUPPORTED, w + ": only SIE_FP64 has a backward pass in this build");
   if (grad_e && !aligned(grad_e, sizeof(double)))
     return fail(SIE_ERR_INVALID_ARG, w + ": grad_e is misaligned");
   if (e_frag_out && !aligned(e_frag_out, sizeof(double)))
@@ -707,6 +858,10 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
   st = hip_check(hipGetLastError(), "launch gradient fill");
   if (st != SIE_OK) return st;
 
+  if (pl.split) {
+    st = stage_split(T.desc, s);
+    if (st != SIE_OK) return st;
+  }
   for (size_t q = 0; q < n_rounds; ++q) {
     const size_t r0 = T.round_begin[q], r1 = T.round_begin[q + 1];
     if (r1 == r0) continue;
@@ -714,46 +869,21 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
     const sie::Item* ri = d_items + r0;
     {
       ProfScope ps(s, 0);
-      hipLaunchKernelGGL(sie::k_build_w_f64, dim3(unsigned(T.items[r1 - 1].blk_end)),
-                         dim3(256), 0, s, d_desc, ri, cnt, arena);
+      if (pl.split)
+        hipLaunchKernelGGL(sie::k_build_w_bf16x3, dim3(unsigned(T.items[r1 - 1].blk_end)),
+                           dim3(sie::kThreads), 0, s, d_desc, ri, cnt,
+                           reinterpret_cast<float*>(dev(pl.off_arena)));
+      else
+        build_round_f64(T, q, s, d_desc, d_items, arena);
     }
-    {
-      ProfScope ps(s, 1);
-      hipLaunchKernelGGL(sie::k_hat, dim3(unsigned(T.items[r1 - 1].part_end)), dim3(256), 0, s,
-                         d_desc, ri, cnt, arena, d_part, pl.pstride, grad_e);
-    }
-    {
-      ProfScope ps(s, 4);
-      const auto& L = launches[q];
-      const AdjLaunch& lo = L[sie::kAdjOvvv];
-      if (lo.n_wg)
-        hipLaunchKernelGGL(sie::k_adj_contract<sie::kAdjOvvv>, dim3(unsigned(lo.n_wg)),
-                           dim3(sie::kAThreads), 0, s, d_desc, ri, d_groups + lo.group_off,
-                           lo.n_groups, d_recs, arena);
-      const AdjLaunch& lv = L[sie::kAdjT2vv];
-      if (lv.n_wg)
-        hipLaunchKernelGGL(sie::k_adj_contract<sie::kAdjT2vv>, dim3(unsigned(lv.n_wg)),
-                           dim3(sie::kAThreads), 0, s, d_desc, ri, d_groups + lv.group_off,
-                           lv.n_groups, d_recs, arena);
-      const AdjLaunch& lt = L[sie::kAdjT2oo];
-      if (lt.n_wg)
-        hipLaunchKernelGGL(sie::k_adj_contract<sie::kAdjT2oo>, dim3(unsigned(lt.n_wg)),
-                           dim3(sie::kAThreads), 0, s, d_desc, ri, d_groups + lt.group_off,
-                           lt.n_groups, d_recs, arena);
-      const AdjLaunch& lr = L[sie::kAdjOoov];
-      if (lr.n_wg)
-        hipLaunchKernelGGL(sie::k_adj_contract<sie::kAdjOoov>, dim3(unsigned(lr.n_wg)),
-                           dim3(sie::kAThreads), 0, s, d_desc, ri, d_groups + lr.group_off,
-                           lr.n_groups, d_recs, arena);
-      const AdjLaunch& lp = L[sie::kAdjOvov];
-      if (lp.n_wg)
-        hipLaunchKernelGGL(sie::k_adj_ovov, dim3(unsigned(lp.n_wg)), dim3(256), 0, s, d_desc, ri,
-                           d_groups + lp.group_off, lp.n_groups, d_recs, arena);
-      const AdjLaunch& l1 = L[sie::kAdjT1];
-      if (l1.n_wg)
-        hipLaunchKernelGGL(sie::k_adj_t1, dim3(unsigned(l1.n_wg)), dim3(256), 0, s, d_desc, ri,
-                           d_groups + l1.group_off, l1.n_groups, d_recs, arena);
-    }
+    if (pl.split)
+      backward_round<float, float>(launches[q], s, d_desc, ri, cnt, d_groups, d_recs,
+                                   reinterpret_cast<float*>(dev(pl.off_arena)), d_part,
+                                   pl.pstride, grad_e, unsigned(T.items[r1 - 1].part_end));
+    else
+      backward_round<double, double>(launches[q], s, d_desc, ri, cnt, d_groups, d_recs, arena,
+                                     d_part, pl.pstride, grad_e,
+                                     unsigned(T.items[r1 - 1].part_end));
     st = hip_check(hipGetLastError(), "launch backward kernels");
     if (st != SIE_OK) return st;
   }

@@ -29,10 +29,11 @@ struct FragDesc {
   int no, nv;
   int Kv, Ko;             // padded contraction lengths of the split copies
   int vec;                // float64: rows may be read 16 bytes at a time
+  int variant;            // float64: tile shape of the W-tilde build (see wshape)
   int n_part;             // epilogue partial slots per unit
   int64_t unit_base;      // first entry of this fragment in the per-unit arrays
   int64_t half;           // elements per partial cube (aligned)
-  int64_t tiles;          // build tiles per layout
+  int64_t tiles;          // split: build tiles per layout; float64: build work-groups per unit
   // gradient outputs (float64, input shapes; backward only)
   double* g_t1;
   double* g_t2;
@@ -45,7 +46,8 @@ struct Item {
   int frag;               // fragment index
   int unit;               // unit index u within the fragment (tetrahedral order)
   int64_t cube_off;       // element offset of the item's two partial cubes
-  int64_t blk_end;        // inclusive end of the item's build blocks (prefix sum)
+  int64_t blk_end;        // inclusive end of the item's build blocks (prefix sum over the
+                          // item's build segment: the round's items of one tile variant)
   int64_t part_end;       // inclusive end of the item's epilogue blocks (prefix sum)
 };
 

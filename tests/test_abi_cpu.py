@@ -155,9 +155,28 @@ def test_backward_workspace_and_errors(lib):
     assert backward(lib, f, ctypes.byref(_lib.SieFragmentGrad(FAKE, FAKE + 4, None, None, None))
                     ) == _lib.SIE_ERR_INVALID_ARG
     assert backward(lib, f, ctypes.byref(g), grad_e=FAKE + 4) == _lib.SIE_ERR_INVALID_ARG
-    assert backward(lib, f, ctypes.byref(g), prec=_lib.SIE_SPLIT_BF16) == _lib.SIE_ERR_UNSUPPORTED
     assert backward(lib, f, ctypes.byref(g), ws=None) == _lib.SIE_ERR_WORKSPACE
     assert backward(lib, f, ctypes.byref(g), ws_bytes=4096) == _lib.SIE_ERR_WORKSPACE
     fp = frag(keep=keep, frag_proj=FAKE)
     assert backward(lib, fp, ctypes.byref(g)) == _lib.SIE_ERR_UNSUPPORTED
     assert len(_lib.last_error()) > 0
+
+
+def test_tile_table(lib):
+    n = lib.sie_tile_variants()
+    assert n >= 2
+    shape = (ctypes.c_int32 * 4)()
+    for v in range(n):
+        assert lib.sie_tile_variant_shape(v, shape) == _lib.SIE_OK
+        assert all(x >= 1 for x in shape)
+    assert lib.sie_tile_variant_shape(n, shape) == _lib.SIE_ERR_INVALID_ARG
+    arr = lambda *x: (ctypes.c_int32 * len(x))(*x)  # noqa: E731
+    assert lib.sie_set_tile_table(2, arr(100, 400), arr(1, 0)) == _lib.SIE_OK
+    assert lib.sie_set_tile_table(2, arr(400, 100), arr(1, 0)) == _lib.SIE_ERR_INVALID_ARG
+    assert lib.sie_set_tile_table(1, arr(100), arr(n)) == _lib.SIE_ERR_INVALID_ARG
+    assert lib.sie_set_tile_table(1, None, None) == _lib.SIE_ERR_INVALID_ARG
+    assert lib.sie_set_tile_table(0, None, None) == _lib.SIE_OK
+    # the work-group count of a fragment depends on its variant only through sizing
+    keep = []
+    f = frag(keep=keep)
+    assert lib.sie_triples_workspace_size(ctypes.byref(f), 1, _lib.SIE_FP64, 0) > 0

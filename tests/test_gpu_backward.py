@@ -80,8 +80,8 @@ def test_energy_output_matches_forward_and_scaling():
     g1 = gpu_grad(f, e_frag=e_frag)
     assert float(e_frag.item()) == e_fwd                   # same kernels, same order
     g25 = gpu_grad(f, grad_e=2.5)
-    for n in NAMES:
-        assert np.allclose(g25[n], 2.5 * g1[n], rtol=1e-14, atol=0.0), n
+    for n in NAMES:      # the scale enters before the contractions: rounding differs
+        assert np.abs(g25[n] - 2.5 * g1[n]).max() <= 1e-13 * np.abs(2.5 * g1[n]).max(), n
     g1b = gpu_grad(f)
     for n in NAMES:
         assert np.array_equal(g1b[n], g1[n]), n            # deterministic
@@ -140,15 +140,26 @@ def test_autograd_function():
         assert np.abs(g - 3.0 * oref[n]).max() <= RTOL * 3.0 * np.abs(oref[n]).max(), n
 
 
-def test_split_backward_is_unsupported():
+@pytest.mark.parametrize("o,v,aux,seed,b_scale", [(4, 20, 40, 40, 1.0), (4, 33, 60, 41, 0.3)])
+def test_split_backward_vs_fp64_oracle(o, v, aux, seed, b_scale):
+    """Split precision (float32 inputs, bf16 hi/lo products, float32 G and H,
+    float64 contractions and sums) against the float64 oracle gradient; the
+    relative error per block is printed and bounded by 1e-5 of the block's
+    largest entry."""
     import torch
     import paper_2412_18553_amd as sie
-    f = make_fragment(3, 9, 20, (11, 40))
+    f = make_fragment(o, v, aux, (11, seed), b_scale=b_scale)
+    _, _, _, ref = energy_gradient(*f.arrays())
     cast = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda", torch.float32)  # noqa: E731
     frag = sie.Fragment(f.eps_occ, f.eps_vir, *[cast(getattr(f, n)) for n in NAMES],
                         precision="split_bf16")
-    with pytest.raises(sie.SieError, match="SIE_ERR_UNSUPPORTED"):
-        sie.backward(frag, workspace=torch.empty(1 << 20, dtype=torch.uint8, device="cuda"))
+    g = sie.backward(frag)
+    torch.cuda.synchronize()
+    for n in NAMES:
+        got = g[n].cpu().numpy()
+        err = np.abs(got - ref[n]).max() / np.abs(ref[n]).max()
+        print(f"  split {n}: max|err|/max|g| = {err:.2e}", flush=True)
+        assert err <= 1e-5, (n, err)
 
 
 # ------------------------------------------------------------- full size

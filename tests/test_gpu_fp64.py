@@ -110,3 +110,20 @@ def test_o24v200_full_size():
     for rec in gu["units"]:
         u = pos[tuple(rec["ijk"])]
         assert abs(tri[u] - rec["energy"]) <= RTOL * abs(rec["energy"]), rec
+
+
+@pytest.mark.parametrize("o,v,aux,seed", [(5, 45, 40, 21), (4, 70, 60, 22), (3, 130, 60, 23)])
+def test_every_tile_variant(o, v, aux, seed):
+    """Each compiled tile shape of the build, forced through the tile table,
+    against the oracle (ragged: 45, 70 and 130 are off every tile edge)."""
+    import paper_2412_18553_amd as sie
+    f = make_fragment(o, v, aux, (7, seed))
+    e_ref = T.energy_literal_vectorized(*f.arrays())
+    try:
+        for variant in range(len(sie.tile_variants())):
+            print(f"case o={o} v={v} variant={variant}", flush=True)
+            sie.set_tile_table([(2048, variant)])
+            e_gpu, tri = run_gpu(f)
+            assert abs(e_gpu - e_ref) <= RTOL * abs(e_ref), (variant, e_gpu, e_ref)
+    finally:
+        sie.set_tile_table(None)
