@@ -106,7 +106,7 @@ int64_t sie_occupied_triples(int32_t n_occ);
 
 /* Workspace bytes the energy entry points need for the `n` fragments
  * frags[0..n-1] (host array) at precision `p`, given that at most `max_bytes`
- * may be used (0 = the library's default cap of 2 GiB, or the value of the
+ * may be used (0 = the library's default cap of 16 GiB, or the value of the
  * environment variable SIE_MAX_WORKSPACE_BYTES).  Beyond a fixed part (tables,
  * per-triple partial sums and, for SIE_SPLIT_BF16, the bf16 hi/lo copies of
  * the float32 inputs) the workspace holds the W-tilde cubes of as many

@@ -231,26 +231,28 @@ def backward(frags, *, grad_e: torch.Tensor | None = None, grads=None,
 class SieTriples(torch.autograd.Function):
     """E_x as a differentiable function of (t1, t2, ovvv, ooov, ovov).
 
-    SieTriples.apply(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov) returns a 0-d
-    float64 tensor; backward calls the library's adjoint (float64 only) and
-    returns symmetrized gradients cast to each input's dtype."""
+    SieTriples.apply(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov[, precision])
+    returns a 0-d float64 tensor; backward calls the library's adjoint and
+    returns the symmetrized gradients cast to each input's dtype.  precision
+    is "fp64" (float64 inputs) or "split_bf16" (float32 inputs)."""
 
     @staticmethod
-    def forward(ctx, eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov):
-        frag = Fragment(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, "fp64")
+    def forward(ctx, eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, precision="fp64"):
+        frag = Fragment(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, precision)
         ctx.frag = frag
         return energy(frag)[0].clone()
 
     @staticmethod
     def backward(ctx, grad_out):
         frag = ctx.frag
-        want = [name for name, need in zip(GRAD_NAMES, ctx.needs_input_grad[2:]) if need]
+        want = [name for name, need in zip(GRAD_NAMES, ctx.needs_input_grad[2:7]) if need]
         if not want:
-            return (None,) * 7
+            return (None,) * 8
         ge = grad_out.detach().reshape(1).to(device=frag.device, dtype=torch.float64).contiguous()
         g = backward(frag, grad_e=ge, want=want)
         return (None, None) + tuple(
-            g[name].to(getattr(frag, name).dtype) if name in g else None for name in GRAD_NAMES)
+            g[name].to(getattr(frag, name).dtype) if name in g else None
+            for name in GRAD_NAMES) + (None,)
 
 
 def triples_energy(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, *, precision="fp64",

@@ -5,8 +5,9 @@ python -m paper_2412_18553_amd.autotune [--nv 48,64,...] [--n-occ 8] [--write]
 For each virtual-orbital count in the list it times every compiled tile
 variant (sie_tile_variants) on one synthetic fragment of that size (random
 inputs of the right shapes; the values do not change the work), keeps the
-fastest, merges neighbouring sizes with the same winner into ranges and
-prints the table.  With --write it rewrites csrc/tile_table.inc, the table
+fastest (the default variant 0 is kept unless another is faster by more than
+--margin, so that timing noise does not flip the table), merges neighbouring
+sizes with the same winner into ranges and prints the table.  With --write it rewrites csrc/tile_table.inc, the table
 compiled into the library (rebuild afterwards with
 `python -m paper_2412_18553_amd.build`).  Needs a GPU.
 """
@@ -80,8 +81,9 @@ def write_table(table, results, path=TABLE) -> None:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--nv", default="48,64,80,96,120,144,160,200,240,280,320,400")
-    ap.add_argument("--n-occ", type=int, default=8)
+    ap.add_argument("--nv", default="48,64,80,96,120,160,200,240,320,400")
+    ap.add_argument("--n-occ", type=int, default=16)
+    ap.add_argument("--margin", type=float, default=0.03)
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--write", action="store_true")
     ap.add_argument("--table-path", default=TABLE, help="where --write puts the table")
@@ -93,6 +95,8 @@ def main():
             frag = random_fragment(args.n_occ, nv)
             times = [time_variant(frag, v, args.reps) for v in range(len(shapes))]
             win = min(range(len(times)), key=times.__getitem__)
+            if times[0] <= (1.0 + args.margin) * times[win]:
+                win = 0
             best.append((nv, win))
             results.append((nv, times))
             print(json.dumps({"n_vir": nv, "ms": [round(t, 3) for t in times], "best": win}),

@@ -293,12 +293,14 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
 struct WShape {
   int blk, tr, tc, bpc;
 };
-constexpr int kWVariants = 4;
+constexpr int kWVariants = 6;
 __host__ __device__ inline WShape wshape(int v) {
   switch (v) {
     case 1: return WShape{4, 2, 2, 1};
     case 2: return WShape{2, 2, 2, 2};
     case 3: return WShape{8, 1, 1, 2};
+    case 4: return WShape{4, 4, 2, 1};
+    case 5: return WShape{4, 2, 4, 1};
     default: return WShape{4, 2, 2, 2};
   }
 }

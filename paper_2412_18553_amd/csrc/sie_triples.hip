@@ -29,7 +29,7 @@ sie_status fail(sie_status s, const std::string& msg) {
   return s;
 }
 
-constexpr size_t kDefaultCap = size_t(2) << 30;   // 2 GiB
+constexpr size_t kDefaultCap = size_t(16) << 30;  // 16 GiB of the 288 GB of HBM
 constexpr int kMaxPartials = 256;                  // epilogue blocks per unit
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -503,6 +503,14 @@ void launch_build_f64(int variant, unsigned grid, hipStream_t s, const sie::Frag
       break;
     case 3:
       hipLaunchKernelGGL((sie::k_build_w_f64<8, 1, 1, 2>), dim3(grid), dim3(256), 0, s, desc,
+                         items, n_items, arena);
+      break;
+    case 4:
+      hipLaunchKernelGGL((sie::k_build_w_f64<4, 4, 2, 1>), dim3(grid), dim3(256), 0, s, desc,
+                         items, n_items, arena);
+      break;
+    case 5:
+      hipLaunchKernelGGL((sie::k_build_w_f64<4, 2, 4, 1>), dim3(grid), dim3(256), 0, s, desc,
                          items, n_items, arena);
       break;
     default:
