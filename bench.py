@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--precision", default=None, choices=["fp64", "split_bf16"],
                     help="batched mode: precision of the evaluation (default fp64)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="first copy BYTES device-to-device (a known-size transfer against "
+                         "which hardware byte counters are scaled)")
     ap.add_argument("--cpu-a", default="120,121",
                     help="outer virtual indices a of the CPU-baseline sample")
     return ap.parse_args()
@@ -141,6 +144,14 @@ def main():
     mode = args.mode
     name = args.workload or DEFAULT_WORKLOAD[mode]
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"# calibration copy: {src.numel() * 8} bytes device to device")
+        del src, dst
     t0 = time.perf_counter()
     result = {"metric": "(T) TFLOP/s", "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
               "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
@@ -157,7 +168,8 @@ def main():
         F = flops(o, v)
         if mode == "backward":
             ws = torch.empty(sie.backward_workspace_size(fr), dtype=torch.uint8, device=dev)
-            grads = [{n: torch.empty_like(getattr(fr, n)) for n in sie.GRAD_NAMES}]
+            grads = [{n: torch.empty_like(getattr(fr, n), dtype=torch.float64)
+                      for n in sie.GRAD_NAMES}]
             step = lambda: sie.backward(fr, grads=grads, e_frag=out, workspace=ws)  # noqa: E731
         else:
             ws = torch.empty(sie.workspace_size(fr), dtype=torch.uint8, device=dev)

@@ -197,8 +197,9 @@ sie_status sie_profile_collect(double* ms, int64_t* launches);
 
 /* Tile shapes of the float64 W-tilde build (autotuning).  The build kernel
  * is compiled for sie_tile_variants() tile shapes; sie_tile_variant_shape
- * writes variant v's shape into shape[4] (host): blocks per wave, 16-wide
- * MFMA row tiles and col tiles per wave, work-groups per CU targeted.  A
+ * writes variant v's shape into shape[6] (host): blocks per wave, 16-wide
+ * MFMA row tiles and col tiles per wave, work-groups per CU targeted, and
+ * the work-group's waves along rows and cols (1, 1: waves along blocks).  A
  * fragment's variant is the first table entry whose bound is >= its n_vir
  * (variant 0 past the last).  sie_set_tile_table installs a table of n
  * entries (host arrays: strictly ascending bounds >= 1, valid variants) for

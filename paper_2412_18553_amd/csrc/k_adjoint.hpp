@@ -32,10 +32,11 @@ namespace sie {
 // G and H, in place of the two partial cubes of each unit.
 // ---------------------------------------------------------------------------
 
-// Same orbit traversal as k_epilogue (float64 partial cubes, Wt[a][b][c] =
+// Same orbit traversal as k_epilogue (partial cubes, Wt[a][b][c] =
 // P1[a][b][c] + P2[b][a][c]): the work-group that reads an orbit's blocks of
 // both cubes writes G[a][b][c] over the first and H[a][b][c] over the second
-// at exactly those blocks.  Also
+// at exactly those blocks, and G transposed (Gt[a][b][c] = G(c, b, a)) into
+// the unit's third cube.  Also
 // writes the unit's energy partials (as k_epilogue).  grad_e[frag] (or 1)
 // scales G and H.
 template <typename CubeT, typename InT>
@@ -70,6 +71,7 @@ __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
   const double scale = ((i == j || j == k) ? 1.0 : 2.0) * (grad_e ? gptr(grad_e)[it.frag] : 1.0);
   CubeT* __restrict__ w1 = arena + it.cube_off;
   CubeT* __restrict__ w2 = w1 + fd.half;
+  CubeT* __restrict__ w3 = w2 + fd.half;     // G transposed, Gt[a][b][c] = G(c, b, a)
   const int64_t nonv = (int64_t)no * nv;
   const InT* ov_ij = ovov + (int64_t)i * nv * nonv + (int64_t)j * nv;
   const InT* ov_ik = ovov + (int64_t)i * nv * nonv + (int64_t)k * nv;
@@ -144,6 +146,15 @@ __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
       const int64_t pos = ((int64_t)a * nv + b) * nv + c;
       gptr_w(w1)[pos] = CubeT(scale * (rw + rz) / d);
       gptr_w(w2)[pos] = CubeT(scale * rw / d);
+      // G at (c, b, a), stored at this thread's (a, b, c) of the transposed
+      // cube (contiguous across the wave); R' at (c, b, a) combines the same
+      // six permuted values with the roles of (abc, cba), (cab, acb) and
+      // (bca, bac) exchanged.
+      const double rz_t = 4.0 * sz[s_cba][e_cba] + sz[s_acb][e_acb] + sz[s_bac][e_bac] -
+                          2.0 * (sz[s][e_abc] + sz[s_cab][e_cab] + sz[s_bca][e_bca]);
+      const double rw_t = 4.0 * sw[s_cba][e_cba] + sw[s_acb][e_acb] + sw[s_bac][e_bac] -
+                          2.0 * (sw[s][e_abc] + sw[s_cab][e_cab] + sw[s_bca][e_bca]);
+      gptr_w(w3)[pos] = CubeT(scale * (rw_t + rz_t) / d);
     }
     __syncthreads();
   }
@@ -214,56 +225,70 @@ struct AdjRec {
   int pad;
 };
 
-constexpr int kABB = 8;        // blocks per work-group
-constexpr int kAR = 64;        // MFMA rows per work-group
-constexpr int kAC = 32;        // MFMA cols per work-group
-constexpr int kAKc = 8;        // K chunk
-constexpr int kAPlanes = kAKc / 2;
-constexpr int kAThreads = 64 * (kAR / 16) * (kAC / 16);
-constexpr int kALdsB = kABB * kAR;                 // first LDS row of the B side
-constexpr int kALdsRows = kABB * kAR + kABB * kAC;
-static_assert(kAPlanes == 4, "one k-pair plane per MFMA lane group");
+// Tiles of the G contractions (4 waves per work-group, operands loaded from
+// L1/L2 straight into registers, two K-chunks of 8 in flight):
+//   per-block classes (ovvv, t2 from the l-sums): wave w owns blocks
+//     4w .. 4w + 3 x 32 rows x 32 cols, the work-group 16 blocks x 32 x 32;
+//   summed-block classes (t2 from the d-sums, ooov): the first summed
+//     virtual runs in groups of kARB as the block index of both operands,
+//     summed at the end; waves tile 64 x 64 (t2: 2 x 2 waves of 32 x 32) or
+//     128 x 32 (ooov, whose cols are the few occupied: 4 x 1 waves).
+constexpr int kABlk = 4;                 // blocks per wave, per-block classes
+constexpr int kARB = 2;                  // summed-block group (blocks per wave) of the others
+constexpr int kAT = 2;                   // 16-wide MFMA tiles per wave along rows and cols
+constexpr int kAKc = 8;                  // K chunk
+constexpr int kAThreads = 256;
 
-// Element (beta, x, k) of the A side (rows, always G) is a[beta*a_b + x*a_x + k*a_k];
-// of the B side (cols) b[beta*b_b + x*b_x + k*b_k] with b_b = 0 when the B side
-// is shared by all blocks.
+// Element (beta, x, k) of the A side (rows, always G or its transpose) is
+// a[beta*a_b + x*a_x + k*a_k]; of the B side (cols) b[beta*b_b + x*b_x +
+// k*b_k] times `scale`, with b_b = 0 when the B side is shared by all blocks.
 template <typename CubeT, typename InT>
 struct ATerm {
   const CubeT* a;
   int64_t a_b, a_x, a_k;
   const InT* b;
   int64_t b_b, b_x, b_k;
-  double scale;        // applied to the B side
-  int nblk;            // valid blocks (summed-block classes); per-block: the tile's
+  double scale;
+  int nblk;            // valid blocks (summed-block classes)
 };
 
+// Term `kind` of class CLS for unit (i, j, k) at tile origin (blk0, row0,
+// col0); block group g (summed-block classes).  G[a][b][c] has strides
+// (nv^2, nv, 1), its transpose Gt[a][b][c] = G(c, b, a) has (1, nv, nv^2) in
+// G's (a, b, c): for each kind the layout giving unit stride along the rows
+// or K is used.
 template <int CLS, typename CubeT, typename InT>
 __device__ __forceinline__ ATerm<CubeT, InT> make_adj(int kind, int g, int i, int j, int k, int no_,
-                                                      int nv_, const CubeT* G, const InT* t2,
-                                                      const InT* ovvv, const InT* ooov, int blk0,
-                                                      int row0, int col0) {
+                                                      int nv_, const CubeT* G, const CubeT* Gt,
+                                                      const InT* t2, const InT* ovvv,
+                                                      const InT* ooov, int blk0, int row0,
+                                                      int col0) {
   const int64_t nv = nv_, no = no_, nv2 = nv * nv;
-  const int64_t sA = nv2, sB = nv, sC = 1;
+  const int64_t sA = nv2, sB = nv, sC = 1;       // strides of a, b, c in G
+  const int64_t tA = 1, tB = nv, tC = nv2;       // ... in Gt
   ATerm<CubeT, InT> t;
   t.scale = 1.0;
-  t.nblk = kABB;
+  t.nblk = kABlk;
   if (CLS == kAdjOvvv) {
-    // dovvv[x][p][q][d] += sum_r Gperm[p][q][r] t2[s1][s2][r][d]
-    const int64_t Sb = pick6(kind, sA, sA, sC, sB, sC, sB);
-    const int64_t Sx = pick6(kind, sB, sC, sA, sC, sB, sA);
-    const int64_t Sk = pick6(kind, sC, sB, sB, sA, sA, sC);
+    // dovvv[x][p][q][d] += sum_r Gperm[p][q][r] t2[s1][s2][r][d], t2 read as
+    // its twin t2[s2][s1][d][r] (K contiguous)
+    const bool tr = kind == 2 || kind == 4;
+    const int64_t Sb = tr ? tC : pick6(kind, sA, sA, sC, sB, sC, sB);
+    const int64_t Sx = tr ? pick6<int64_t>(kind, 0, 0, tA, 0, tB, 0) : pick6(kind, sB, sC, sA, sC, sB, sA);
+    const int64_t Sk = tr ? pick6<int64_t>(kind, 0, 0, tB, 0, tA, 0) : pick6(kind, sC, sB, sB, sA, sA, sC);
     const int64_t s1 = pick6(kind, k, j, j, i, i, k), s2 = pick6(kind, j, k, i, k, j, i);
-    t.a = G + blk0 * Sb + row0 * Sx;
+    t.a = (tr ? Gt : G) + blk0 * Sb + row0 * Sx;
     t.a_b = Sb; t.a_x = Sx; t.a_k = Sk;
-    t.b = t2 + (s1 * no + s2) * nv2 + col0;
-    t.b_b = 0; t.b_x = 1; t.b_k = nv;
+    t.b = t2 + (s2 * no + s1) * nv2 + col0 * nv;
+    t.b_b = 0; t.b_x = nv; t.b_k = 1;
   } else if (CLS == kAdjT2oo) {
     // dt2[p][l][y][z] += -sum_K Gperm[y][z][K] ooov[m][l][n][K]
-    const int64_t Sy = pick6(kind, sA, sA, sC, sC, sB, sB);
-    const int64_t Sz = pick6(kind, sC, sB, sA, sB, sC, sA);
-    const int64_t SK = pick6(kind, sB, sC, sB, sA, sA, sC);
+    const bool tr = kind == 2 || kind == 3;
+    const int64_t Sy = tr ? tC : pick6(kind, sA, sA, sC, sC, sB, sB);
+    const int64_t Sz = tr ? pick6<int64_t>(kind, 0, 0, tA, tB, 0, 0) : pick6(kind, sC, sB, sA, sB, sC, sA);
+    const int64_t SK = tr ? pick6<int64_t>(kind, 0, 0, tB, tA, 0, 0) : pick6(kind, sB, sC, sB, sA, sA, sC);
     const int64_t m = pick6(kind, k, j, i, j, k, i), n = pick6(kind, j, k, j, i, i, k);
-    t.a = G + blk0 * Sy + row0 * Sz;
+    t.a = (tr ? Gt : G) + blk0 * Sy + row0 * Sz;
     t.a_b = Sy; t.a_x = Sz; t.a_k = SK;
     t.b = ooov + ((m * no + col0) * no + n) * nv;
     t.b_b = 0; t.b_x = no * nv; t.b_k = 1;
@@ -276,12 +301,12 @@ __device__ __forceinline__ ATerm<CubeT, InT> make_adj(int kind, int g, int i, in
     const int64_t Bb = pick6(kind, nv2, nv2, nv, nv2, nv, nv);
     const int64_t Bk = pick6(kind, nv, nv, nv2, nv, nv2, nv2);
     const int64_t x = pick6(kind, i, i, k, j, k, j);
-    const int64_t k10 = int64_t(g) * kABB;
+    const int64_t k10 = int64_t(g) * kARB;
     t.a = G + k10 * Ab + row0 * Ax;
     t.a_b = Ab; t.a_x = Ax; t.a_k = Ak;
     t.b = ovvv + x * nv2 * nv + k10 * Bb + col0;
     t.b_b = Bb; t.b_x = 1; t.b_k = Bk;
-    t.nblk = nv_ - int(k10) < kABB ? nv_ - int(k10) : kABB;
+    t.nblk = nv_ - int(k10) < kARB ? nv_ - int(k10) : kARB;
   } else {   // kAdjOoov
     // dooov[m][l][n][x] += -sum_{k1, k2} Gperm[k1][x][k2] t2[..l..][k1][k2]
     const int64_t Ab = pick6(kind, sA, sA, sA, sB, sB, sA);
@@ -290,131 +315,100 @@ __device__ __forceinline__ ATerm<CubeT, InT> make_adj(int kind, int g, int i, in
     const int64_t base = pick6(kind, i * no * nv2, i * no * nv2, k * nv2, k * nv2, j * no * nv2,
                                j * nv2);
     const int64_t Bl = pick6(kind, nv2, nv2, no * nv2, no * nv2, nv2, no * nv2);
-    const int64_t k10 = int64_t(g) * kABB;
+    const int64_t k10 = int64_t(g) * kARB;
     t.a = G + k10 * Ab + row0 * Ax;
     t.a_b = Ab; t.a_x = Ax; t.a_k = Ak;
     t.b = t2 + base + col0 * Bl + k10 * nv;
     t.b_b = nv; t.b_x = Bl; t.b_k = 1;
     t.scale = -1.0;
-    t.nblk = nv_ - int(k10) < kABB ? nv_ - int(k10) : kABB;
+    t.nblk = nv_ - int(k10) < kARB ? nv_ - int(k10) : kARB;
   }
   return t;
 }
 
-// Staging order of an operand's (beta, x, k-pair) units: the dimension with
-// unit stride walks fastest so that consecutive threads read consecutive
-// addresses.
-enum { kFastK = 0, kFastX = 1, kFastB = 2 };
-
-__device__ __forceinline__ int fast_dim(int64_t sb, int64_t sx, int64_t sk) {
-  return sk == 1 ? kFastK : (sx == 1 ? kFastX : (sb == 1 ? kFastB : kFastX));
-}
-
-template <int X>
-__device__ __forceinline__ void unit_coords(int mode, int u, int& beta, int& x, int& kp) {
-  constexpr int lx = X == 64 ? 6 : (X == 32 ? 5 : 4);
-  if (mode == kFastK) {
-    kp = u & (kAPlanes - 1);
-    const int rr = u >> 2;
-    x = rr & (X - 1);
-    beta = rr >> lx;
-  } else if (mode == kFastX) {
-    x = u & (X - 1);
-    const int rest = u >> lx;
-    beta = rest & (kABB - 1);
-    kp = rest >> 3;
-  } else {
-    beta = u & (kABB - 1);
-    x = (u >> 3) & (X - 1);
-    kp = u >> (3 + lx);
-  }
-}
-
-// k-pair (k, k+1) of one row; entries past nK read in bounds and count zero.
-template <typename T>
-__device__ __forceinline__ double2 pair_at(const T* row, int64_t ks, int k, int nK, double s) {
-  const SIE_GLOBAL T* g = gptr(row);
-  const int k0 = k < nK ? k : nK - 1;
-  const int k1 = k + 1 < nK ? k + 1 : nK - 1;
-  double2 v;
-  v.x = (k < nK ? s : 0.0) * (double)g[(int64_t)k0 * ks];
-  v.y = (k + 1 < nK ? s : 0.0) * (double)g[(int64_t)k1 * ks];
-  return v;
-}
-
-constexpr int kAUnitsA = kABB * kAR * kAPlanes / kAThreads;   // 4
-constexpr int kAUnitsB = kABB * kAC * kAPlanes / kAThreads;   // 2
-
-struct AStage {
-  double2 a[kAUnitsA];
-  double2 b[kAUnitsB];
+// Registers of one K-chunk for one wave: A side (G) for kABlk blocks x kAT
+// row tiles, B side for kABlk blocks (or the shared row) x kAT col tiles.
+template <int BLK>
+struct AChunk {
+  double a[BLK][kAT][2];
+  double b[BLK][kAT][2];
 };
 
-// Global loads of chunk c of term t.  `nrow`, `ncol`: valid rows / cols of
-// the tile; `nblk`: valid blocks (rows of blocks past it read block 0 and,
-// for summed blocks, count zero).
-template <typename Term>
-__device__ __forceinline__ void adj_load(const Term& t, bool reduce, int c, int nK, int nrow,
-                                         int ncol, int nblk, int tid, AStage& st) {
-  const int k0 = c * kAKc;
-  const int ma = fast_dim(t.a_b, t.a_x, t.a_k);
-#pragma unroll
-  for (int m = 0; m < kAUnitsA; ++m) {
-    int beta, x, kp;
-    unit_coords<kAR>(ma, tid + m * kAThreads, beta, x, kp);
-    const bool bok = beta < nblk;
-    const int bb = bok ? beta : 0;
-    const int xx = x < nrow ? x : nrow - 1;
-    const double s = (reduce && !bok) ? 0.0 : 1.0;
-    st.a[m] = pair_at(t.a + bb * t.a_b + xx * t.a_x, t.a_k, k0 + 2 * kp, nK, s);
-  }
-  const int mb = fast_dim(t.b_b == 0 ? 2 : t.b_b, t.b_x, t.b_k);
-#pragma unroll
-  for (int m = 0; m < kAUnitsB; ++m) {
-    const int u = tid + m * kAThreads;
-    int beta, x, kp;
-    unit_coords<kAC>(mb, u, beta, x, kp);
-    const int bb = beta < nblk ? beta : 0;
-    const int xx = x < ncol ? x : ncol - 1;
-    st.b[m] = pair_at(t.b + bb * t.b_b + xx * t.b_x, t.b_k, k0 + 2 * kp, nK, t.scale);
+// The lane's k-pair (k, k+1) of one row; past nK in bounds and zero (the
+// A side carries no zeroing: B's zeros cancel it).  `vec`: unit stride and
+// 16-byte aligned pairs.
+template <typename T>
+__device__ __forceinline__ void apair(const T* row, int64_t ks, int k, int nK, double s, bool vec,
+                                      double (&out)[2]) {
+  const SIE_GLOBAL T* g = gptr(row);
+  if (vec && k + 1 < nK) {
+    if (sizeof(T) == 8) {
+      const d2v v = *(const SIE_GLOBAL d2v*)(g + k);
+      out[0] = s * v.x;
+      out[1] = s * v.y;
+    } else {
+      out[0] = s * (double)g[k];
+      out[1] = s * (double)g[k + 1];
+    }
+  } else {
+    const int k0 = k < nK ? k : nK - 1;
+    const int k1 = k + 1 < nK ? k + 1 : nK - 1;
+    out[0] = (k < nK ? s : 0.0) * (double)g[(int64_t)k0 * ks];
+    out[1] = (k + 1 < nK ? s : 0.0) * (double)g[(int64_t)k1 * ks];
   }
 }
 
-template <typename Term>
-__device__ __forceinline__ void adj_store(const Term& t, int tid, const AStage& st,
-                                          double2* buf) {
-  const int ma = fast_dim(t.a_b, t.a_x, t.a_k);
+// Lane rows of one term: clamped A-side rows x_rt and B-side rows x_ct.
+template <int BLK, typename CubeT, typename InT>
+__device__ __forceinline__ void adj_load(const ATerm<CubeT, InT>& t, bool reduce, int c, int nK,
+                                         int rbase, int cbase, int nrow, int ncol, int nblk,
+                                         int r, int g, bool vec, AChunk<BLK>& x) {
+  const int k = c * kAKc + 2 * g;
+  const bool va = vec && t.a_k == 1, vb = vec && t.b_k == 1;
 #pragma unroll
-  for (int m = 0; m < kAUnitsA; ++m) {
-    int beta, x, kp;
-    unit_coords<kAR>(ma, tid + m * kAThreads, beta, x, kp);
-    buf[kp * kALdsRows + beta * kAR + x] = st.a[m];
+  for (int rt = 0; rt < kAT; ++rt) {
+    const int xr = min(rbase + 16 * rt + r, nrow - 1);
+#pragma unroll
+    for (int beta = 0; beta < BLK; ++beta) {
+      const bool ok = beta < nblk;
+      const int bb = ok ? beta : 0;
+      apair(t.a + bb * t.a_b + xr * t.a_x, t.a_k, k, nK, (reduce && !ok) ? 0.0 : 1.0, va,
+            x.a[beta][rt]);
+    }
   }
-  const int mb = fast_dim(t.b_b == 0 ? 2 : t.b_b, t.b_x, t.b_k);
 #pragma unroll
-  for (int m = 0; m < kAUnitsB; ++m) {
-    int beta, x, kp;
-    unit_coords<kAC>(mb, tid + m * kAThreads, beta, x, kp);
-    buf[kp * kALdsRows + kALdsB + beta * kAC + x] = st.b[m];
+  for (int ct = 0; ct < kAT; ++ct) {
+    const int xc = min(cbase + 16 * ct + r, ncol - 1);
+    if (reduce) {
+#pragma unroll
+      for (int beta = 0; beta < BLK; ++beta) {
+        const int bb = beta < nblk ? beta : 0;
+        apair(t.b + bb * t.b_b + xc * t.b_x, t.b_k, k, nK, t.scale, vb, x.b[beta][ct]);
+      }
+    } else {
+      apair(t.b + xc * t.b_x, t.b_k, k, nK, t.scale, vb, x.b[0][ct]);
+    }
   }
 }
 
-// One chunk of MFMAs; lane group g holds k-pair plane g.  A shared B side
-// (b_b = 0) was staged identically in every block, so block beta always
-// reads its own rows.
-__device__ __forceinline__ void adj_mma(const double2* buf, int g, int rrow, int rcol,
-                                        d4 (&acc)[kABB]) {
-  const double2* pl = buf + g * kALdsRows;
-  double2 a[kABB], b[kABB];
+// acc[beta][rt][ct] += A[beta][rt] * B[beta or shared][ct] over the chunk;
+// row / col tiles wholly outside the output (uniform) are skipped.
+template <int BLK>
+__device__ __forceinline__ void adj_mma(const AChunk<BLK>& x, bool reduce, bool r1, bool c1,
+                                        d4 (&acc)[BLK][kAT][kAT]) {
 #pragma unroll
-  for (int beta = 0; beta < kABB; ++beta) {
-    a[beta] = pl[beta * kAR + rrow];
-    b[beta] = pl[kALdsB + beta * kAC + rcol];
-  }
+  for (int s = 0; s < 2; ++s)
 #pragma unroll
-  for (int beta = 0; beta < kABB; ++beta) acc[beta] = mfma16x16x4(a[beta].x, b[beta].x, acc[beta]);
+    for (int rt = 0; rt < kAT; ++rt)
 #pragma unroll
-  for (int beta = 0; beta < kABB; ++beta) acc[beta] = mfma16x16x4(a[beta].y, b[beta].y, acc[beta]);
+      for (int ct = 0; ct < kAT; ++ct) {
+        if ((rt == 1 && !r1) || (ct == 1 && !c1)) continue;
+#pragma unroll
+        for (int beta = 0; beta < BLK; ++beta)
+          acc[beta][rt][ct] = mfma16x16x4(x.a[beta][rt][s], reduce ? x.b[beta][ct][s]
+                                                                    : x.b[0][ct][s],
+                                          acc[beta][rt][ct]);
+      }
 }
 
 struct AdjOut {
@@ -447,18 +441,23 @@ __device__ __forceinline__ AdjOut adj_out(const FragDesc& fd, const AdjGroup& gr
   return o;
 }
 
+// Work-group tile of a class: (blocks, rows, cols) per work-group.
+__host__ __device__ inline void adj_tile_shape(int cls, int& tb, int& tr, int& tc) {
+  const bool red = cls == kAdjT2vv || cls == kAdjOoov;
+  tb = red ? 1 : 4 * kABlk;
+  tr = cls == kAdjT2vv ? 2 * 16 * kAT : cls == kAdjOoov ? 4 * 16 * kAT : 16 * kAT;
+  tc = cls == kAdjT2vv ? 2 * 16 * kAT : 16 * kAT;
+}
+
 // Work-groups per output slice of a class for a fragment.
 __host__ __device__ inline int64_t adj_tiles(int cls, int no, int nv) {
-  const int64_t nrt = (nv + kAR - 1) / kAR;
-  const int64_t nbt = (nv + kABB - 1) / kABB;
-  switch (cls) {
-    case kAdjOvvv: return nbt * nrt * ((nv + kAC - 1) / kAC);
-    case kAdjT2oo: return nbt * nrt * ((no + kAC - 1) / kAC);
-    case kAdjT2vv: return nrt * ((nv + kAC - 1) / kAC);
-    case kAdjOoov: return nrt * ((no + kAC - 1) / kAC);
-    case kAdjOvov: return (int64_t(nv) * nv + 255) / 256;
-    default: return (nv + 63) / 64;
-  }
+  if (cls == kAdjOvov) return (int64_t(nv) * nv + 255) / 256;
+  if (cls == kAdjT1) return (nv + 63) / 64;
+  int tb, tr, tc;
+  adj_tile_shape(cls, tb, tr, tc);
+  const int nb = (cls == kAdjT2vv || cls == kAdjOoov) ? 1 : nv;
+  const int nc = (cls == kAdjT2oo || cls == kAdjOoov) ? no : nv;
+  return int64_t((nb + tb - 1) / tb) * ((nv + tr - 1) / tr) * ((nc + tc - 1) / tc);
 }
 
 __device__ __forceinline__ int find_group(const AdjGroup* __restrict__ gs, int n, int64_t x) {
@@ -470,9 +469,10 @@ __device__ __forceinline__ int find_group(const AdjGroup* __restrict__ gs, int n
   return lo;
 }
 
-// Grid: the concatenated tiles of the launch's groups.  Block: kAThreads.
+// Grid: the concatenated tiles of the launch's groups.  Block: 256 threads.
+// arena holds per unit G, H and Gt (cube_off, + half, + 2 half).
 template <int CLS, typename CubeT, typename InT>
-__global__ __launch_bounds__(kAThreads, 1) void k_adj_contract(
+__global__ __launch_bounds__(kAThreads, 2) void k_adj_contract(
     const FragDesc* __restrict__ descs, const Item* __restrict__ items,
     const AdjGroup* __restrict__ groups, int n_groups, const AdjRec* __restrict__ recs,
     const CubeT* __restrict__ arena) {
@@ -483,102 +483,96 @@ __global__ __launch_bounds__(kAThreads, 1) void k_adj_contract(
   const FragDesc fd = descs[gr.frag];
   const int no = fd.no, nv = fd.nv;
   const AdjOut o = adj_out<CLS>(fd, gr);
-
-  // tile of the slice
-  const int nrt = (o.nr + kAR - 1) / kAR, nct = (o.nc + kAC - 1) / kAC;
+  int TB, TR, TC;
+  adj_tile_shape(CLS, TB, TR, TC);
+  const int nrt = (o.nr + TR - 1) / TR, nct = (o.nc + TC - 1) / TC;
   const int ntile = int(adj_tiles(CLS, no, nv));
   int t = xcd_tile(int(int64_t(blockIdx.x) - start), ntile);
   const int tb = t / (nrt * nct);
   t -= tb * nrt * nct;
-  const int tr = t / nct, tc = t - tr * nct;
-  const int blk0 = tb * kABB, row0 = tr * kAR, col0 = tc * kAC;
-  const int nrow = min(kAR, o.nr - row0), ncol = min(kAC, o.nc - col0);
-  const int nblk_tile = kReduce ? kABB : min(kABB, o.nb - blk0);
+  const int trow = t / nct, tcol = t - trow * nct;
 
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, g = lane >> 4;
-  const int rq = wave % (kAR / 16), ch = wave / (kAR / 16);
-  const int rrow = rq * 16 + r, rcol = ch * 16 + r;
+  // this wave's part of the tile
+  constexpr int BLK = kReduce ? kARB : kABlk;
+  const int blk0 = kReduce ? 0 : tb * TB + wave * kABlk;
+  const int row0 = trow * TR + (CLS == kAdjT2vv ? (wave & 1) * 16 * kAT
+                                : CLS == kAdjOoov ? wave * 16 * kAT : 0);
+  const int col0 = tcol * TC + (CLS == kAdjT2vv ? (wave >> 1) * 16 * kAT : 0);
+  if ((!kReduce && blk0 >= o.nb) || row0 >= o.nr || col0 >= o.nc) return;   // no barriers
+  const int nrow = min(16 * kAT, o.nr - row0), ncol = min(16 * kAT, o.nc - col0);
+  const int nblk_tile = kReduce ? BLK : min(kABlk, o.nb - blk0);
+  const bool r1 = nrow > 16, c1 = ncol > 16;
+  const bool vec = fd.vec != 0;
 
-  __shared__ double2 lds[2][kAPlanes * kALdsRows];
-  d4 acc[kABB];
+  d4 acc[BLK][kAT][kAT];
 #pragma unroll
-  for (int q = 0; q < kABB; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < BLK; ++b)
+#pragma unroll
+    for (int p = 0; p < kAT; ++p)
+#pragma unroll
+      for (int q = 0; q < kAT; ++q) acc[b][p][q] = d4{0.0, 0.0, 0.0, 0.0};
 
   const InT* t2p = static_cast<const InT*>(fd.t2);
   const InT* ovvvp = static_cast<const InT*>(fd.ovvv);
   const InT* ooovp = static_cast<const InT*>(fd.ooov);
   const int nchunk = (nv + kAKc - 1) / kAKc;
 
-  auto term_of = [&](int rec) {
+  for (int rec = gr.rec_begin; rec < gr.rec_end; ++rec) {
     const AdjRec rr = recs[rec];
     const Item it = items[rr.item];
     int i, j, k;
     decode_sorted_triple(it.unit, no, i, j, k);
-    return make_adj<CLS, CubeT, InT>(rr.kind, rr.g, i, j, k, no, nv, arena + it.cube_off, t2p, ovvvp,
-                         ooovp, blk0, row0, col0);
-  };
-
-  int rec = gr.rec_begin, c = 0;
-  ATerm<CubeT, InT> tcur = term_of(rec);
-  AStage st;
-  adj_load(tcur, kReduce, 0, nv, nrow, ncol, kReduce ? tcur.nblk : nblk_tile, tid, st);
-  adj_store(tcur, tid, st, lds[0]);
-  __syncthreads();
-  int buf = 0;
-  while (true) {
-    int recn = rec, cn = c + 1;
-    ATerm<CubeT, InT> tn = tcur;
-    bool more = true;
-    if (cn >= nchunk) {
-      if (rec + 1 >= gr.rec_end) {
-        more = false;
-      } else {
-        recn = rec + 1;
-        cn = 0;
-        tn = term_of(recn);
-      }
+    const CubeT* G = arena + it.cube_off;
+    const ATerm<CubeT, InT> tm = make_adj<CLS, CubeT, InT>(
+        rr.kind, rr.g, i, j, k, no, nv, G, G + 2 * fd.half, t2p, ovvvp, ooovp, blk0, row0, col0);
+    const int nblk = kReduce ? tm.nblk : nblk_tile;
+    AChunk<BLK> b0, b1;
+    adj_load(tm, kReduce, 0, nv, 0, 0, nrow, ncol, nblk, r, g, vec, b0);
+    for (int c = 0;; c += 2) {
+      adj_load(tm, kReduce, c + 1, nv, 0, 0, nrow, ncol, nblk, r, g, vec, b1);
+      adj_mma(b0, kReduce, r1, c1, acc);
+      if (c + 1 >= nchunk) break;
+      adj_load(tm, kReduce, c + 2, nv, 0, 0, nrow, ncol, nblk, r, g, vec, b0);
+      adj_mma(b1, kReduce, r1, c1, acc);
+      if (c + 2 >= nchunk) break;
     }
-    if (more) adj_load(tn, kReduce, cn, nv, nrow, ncol, kReduce ? tn.nblk : nblk_tile, tid, st);
-    adj_mma(lds[buf], g, rrow, rcol, acc);
-    if (!more) break;
-    adj_store(tn, tid, st, lds[buf ^ 1]);
-    __syncthreads();
-    buf ^= 1;
-    rec = recn;
-    c = cn;
-    tcur = tn;
   }
 
-  // acc[beta][v] = out[blk0 + beta][row0 + rq*16 + 4v + g][col0 + rcol]
-  const int col = col0 + rcol;
-  if (kReduce) {
-    d4 s = acc[0];
+  // acc[beta][rt][ct][v] = out[blk0 + beta][row0 + 16 rt + 4 v + g][col0 + 16 ct + r]
 #pragma unroll
-    for (int beta = 1; beta < kABB; ++beta) s += acc[beta];
+  for (int rt = 0; rt < kAT; ++rt)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = row0 + rq * 16 + 4 * v + g;
-      if (row < o.nr && col < o.nc) {
-        SIE_GLOBAL double* p = gptr_w(o.out) + row * o.orow + col * o.ocol;
-        *p = *p + s[v];
-      }
-    }
-  } else {
+    for (int ct = 0; ct < kAT; ++ct) {
+      const int col = col0 + 16 * ct + r;
+      if (kReduce) {
+        d4 sum = acc[0][rt][ct];
 #pragma unroll
-    for (int beta = 0; beta < kABB; ++beta) {
-      const int blk = blk0 + beta;
+        for (int beta = 1; beta < BLK; ++beta) sum += acc[beta][rt][ct];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = row0 + rq * 16 + 4 * v + g;
-        if (blk < o.nb && row < o.nr && col < o.nc) {
-          SIE_GLOBAL double* p = gptr_w(o.out) + blk * o.ob + row * o.orow + col * o.ocol;
-          *p = *p + acc[beta][v];
+        for (int v = 0; v < 4; ++v) {
+          const int row = row0 + 16 * rt + 4 * v + g;
+          if (row < o.nr && col < o.nc) {
+            SIE_GLOBAL double* p = gptr_w(o.out) + row * o.orow + col * o.ocol;
+            *p = *p + sum[v];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int beta = 0; beta < BLK; ++beta) {
+          const int blk = blk0 + beta;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = row0 + 16 * rt + 4 * v + g;
+            if (blk < o.nb && row < o.nr && col < o.nc) {
+              SIE_GLOBAL double* p = gptr_w(o.out) + blk * o.ob + row * o.orow + col * o.ocol;
+              *p = *p + acc[beta][rt][ct][v];
+            }
+          }
         }
       }
     }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -639,71 +633,90 @@ __device__ __forceinline__ double block_sum_fixed256(double v, double* red) {
   return s;
 }
 
-// dt1[p][y] for y in a 64-wide tile.  Block: 256 threads.
+// dt1 in two passes over a batch of records [b0, b0 + gridDim.x).  Pass 1:
+// one work-group per H record writes that record's contribution to all n_v
+// entries of its t1 row into part[(rec - b0) * pstride + y]; pass 2 adds
+// each group's records of the batch in list order.
+//   kind 0: y = c, sum_{a,b} H[a][b][c] ovov[i][a][j][b]
+//   kind 1: y = b, sum_{a,c} H[a][b][c] ovov[i][a][k][c]
+//   kind 2: y = a, sum_{b,c} H[a][b][c] ovov[j][b][k][c]
+// Lanes run along c (contiguous in H) in chunks of 64, so H streams once per
+// record, coalesced.  Grid: the launch's T1 records.  Block: 256 threads.
 template <typename CubeT, typename InT>
-__global__ __launch_bounds__(256) void k_adj_t1(const FragDesc* __restrict__ descs,
-                                                const Item* __restrict__ items,
-                                                const AdjGroup* __restrict__ groups,
-                                                int n_groups, const AdjRec* __restrict__ recs,
-                                                const CubeT* __restrict__ arena) {
-  __shared__ double red[4];
-  __shared__ double part[4][64];
-  const int gi = find_group(groups, n_groups, blockIdx.x);
-  const AdjGroup gr = groups[gi];
-  const int64_t start = gi ? groups[gi - 1].wg_end : 0;
-  const FragDesc fd = descs[gr.frag];
+__global__ __launch_bounds__(256) void k_adj_t1_part(const FragDesc* __restrict__ descs,
+                                                     const Item* __restrict__ items,
+                                                     const AdjRec* __restrict__ recs, int b0,
+                                                     const CubeT* __restrict__ arena,
+                                                     double* __restrict__ part, int pstride) {
+  __shared__ double red[4][64];
+  const int q = b0 + blockIdx.x;
+  const AdjRec rr = recs[q];
+  const Item it = items[rr.item];
+  const FragDesc fd = descs[it.frag];
   const int no = fd.no, nv = fd.nv;
-  const int y0 = int(int64_t(blockIdx.x) - start) * 64;
-  const int ny = min(64, nv - y0);
-  const InT* ovov = static_cast<const InT*>(fd.ovov);
+  int i, j, k;
+  decode_sorted_triple(it.unit, no, i, j, k);
+  const SIE_GLOBAL CubeT* H = gptr(arena + it.cube_off + fd.half);
+  const SIE_GLOBAL InT* ovov = gptr(static_cast<const InT*>(fd.ovov));
   const int64_t nv2 = int64_t(nv) * nv, onv = int64_t(no) * nv;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double mine = 0.0;   // thread y0 + threadIdx.x's sum (threads < ny)
-  for (int q = gr.rec_begin; q < gr.rec_end; ++q) {
-    const AdjRec rr = recs[q];
-    const Item it = items[rr.item];
-    int i, j, k;
-    decode_sorted_triple(it.unit, no, i, j, k);
-    const SIE_GLOBAL CubeT* H = gptr(arena + it.cube_off + fd.half);
-    if (rr.kind == 0) {
-      // y = c: sum_{a,b} H[a][b][c] ovov[i][a][j][b]; lanes over c, waves over (a, b)
+  double* out = part + int64_t(blockIdx.x) * pstride;
+  if (rr.kind == 0) {
+    const SIE_GLOBAL InT* m = ovov + int64_t(i) * nv * onv + int64_t(j) * nv;   // m[a*onv + b]
+    for (int c0 = 0; c0 < nv; c0 += 64) {
+      const int c = c0 + lane;
       double s = 0.0;
-      if (lane < ny) {
-        const int c = y0 + lane;
+      if (c < nv)
         for (int64_t ab = wave; ab < nv2; ab += 4) {
-          const int a = int(ab / nv), b = int(ab - int64_t(a) * nv);
-          s += (double)H[ab * nv + c] *
-               (double)gptr(ovov)[(int64_t(i) * nv + a) * onv + int64_t(j) * nv + b];
+          const int aa = int(ab / nv), bb = int(ab - int64_t(aa) * nv);
+          s += (double)H[ab * nv + c] * (double)m[aa * onv + bb];
         }
-      }
-      part[wave][lane] = s;
+      red[wave][lane] = s;
       __syncthreads();
-      if (threadIdx.x < 64) mine += ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+      if (wave == 0 && c < nv)
+        out[c] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
       __syncthreads();
-    } else {
-      // kind 1: y = b, sum_{a,c} H[a][b][c] ovov[i][a][k][c]
-      // kind 2: y = a, sum_{b,c} H[a][b][c] ovov[j][b][k][c]
-      for (int yy = 0; yy < ny; ++yy) {
-        const int y = y0 + yy;
+    }
+  } else {
+    // kind 1: y = b, weight M[a][c] = ovov[i][a][k][c], H row (a, y)
+    // kind 2: y = a, weight M[b][c] = ovov[j][b][k][c], H row (y, b)
+    const SIE_GLOBAL InT* m = rr.kind == 1 ? ovov + int64_t(i) * nv * onv + int64_t(k) * nv
+                                           : ovov + int64_t(j) * nv * onv + int64_t(k) * nv;
+    for (int y = wave; y < nv; y += 4) {
+      double tot = 0.0;
+      for (int c0 = 0; c0 < nv; c0 += 64) {
+        const int c = c0 + lane;
         double s = 0.0;
-        for (int64_t e = threadIdx.x; e < nv2; e += 256) {
-          const int u = int(e / nv), c = int(e - int64_t(u) * nv);
-          if (rr.kind == 1)
-            s += (double)H[(int64_t(u) * nv + y) * nv + c] *
-                 (double)gptr(ovov)[(int64_t(i) * nv + u) * onv + int64_t(k) * nv + c];
-          else
-            s += (double)H[(int64_t(y) * nv + u) * nv + c] *
-                 (double)gptr(ovov)[(int64_t(j) * nv + u) * onv + int64_t(k) * nv + c];
-        }
-        const double tot = block_sum_fixed256(s, red);
-        if (threadIdx.x == yy) mine += tot;
+        if (c < nv)
+          for (int u = 0; u < nv; ++u) {
+            const int64_t h = rr.kind == 1 ? (int64_t(u) * nv + y) * nv + c
+                                           : (int64_t(y) * nv + u) * nv + c;
+            s += (double)H[h] * (double)m[int64_t(u) * onv + c];
+          }
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        tot += s;
       }
+      if (lane == 0) out[y] = tot;
     }
   }
-  if (threadIdx.x < ny) {
-    SIE_GLOBAL double* p = gptr_w(fd.g_t1) + int64_t(gr.a0) * nv + y0 + threadIdx.x;
-    *p = *p + mine;
-  }
+}
+
+// dt1[p][y] += sum over the group's records in [b0, b1) (list order) of
+// part[(rec - b0) * pstride + y].  Grid: ceil(max n_v / 256) x groups.
+// Block: 256 threads.
+__global__ __launch_bounds__(256) void k_adj_t1_sum(const FragDesc* __restrict__ descs,
+                                                    const AdjGroup* __restrict__ groups, int b0,
+                                                    int b1, const double* __restrict__ part,
+                                                    int pstride) {
+  const AdjGroup gr = groups[blockIdx.y];
+  const FragDesc fd = descs[gr.frag];
+  const int y = blockIdx.x * 256 + threadIdx.x;
+  const int q0 = max(gr.rec_begin, b0), q1 = min(gr.rec_end, b1);
+  if (y >= fd.nv || q0 >= q1) return;
+  double s = 0.0;
+  for (int q = q0; q < q1; ++q) s += part[int64_t(q - b0) * pstride + y];
+  SIE_GLOBAL double* p = gptr_w(fd.g_t1) + int64_t(gr.a0) * fd.nv + y;
+  *p = *p + s;
 }
 
 // ---------------------------------------------------------------------------

@@ -279,39 +279,57 @@ __device__ __forceinline__ void build_wtile(const double* t2, const double* ovvv
 // Map a linear block index to a tile so that the blocks the hardware places
 // on one XCD (block index mod 8) cover a contiguous range of tiles and share
 // their operand rows in that XCD's L2.
+#ifndef SIE_XCD_MAP
+#define SIE_XCD_MAP 1
+#endif
 __device__ __forceinline__ int xcd_tile(int bid, int n) {
+  if (!SIE_XCD_MAP) return bid;
   constexpr int kXcd = 8;
   const int q = n / kXcd, r = n % kXcd;
   const int xcd = bid % kXcd, local = bid / kXcd;
   return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
-// Tile shapes of the float64 build: BLK blocks per wave (4 waves per
-// work-group), TR x TC 16-wide MFMA tiles per wave along rows x cols, and
-// the occupancy target BPC (work-groups per CU).  Variant 0 is the default;
-// a tile table (sie_set_tile_table) picks one per fragment by n_v.
+// Tile shapes of the float64 build: BLK blocks per wave, TR x TC 16-wide
+// MFMA tiles per wave along rows x cols, the occupancy target BPC
+// (work-groups per CU), and how the 4 waves of a work-group tile it: WR x WC
+// waves along rows x cols (then all waves share the BLK blocks), or, with
+// WR = WC = 1, 4 waves along the blocks (4 BLK blocks per work-group).  Waves
+// that share blocks share the per-block operand rows, which the work-group
+// then reads from L2 once for more output columns (or rows).  Variant 0 is
+// the default; a tile table (sie_set_tile_table) picks one per fragment by n_v.
 struct WShape {
-  int blk, tr, tc, bpc;
+  int blk, tr, tc, bpc, wr, wc;
 };
-constexpr int kWVariants = 6;
+constexpr int kWVariants = 9;
 __host__ __device__ inline WShape wshape(int v) {
   switch (v) {
-    case 1: return WShape{4, 2, 2, 1};
-    case 2: return WShape{2, 2, 2, 2};
-    case 3: return WShape{8, 1, 1, 2};
-    case 4: return WShape{4, 4, 2, 1};
-    case 5: return WShape{4, 2, 4, 1};
-    default: return WShape{4, 2, 2, 2};
+    case 1: return WShape{4, 2, 2, 1, 1, 1};
+    case 2: return WShape{2, 2, 2, 2, 1, 1};
+    case 3: return WShape{8, 1, 1, 2, 1, 1};
+    case 4: return WShape{4, 4, 2, 1, 1, 1};
+    case 5: return WShape{4, 2, 4, 1, 1, 1};
+    case 6: return WShape{4, 2, 2, 2, 2, 2};
+    case 7: return WShape{4, 2, 2, 2, 1, 4};
+    case 8: return WShape{4, 2, 2, 2, 4, 1};
+    default: return WShape{4, 2, 2, 2, 1, 1};
   }
 }
 
+// Work-group tile (blocks, rows, cols) of a shape.
+__host__ __device__ inline void wtile(const WShape& w, int& bb, int& er, int& ec) {
+  const bool grid = w.wr * w.wc > 1;
+  bb = grid ? w.blk : kWWaves * w.blk;
+  er = 16 * w.tr * (grid ? w.wr : 1);
+  ec = 16 * w.tc * (grid ? w.wc : 1);
+}
+
 // Build work-groups of one unit for a fragment of n_v virtuals: two layouts
-// x (4 BLK)-block x (16 TR)-row x (16 TC)-col tiles.
+// x the work-group tiles of the variant's shape.
 __host__ __device__ inline int64_t wbuild_tiles(int nv, int variant) {
-  const WShape w = wshape(variant);
-  const int64_t bb = int64_t(kWWaves) * w.blk;
-  return 2 * ((nv + bb - 1) / bb) * ((nv + 16 * w.tr - 1) / (16 * w.tr)) *
-         ((nv + 16 * w.tc - 1) / (16 * w.tc));
+  int bb, er, ec;
+  wtile(wshape(variant), bb, er, ec);
+  return 2 * int64_t((nv + bb - 1) / bb) * ((nv + er - 1) / er) * ((nv + ec - 1) / ec);
 }
 
 // Partial cube of one layout over one tile of one unit, written to the
@@ -319,12 +337,15 @@ __host__ __device__ inline int64_t wbuild_tiles(int nv, int variant) {
 // the concatenated build work-groups of the round's items (all of one tile
 // variant).  Block: 256 threads.  VEC (FragDesc::vec): n_v is even and the
 // t2 / ovvv bases are 16-byte aligned, so d-rows are read 16 bytes at a time.
-template <int BLK, int TR, int TC, int BPC>
+template <int BLK, int TR, int TC, int BPC, int WR = 1, int WC = 1>
 __global__ __launch_bounds__(256, BPC) void k_build_w_f64(const FragDesc* __restrict__ descs,
                                                           const Item* __restrict__ items,
                                                           int n_items,
                                                           double* __restrict__ arena) {
-  constexpr int BB = kWWaves * BLK, ER = 16 * TR, EC = 16 * TC;
+  constexpr bool GRID = WR * WC > 1;
+  static_assert(!GRID || WR * WC == kWWaves, "wave grid covers the work-group");
+  constexpr int BB = GRID ? BLK : kWWaves * BLK;
+  constexpr int ER = 16 * TR * (GRID ? WR : 1), EC = 16 * TC * (GRID ? WC : 1);
   const int ri = find_item<true>(items, n_items, blockIdx.x);
   const int64_t start = ri ? items[ri - 1].blk_end : 0;
   const Item it = items[ri];
@@ -343,10 +364,11 @@ __global__ __launch_bounds__(256, BPC) void k_build_w_f64(const FragDesc* __rest
   const int tr = t / nct, tc = t - tr * nct;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, g = lane >> 4;
-  const int blk0 = tb * BB + wave * BLK;
-  const int row0 = tr * ER, col0 = tc * EC;
-  if (blk0 >= nv) return;                       // no barrier follows: waves may leave
-  const int nrow = min(ER, nv - row0), ncol = min(EC, nv - col0);
+  const int blk0 = tb * BB + (GRID ? 0 : wave * BLK);
+  const int row0 = tr * ER + (GRID ? (wave % WR) * 16 * TR : 0);
+  const int col0 = tc * EC + (GRID ? (wave / WR) * 16 * TC : 0);
+  if (blk0 >= nv || row0 >= nv || col0 >= nv) return;   // no barrier follows: waves may leave
+  const int nrow = min(16 * TR, nv - row0), ncol = min(16 * TC, nv - col0);
   const int last = min(BLK, nv - blk0) - 1;
   const double* t2 = static_cast<const double*>(fd.t2);
   const double* ovvv = static_cast<const double*>(fd.ovvv);

@@ -91,21 +91,26 @@ struct Plan {
   int64_t total_units = 0, total_work = 0;
   int pstride = 0;
   size_t off_desc = 0, off_eps = 0, off_units = 0, off_part = 0, off_efrag = 0, off_items = 0;
-  size_t off_split = 0, off_adj = 0, off_arena = 0;
+  size_t off_split = 0, off_adj = 0, off_t1 = 0, off_arena = 0;
+  int nv_max = 1;            // largest n_vir (row stride of the t1 partials)
   size_t adj_recs = 0;       // bound on the adjoint records (= groups) of all rounds
   size_t fixed_bytes = 0;    // everything before the arena
-  size_t min_arena = 0;      // the largest cube pair of any fragment
-  size_t all_arena = 0;      // every unit's cube pair at once
+  int cubes = 2;             // cubes per unit in flight (backward: G, H and G transposed)
+  size_t min_arena = 0;      // the largest cube set of any fragment
+  size_t all_arena = 0;      // every unit's cube set at once
 };
 
 // Records per unit of the backward pass: 6 + 6 per-block terms, 6 + 6 summed
-// terms per block group of kABB virtuals, 3 + 3 H terms.
+// terms per block group of kARB virtuals, 3 + 3 H terms.
+constexpr int kT1Batch = 4096;    // t1 records per partial-sum batch (backward)
+
 size_t adj_recs_per_unit(int nv) {
-  return size_t(18) + size_t(12) * size_t((nv + sie::kABB - 1) / sie::kABB);
+  return size_t(18) + size_t(12) * size_t((nv + sie::kARB - 1) / sie::kARB);
 }
 
 Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad = false) {
   Plan p;
+  p.cubes = grad ? 3 : 2;
   p.split = prec == SIE_SPLIT_BF16;
   size_t eps_n = 0, split_bytes = 0;
   for (int x = 0; x < n; ++x) {
@@ -115,10 +120,11 @@ Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad =
     p.pstride = fp.n_part > p.pstride ? fp.n_part : p.pstride;
     eps_n += size_t(fp.no + fp.nv);
     split_bytes += fp.split_bytes;
-    const size_t pair = 2 * fp.half_bytes;
+    const size_t pair = size_t(grad ? 3 : 2) * fp.half_bytes;
     p.min_arena = fp.work_units > 0 && pair > p.min_arena ? pair : p.min_arena;
     p.all_arena += pair * size_t(fp.work_units);
     if (grad) p.adj_recs += size_t(fp.work_units) * adj_recs_per_unit(fp.nv);
+    p.nv_max = fp.nv > p.nv_max ? fp.nv : p.nv_max;
     p.frags.push_back(fp);
   }
   size_t off = 0;
@@ -138,6 +144,8 @@ Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad =
   off = align_up(off + split_bytes, 256);
   p.off_adj = off;
   off = align_up(off + (sizeof(sie::AdjRec) + sizeof(sie::AdjGroup)) * p.adj_recs + 256, 256);
+  p.off_t1 = off;
+  if (grad) off = align_up(off + sizeof(double) * size_t(kT1Batch) * size_t(p.nv_max), 256);
   p.off_arena = off;
   p.fixed_bytes = off;
   return p;
@@ -281,6 +289,8 @@ sie_status sie_tile_variant_shape(int32_t variant, int32_t* shape) {
   shape[1] = w.tr;
   shape[2] = w.tc;
   shape[3] = w.bpc;
+  shape[4] = w.wr;
+  shape[5] = w.wc;
   return SIE_OK;
 }
 
@@ -441,7 +451,7 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
     const size_t elem = pl.split ? sizeof(float) : sizeof(double);
     for (size_t r = 0; r < order.size(); ++r) {
       const FragPlan& fp = pl.frags[size_t(order[r].first)];
-      const size_t pair = 2 * fp.half_bytes;
+      const size_t pair = size_t(pl.cubes) * fp.half_bytes;
       if (r == 0 || used + pair > arena_bytes) {
         round_begin.push_back(r);
         used = 0;
@@ -512,6 +522,18 @@ void launch_build_f64(int variant, unsigned grid, hipStream_t s, const sie::Frag
     case 5:
       hipLaunchKernelGGL((sie::k_build_w_f64<4, 2, 4, 1>), dim3(grid), dim3(256), 0, s, desc,
                          items, n_items, arena);
+      break;
+    case 6:
+      hipLaunchKernelGGL((sie::k_build_w_f64<4, 2, 2, 2, 2, 2>), dim3(grid), dim3(256), 0, s,
+                         desc, items, n_items, arena);
+      break;
+    case 7:
+      hipLaunchKernelGGL((sie::k_build_w_f64<4, 2, 2, 2, 1, 4>), dim3(grid), dim3(256), 0, s,
+                         desc, items, n_items, arena);
+      break;
+    case 8:
+      hipLaunchKernelGGL((sie::k_build_w_f64<4, 2, 2, 2, 4, 1>), dim3(grid), dim3(256), 0, s,
+                         desc, items, n_items, arena);
       break;
     default:
       hipLaunchKernelGGL((sie::k_build_w_f64<4, 2, 2, 2>), dim3(grid), dim3(256), 0, s, desc,
@@ -669,6 +691,7 @@ struct AdjLaunch {
   size_t group_off = 0;   // first group in the uploaded group table
   int n_groups = 0;
   int64_t n_wg = 0;
+  int rec_begin = 0, rec_end = 0;   // the class's records in the uploaded record table
 };
 
 void adj_round_lists(const Tables& T, size_t r0, size_t r1, std::vector<sie::AdjGroup>& groups,
@@ -699,7 +722,7 @@ void adj_round_lists(const Tables& T, size_t r0, size_t r1, std::vector<sie::Adj
         while (sie::tri(j + 1) <= u) ++j;
         k = int(u - sie::tri(j));
       }
-      const int ng = sie::adj_reduce(cls) ? (d.nv + sie::kABB - 1) / sie::kABB : 1;
+      const int ng = sie::adj_reduce(cls) ? (d.nv + sie::kARB - 1) / sie::kARB : 1;
       for (int kind = 0; kind < sie::adj_kinds(cls); ++kind) {
         Key key{it.frag, 0, 0};
         sie::adj_slice(cls, kind, i, j, k, key.a0, key.a1);
@@ -713,6 +736,7 @@ void adj_round_lists(const Tables& T, size_t r0, size_t r1, std::vector<sie::Adj
                      [](const auto& a, const auto& b) { return a.first < b.first; });
     launch[cls].group_off = groups.size();
     launch[cls].n_groups = 0;
+    launch[cls].rec_begin = int(recs.size());
     int64_t wg = 0;
     for (size_t q = 0; q < list.size();) {
       size_t e = q;
@@ -734,6 +758,7 @@ void adj_round_lists(const Tables& T, size_t r0, size_t r1, std::vector<sie::Adj
       q = e;
     }
     launch[cls].n_wg = wg;
+    launch[cls].rec_end = int(recs.size());
   }
 }
 
@@ -742,7 +767,8 @@ template <typename CubeT, typename InT>
 void backward_round(const std::array<AdjLaunch, sie::kAdjClasses>& L, hipStream_t s,
                     const sie::FragDesc* d_desc, const sie::Item* ri, int cnt,
                     const sie::AdjGroup* d_groups, const sie::AdjRec* d_recs, CubeT* arena,
-                    double* d_part, int pstride, const double* grad_e, unsigned n_epi) {
+                    double* d_part, int pstride, const double* grad_e, unsigned n_epi,
+                    double* t1_part, int nv_max) {
   {
     ProfScope ps(s, 1);
     hipLaunchKernelGGL((sie::k_hat<CubeT, InT>), dim3(n_epi), dim3(256), 0, s, d_desc, ri, cnt,
@@ -765,10 +791,19 @@ void backward_round(const std::array<AdjLaunch, sie::kAdjClasses>& L, hipStream_
                        d_desc, ri, d_groups + lp.group_off, lp.n_groups, d_recs,
                        static_cast<const CubeT*>(arena));
   const AdjLaunch& l1 = L[sie::kAdjT1];
-  if (l1.n_wg)
-    hipLaunchKernelGGL((sie::k_adj_t1<CubeT, InT>), dim3(unsigned(l1.n_wg)), dim3(256), 0, s,
-                       d_desc, ri, d_groups + l1.group_off, l1.n_groups, d_recs,
-                       static_cast<const CubeT*>(arena));
+  if (l1.n_groups) {
+    const int r0 = l1.rec_begin, r1 = l1.rec_end;
+    for (int b0 = r0; b0 < r1; b0 += kT1Batch) {
+      const int b1 = b0 + kT1Batch < r1 ? b0 + kT1Batch : r1;
+      hipLaunchKernelGGL((sie::k_adj_t1_part<CubeT, InT>), dim3(unsigned(b1 - b0)), dim3(256), 0,
+                         s, d_desc, ri, d_recs, b0, static_cast<const CubeT*>(arena), t1_part,
+                         nv_max);
+      hipLaunchKernelGGL(sie::k_adj_t1_sum, dim3(unsigned((nv_max + 255) / 256),
+                                                 unsigned(l1.n_groups)),
+                         dim3(256), 0, s, d_desc, d_groups + l1.group_off, b0, b1, t1_part,
+                         nv_max);
+    }
+  }
 }
 
 sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const double* grad_e,
@@ -845,6 +880,7 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
   double* d_part = reinterpret_cast<double*>(dev(pl.off_part));
   double* d_efrag = e_frag_out ? e_frag_out : reinterpret_cast<double*>(dev(pl.off_efrag));
   double* arena = reinterpret_cast<double*>(dev(pl.off_arena));
+  double* t1_part = reinterpret_cast<double*>(dev(pl.off_t1));
 
   auto fill = [&](double* ptr, int64_t count) {
     if (!ptr || count <= 0) return;
@@ -887,11 +923,12 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
     if (pl.split)
       backward_round<float, float>(launches[q], s, d_desc, ri, cnt, d_groups, d_recs,
                                    reinterpret_cast<float*>(dev(pl.off_arena)), d_part,
-                                   pl.pstride, grad_e, unsigned(T.items[r1 - 1].part_end));
+                                   pl.pstride, grad_e, unsigned(T.items[r1 - 1].part_end),
+                                   t1_part, pl.nv_max);
     else
       backward_round<double, double>(launches[q], s, d_desc, ri, cnt, d_groups, d_recs, arena,
                                      d_part, pl.pstride, grad_e,
-                                     unsigned(T.items[r1 - 1].part_end));
+                                     unsigned(T.items[r1 - 1].part_end), t1_part, pl.nv_max);
     st = hip_check(hipGetLastError(), "launch backward kernels");
     if (st != SIE_OK) return st;
   }

@@ -165,7 +165,7 @@ def test_backward_workspace_and_errors(lib):
 def test_tile_table(lib):
     n = lib.sie_tile_variants()
     assert n >= 2
-    shape = (ctypes.c_int32 * 4)()
+    shape = (ctypes.c_int32 * 6)()
     for v in range(n):
         assert lib.sie_tile_variant_shape(v, shape) == _lib.SIE_OK
         assert all(x >= 1 for x in shape)
