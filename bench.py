@@ -55,11 +55,14 @@ def flops(o, v):
     return 2.0 * o ** 3 * v ** 4 + 2.0 * o ** 4 * v ** 3
 
 
-def build_work(o, v):
+def build_work(o, v, pair=True):
     """Flops of the W-tilde build actually launched for one fragment: every
-    occupied triple that is not i = j = k, 6 K = n_v and 6 K = n_o terms."""
+    occupied triple that is not i = j = k, two layouts of 3 K = n_v and 3
+    K = n_o terms each; a triple with exactly two equal indices (n_o (n_o - 1)
+    of them) builds one layout in the energy (`pair`), both in the gradient."""
     n_units = o * (o + 1) * (o + 2) // 6
-    return (n_units - o) * (12.0 * v ** 4 + 12.0 * o * v ** 3)
+    n_pair = o * (o - 1) if pair else 0
+    return (n_units - o - 0.5 * n_pair) * (12.0 * v ** 4 + 12.0 * o * v ** 3)
 
 
 def cpu_baseline(frag, a_values):
@@ -82,6 +85,43 @@ def cpu_baseline(frag, a_values):
             "sample": f"oracle.energy_literal_vectorized over the {n_tri} virtual triples "
                       f"with a in {list(a_values)} of the same {o}/{v} fragment ({dt:.1f} s)",
             "seconds": dt}
+
+
+def sources_sha256():
+    """Hash of the kernel sources (csrc/), against which a recorded counter
+    measurement is matched: any change to them voids the measurement."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2412_18553_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        h.update(name.encode())
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the FETCH_SIZE /
+    WRITE_SIZE counter passes recorded in profiles/*.md (a line
+    `<!-- traffic: {json} -->`), or None when none was taken with the current
+    kernel sources."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    want = sources_sha256()
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(pdir, name)) as fh:
+            for line in fh:
+                line = line.strip()
+                if not (line.startswith("<!-- traffic:") and line.endswith("-->")):
+                    continue
+                rec = json.loads(line[len("<!-- traffic:"):-len("-->")])
+                if (rec.get("kernel"), rec.get("workload"), rec.get("sources_sha256")) == \
+                        (kernel, workload, want):
+                    return rec
+    return None
 
 
 def log(msg):
@@ -120,12 +160,21 @@ def timed(step, steps, warmup):
     return start.elapsed_time(stop) / steps, prof
 
 
-def roofline(prof, cls, kernel, work_per_step, steps, peak, scale=1.0, bound="mfma"):
+def roofline(prof, cls, kernel, work_per_step, steps, peak, scale=1.0, bound="mfma",
+             workload=None):
     ms, n = prof[cls]
     achieved = scale * work_per_step * steps / (ms * 1e-3) / 1e12
-    return {"bound": bound, "kernel": kernel, "achieved": round(achieved, 3), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-            "launches": int(n), "avg_launch_ms": round(ms / max(n, 1), 4)}
+    out = {"bound": bound, "kernel": kernel, "achieved": round(achieved, 3), "peak": peak,
+           "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+           "launches": int(n), "avg_launch_ms": round(ms / max(n, 1), 4)}
+    rec = recorded_traffic(kernel, workload) if workload else None
+    if rec:
+        # HBM bytes per launch (counters, copy-calibrated) against the
+        # algorithmic bytes per launch
+        out.update(traffic=rec["bytes_per_launch"], traffic_unit="bytes/launch",
+                   algorithmic_bytes=rec["algorithmic_bytes_per_launch"],
+                   traffic_source=rec["profile"])
+    return out
 
 
 def main():
@@ -182,7 +231,7 @@ def main():
             result.update(value=round(F / (ms * 1e-3) / 1e12, 3), dtype="f64",
                           config={"workload": desc, "precision": "fp64", "fragments": 1})
             result["roofline"] = roofline(prof, "w_build", "k_build_w_f64", bw, args.steps,
-                                          PEAK_FP64_MFMA_TFLOPS)
+                                          PEAK_FP64_MFMA_TFLOPS, workload=name)
         elif mode == "split":
             result.update(value=round(F / (ms * 1e-3) / 1e12, 3), dtype="bf16x3/f32",
                           config={"workload": desc + " (float32 inputs)",
@@ -197,7 +246,8 @@ def main():
                           value=round(3.0 * F / (ms * 1e-3) / 1e12, 3), dtype="f64",
                           config={"workload": desc, "precision": "fp64", "fragments": 1,
                                   "outputs": "dE/d(t1, t2, ovvv, ooov, ovov)"})
-            result["roofline"] = roofline(prof, "grad", "k_adj_contract", 2.0 * bw, args.steps,
+            result["roofline"] = roofline(prof, "grad", "k_adj_contract",
+                                          2.0 * build_work(o, v, pair=False), args.steps,
                                           PEAK_FP64_MFMA_TFLOPS)
         result.update(ms_per_step=round(ms, 3), fragments_per_s=round(1000.0 / ms, 4),
                       energy=energy)

@@ -40,7 +40,7 @@ __host__ __device__ __forceinline__ int64_t tri(int64_t n) {     // n(n+1)/2
 
 // Linear index u of a sorted triple p >= q >= r (lexicographic in (p, q, r))
 // back to (p, q, r).  `bound` is an upper bound on p.
-__device__ __forceinline__ void decode_sorted_triple(int64_t u, int bound,
+__host__ __device__ __forceinline__ void decode_sorted_triple(int64_t u, int bound,
                                                      int& p, int& q, int& r) {
   int pp = 0;
   while (pp + 1 < bound && tetra(pp + 1) <= u) ++pp;
@@ -50,6 +50,25 @@ __device__ __forceinline__ void decode_sorted_triple(int64_t u, int bound,
   p = pp;
   q = qq;
   r = (int)(rem - tri(qq));
+}
+
+// Occupied triple (i, j, k) with which unit u (sorted p >= q >= r) is
+// evaluated.  With `pair` set, a unit p > q = r is evaluated as (q, q, p):
+// the unit energy sum_abc Wt R'[Wt + Vt] / D is unchanged by a simultaneous
+// permutation of the occupied and the virtual indices (Wt, Vt and D are
+// invariant under it and R' commutes with it), and with the two equal
+// indices first, Wt[a][b][c] = Wt[b][a][c], so the second layout's partial
+// cube equals the first's (P2[x][y][z] = P1[x][y][z]): only the first layout
+// is built.  Returns whether the unit is such a pair unit.
+__host__ __device__ __forceinline__ bool unit_triple(int64_t u, int bound, bool pair, int& i,
+                                                     int& j, int& k) {
+  decode_sorted_triple(u, bound, i, j, k);
+  if (!pair || i == k) return false;
+  if (j == k) {
+    k = i;
+    i = j;
+  }
+  return i == j;
 }
 
 }  // namespace sie

@@ -215,10 +215,10 @@ __device__ __forceinline__ void stage_load_s(const TermS& t, int c, const TileDi
   int x = u >> 2;
   x = x < xsmax ? x : xsmax;
   const SIE_GLOBAL u4v* p = gptr(t.sh + ((int64_t)x * t.sh_x + g0 + gq) * 2);
-  const uint32_t flip = t.neg ? 0x80008000u : 0u;
-  const u4v h = p[0] ^ flip, l = p[1] ^ flip;
-  st.shh = h;
-  st.shl = l;
+  // loaded values are left untouched until stage_store_s (after the chunk's
+  // MFMAs), so the loads stay in flight across them
+  st.shh = p[0];
+  st.shl = p[1];
 }
 
 // LDS: [group in chunk (4)][hi, lo][row] of u4v (8 bf16).
@@ -239,31 +239,43 @@ __device__ __forceinline__ void stage_store_s(const TermS& t, int tid, const Sta
   const int u = tid;
   if (u < Xs * 4) {
     const int gq = u & 3, x = u >> 2;
-    buf[gq][0][kShBase + x] = st.shh;
-    buf[gq][1][kShBase + x] = st.shl;
+    const uint32_t flip = t.neg ? 0x80008000u : 0u;   // sign of the occupied sums
+    buf[gq][0][kShBase + x] = st.shh ^ flip;
+    buf[gq][1][kShBase + x] = st.shl ^ flip;
   }
 }
 
 __device__ __forceinline__ void mma_chunk_s(bool a_is_bl, const u4v (*buf)[2][kLdsRows], int g,
                                             int rrow, int rcol, f4 (&acc)[kBB]) {
+  // the three products of each block in turn over all blocks: consecutive
+  // MFMAs never feed each other
+  u4v vh[kBB], vl[kBB];
   if (a_is_bl) {
     const u4v sh = buf[g][0][kShBase + rcol], sl = buf[g][1][kShBase + rcol];
 #pragma unroll
     for (int beta = 0; beta < kBB; ++beta) {
-      const u4v ah = buf[g][0][beta * kRows + rrow], al = buf[g][1][beta * kRows + rrow];
-      acc[beta] = mfma_bf16(al, sh, acc[beta]);
-      acc[beta] = mfma_bf16(ah, sl, acc[beta]);
-      acc[beta] = mfma_bf16(ah, sh, acc[beta]);
+      vh[beta] = buf[g][0][beta * kRows + rrow];
+      vl[beta] = buf[g][1][beta * kRows + rrow];
     }
+#pragma unroll
+    for (int beta = 0; beta < kBB; ++beta) acc[beta] = mfma_bf16(vl[beta], sh, acc[beta]);
+#pragma unroll
+    for (int beta = 0; beta < kBB; ++beta) acc[beta] = mfma_bf16(vh[beta], sl, acc[beta]);
+#pragma unroll
+    for (int beta = 0; beta < kBB; ++beta) acc[beta] = mfma_bf16(vh[beta], sh, acc[beta]);
   } else {
     const u4v sh = buf[g][0][kShBase + rrow], sl = buf[g][1][kShBase + rrow];
 #pragma unroll
     for (int beta = 0; beta < kBB; ++beta) {
-      const u4v bh = buf[g][0][beta * kCols + rcol], bl = buf[g][1][beta * kCols + rcol];
-      acc[beta] = mfma_bf16(sl, bh, acc[beta]);
-      acc[beta] = mfma_bf16(sh, bl, acc[beta]);
-      acc[beta] = mfma_bf16(sh, bh, acc[beta]);
+      vh[beta] = buf[g][0][beta * kCols + rcol];
+      vl[beta] = buf[g][1][beta * kCols + rcol];
     }
+#pragma unroll
+    for (int beta = 0; beta < kBB; ++beta) acc[beta] = mfma_bf16(sl, vh[beta], acc[beta]);
+#pragma unroll
+    for (int beta = 0; beta < kBB; ++beta) acc[beta] = mfma_bf16(sh, vl[beta], acc[beta]);
+#pragma unroll
+    for (int beta = 0; beta < kBB; ++beta) acc[beta] = mfma_bf16(sh, vh[beta], acc[beta]);
   }
 }
 
@@ -282,10 +294,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_build_w_bf16x3(const FragDesc* 
   const int ri = find_item<true>(items, n_items, blockIdx.x);
   const int64_t start = ri ? items[ri - 1].blk_end : 0;
   const FragDesc fd = descs[items[ri].frag];
-  const BlockWork w = block_work(fd, items, ri, int64_t(blockIdx.x) - start);
   int i, j, k;
-  decode_sorted_triple(w.it.unit, fd.no, i, j, k);
+  const bool one = unit_triple(items[ri].unit, fd.no, fd.pair, i, j, k);
   if (i == k) return;
+  const BlockWork w = block_work(fd, items, ri, int64_t(blockIdx.x) - start, one);
   const int nv = fd.nv;
   const bool l2 = w.l2;
   const int blk0 = w.blk0, row0 = w.row0, col0 = w.col0;

@@ -324,18 +324,18 @@ __host__ __device__ inline void wtile(const WShape& w, int& bb, int& er, int& ec
   ec = 16 * w.tc * (grid ? w.wc : 1);
 }
 
-// Build work-groups of one unit for a fragment of n_v virtuals: two layouts
-// x the work-group tiles of the variant's shape.
+// Build work-groups of one layout of one unit for a fragment of n_v
+// virtuals: the work-group tiles of the variant's shape over the cube.
 __host__ __device__ inline int64_t wbuild_tiles(int nv, int variant) {
   int bb, er, ec;
   wtile(wshape(variant), bb, er, ec);
-  return 2 * int64_t((nv + bb - 1) / bb) * ((nv + er - 1) / er) * ((nv + ec - 1) / ec);
+  return int64_t((nv + bb - 1) / bb) * ((nv + er - 1) / er) * ((nv + ec - 1) / ec);
 }
 
 // Partial cube of one layout over one tile of one unit, written to the
 // unit's first (L1) or second (L2) cube in (block, row, col) order.  Grid:
 // the concatenated build work-groups of the round's items (all of one tile
-// variant).  Block: 256 threads.  VEC (FragDesc::vec): n_v is even and the
+// variant): two layouts per unit, one for a pair unit (unit_triple).  Block: 256 threads.  VEC (FragDesc::vec): n_v is even and the
 // t2 / ovvv bases are 16-byte aligned, so d-rows are read 16 bytes at a time.
 template <int BLK, int TR, int TC, int BPC, int WR = 1, int WC = 1>
 __global__ __launch_bounds__(256, BPC) void k_build_w_f64(const FragDesc* __restrict__ descs,
@@ -351,12 +351,12 @@ __global__ __launch_bounds__(256, BPC) void k_build_w_f64(const FragDesc* __rest
   const Item it = items[ri];
   const FragDesc fd = descs[it.frag];
   int i, j, k;
-  decode_sorted_triple(it.unit, fd.no, i, j, k);
+  const bool one = unit_triple(it.unit, fd.no, fd.pair, i, j, k);
   if (i == k) return;
   const int nv = fd.nv;
   const int nbt = (nv + BB - 1) / BB, nrt = (nv + ER - 1) / ER, nct = (nv + EC - 1) / EC;
   const int per = nbt * nrt * nct;
-  int t = xcd_tile(int(int64_t(blockIdx.x) - start), 2 * per);
+  int t = xcd_tile(int(int64_t(blockIdx.x) - start), one ? per : 2 * per);
   const bool l2 = t >= per;
   if (l2) t -= per;
   const int tb = t / (nrt * nct);
@@ -449,12 +449,13 @@ struct BlockWork {
   int blk0, row0, col0;
 };
 
+// `one`: the item is a pair unit, which builds only the first layout.
 __device__ __forceinline__ BlockWork block_work(const FragDesc& fd, const Item* items, int r,
-                                                int64_t local) {
+                                                int64_t local, bool one) {
   BlockWork w;
   w.it = items[r];
   const int64_t T = fd.tiles;
-  int64_t t = xcd_tile(int(local), int(2 * T));
+  int64_t t = xcd_tile(int(local), int(one ? T : 2 * T));
   w.l2 = t >= T;
   if (w.l2) t -= T;
   const int nv = fd.nv;
@@ -508,8 +509,8 @@ __device__ __forceinline__ double block_sum_256(double v, double* red) {
 
 // Per-unit partial sums of Wt R'[Wt + Vt] / D over symmetric orbits of
 // 8 x 8 x 8 virtual blocks (A >= B >= C and their permuted images).
-// Wt[a][b][c] = cube1[a][b][c] (+ cube2[b][a][c] with TWO, the split build's
-// partial cubes), float64 or float32 cubes; V-tilde from t1 and ovov (float64
+// Wt[a][b][c] = cube1[a][b][c] (+ cube2[b][a][c] with TWO; cube2 is cube1
+// itself for a pair unit, see unit_triple), float64 or float32 cubes; V-tilde from t1 and ovov (float64
 // or float32 inputs), all arithmetic in float64.  Grid: the concatenated
 // epilogue blocks of the round's items (n_part per item; block p of an item
 // takes orbits p, p + n_part, ...).
@@ -524,7 +525,7 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
   const FragDesc fd = descs[it.frag];
   const int slot = int(int64_t(blockIdx.x) - start);
   int i, j, k;
-  decode_sorted_triple(it.unit, fd.no, i, j, k);
+  const bool one = unit_triple(it.unit, fd.no, fd.pair, i, j, k);
   __shared__ double sz[6][kOrbSlot];
   __shared__ double red[4];
   double* out = partials + (fd.unit_base + it.unit) * pstride + slot;
@@ -542,7 +543,7 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
   const double* __restrict__ ev = eps + no;
   const double eijk = gptr(eps)[i] + gptr(eps)[j] + gptr(eps)[k];
   const CubeT* __restrict__ w1 = arena + it.cube_off;
-  const CubeT* __restrict__ w2 = w1 + fd.half;
+  const CubeT* __restrict__ w2 = one ? w1 : w1 + fd.half;   // pair unit: P2 = P1
   const int64_t nonv = (int64_t)no * nv;
   const InT* ov_ij = ovov + (int64_t)i * nv * nonv + (int64_t)j * nv;   // (ia|jb) = ov_ij[a*nonv + b]
   const InT* ov_ik = ovov + (int64_t)i * nv * nonv + (int64_t)k * nv;

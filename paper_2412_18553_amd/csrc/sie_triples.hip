@@ -96,6 +96,7 @@ struct Plan {
   size_t adj_recs = 0;       // bound on the adjoint records (= groups) of all rounds
   size_t fixed_bytes = 0;    // everything before the arena
   int cubes = 2;             // cubes per unit in flight (backward: G, H and G transposed)
+  bool pair = false;         // pair units build one layout into one cube (energy only)
   size_t min_arena = 0;      // the largest cube set of any fragment
   size_t all_arena = 0;      // every unit's cube set at once
 };
@@ -111,6 +112,7 @@ size_t adj_recs_per_unit(int nv) {
 Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad = false) {
   Plan p;
   p.cubes = grad ? 3 : 2;
+  p.pair = !grad;
   p.split = prec == SIE_SPLIT_BF16;
   size_t eps_n = 0, split_bytes = 0;
   for (int x = 0; x < n; ++x) {
@@ -122,7 +124,9 @@ Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad =
     split_bytes += fp.split_bytes;
     const size_t pair = size_t(grad ? 3 : 2) * fp.half_bytes;
     p.min_arena = fp.work_units > 0 && pair > p.min_arena ? pair : p.min_arena;
-    p.all_arena += pair * size_t(fp.work_units);
+    // units with exactly two equal occupied indices: n_o (n_o - 1)
+    const size_t n_pair = p.pair ? size_t(fp.no) * size_t(fp.no - 1) : 0;
+    p.all_arena += pair * (size_t(fp.work_units) - n_pair) + fp.half_bytes * n_pair;
     if (grad) p.adj_recs += size_t(fp.work_units) * adj_recs_per_unit(fp.nv);
     p.nv_max = fp.nv > p.nv_max ? fp.nv : p.nv_max;
     p.frags.push_back(fp);
@@ -404,6 +408,7 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
     d.half = int64_t(fp.half_bytes / (pl.split ? sizeof(float) : sizeof(double)));
     // split: tiles per layout (two layouts); float64: work-groups per unit
     d.variant = pl.split ? 0 : tile_variant(fp.nv);
+    d.pair = pl.pair ? 1 : 0;
     d.tiles = pl.split ? sie::build_tiles(fp.nv) : sie::wbuild_tiles(fp.nv, d.variant);
     d.vS = d.tS = d.tT = d.oT = nullptr;
     d.g_t1 = grads ? grads[x].t1 : nullptr;
@@ -425,20 +430,32 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
     unit_base += fp.n_units;
   }
 
-  // units that are not i = j = k, longest first (stable within a fragment)
-  std::vector<std::pair<int, int>> order;   // (fragment, unit)
+  // units that are not i = j = k, longest first (stable within a fragment);
+  // a pair unit (sie::unit_triple) builds one layout and costs half
+  struct Unit {
+    int frag, unit;
+    bool one;
+    double cost;
+  };
+  std::vector<Unit> order;
   order.reserve(size_t(pl.total_work));
   for (int x = 0; x < n; ++x) {
-    const int no = pl.frags[size_t(x)].no;
+    const FragPlan& fp = pl.frags[size_t(x)];
     int u = 0;
-    for (int i = 0; i < no; ++i)
+    for (int i = 0; i < fp.no; ++i)
       for (int j = 0; j <= i; ++j)
         for (int k = 0; k <= j; ++k, ++u)
-          if (i != k) order.emplace_back(x, u);
+          if (i != k) {
+            const bool one = pl.pair && (i == j || j == k);
+            order.push_back({x, u, one, one ? 0.5 * fp.unit_cost : fp.unit_cost});
+          }
   }
-  std::stable_sort(order.begin(), order.end(), [&](const auto& a, const auto& b) {
-    return pl.frags[size_t(a.first)].unit_cost > pl.frags[size_t(b.first)].unit_cost;
-  });
+  std::stable_sort(order.begin(), order.end(),
+                   [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
+  auto layouts = [&](const sie::Item& it) {   // build layouts (and cubes) of an item
+    int i, j, k;
+    return sie::unit_triple(it.unit, pl.frags[size_t(it.frag)].no, pl.pair, i, j, k) ? 1 : 2;
+  };
 
   // rounds: consecutive items whose cube pairs fit in the arena
   std::vector<sie::Item>& items = T.items;
@@ -450,8 +467,8 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
     int64_t blk = 0, part = 0;
     const size_t elem = pl.split ? sizeof(float) : sizeof(double);
     for (size_t r = 0; r < order.size(); ++r) {
-      const FragPlan& fp = pl.frags[size_t(order[r].first)];
-      const size_t pair = size_t(pl.cubes) * fp.half_bytes;
+      const FragPlan& fp = pl.frags[size_t(order[r].frag)];
+      const size_t pair = size_t(order[r].one ? 1 : pl.cubes) * fp.half_bytes;
       if (r == 0 || used + pair > arena_bytes) {
         round_begin.push_back(r);
         used = 0;
@@ -459,11 +476,11 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
         part = 0;
       }
       sie::Item& it = items[r];
-      it.frag = order[r].first;
-      it.unit = order[r].second;
+      it.frag = order[r].frag;
+      it.unit = order[r].unit;
       it.cube_off = int64_t(used / elem);
       used += pair;
-      blk += (pl.split ? 2 : 1) * desc[size_t(it.frag)].tiles;
+      blk += layouts(it) * desc[size_t(it.frag)].tiles;
       part += fp.n_part;
       it.blk_end = blk;
       it.part_end = part;
@@ -491,7 +508,7 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
         seg0 = r;
         blk = 0;
       }
-      blk += (pl.split ? 2 : 1) * desc[size_t(it.frag)].tiles;
+      blk += layouts(it) * desc[size_t(it.frag)].tiles;
       part += pl.frags[size_t(it.frag)].n_part;
       it.blk_end = blk;
       it.part_end = part;

@@ -30,10 +30,12 @@ struct FragDesc {
   int Kv, Ko;             // padded contraction lengths of the split copies
   int vec;                // float64: rows may be read 16 bytes at a time
   int variant;            // float64: tile shape of the W-tilde build (see wshape)
+  int pair;               // 1: pair units (two equal occupied indices) build only the
+                          // first layout's cube (unit_triple); 0: both, as the adjoint needs
   int n_part;             // epilogue partial slots per unit
   int64_t unit_base;      // first entry of this fragment in the per-unit arrays
   int64_t half;           // elements per partial cube (aligned)
-  int64_t tiles;          // split: build tiles per layout; float64: build work-groups per unit
+  int64_t tiles;          // build work-groups of one layout of one unit
   // gradient outputs (float64, input shapes; backward only)
   double* g_t1;
   double* g_t2;
