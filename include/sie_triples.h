@@ -87,6 +87,10 @@ typedef struct {
 
 #define SIE_MAX_OCC 256
 #define SIE_MAX_VIR 2048
+/* Also s (n_occ^2 n_vir^2 + n_vir^3 + n_vir^2) < 2^32 with s the element size
+ * (8 for SIE_FP64, 4 for SIE_SPLIT_BF16): the kernels address each operand
+ * with 32-bit byte offsets (40 occupied and 400 virtuals fit in float64);
+ * larger fragments get SIE_ERR_UNSUPPORTED. */
 
 /* Gradient outputs of one fragment for sie_triples_backward: device float64
  * arrays with the shapes of the inputs of the same name, or NULL to skip that
@@ -197,9 +201,14 @@ sie_status sie_profile_collect(double* ms, int64_t* launches);
 
 /* Tile shapes of the float64 W-tilde build (autotuning).  The build kernel
  * is compiled for sie_tile_variants() tile shapes; sie_tile_variant_shape
- * writes variant v's shape into shape[6] (host): blocks per wave, 16-wide
- * MFMA row tiles and col tiles per wave, work-groups per CU targeted, and
- * the work-group's waves along rows and cols (1, 1: waves along blocks).  A
+ * writes variant v's shape into shape[7] (host): blocks per wave, 16-wide
+ * MFMA row tiles and col tiles per wave, work-groups per CU targeted, the
+ * work-group's waves along rows and cols (1, 1: waves along blocks), and the
+ * number of partial-cube layouts (2, or 3: the terms regrouped so that the
+ * per-block operand of every term lies on one MFMA side; the row and col
+ * tiles then count the per-block side and the shared side; the gradient
+ * always builds with a 2-layout shape, variant 0 in place of a 3-layout
+ * one).  A
  * fragment's variant is the first table entry whose bound is >= its n_vir
  * (variant 0 past the last).  sie_set_tile_table installs a table of n
  * entries (host arrays: strictly ascending bounds >= 1, valid variants) for

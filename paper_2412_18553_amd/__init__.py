@@ -268,11 +268,11 @@ def triples_energy(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, *, precision="fp6
 
 def tile_variants():
     """Tile shapes of the float64 build: [(blocks/wave, row tiles, col tiles, WGs/CU,
-    wave rows, wave cols)] (see sie_tile_variant_shape)."""
+    wave rows, wave cols, layouts)] (see sie_tile_variant_shape)."""
     lib = _lib.load()
     out = []
     for v in range(lib.sie_tile_variants()):
-        shape = (ctypes.c_int32 * 6)()
+        shape = (ctypes.c_int32 * 7)()
         _lib.check(lib.sie_tile_variant_shape(v, shape))
         out.append(tuple(shape))
     return out

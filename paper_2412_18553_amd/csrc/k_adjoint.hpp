@@ -334,27 +334,35 @@ struct AChunk {
   double b[BLK][kAT][2];
 };
 
-// The lane's k-pair (k, k+1) of one row; past nK in bounds and zero (the
-// A side carries no zeroing: B's zeros cancel it).  `vec`: unit stride and
-// 16-byte aligned pairs.
+// Element at byte offset `off` from a wave-uniform base (32-bit lane
+// offsets; the host limits operand extents to 4 GiB, see check_fragment).
 template <typename T>
-__device__ __forceinline__ void apair(const T* row, int64_t ks, int k, int nK, double s, bool vec,
-                                      double (&out)[2]) {
-  const SIE_GLOBAL T* g = gptr(row);
+__device__ __forceinline__ T aload(const void* base, uint32_t off) {
+  return *(const SIE_GLOBAL T*)(gptr(reinterpret_cast<const char*>(base)) + off);
+}
+
+// The lane's k-pair (k, k+1) of one row (byte offset `row` from `base`, K
+// stride ks elements); past nK in bounds and zero (the A side carries no
+// zeroing: B's zeros cancel it).  `vec`: unit stride and 16-byte aligned pairs.
+template <typename T>
+__device__ __forceinline__ void apair(const T* base, uint32_t row, int64_t ks, int k, int nK,
+                                      double s, bool vec, double (&out)[2]) {
   if (vec && k + 1 < nK) {
+    const uint32_t o = row + uint32_t(k) * uint32_t(sizeof(T));
     if (sizeof(T) == 8) {
-      const d2v v = *(const SIE_GLOBAL d2v*)(g + k);
+      const d2v v = aload<d2v>(base, o);
       out[0] = s * v.x;
       out[1] = s * v.y;
     } else {
-      out[0] = s * (double)g[k];
-      out[1] = s * (double)g[k + 1];
+      out[0] = s * (double)aload<T>(base, o);
+      out[1] = s * (double)aload<T>(base, o + uint32_t(sizeof(T)));
     }
   } else {
-    const int k0 = k < nK ? k : nK - 1;
-    const int k1 = k + 1 < nK ? k + 1 : nK - 1;
-    out[0] = (k < nK ? s : 0.0) * (double)g[(int64_t)k0 * ks];
-    out[1] = (k + 1 < nK ? s : 0.0) * (double)g[(int64_t)k1 * ks];
+    const uint32_t kb = uint32_t(ks * int64_t(sizeof(T)));
+    const uint32_t k0 = uint32_t(k < nK ? k : nK - 1);
+    const uint32_t k1 = uint32_t(k + 1 < nK ? k + 1 : nK - 1);
+    out[0] = (k < nK ? s : 0.0) * (double)aload<T>(base, row + k0 * kb);
+    out[1] = (k + 1 < nK ? s : 0.0) * (double)aload<T>(base, row + k1 * kb);
   }
 }
 
@@ -367,26 +375,26 @@ __device__ __forceinline__ void adj_load(const ATerm<CubeT, InT>& t, bool reduce
   const bool va = vec && t.a_k == 1, vb = vec && t.b_k == 1;
 #pragma unroll
   for (int rt = 0; rt < kAT; ++rt) {
-    const int xr = min(rbase + 16 * rt + r, nrow - 1);
+    const uint32_t xr =
+        uint32_t(min(rbase + 16 * rt + r, nrow - 1) * t.a_x * int64_t(sizeof(CubeT)));
 #pragma unroll
     for (int beta = 0; beta < BLK; ++beta) {
       const bool ok = beta < nblk;
-      const int bb = ok ? beta : 0;
-      apair(t.a + bb * t.a_b + xr * t.a_x, t.a_k, k, nK, (reduce && !ok) ? 0.0 : 1.0, va,
+      apair(t.a + (ok ? beta : 0) * t.a_b, xr, t.a_k, k, nK, (reduce && !ok) ? 0.0 : 1.0, va,
             x.a[beta][rt]);
     }
   }
 #pragma unroll
   for (int ct = 0; ct < kAT; ++ct) {
-    const int xc = min(cbase + 16 * ct + r, ncol - 1);
+    const uint32_t xc =
+        uint32_t(min(cbase + 16 * ct + r, ncol - 1) * t.b_x * int64_t(sizeof(InT)));
     if (reduce) {
 #pragma unroll
-      for (int beta = 0; beta < BLK; ++beta) {
-        const int bb = beta < nblk ? beta : 0;
-        apair(t.b + bb * t.b_b + xc * t.b_x, t.b_k, k, nK, t.scale, vb, x.b[beta][ct]);
-      }
+      for (int beta = 0; beta < BLK; ++beta)
+        apair(t.b + (beta < nblk ? beta : 0) * t.b_b, xc, t.b_k, k, nK, t.scale, vb,
+              x.b[beta][ct]);
     } else {
-      apair(t.b + xc * t.b_x, t.b_k, k, nK, t.scale, vb, x.b[0][ct]);
+      apair(t.b, xc, t.b_k, k, nK, t.scale, vb, x.b[0][ct]);
     }
   }
 }
@@ -492,7 +500,8 @@ __global__ __launch_bounds__(kAThreads, 2) void k_adj_contract(
   t -= tb * nrt * nct;
   const int trow = t / nct, tcol = t - trow * nct;
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int r = lane & 15, g = lane >> 4;
   // this wave's part of the tile
   constexpr int BLK = kReduce ? kARB : kABlk;

@@ -146,12 +146,15 @@ struct WChunk {
   double sh[NS][2];           // [tile][k of the pair]
 };
 
-// Lane pointers of one term: per-block rows (block 0) and shared rows of the
-// lane's tiles, clamped into the valid range.
+// Lane offsets of one term, in bytes from the term's (wave-uniform) operand
+// bases: per-block rows (block 0) and shared rows of the lane's tiles,
+// clamped into the valid range.  Uniform 64-bit bases plus 32-bit lane
+// offsets keep the address registers of a chunk to one per row set (the
+// host limits operand extents to 4 GiB, see check_fragment).
 template <int NB, int NS>
 struct WLane {
-  const double* bl[NB];
-  const double* sh[NS];
+  uint32_t bl[NB];
+  uint32_t sh[NS];
 };
 
 template <bool A_IS_BL, int NB, int NS>
@@ -160,10 +163,15 @@ __device__ __forceinline__ WLane<NB, NS> wlane(const WTerm& t, int r, int nrow, 
   const int nb = A_IS_BL ? nrow : ncol;   // valid extent of the per-block side
   const int ns = A_IS_BL ? ncol : nrow;
 #pragma unroll
-  for (int q = 0; q < NB; ++q) p.bl[q] = t.bl + min(16 * q + r, nb - 1) * t.bl_x;
+  for (int q = 0; q < NB; ++q) p.bl[q] = uint32_t(min(16 * q + r, nb - 1) * t.bl_x * 8);
 #pragma unroll
-  for (int q = 0; q < NS; ++q) p.sh[q] = t.sh + min(16 * q + r, ns - 1) * t.sh_x;
+  for (int q = 0; q < NS; ++q) p.sh[q] = uint32_t(min(16 * q + r, ns - 1) * t.sh_x * 8);
   return p;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_off(const double* base, uint32_t off) {
+  return *(const SIE_GLOBAL T*)(gptr(reinterpret_cast<const char*>(base)) + off);
 }
 
 // Chunk c of a term; blocks past `last` read block `last`.
@@ -173,42 +181,46 @@ __device__ __forceinline__ void load_wchunk(const WTerm& t, const WLane<NB, NS>&
   const int k0 = kWChunk * c + 2 * g;
   if (VEC && kWChunk * c + kWChunk <= t.nK) {
     // K contiguous, 16-byte aligned rows of even length
+    const uint32_t kb = uint32_t(k0) * 8u;
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
-      const d2v s0 = *(const SIE_GLOBAL d2v*)(gptr(p.sh[q]) + k0);
+      const d2v s0 = ld_off<d2v>(t.sh, p.sh[q] + kb);
       x.sh[q][0] = s0.x;
       x.sh[q][1] = s0.y;
     }
 #pragma unroll
-    for (int q = 0; q < NB; ++q)
+    for (int beta = 0; beta < BLK; ++beta) {
+      const double* b = t.bl + (int64_t)(beta < last ? beta : last) * t.bl_b;
 #pragma unroll
-      for (int beta = 0; beta < BLK; ++beta) {
-        const d2v u = *(const SIE_GLOBAL d2v*)(gptr(p.bl[q]) +
-                                                 (int64_t)(beta < last ? beta : last) * t.bl_b + k0);
+      for (int q = 0; q < NB; ++q) {
+        const d2v u = ld_off<d2v>(b, p.bl[q] + kb);
         x.bl[beta][q][0] = u.x;
         x.bl[beta][q][1] = u.y;
       }
+    }
   } else {
-    int kc[2];
+    uint32_t ks[2], kbl[2];
     double m[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int k = k0 + s;
-      kc[s] = k < t.nK ? k : t.nK - 1;
+      const uint32_t kc = uint32_t(k < t.nK ? k : t.nK - 1);
+      ks[s] = kc * uint32_t(t.sh_k * 8);
+      kbl[s] = kc * uint32_t(t.bl_k * 8);
       m[s] = k < t.nK ? t.scale : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < NS; ++q)
 #pragma unroll
-      for (int s = 0; s < 2; ++s) x.sh[q][s] = m[s] * gptr(p.sh[q])[(int64_t)kc[s] * t.sh_k];
+      for (int s = 0; s < 2; ++s) x.sh[q][s] = m[s] * ld_off<double>(t.sh, p.sh[q] + ks[s]);
 #pragma unroll
-    for (int q = 0; q < NB; ++q)
+    for (int beta = 0; beta < BLK; ++beta) {
+      const double* b = t.bl + (int64_t)(beta < last ? beta : last) * t.bl_b;
 #pragma unroll
-      for (int beta = 0; beta < BLK; ++beta) {
-        const SIE_GLOBAL double* b = gptr(p.bl[q]) + (int64_t)(beta < last ? beta : last) * t.bl_b;
+      for (int q = 0; q < NB; ++q)
 #pragma unroll
-        for (int s = 0; s < 2; ++s) x.bl[beta][q][s] = b[(int64_t)kc[s] * t.bl_k];
-      }
+        for (int s = 0; s < 2; ++s) x.bl[beta][q][s] = ld_off<double>(b, p.bl[q] + kbl[s]);
+    }
   }
 }
 
@@ -235,15 +247,11 @@ __device__ __forceinline__ void mma_wchunk(
 
 // One term: two chunks in flight (loads of chunk c + 1 issued before the
 // MFMAs of chunk c); loads past the end are clamped, masked and unused.
-template <bool L2, int Q, bool VEC, int BLK, int TR, int TC>
-__device__ __forceinline__ void run_wterm(const double* t2, const double* ovvv,
-                                          const double* ooov, int i, int j, int k, int no, int nv,
-                                          int blk0, int row0, int col0, int nrow, int ncol,
-                                          int last, int r, int g, d4 (&acc)[BLK][TR][TC]) {
-  constexpr bool A = wterm_a_is_bl<L2, Q>();
-  constexpr bool V = VEC && Q < 3;
+// A: the per-block operand is on the MFMA A side (rows); V: 16-byte loads.
+template <bool A, bool V, int BLK, int TR, int TC>
+__device__ __forceinline__ void run_term(const WTerm& t, int nrow, int ncol, int last, int r,
+                                         int g, d4 (&acc)[BLK][TR][TC]) {
   constexpr int NB = A ? TR : TC, NS = A ? TC : TR;
-  const WTerm t = make_wterm<L2, Q>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0);
   const WLane<NB, NS> p = wlane<A, NB, NS>(t, r, nrow, ncol);
   const int nch = (t.nK + kWChunk - 1) / kWChunk;
   WChunk<BLK, NB, NS> b0, b1;
@@ -256,6 +264,16 @@ __device__ __forceinline__ void run_wterm(const double* t2, const double* ovvv,
     mma_wchunk<A, BLK, TR, TC>(b1, nrow, ncol, acc);
     if (c + 2 >= nch) break;
   }
+}
+
+template <bool L2, int Q, bool VEC, int BLK, int TR, int TC>
+__device__ __forceinline__ void run_wterm(const double* t2, const double* ovvv,
+                                          const double* ooov, int i, int j, int k, int no, int nv,
+                                          int blk0, int row0, int col0, int nrow, int ncol,
+                                          int last, int r, int g, d4 (&acc)[BLK][TR][TC]) {
+  run_term<wterm_a_is_bl<L2, Q>(), VEC && Q < 3, BLK, TR, TC>(
+      make_wterm<L2, Q>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0), nrow, ncol, last, r,
+      g, acc);
 }
 
 template <bool L2, bool VEC, int BLK, int TR, int TC>
@@ -274,6 +292,119 @@ __device__ __forceinline__ void build_wtile(const double* t2, const double* ovvv
   SIE_WTERM(4);
   SIE_WTERM(5);
 #undef SIE_WTERM
+}
+
+// ---------------------------------------------------------------------------
+// Three-layout float64 build.  The twelve terms are regrouped by which MFMA
+// side their per-block operand sits on, so that a work-group can span the
+// whole shared side and read each per-block row once:
+//   layout A, cube [a][b][c]: block a, per-block rows b, shared cols c
+//     (X^abc_ijk and X^bac_jik d-sums, X^cba_kji and X^cab_kij l-sums);
+//   layout B, cube [a][b][c]: block a, shared rows b, per-block cols c
+//     (the first layout's other four terms);
+//   layout C, cube [b][a][c]: block b, shared rows a, per-block cols c
+//     (the second layout's other four terms);
+// Wt[a][b][c] = A[a][b][c] + B[a][b][c] + C[b][a][c].  For a pair unit
+// (i = j, see unit_triple) C equals B as an array, so only A and B are built.
+// ---------------------------------------------------------------------------
+
+// Layout-A terms of the second layout re-blocked on a: X^bac_jik d-sum
+// ovvv[j][b][a][d] t2[k][i][c][d] and X^cab_kij l-sum
+// -sum_l t2[l][j][a][b] ooov[i][l][k][c]; block a, rows b, cols c.
+template <int Q>
+__device__ __forceinline__ WTerm make_wterm_a(const double* __restrict__ t2,
+                                              const double* __restrict__ ovvv,
+                                              const double* __restrict__ ooov, int i, int j,
+                                              int k, int no_, int nv_, int blk0, int row0,
+                                              int col0) {
+  const int64_t nv = nv_, no = no_, nv2 = nv * nv, nonv = no * nv;
+  WTerm t;
+  t.nK = nv_;
+  t.scale = 1.0;
+  if (Q == 0) {
+    t.bl = ovvv + ((j * nv + row0) * nv + blk0) * nv; t.bl_b = nv; t.bl_x = nv2; t.bl_k = 1;
+    t.sh = t2 + ((k * no + i) * nv + col0) * nv; t.sh_x = nv; t.sh_k = 1;
+  } else {
+    t.bl = t2 + (j * nv + blk0) * nv + row0; t.bl_b = nv; t.bl_x = 1; t.bl_k = nonv * nv;
+    t.sh = ooov + (i * no * no + k) * nv + col0; t.sh_x = 1; t.sh_k = nonv; t.scale = -1.0;
+    t.nK = no_;
+  }
+  return t;
+}
+
+// All terms of layout LAY into acc: layout A (LAY 0) has the per-block
+// operand on the rows (acc[BLK][P][S]); B and C (LAY 1, 2) on the cols
+// (acc[BLK][S][P]).
+template <int LAY, bool VEC, int BLK, int TR, int TC>
+__device__ __forceinline__ void build_wtile3(const double* t2, const double* ovvv,
+                                             const double* ooov, int i, int j, int k, int no,
+                                             int nv, int blk0, int row0, int col0, int nrow,
+                                             int ncol, int last, int r, int g,
+                                             d4 (&acc)[BLK][TR][TC]) {
+  if (LAY == 0) {
+    run_wterm<false, 0, VEC, BLK, TR, TC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0,
+                                          nrow, ncol, last, r, g, acc);
+    run_term<true, VEC, BLK, TR, TC>(
+        make_wterm_a<0>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0), nrow, ncol, last, r,
+        g, acc);
+    run_wterm<false, 4, VEC, BLK, TR, TC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0,
+                                          nrow, ncol, last, r, g, acc);
+    run_term<true, false, BLK, TR, TC>(
+        make_wterm_a<1>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0), nrow, ncol, last, r,
+        g, acc);
+  } else {
+    constexpr bool L2 = LAY == 2;
+#define SIE_WTERM(Q) \
+  run_wterm<L2, Q, VEC, BLK, TR, TC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, nrow, \
+                                     ncol, last, r, g, acc)
+    if (L2) {
+      SIE_WTERM(0);
+      SIE_WTERM(1);
+      SIE_WTERM(3);
+      SIE_WTERM(4);
+    } else {
+      SIE_WTERM(1);
+      SIE_WTERM(2);
+      SIE_WTERM(3);
+      SIE_WTERM(5);
+    }
+#undef SIE_WTERM
+  }
+}
+
+// Store a wave's accumulators into a cube [block][row][col] of n_v^3: element
+// v of lane (g, r) in acc[beta][rt][ct] holds
+// P[blk0 + beta][row0 + 16 rt + 4 v + g][col0 + 16 ct + r].
+template <int BLK, int TR, int TC>
+__device__ __forceinline__ void store_wtile(double* __restrict__ out, int nv, int blk0, int row0,
+                                            int col0, int r, int g,
+                                            const d4 (&acc)[BLK][TR][TC]) {
+#pragma unroll
+  for (int beta = 0; beta < BLK; ++beta) {
+    const int blk = blk0 + beta;
+#pragma unroll
+    for (int rt = 0; rt < TR; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < TC; ++ct) {
+        const int col = col0 + 16 * ct + r;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = row0 + 16 * rt + 4 * v + g;
+          if (blk < nv && row < nv && col < nv)
+            gptr_w(out)[((int64_t)blk * nv + row) * nv + col] = acc[beta][rt][ct][v];
+        }
+      }
+  }
+}
+
+template <int BLK, int TR, int TC>
+__device__ __forceinline__ void zero_acc(d4 (&acc)[BLK][TR][TC]) {
+#pragma unroll
+  for (int b = 0; b < BLK; ++b)
+#pragma unroll
+    for (int p = 0; p < TR; ++p)
+#pragma unroll
+      for (int q = 0; q < TC; ++q) acc[b][p][q] = d4{0.0, 0.0, 0.0, 0.0};
 }
 
 // Map a linear block index to a tile so that the blocks the hardware places
@@ -296,23 +427,33 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
 // waves along rows x cols (then all waves share the BLK blocks), or, with
 // WR = WC = 1, 4 waves along the blocks (4 BLK blocks per work-group).  Waves
 // that share blocks share the per-block operand rows, which the work-group
-// then reads from L2 once for more output columns (or rows).  Variant 0 is
-// the default; a tile table (sie_set_tile_table) picks one per fragment by n_v.
+// then reads from L2 once for more output columns (or rows).  Shapes with
+// lay = 3 use the three-layout build (k_build_w3_f64), TR and TC then
+// counting tiles of the per-block and of the shared side.  Variant 0 is the
+// default; a tile table (sie_set_tile_table) picks one per fragment by n_v.
 struct WShape {
   int blk, tr, tc, bpc, wr, wc;
+  int lay;     // 2: two-layout build (k_build_w_f64); 3: k_build_w3_f64 with tr = P
+               // (per-block side tiles) and tc = S (shared side tiles)
 };
-constexpr int kWVariants = 9;
+constexpr int kWVariants = 15;
 __host__ __device__ inline WShape wshape(int v) {
   switch (v) {
-    case 1: return WShape{4, 2, 2, 1, 1, 1};
-    case 2: return WShape{2, 2, 2, 2, 1, 1};
-    case 3: return WShape{8, 1, 1, 2, 1, 1};
-    case 4: return WShape{4, 4, 2, 1, 1, 1};
-    case 5: return WShape{4, 2, 4, 1, 1, 1};
-    case 6: return WShape{4, 2, 2, 2, 2, 2};
-    case 7: return WShape{4, 2, 2, 2, 1, 4};
-    case 8: return WShape{4, 2, 2, 2, 4, 1};
-    default: return WShape{4, 2, 2, 2, 1, 1};
+    case 1: return WShape{4, 2, 2, 1, 1, 1, 2};
+    case 2: return WShape{2, 2, 2, 2, 1, 1, 2};
+    case 3: return WShape{8, 1, 1, 2, 1, 1, 2};
+    case 4: return WShape{4, 4, 2, 1, 1, 1, 2};
+    case 5: return WShape{4, 2, 4, 1, 1, 1, 2};
+    case 6: return WShape{4, 2, 2, 2, 2, 2, 2};
+    case 7: return WShape{4, 2, 2, 2, 1, 4, 2};
+    case 8: return WShape{4, 2, 2, 2, 4, 1, 2};
+    case 9: return WShape{1, 1, 13, 2, 1, 1, 3};
+    case 10: return WShape{1, 2, 7, 2, 1, 1, 3};
+    case 11: return WShape{2, 1, 7, 2, 1, 1, 3};
+    case 12: return WShape{1, 1, 10, 2, 1, 1, 3};
+    case 13: return WShape{1, 2, 10, 1, 1, 1, 3};
+    case 14: return WShape{1, 2, 4, 2, 1, 1, 3};
+    default: return WShape{4, 2, 2, 2, 1, 1, 2};
   }
 }
 
@@ -362,7 +503,8 @@ __global__ __launch_bounds__(256, BPC) void k_build_w_f64(const FragDesc* __rest
   const int tb = t / (nrt * nct);
   t -= tb * nrt * nct;
   const int tr = t / nct, tc = t - tr * nct;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int r = lane & 15, g = lane >> 4;
   const int blk0 = tb * BB + (GRID ? 0 : wave * BLK);
   const int row0 = tr * ER + (GRID ? (wave % WR) * 16 * TR : 0);
@@ -375,12 +517,7 @@ __global__ __launch_bounds__(256, BPC) void k_build_w_f64(const FragDesc* __rest
   const double* ooov = static_cast<const double*>(fd.ooov);
 
   d4 acc[BLK][TR][TC];
-#pragma unroll
-  for (int b = 0; b < BLK; ++b)
-#pragma unroll
-    for (int p = 0; p < TR; ++p)
-#pragma unroll
-      for (int q = 0; q < TC; ++q) acc[b][p][q] = d4{0.0, 0.0, 0.0, 0.0};
+  zero_acc(acc);
 
 #define SIE_WTILE(L, V) \
   build_wtile<L, V, BLK, TR, TC>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, row0, col0, nrow, \
@@ -394,24 +531,73 @@ __global__ __launch_bounds__(256, BPC) void k_build_w_f64(const FragDesc* __rest
   }
 #undef SIE_WTILE
 
-  // element v of lane (g, r) in acc[beta][rt][ct] holds
-  // P[blk0 + beta][row0 + 16 rt + 4 v + g][col0 + 16 ct + r]
-  double* __restrict__ out = arena + it.cube_off + (l2 ? fd.half : 0);
-#pragma unroll
-  for (int beta = 0; beta < BLK; ++beta) {
-    const int blk = blk0 + beta;
-#pragma unroll
-    for (int rt = 0; rt < TR; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < TC; ++ct) {
-        const int col = col0 + 16 * ct + r;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = row0 + 16 * rt + 4 * v + g;
-          if (blk < nv && row < nv && col < nv)
-            gptr_w(out)[((int64_t)blk * nv + row) * nv + col] = acc[beta][rt][ct][v];
-        }
-      }
+  store_wtile(arena + it.cube_off + (l2 ? fd.half : 0), nv, blk0, row0, col0, r, g, acc);
+}
+
+// Three-layout build (build_wtile3): partial cubes A, B, C of one tile of
+// one unit.  A work-group is 4 waves along the blocks (4 BLK blocks) x 16 P
+// rows or cols of the per-block side x 16 S of the shared side, so with
+// 16 S >= n_v it spans the shared side and each per-block operand row is
+// read by one work-group only.  Grid: the concatenated work-groups of the
+// round's items, three layouts per unit, two (A, B) for a pair unit.
+template <int BLK, int P, int S, int BPC>
+__global__ __launch_bounds__(256, BPC) void k_build_w3_f64(const FragDesc* __restrict__ descs,
+                                                           const Item* __restrict__ items,
+                                                           int n_items,
+                                                           double* __restrict__ arena) {
+  constexpr int BB = kWWaves * BLK, EP = 16 * P, ES = 16 * S;
+  const int ri = find_item<true>(items, n_items, blockIdx.x);
+  const int64_t start = ri ? items[ri - 1].blk_end : 0;
+  const Item it = items[ri];
+  const FragDesc fd = descs[it.frag];
+  int i, j, k;
+  const bool one = unit_triple(it.unit, fd.no, fd.pair, i, j, k);
+  if (i == k) return;
+  const int nv = fd.nv;
+  const int nbt = (nv + BB - 1) / BB, npt = (nv + EP - 1) / EP, nst = (nv + ES - 1) / ES;
+  const int per = nbt * npt * nst;
+  int t = xcd_tile(int(int64_t(blockIdx.x) - start), (one ? 2 : 3) * per);
+  const int lay = t / per;
+  t -= lay * per;
+  const int tb = t / (npt * nst);
+  t -= tb * npt * nst;
+  const int tp = t / nst, ts = t - tp * nst;   // work-groups sharing per-block rows are adjacent
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  const int r = lane & 15, g = lane >> 4;
+  const int blk0 = tb * BB + wave * BLK;
+  if (blk0 >= nv) return;   // no barrier follows: waves may leave
+  const int p0 = tp * EP, s0 = ts * ES;
+  const int np = min(EP, nv - p0), ns = min(ES, nv - s0);
+  const int last = min(BLK, nv - blk0) - 1;
+  const double* t2 = static_cast<const double*>(fd.t2);
+  const double* ovvv = static_cast<const double*>(fd.ovvv);
+  const double* ooov = static_cast<const double*>(fd.ooov);
+  double* __restrict__ out = arena + it.cube_off + lay * fd.half;
+  if (lay == 0) {   // per-block rows, shared cols
+    d4 acc[BLK][P][S];
+    zero_acc(acc);
+    if (fd.vec)
+      build_wtile3<0, true>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, p0, s0, np, ns, last, r, g,
+                            acc);
+    else
+      build_wtile3<0, false>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, p0, s0, np, ns, last, r,
+                             g, acc);
+    store_wtile(out, nv, blk0, p0, s0, r, g, acc);
+  } else {          // shared rows, per-block cols
+    d4 acc[BLK][S][P];
+    zero_acc(acc);
+#define SIE_W3(L, V) \
+  build_wtile3<L, V>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, s0, p0, ns, np, last, r, g, acc)
+    if (lay == 1) {
+      if (fd.vec) SIE_W3(1, true);
+      else SIE_W3(1, false);
+    } else {
+      if (fd.vec) SIE_W3(2, true);
+      else SIE_W3(2, false);
+    }
+#undef SIE_W3
+    store_wtile(out, nv, blk0, s0, p0, r, g, acc);
   }
 }
 
@@ -509,12 +695,13 @@ __device__ __forceinline__ double block_sum_256(double v, double* red) {
 
 // Per-unit partial sums of Wt R'[Wt + Vt] / D over symmetric orbits of
 // 8 x 8 x 8 virtual blocks (A >= B >= C and their permuted images).
-// Wt[a][b][c] = cube1[a][b][c] (+ cube2[b][a][c] with TWO; cube2 is cube1
-// itself for a pair unit, see unit_triple), float64 or float32 cubes; V-tilde from t1 and ovov (float64
-// or float32 inputs), all arithmetic in float64.  Grid: the concatenated
+// Wt[a][b][c] = P1[a][b][c] + P2[b][a][c] from the two-layout builds, or
+// A[a][b][c] + B[a][b][c] + C[b][a][c] from the three-layout build
+// (FragDesc::lay3), float64 or float32 cubes; V-tilde from t1 and ovov
+// (float64 or float32 inputs), all arithmetic in float64.  Grid: the concatenated
 // epilogue blocks of the round's items (n_part per item; block p of an item
 // takes orbits p, p + n_part, ...).
-template <typename CubeT, typename InT, bool TWO>
+template <typename CubeT, typename InT>
 __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ descs,
                                                   const Item* __restrict__ items, int n_items,
                                                   const CubeT* __restrict__ arena,
@@ -542,8 +729,12 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
   const int64_t n_orb = tetra(nb);
   const double* __restrict__ ev = eps + no;
   const double eijk = gptr(eps)[i] + gptr(eps)[j] + gptr(eps)[k];
+  // Wt = w1[a][b][c] (+ w2[a][b][c], three layouts) + w3[b][a][c]; a pair unit
+  // has P2 = P1 (two layouts) or C = B (three layouts)
+  const bool l3 = fd.lay3;
   const CubeT* __restrict__ w1 = arena + it.cube_off;
-  const CubeT* __restrict__ w2 = one ? w1 : w1 + fd.half;   // pair unit: P2 = P1
+  const CubeT* __restrict__ w2 = w1 + fd.half;
+  const CubeT* __restrict__ w3 = l3 ? (one ? w2 : w2 + fd.half) : (one ? w1 : w2);
   const int64_t nonv = (int64_t)no * nv;
   const InT* ov_ij = ovov + (int64_t)i * nv * nonv + (int64_t)j * nv;   // (ia|jb) = ov_ij[a*nonv + b]
   const InT* ov_ik = ovov + (int64_t)i * nv * nonv + (int64_t)k * nv;
@@ -571,8 +762,10 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
       const int c = kOrb * pick3(p2, t0, t1b, t2b) + (e & 7);
       double w = 0.0, z = 0.0;
       if (a < nv && b < nv && c < nv) {
-        w = (double)gptr(w1)[((int64_t)a * nv + b) * nv + c];
-        if (TWO) w += (double)gptr(w2)[((int64_t)b * nv + a) * nv + c];
+        const int64_t abc = ((int64_t)a * nv + b) * nv + c;
+        w = (double)gptr(w1)[abc];
+        if (l3) w += (double)gptr(w2)[abc];
+        w += (double)gptr(w3)[((int64_t)b * nv + a) * nv + c];
         const double vt = (double)gptr(ov_ij)[(int64_t)a * nonv + b] * (double)gptr(t1k)[c] +
                           (double)gptr(ov_ik)[(int64_t)a * nonv + c] * (double)gptr(t1j)[b] +
                           (double)gptr(ov_jk)[(int64_t)b * nonv + c] * (double)gptr(t1i)[a];

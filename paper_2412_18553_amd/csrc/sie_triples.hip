@@ -56,6 +56,10 @@ struct FragPlan {
   size_t split_bytes = 0;    // vS + tS + tT + oT
   size_t half_bytes = 0;     // one partial cube (aligned)
   double unit_cost = 0.0;    // flops per unit (ordering key)
+  int variant = 0;           // float64 build tile shape (sie::wshape)
+  bool lay3 = false;         // three-layout build (float64 energy only)
+  int cubes = 2;             // partial cubes of a unit in flight
+  int cubes_pair = 1;        // ... of a pair unit (sie::unit_triple)
 };
 
 FragPlan frag_plan(int no, int nv, bool split) {
@@ -109,6 +113,8 @@ size_t adj_recs_per_unit(int nv) {
   return size_t(18) + size_t(12) * size_t((nv + sie::kARB - 1) / sie::kARB);
 }
 
+int tile_variant(int nv);
+
 Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad = false) {
   Plan p;
   p.cubes = grad ? 3 : 2;
@@ -117,16 +123,26 @@ Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad =
   size_t eps_n = 0, split_bytes = 0;
   for (int x = 0; x < n; ++x) {
     FragPlan fp = frag_plan(frags[x].n_occ, frags[x].n_vir, p.split);
+    // the adjoint rebuilds W-tilde with a two-layout shape (its G and H
+    // cubes follow that layout); the energy takes the table's shape
+    if (!p.split) {
+      fp.variant = tile_variant(fp.nv);
+      if (grad && sie::wshape(fp.variant).lay == 3) fp.variant = 0;
+      fp.lay3 = sie::wshape(fp.variant).lay == 3;
+    }
+    fp.cubes = grad ? 3 : fp.lay3 ? 3 : 2;
+    fp.cubes_pair = grad ? 3 : fp.lay3 ? 2 : 1;
     p.total_units += fp.n_units;
     p.total_work += fp.work_units;
     p.pstride = fp.n_part > p.pstride ? fp.n_part : p.pstride;
     eps_n += size_t(fp.no + fp.nv);
     split_bytes += fp.split_bytes;
-    const size_t pair = size_t(grad ? 3 : 2) * fp.half_bytes;
+    const size_t pair = size_t(fp.cubes) * fp.half_bytes;
     p.min_arena = fp.work_units > 0 && pair > p.min_arena ? pair : p.min_arena;
     // units with exactly two equal occupied indices: n_o (n_o - 1)
     const size_t n_pair = p.pair ? size_t(fp.no) * size_t(fp.no - 1) : 0;
-    p.all_arena += pair * (size_t(fp.work_units) - n_pair) + fp.half_bytes * n_pair;
+    p.all_arena += pair * (size_t(fp.work_units) - n_pair) +
+                   size_t(fp.cubes_pair) * fp.half_bytes * n_pair;
     if (grad) p.adj_recs += size_t(fp.work_units) * adj_recs_per_unit(fp.nv);
     p.nv_max = fp.nv > p.nv_max ? fp.nv : p.nv_max;
     p.frags.push_back(fp);
@@ -190,6 +206,13 @@ sie_status check_fragment(const sie_fragment* f, sie_precision prec, const char*
                 w + ": max(eps_occ) >= min(eps_vir): a triples denominator would not be negative");
   if (f->frag_proj)
     return fail(SIE_ERR_UNSUPPORTED, w + ": fragment projector C^f is not supported by this build");
+  // the float64 build and the gradient contractions address each operand
+  // with 32-bit byte offsets from a per-term base: the largest extent is an
+  // l-sum's t2 pair block plus a row
+  const double o = f->n_occ, v = f->n_vir;
+  if (double(esz) * (o * o * v * v + v * v * v + v * v) >= 4294967296.0)
+    return fail(SIE_ERR_UNSUPPORTED,
+                w + ": (element size) x (n_occ^2 n_vir^2 + n_vir^3 + n_vir^2) must be below 2^32");
   return SIE_OK;
 }
 
@@ -295,6 +318,7 @@ sie_status sie_tile_variant_shape(int32_t variant, int32_t* shape) {
   shape[3] = w.bpc;
   shape[4] = w.wr;
   shape[5] = w.wc;
+  shape[6] = w.lay;
   return SIE_OK;
 }
 
@@ -407,8 +431,9 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
     d.unit_base = unit_base;
     d.half = int64_t(fp.half_bytes / (pl.split ? sizeof(float) : sizeof(double)));
     // split: tiles per layout (two layouts); float64: work-groups per unit
-    d.variant = pl.split ? 0 : tile_variant(fp.nv);
+    d.variant = fp.variant;
     d.pair = pl.pair ? 1 : 0;
+    d.lay3 = fp.lay3 ? 1 : 0;
     d.tiles = pl.split ? sie::build_tiles(fp.nv) : sie::wbuild_tiles(fp.nv, d.variant);
     d.vS = d.tS = d.tT = d.oT = nullptr;
     d.g_t1 = grads ? grads[x].t1 : nullptr;
@@ -447,14 +472,16 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
         for (int k = 0; k <= j; ++k, ++u)
           if (i != k) {
             const bool one = pl.pair && (i == j || j == k);
-            order.push_back({x, u, one, one ? 0.5 * fp.unit_cost : fp.unit_cost});
+            order.push_back({x, u, one, one ? (fp.lay3 ? 2.0 / 3.0 : 0.5) * fp.unit_cost : fp.unit_cost});
           }
   }
   std::stable_sort(order.begin(), order.end(),
                    [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
-  auto layouts = [&](const sie::Item& it) {   // build layouts (and cubes) of an item
+  auto layouts = [&](const sie::Item& it) {   // build layouts of an item
     int i, j, k;
-    return sie::unit_triple(it.unit, pl.frags[size_t(it.frag)].no, pl.pair, i, j, k) ? 1 : 2;
+    const FragPlan& fp = pl.frags[size_t(it.frag)];
+    const bool one = sie::unit_triple(it.unit, fp.no, pl.pair, i, j, k);
+    return (fp.lay3 ? 3 : 2) - (one ? 1 : 0);
   };
 
   // rounds: consecutive items whose cube pairs fit in the arena
@@ -468,7 +495,7 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
     const size_t elem = pl.split ? sizeof(float) : sizeof(double);
     for (size_t r = 0; r < order.size(); ++r) {
       const FragPlan& fp = pl.frags[size_t(order[r].frag)];
-      const size_t pair = size_t(order[r].one ? 1 : pl.cubes) * fp.half_bytes;
+      const size_t pair = size_t(order[r].one ? fp.cubes_pair : fp.cubes) * fp.half_bytes;
       if (r == 0 || used + pair > arena_bytes) {
         round_begin.push_back(r);
         used = 0;
@@ -551,6 +578,30 @@ void launch_build_f64(int variant, unsigned grid, hipStream_t s, const sie::Frag
     case 8:
       hipLaunchKernelGGL((sie::k_build_w_f64<4, 2, 2, 2, 4, 1>), dim3(grid), dim3(256), 0, s,
                          desc, items, n_items, arena);
+      break;
+    case 9:
+      hipLaunchKernelGGL((sie::k_build_w3_f64<1, 1, 13, 2>), dim3(grid), dim3(256), 0, s, desc,
+                         items, n_items, arena);
+      break;
+    case 10:
+      hipLaunchKernelGGL((sie::k_build_w3_f64<1, 2, 7, 2>), dim3(grid), dim3(256), 0, s, desc,
+                         items, n_items, arena);
+      break;
+    case 11:
+      hipLaunchKernelGGL((sie::k_build_w3_f64<2, 1, 7, 2>), dim3(grid), dim3(256), 0, s, desc,
+                         items, n_items, arena);
+      break;
+    case 12:
+      hipLaunchKernelGGL((sie::k_build_w3_f64<1, 1, 10, 2>), dim3(grid), dim3(256), 0, s, desc,
+                         items, n_items, arena);
+      break;
+    case 13:
+      hipLaunchKernelGGL((sie::k_build_w3_f64<1, 2, 10, 1>), dim3(grid), dim3(256), 0, s, desc,
+                         items, n_items, arena);
+      break;
+    case 14:
+      hipLaunchKernelGGL((sie::k_build_w3_f64<1, 2, 4, 2>), dim3(grid), dim3(256), 0, s, desc,
+                         items, n_items, arena);
       break;
     default:
       hipLaunchKernelGGL((sie::k_build_w_f64<4, 2, 2, 2>), dim3(grid), dim3(256), 0, s, desc,
@@ -666,7 +717,7 @@ sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag
       }
       {
         ProfScope ps(s, 1);
-        hipLaunchKernelGGL((sie::k_epilogue<double, double, true>), dim3(n_epi), dim3(256), 0, s,
+        hipLaunchKernelGGL((sie::k_epilogue<double, double>), dim3(n_epi), dim3(256), 0, s,
                            d_desc, ri, cnt, arena, d_part, pl.pstride);
       }
     } else {
@@ -678,7 +729,7 @@ sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag
       }
       {
         ProfScope ps(s, 1);
-        hipLaunchKernelGGL((sie::k_epilogue<float, float, true>), dim3(n_epi), dim3(256), 0, s, d_desc,
+        hipLaunchKernelGGL((sie::k_epilogue<float, float>), dim3(n_epi), dim3(256), 0, s, d_desc,
                            ri, cnt, arena, d_part, pl.pstride);
       }
     }

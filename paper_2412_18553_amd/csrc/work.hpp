@@ -32,6 +32,8 @@ struct FragDesc {
   int variant;            // float64: tile shape of the W-tilde build (see wshape)
   int pair;               // 1: pair units (two equal occupied indices) build only the
                           // first layout's cube (unit_triple); 0: both, as the adjoint needs
+  int lay3;               // float64 energy: three-layout build (k_build_w3_f64), three
+                          // partial cubes per unit (two for a pair unit)
   int n_part;             // epilogue partial slots per unit
   int64_t unit_base;      // first entry of this fragment in the per-unit arrays
   int64_t half;           // elements per partial cube (aligned)

@@ -78,6 +78,7 @@ def test_valid_workspace_query(lib):
     (dict(eps_occ=[-1.0, 0.5], eps_vir=[0.4, 1.0], o=2, v=2), _lib.SIE_ERR_INVALID_ARG),
     (dict(eps_occ=[-1.0, float("nan")], o=2), _lib.SIE_ERR_INVALID_ARG),
     (dict(frag_proj=FAKE), _lib.SIE_ERR_UNSUPPORTED),
+    (dict(o=100, v=700), _lib.SIE_ERR_UNSUPPORTED),             # float64 extent > 2^32 bytes
 ])
 def test_argument_errors(lib, kw, code):
     keep = []
@@ -165,10 +166,11 @@ def test_backward_workspace_and_errors(lib):
 def test_tile_table(lib):
     n = lib.sie_tile_variants()
     assert n >= 2
-    shape = (ctypes.c_int32 * 6)()
+    shape = (ctypes.c_int32 * 7)()
     for v in range(n):
         assert lib.sie_tile_variant_shape(v, shape) == _lib.SIE_OK
         assert all(x >= 1 for x in shape)
+        assert shape[6] in (2, 3)
     assert lib.sie_tile_variant_shape(n, shape) == _lib.SIE_ERR_INVALID_ARG
     arr = lambda *x: (ctypes.c_int32 * len(x))(*x)  # noqa: E731
     assert lib.sie_set_tile_table(2, arr(100, 400), arr(1, 0)) == _lib.SIE_OK

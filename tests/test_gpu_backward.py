@@ -64,6 +64,24 @@ def test_gradient_vs_oracle(o, v, aux, seed):
         assert err <= RTOL, (n, err)
 
 
+def test_gradient_with_three_layout_table():
+    """A tile table that selects a three-layout build shape for the energy:
+    the gradient rebuilds W-tilde with a two-layout shape and is unchanged."""
+    import paper_2412_18553_amd as sie
+    three = [v for v, s in enumerate(sie.tile_variants()) if s[6] == 3]
+    assert three
+    f = make_fragment(4, 20, 30, (11, 12))
+    _, _, _, ref = energy_gradient(*f.arrays())
+    try:
+        sie.set_tile_table([(2048, three[0])])
+        got = gpu_grad(f)
+    finally:
+        sie.set_tile_table(None)
+    for n in NAMES:
+        scale = max(np.abs(ref[n]).max(), 1e-300)
+        assert np.abs(got[n] - ref[n]).max() <= RTOL * scale, n
+
+
 def test_one_occupied_gradient_is_zero():
     f = make_fragment(1, 12, 20, (11, 9))
     got = gpu_grad(f)

@@ -119,11 +119,17 @@ def test_every_tile_variant(o, v, aux, seed):
     import paper_2412_18553_amd as sie
     f = make_fragment(o, v, aux, (7, seed))
     e_ref = T.energy_literal_vectorized(*f.arrays())
+    tri0 = None
     try:
         for variant in range(len(sie.tile_variants())):
             print(f"case o={o} v={v} variant={variant}", flush=True)
             sie.set_tile_table([(2048, variant)])
             e_gpu, tri = run_gpu(f)
             assert abs(e_gpu - e_ref) <= RTOL * abs(e_ref), (variant, e_gpu, e_ref)
+            # per-unit energies agree between shapes (an error in one layout's
+            # terms could cancel in the total only by accident)
+            tri0 = tri if tri0 is None else tri0
+            scale = np.max(np.abs(tri0))
+            assert np.max(np.abs(tri - tri0)) <= RTOL * scale, variant
     finally:
         sie.set_tile_table(None)
