@@ -55,14 +55,23 @@ def flops(o, v):
     return 2.0 * o ** 3 * v ** 4 + 2.0 * o ** 4 * v ** 3
 
 
-def build_work(o, v, pair=True):
+def build_work(o, v, pair=True, lay3=False):
     """Flops of the W-tilde build actually launched for one fragment: every
-    occupied triple that is not i = j = k, two layouts of 3 K = n_v and 3
-    K = n_o terms each; a triple with exactly two equal indices (n_o (n_o - 1)
-    of them) builds one layout in the energy (`pair`), both in the gradient."""
+    occupied triple that is not i = j = k, 12 terms (6 with K = n_v, 6 with
+    K = n_o) in two layouts of six or three layouts of four (`lay3`); a triple
+    with exactly two equal indices (n_o (n_o - 1) of them) builds one of two
+    layouts or two of three in the energy (`pair`), all of them in the gradient."""
     n_units = o * (o + 1) * (o + 2) // 6
     n_pair = o * (o - 1) if pair else 0
-    return (n_units - o - 0.5 * n_pair) * (12.0 * v ** 4 + 12.0 * o * v ** 3)
+    saved = (1.0 / 3.0 if lay3 else 0.5) * n_pair
+    return (n_units - o - saved) * (12.0 * v ** 4 + 12.0 * o * v ** 3)
+
+
+def lay3_of(v):
+    """Whether the float64 energy of a fragment with v virtuals uses the
+    three-layout build under the installed tile table."""
+    import paper_2412_18553_amd as sie
+    return sie.tile_variants()[sie.tile_variant_of(v)][6] == 3
 
 
 def cpu_baseline(frag, a_values):
@@ -230,8 +239,11 @@ def main():
         if mode == "fp64":
             result.update(value=round(F / (ms * 1e-3) / 1e12, 3), dtype="f64",
                           config={"workload": desc, "precision": "fp64", "fragments": 1})
-            result["roofline"] = roofline(prof, "w_build", "k_build_w_f64", bw, args.steps,
-                                          PEAK_FP64_MFMA_TFLOPS, workload=name)
+            l3 = lay3_of(v)
+            kernel = "k_build_w3_f64" if l3 else "k_build_w_f64"
+            result["roofline"] = roofline(prof, "w_build", kernel, build_work(o, v, lay3=l3),
+                                          args.steps, PEAK_FP64_MFMA_TFLOPS, workload=name)
+            result["roofline"]["tile_variant"] = sie.tile_variant_of(v)
         elif mode == "split":
             result.update(value=round(F / (ms * 1e-3) / 1e12, 3), dtype="bf16x3/f32",
                           config={"workload": desc + " (float32 inputs)",
@@ -265,7 +277,7 @@ def main():
         step = lambda: sie.energy_batched(frs, workspace=ws, out=e_frag, total=e_tot)  # noqa: E731
         ms, prof = timed(step, args.steps, args.warmup)
         F = sum(flops(o, v) for (o, v, _, _) in shapes)
-        bw = sum(build_work(o, v) for (o, v, _, _) in shapes)
+        bw = sum(build_work(o, v, lay3=(prec == "fp64" and lay3_of(v))) for (o, v, _, _) in shapes)
         result.update(value=round(F / (ms * 1e-3) / 1e12, 3),
                       dtype="f64" if prec == "fp64" else "bf16x3/f32",
                       config={"workload": f"{name}: {len(frs)} fragments, n_occ "
@@ -273,9 +285,9 @@ def main():
                               "precision": prec, "fragments": len(frs)},
                       ms_per_step=round(ms, 3), fragments_per_s=round(len(frs) * 1000.0 / ms, 4),
                       energy=float(e_tot.item()))
-        if prec == "fp64":
-            result["roofline"] = roofline(prof, "w_build", "k_build_w_f64", bw, args.steps,
-                                          PEAK_FP64_MFMA_TFLOPS)
+        if prec == "fp64":   # the batch mixes the build shapes its fragment sizes select
+            result["roofline"] = roofline(prof, "w_build", "k_build_w_f64 / k_build_w3_f64", bw,
+                                          args.steps, PEAK_FP64_MFMA_TFLOPS)
         else:
             result["roofline"] = roofline(prof, "w_build", "k_build_w_bf16x3", bw, args.steps,
                                           PEAK_BF16_MFMA_TFLOPS, scale=3.0)

@@ -201,14 +201,14 @@ sie_status sie_profile_collect(double* ms, int64_t* launches);
 
 /* Tile shapes of the float64 W-tilde build (autotuning).  The build kernel
  * is compiled for sie_tile_variants() tile shapes; sie_tile_variant_shape
- * writes variant v's shape into shape[7] (host): blocks per wave, 16-wide
+ * writes variant v's shape into shape[8] (host): blocks per wave, 16-wide
  * MFMA row tiles and col tiles per wave, work-groups per CU targeted, the
  * work-group's waves along rows and cols (1, 1: waves along blocks), and the
  * number of partial-cube layouts (2, or 3: the terms regrouped so that the
  * per-block operand of every term lies on one MFMA side; the row and col
  * tiles then count the per-block side and the shared side; the gradient
  * always builds with a 2-layout shape, variant 0 in place of a 3-layout
- * one).  A
+ * one), and the k-steps per K-chunk (2: chunks of 8; 4: chunks of 16).  A
  * fragment's variant is the first table entry whose bound is >= its n_vir
  * (variant 0 past the last).  sie_set_tile_table installs a table of n
  * entries (host arrays: strictly ascending bounds >= 1, valid variants) for
@@ -217,6 +217,9 @@ sie_status sie_profile_collect(double* ms, int64_t* launches);
  * called while another thread runs an evaluation. */
 int32_t sie_tile_variants(void);
 sie_status sie_tile_variant_shape(int32_t variant, int32_t* shape);
+/* The variant the float64 energy of a fragment with n_vir virtuals builds
+ * with under the installed table, or -1 for n_vir < 1. */
+int32_t sie_tile_variant_of(int32_t n_vir);
 sie_status sie_set_tile_table(int32_t n, const int32_t* nv_max, const int32_t* variant);
 
 const char* sie_last_error(void);

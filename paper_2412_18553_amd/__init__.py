@@ -268,14 +268,20 @@ def triples_energy(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, *, precision="fp6
 
 def tile_variants():
     """Tile shapes of the float64 build: [(blocks/wave, row tiles, col tiles, WGs/CU,
-    wave rows, wave cols, layouts)] (see sie_tile_variant_shape)."""
+    wave rows, wave cols, layouts, k-steps per chunk)] (see sie_tile_variant_shape)."""
     lib = _lib.load()
     out = []
     for v in range(lib.sie_tile_variants()):
-        shape = (ctypes.c_int32 * 7)()
+        shape = (ctypes.c_int32 * 8)()
         _lib.check(lib.sie_tile_variant_shape(v, shape))
         out.append(tuple(shape))
     return out
+
+
+def tile_variant_of(n_vir: int) -> int:
+    """The tile variant the float64 energy of a fragment with n_vir virtuals
+    builds with under the installed table."""
+    return int(_lib.load().sie_tile_variant_of(int(n_vir)))
 
 
 def set_tile_table(table=None) -> None:

@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "SIE_OK", 1: "SIE_ERR_INVALID_ARG", 2: "SIE_ERR_UNSUPPORTED",
 EXPORTED = ["sie_abi_version", "sie_last_error", "sie_occupied_triples",
             "sie_triples_workspace_size", "sie_triples_energy", "sie_triples_energy_batched",
             "sie_triples_backward_workspace_size", "sie_triples_backward",
-            "sie_tile_variants", "sie_tile_variant_shape", "sie_set_tile_table",
+            "sie_tile_variants", "sie_tile_variant_shape", "sie_tile_variant_of",
+            "sie_set_tile_table",
             "sie_profile_enable", "sie_profile_collect"]
 PROF_CLASSES = ("w_build", "epilogue", "reduce", "split", "grad")
 
@@ -100,6 +101,8 @@ def load() -> ctypes.CDLL:
     lib.sie_tile_variants.argtypes = []
     lib.sie_tile_variant_shape.restype = ctypes.c_int
     lib.sie_tile_variant_shape.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.sie_tile_variant_of.restype = ctypes.c_int32
+    lib.sie_tile_variant_of.argtypes = [ctypes.c_int32]
     lib.sie_set_tile_table.restype = ctypes.c_int
     lib.sie_set_tile_table.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32)]

@@ -31,6 +31,17 @@ __device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// 1 / d for a normal float64 d: the hardware reciprocal estimate refined by
+// two Newton-Raphson steps r <- r + r (1 - d r) (each squares the relative
+// error), within an ulp or two of the rounded quotient, at a fraction of the
+// cost of an IEEE division.
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
+  r = __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
+  return r;
+}
+
 __host__ __device__ __forceinline__ int64_t tetra(int64_t n) {   // n(n+1)(n+2)/6
   return n * (n + 1) * (n + 2) / 6;
 }

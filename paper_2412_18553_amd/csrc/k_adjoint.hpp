@@ -141,11 +141,11 @@ __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
                         2.0 * (sz[s_cba][e_cba] + sz[s_acb][e_acb] + sz[s_bac][e_bac]);
       const double rw = 4.0 * sw[s][e_abc] + sw[s_cab][e_cab] + sw[s_bca][e_bca] -
                         2.0 * (sw[s_cba][e_cba] + sw[s_acb][e_acb] + sw[s_bac][e_bac]);
-      const double d = eijk - gptr(ev)[a] - gptr(ev)[b] - gptr(ev)[c];
-      acc += sw[s][e_abc] * rz / d;
+      const double id = recip(eijk - gptr(ev)[a] - gptr(ev)[b] - gptr(ev)[c]);   // 1 / D
+      acc += sw[s][e_abc] * rz * id;
       const int64_t pos = ((int64_t)a * nv + b) * nv + c;
-      gptr_w(w1)[pos] = CubeT(scale * (rw + rz) / d);
-      gptr_w(w2)[pos] = CubeT(scale * rw / d);
+      gptr_w(w1)[pos] = CubeT(scale * (rw + rz) * id);
+      gptr_w(w2)[pos] = CubeT(scale * rw * id);
       // G at (c, b, a), stored at this thread's (a, b, c) of the transposed
       // cube (contiguous across the wave); R' at (c, b, a) combines the same
       // six permuted values with the roles of (abc, cba), (cab, acb) and
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
                           2.0 * (sz[s][e_abc] + sz[s_cab][e_cab] + sz[s_bca][e_bca]);
       const double rw_t = 4.0 * sw[s_cba][e_cba] + sw[s_acb][e_acb] + sw[s_bac][e_bac] -
                           2.0 * (sw[s][e_abc] + sw[s_cab][e_cab] + sw[s_bca][e_bca]);
-      gptr_w(w3)[pos] = CubeT(scale * (rw_t + rz_t) / d);
+      gptr_w(w3)[pos] = CubeT(scale * (rw_t + rz_t) * id);
     }
     __syncthreads();
   }

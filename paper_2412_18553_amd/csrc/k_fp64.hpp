@@ -55,7 +55,6 @@ constexpr int kOrb = 8;       // virtual block edge of the epilogue orbits
 // read as ooov[j][l][i][a] and t_ij^ab as t2[i][j][a][b] or its twin.
 // ---------------------------------------------------------------------------
 constexpr int kWWaves = 4;               // waves per work-group
-constexpr int kWChunk = 8;               // K chunk (a k-pair per lane group)
 
 // Element (beta, x, k) of the per-block operand is bl[beta*bl_b + x*bl_x + k*bl_k];
 // element (x, k) of the shared operand is scale * sh[x*sh_x + k*sh_k]; x is
@@ -139,11 +138,15 @@ __device__ __forceinline__ constexpr bool wterm_a_is_bl() {
 }
 
 // Registers of one K-chunk: the per-block operand for BLK blocks x NB tiles
-// of its MFMA side, the shared operand for NS tiles of the other side.
-template <int BLK, int NB, int NS>
+// of its MFMA side, the shared operand for NS tiles of the other side.  A
+// chunk is 4 KS values of K; lane group g holds k = 4 KS c + KS g + s for
+// s < KS (any bijection between lanes and k serves, as long as both operands
+// use the same one).
+template <int BLK, int NB, int NS, int KS>
 struct WChunk {
-  double bl[BLK][NB][2];      // [block][tile][k of the pair]
-  double sh[NS][2];           // [tile][k of the pair]
+  double bl[BLK][NB][KS];     // [block][tile][s]
+  double sh[NS][KS];          // [tile][s], as loaded
+  double m[KS];               // shared-operand factor per s: the term's scale, 0 past K
 };
 
 // Lane offsets of one term, in bytes from the term's (wave-uniform) operand
@@ -174,64 +177,83 @@ __device__ __forceinline__ T ld_off(const double* base, uint32_t off) {
   return *(const SIE_GLOBAL T*)(gptr(reinterpret_cast<const char*>(base)) + off);
 }
 
-// Chunk c of a term; blocks past `last` read block `last`.
-template <bool VEC, int BLK, int NB, int NS>
-__device__ __forceinline__ void load_wchunk(const WTerm& t, const WLane<NB, NS>& p, int c,
-                                            int last, int g, WChunk<BLK, NB, NS>& x) {
-  const int k0 = kWChunk * c + 2 * g;
-  if (VEC && kWChunk * c + kWChunk <= t.nK) {
-    // K contiguous, 16-byte aligned rows of even length
-    const uint32_t kb = uint32_t(k0) * 8u;
+// Full chunk c of a term with K contiguous (16-byte aligned rows of even
+// length), KS / 2 16-byte loads per row; blocks past `last` read block `last`.
+template <int BLK, int NB, int NS, int KS>
+__device__ __forceinline__ void load_wchunk_vec(const WTerm& t, const WLane<NB, NS>& p, int c,
+                                                int last, int g,
+                                                WChunk<BLK, NB, NS, KS>& x) {
+  const uint32_t kb = uint32_t(4 * KS * c + KS * g) * 8u;
 #pragma unroll
-    for (int q = 0; q < NS; ++q) {
-      const d2v s0 = ld_off<d2v>(t.sh, p.sh[q] + kb);
-      x.sh[q][0] = s0.x;
-      x.sh[q][1] = s0.y;
+  for (int s = 0; s < KS; ++s) x.m[s] = t.scale;
+#pragma unroll
+  for (int q = 0; q < NS; ++q)
+#pragma unroll
+    for (int h = 0; h < KS / 2; ++h) {
+      const d2v s0 = ld_off<d2v>(t.sh, p.sh[q] + kb + 16u * h);
+      x.sh[q][2 * h] = s0.x;
+      x.sh[q][2 * h + 1] = s0.y;
     }
 #pragma unroll
-    for (int beta = 0; beta < BLK; ++beta) {
-      const double* b = t.bl + (int64_t)(beta < last ? beta : last) * t.bl_b;
+  for (int beta = 0; beta < BLK; ++beta) {
+    const double* b = t.bl + (int64_t)(beta < last ? beta : last) * t.bl_b;
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const d2v u = ld_off<d2v>(b, p.bl[q] + kb);
-        x.bl[beta][q][0] = u.x;
-        x.bl[beta][q][1] = u.y;
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int h = 0; h < KS / 2; ++h) {
+        const d2v u = ld_off<d2v>(b, p.bl[q] + kb + 16u * h);
+        x.bl[beta][q][2 * h] = u.x;
+        x.bl[beta][q][2 * h + 1] = u.y;
       }
-    }
-  } else {
-    uint32_t ks[2], kbl[2];
-    double m[2];
+  }
+}
+
+// Chunk c of a term, any K stride; k past K reads k = K - 1 (in bounds) and
+// gets factor 0.  The loaded values are used as they arrive: the scale and
+// the zeros are applied when the chunk is consumed (mma_wchunk), so issuing
+// the next chunk's loads never waits for them.
+template <int BLK, int NB, int NS, int KS>
+__device__ __forceinline__ void load_wchunk_gen(const WTerm& t, const WLane<NB, NS>& p, int c,
+                                                int last, int g,
+                                                WChunk<BLK, NB, NS, KS>& x) {
+  const int k0 = 4 * KS * c + KS * g;
+  uint32_t ks[KS], kbl[KS];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int k = k0 + s;
-      const uint32_t kc = uint32_t(k < t.nK ? k : t.nK - 1);
-      ks[s] = kc * uint32_t(t.sh_k * 8);
-      kbl[s] = kc * uint32_t(t.bl_k * 8);
-      m[s] = k < t.nK ? t.scale : 0.0;
-    }
+  for (int s = 0; s < KS; ++s) {
+    const int k = k0 + s;
+    const uint32_t kc = uint32_t(k < t.nK ? k : t.nK - 1);
+    ks[s] = kc * uint32_t(t.sh_k * 8);
+    kbl[s] = kc * uint32_t(t.bl_k * 8);
+    x.m[s] = k < t.nK ? t.scale : 0.0;
+  }
 #pragma unroll
-    for (int q = 0; q < NS; ++q)
+  for (int q = 0; q < NS; ++q)
 #pragma unroll
-      for (int s = 0; s < 2; ++s) x.sh[q][s] = m[s] * ld_off<double>(t.sh, p.sh[q] + ks[s]);
+    for (int s = 0; s < KS; ++s) x.sh[q][s] = ld_off<double>(t.sh, p.sh[q] + ks[s]);
 #pragma unroll
-    for (int beta = 0; beta < BLK; ++beta) {
-      const double* b = t.bl + (int64_t)(beta < last ? beta : last) * t.bl_b;
+  for (int beta = 0; beta < BLK; ++beta) {
+    const double* b = t.bl + (int64_t)(beta < last ? beta : last) * t.bl_b;
 #pragma unroll
-      for (int q = 0; q < NB; ++q)
+    for (int q = 0; q < NB; ++q)
 #pragma unroll
-        for (int s = 0; s < 2; ++s) x.bl[beta][q][s] = ld_off<double>(b, p.bl[q] + kbl[s]);
-    }
+      for (int s = 0; s < KS; ++s) x.bl[beta][q][s] = ld_off<double>(b, p.bl[q] + kbl[s]);
   }
 }
 
 // acc[beta][rt][ct]: rows 16 rt .., cols 16 ct .. of block beta.  Row / col
-// tiles wholly outside the virtual range (uniform) are skipped.
-template <bool A_IS_BL, int BLK, int TR, int TC>
+// tiles wholly outside the virtual range (uniform) are skipped.  SCALED: apply
+// the chunk's per-k factors (general chunks; full 16-byte chunks are d-sums,
+// whose factor is 1).
+template <bool A_IS_BL, int BLK, int TR, int TC, int KS, bool SCALED>
 __device__ __forceinline__ void mma_wchunk(
-    const WChunk<BLK, (A_IS_BL ? TR : TC), (A_IS_BL ? TC : TR)>& x, int nrow, int ncol,
+    const WChunk<BLK, (A_IS_BL ? TR : TC), (A_IS_BL ? TC : TR), KS>& x, int nrow, int ncol,
     d4 (&acc)[BLK][TR][TC]) {
+  constexpr int NS = A_IS_BL ? TC : TR;
 #pragma unroll
-  for (int s = 0; s < 2; ++s)
+  for (int s = 0; s < KS; ++s) {
+    double sh[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) sh[q] = SCALED ? x.sh[q][s] * x.m[s] : x.sh[q][s];
 #pragma unroll
     for (int rt = 0; rt < TR; ++rt)
 #pragma unroll
@@ -240,51 +262,70 @@ __device__ __forceinline__ void mma_wchunk(
 #pragma unroll
         for (int beta = 0; beta < BLK; ++beta)
           acc[beta][rt][ct] = A_IS_BL
-              ? mfma16x16x4(x.bl[beta][rt][s], x.sh[ct][s], acc[beta][rt][ct])
-              : mfma16x16x4(x.sh[rt][s], x.bl[beta][ct][s], acc[beta][rt][ct]);
+              ? mfma16x16x4(x.bl[beta][rt][s], sh[ct], acc[beta][rt][ct])
+              : mfma16x16x4(sh[rt], x.bl[beta][ct][s], acc[beta][rt][ct]);
       }
-}
-
-// One term: two chunks in flight (loads of chunk c + 1 issued before the
-// MFMAs of chunk c); loads past the end are clamped, masked and unused.
-// A: the per-block operand is on the MFMA A side (rows); V: 16-byte loads.
-template <bool A, bool V, int BLK, int TR, int TC>
-__device__ __forceinline__ void run_term(const WTerm& t, int nrow, int ncol, int last, int r,
-                                         int g, d4 (&acc)[BLK][TR][TC]) {
-  constexpr int NB = A ? TR : TC, NS = A ? TC : TR;
-  const WLane<NB, NS> p = wlane<A, NB, NS>(t, r, nrow, ncol);
-  const int nch = (t.nK + kWChunk - 1) / kWChunk;
-  WChunk<BLK, NB, NS> b0, b1;
-  load_wchunk<V>(t, p, 0, last, g, b0);
-  for (int c = 0;; c += 2) {
-    load_wchunk<V>(t, p, c + 1, last, g, b1);
-    mma_wchunk<A, BLK, TR, TC>(b0, nrow, ncol, acc);
-    if (c + 1 >= nch) break;
-    load_wchunk<V>(t, p, c + 2, last, g, b0);
-    mma_wchunk<A, BLK, TR, TC>(b1, nrow, ncol, acc);
-    if (c + 2 >= nch) break;
   }
 }
 
-template <bool L2, int Q, bool VEC, int BLK, int TR, int TC>
+// One term: two chunks in flight (loads of chunk c + 1 issued before the
+// MFMAs of chunk c).  Chunks [0, nvec) use 16-byte loads, the rest (a ragged
+// tail, or every chunk of a strided-K term) general loads; each loop body
+// issues a fixed set of loads (the prefetch index is clamped, never
+// skipped), so the wait before a chunk's MFMAs covers exactly that chunk.
+// A: the per-block operand is on the MFMA A side (rows); V: 16-byte loads;
+// KS: k-steps per chunk (chunks of 4 KS).
+template <bool A, bool V, int BLK, int TR, int TC, int KS>
+__device__ __forceinline__ void run_term(const WTerm& t, int nrow, int ncol, int last, int r,
+                                         int g, d4 (&acc)[BLK][TR][TC]) {
+  constexpr int NB = A ? TR : TC, NS = A ? TC : TR, KC = 4 * KS;
+  const WLane<NB, NS> p = wlane<A, NB, NS>(t, r, nrow, ncol);
+  const int nch = (t.nK + KC - 1) / KC;
+  const int nvec = V ? t.nK / KC : 0;
+  WChunk<BLK, NB, NS, KS> b0, b1;
+  if (nvec > 0) {
+    load_wchunk_vec(t, p, 0, last, g, b0);
+    for (int c = 0;; c += 2) {
+      load_wchunk_vec(t, p, min(c + 1, nvec - 1), last, g, b1);
+      mma_wchunk<A, BLK, TR, TC, KS, false>(b0, nrow, ncol, acc);
+      if (c + 1 >= nvec) break;
+      load_wchunk_vec(t, p, min(c + 2, nvec - 1), last, g, b0);
+      mma_wchunk<A, BLK, TR, TC, KS, false>(b1, nrow, ncol, acc);
+      if (c + 2 >= nvec) break;
+    }
+  }
+  if (nvec < nch) {
+    load_wchunk_gen(t, p, nvec, last, g, b0);
+    for (int c = nvec;; c += 2) {
+      load_wchunk_gen(t, p, c + 1, last, g, b1);
+      mma_wchunk<A, BLK, TR, TC, KS, true>(b0, nrow, ncol, acc);
+      if (c + 1 >= nch) break;
+      load_wchunk_gen(t, p, c + 2, last, g, b0);
+      mma_wchunk<A, BLK, TR, TC, KS, true>(b1, nrow, ncol, acc);
+      if (c + 2 >= nch) break;
+    }
+  }
+}
+
+template <bool L2, int Q, bool VEC, int BLK, int TR, int TC, int KS>
 __device__ __forceinline__ void run_wterm(const double* t2, const double* ovvv,
                                           const double* ooov, int i, int j, int k, int no, int nv,
                                           int blk0, int row0, int col0, int nrow, int ncol,
                                           int last, int r, int g, d4 (&acc)[BLK][TR][TC]) {
-  run_term<wterm_a_is_bl<L2, Q>(), VEC && Q < 3, BLK, TR, TC>(
+  run_term<wterm_a_is_bl<L2, Q>(), VEC && Q < 3, BLK, TR, TC, KS>(
       make_wterm<L2, Q>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0), nrow, ncol, last, r,
       g, acc);
 }
 
-template <bool L2, bool VEC, int BLK, int TR, int TC>
+template <bool L2, bool VEC, int BLK, int TR, int TC, int KS>
 __device__ __forceinline__ void build_wtile(const double* t2, const double* ovvv,
                                             const double* ooov, int i, int j, int k, int no,
                                             int nv, int blk0, int row0, int col0, int nrow,
                                             int ncol, int last, int r, int g,
                                             d4 (&acc)[BLK][TR][TC]) {
 #define SIE_WTERM(Q) \
-  run_wterm<L2, Q, VEC, BLK, TR, TC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, nrow, \
-                                     ncol, last, r, g, acc)
+  run_wterm<L2, Q, VEC, BLK, TR, TC, KS>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, \
+                                         nrow, ncol, last, r, g, acc)
   SIE_WTERM(0);
   SIE_WTERM(1);
   SIE_WTERM(2);
@@ -335,28 +376,28 @@ __device__ __forceinline__ WTerm make_wterm_a(const double* __restrict__ t2,
 // All terms of layout LAY into acc: layout A (LAY 0) has the per-block
 // operand on the rows (acc[BLK][P][S]); B and C (LAY 1, 2) on the cols
 // (acc[BLK][S][P]).
-template <int LAY, bool VEC, int BLK, int TR, int TC>
+template <int LAY, bool VEC, int BLK, int TR, int TC, int KS>
 __device__ __forceinline__ void build_wtile3(const double* t2, const double* ovvv,
                                              const double* ooov, int i, int j, int k, int no,
                                              int nv, int blk0, int row0, int col0, int nrow,
                                              int ncol, int last, int r, int g,
                                              d4 (&acc)[BLK][TR][TC]) {
   if (LAY == 0) {
-    run_wterm<false, 0, VEC, BLK, TR, TC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0,
-                                          nrow, ncol, last, r, g, acc);
-    run_term<true, VEC, BLK, TR, TC>(
+    run_wterm<false, 0, VEC, BLK, TR, TC, KS>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0,
+                                              col0, nrow, ncol, last, r, g, acc);
+    run_term<true, VEC, BLK, TR, TC, KS>(
         make_wterm_a<0>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0), nrow, ncol, last, r,
         g, acc);
-    run_wterm<false, 4, VEC, BLK, TR, TC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0,
-                                          nrow, ncol, last, r, g, acc);
-    run_term<true, false, BLK, TR, TC>(
+    run_wterm<false, 4, VEC, BLK, TR, TC, KS>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0,
+                                              col0, nrow, ncol, last, r, g, acc);
+    run_term<true, false, BLK, TR, TC, KS>(
         make_wterm_a<1>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0), nrow, ncol, last, r,
         g, acc);
   } else {
     constexpr bool L2 = LAY == 2;
 #define SIE_WTERM(Q) \
-  run_wterm<L2, Q, VEC, BLK, TR, TC>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, nrow, \
-                                     ncol, last, r, g, acc)
+  run_wterm<L2, Q, VEC, BLK, TR, TC, KS>(t2, ovvv, ooov, i, j, k, no, nv, blk0, row0, col0, \
+                                         nrow, ncol, last, r, g, acc)
     if (L2) {
       SIE_WTERM(0);
       SIE_WTERM(1);
@@ -435,25 +476,26 @@ struct WShape {
   int blk, tr, tc, bpc, wr, wc;
   int lay;     // 2: two-layout build (k_build_w_f64); 3: k_build_w3_f64 with tr = P
                // (per-block side tiles) and tc = S (shared side tiles)
+  int ks;      // k-steps per K-chunk: 2 (chunks of 8) or 4 (16: a 128-byte line per row)
 };
 constexpr int kWVariants = 15;
 __host__ __device__ inline WShape wshape(int v) {
   switch (v) {
-    case 1: return WShape{4, 2, 2, 1, 1, 1, 2};
-    case 2: return WShape{2, 2, 2, 2, 1, 1, 2};
-    case 3: return WShape{8, 1, 1, 2, 1, 1, 2};
-    case 4: return WShape{4, 4, 2, 1, 1, 1, 2};
-    case 5: return WShape{4, 2, 4, 1, 1, 1, 2};
-    case 6: return WShape{4, 2, 2, 2, 2, 2, 2};
-    case 7: return WShape{4, 2, 2, 2, 1, 4, 2};
-    case 8: return WShape{4, 2, 2, 2, 4, 1, 2};
-    case 9: return WShape{1, 1, 13, 2, 1, 1, 3};
-    case 10: return WShape{1, 2, 7, 2, 1, 1, 3};
-    case 11: return WShape{2, 1, 7, 2, 1, 1, 3};
-    case 12: return WShape{1, 1, 10, 2, 1, 1, 3};
-    case 13: return WShape{1, 2, 10, 1, 1, 1, 3};
-    case 14: return WShape{1, 2, 4, 2, 1, 1, 3};
-    default: return WShape{4, 2, 2, 2, 1, 1, 2};
+    case 1: return WShape{4, 2, 2, 1, 1, 1, 2, 2};
+    case 2: return WShape{2, 2, 2, 2, 1, 1, 2, 2};
+    case 3: return WShape{8, 1, 1, 2, 1, 1, 2, 2};
+    case 4: return WShape{4, 4, 2, 1, 1, 1, 2, 2};
+    case 5: return WShape{4, 2, 4, 1, 1, 1, 2, 2};
+    case 6: return WShape{4, 2, 2, 2, 2, 2, 2, 2};
+    case 7: return WShape{4, 2, 2, 2, 1, 4, 2, 2};
+    case 8: return WShape{4, 2, 2, 2, 4, 1, 2, 2};
+    case 9: return WShape{1, 1, 13, 2, 1, 1, 3, 2};
+    case 10: return WShape{1, 2, 7, 2, 1, 1, 3, 2};
+    case 11: return WShape{2, 1, 7, 2, 1, 1, 3, 2};
+    case 12: return WShape{1, 1, 10, 2, 1, 1, 3, 2};
+    case 13: return WShape{1, 2, 10, 1, 1, 1, 3, 2};
+    case 14: return WShape{1, 2, 4, 2, 1, 1, 3, 2};
+    default: return WShape{4, 2, 2, 2, 1, 1, 2, 2};
   }
 }
 
@@ -476,9 +518,11 @@ __host__ __device__ inline int64_t wbuild_tiles(int nv, int variant) {
 // Partial cube of one layout over one tile of one unit, written to the
 // unit's first (L1) or second (L2) cube in (block, row, col) order.  Grid:
 // the concatenated build work-groups of the round's items (all of one tile
-// variant): two layouts per unit, one for a pair unit (unit_triple).  Block: 256 threads.  VEC (FragDesc::vec): n_v is even and the
-// t2 / ovvv bases are 16-byte aligned, so d-rows are read 16 bytes at a time.
-template <int BLK, int TR, int TC, int BPC, int WR = 1, int WC = 1>
+// variant): two layouts per unit, one for a pair unit (unit_triple).  Block:
+// 256 threads.  VEC (FragDesc::vec): n_v is even and the t2 / ovvv bases are
+// 16-byte aligned, so d-rows are read 16 bytes at a time.  KS: k-steps per
+// K-chunk (chunks of 8 or 16).
+template <int BLK, int TR, int TC, int BPC, int WR = 1, int WC = 1, int KS = 2>
 __global__ __launch_bounds__(256, BPC) void k_build_w_f64(const FragDesc* __restrict__ descs,
                                                           const Item* __restrict__ items,
                                                           int n_items,
@@ -520,7 +564,7 @@ __global__ __launch_bounds__(256, BPC) void k_build_w_f64(const FragDesc* __rest
   zero_acc(acc);
 
 #define SIE_WTILE(L, V) \
-  build_wtile<L, V, BLK, TR, TC>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, row0, col0, nrow, \
+  build_wtile<L, V, BLK, TR, TC, KS>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, row0, col0, nrow, \
                                  ncol, last, r, g, acc)
   if (l2) {
     if (fd.vec) SIE_WTILE(true, true);
@@ -540,7 +584,7 @@ __global__ __launch_bounds__(256, BPC) void k_build_w_f64(const FragDesc* __rest
 // 16 S >= n_v it spans the shared side and each per-block operand row is
 // read by one work-group only.  Grid: the concatenated work-groups of the
 // round's items, three layouts per unit, two (A, B) for a pair unit.
-template <int BLK, int P, int S, int BPC>
+template <int BLK, int P, int S, int BPC, int KS = 2>
 __global__ __launch_bounds__(256, BPC) void k_build_w3_f64(const FragDesc* __restrict__ descs,
                                                            const Item* __restrict__ items,
                                                            int n_items,
@@ -578,17 +622,18 @@ __global__ __launch_bounds__(256, BPC) void k_build_w3_f64(const FragDesc* __res
     d4 acc[BLK][P][S];
     zero_acc(acc);
     if (fd.vec)
-      build_wtile3<0, true>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, p0, s0, np, ns, last, r, g,
+      build_wtile3<0, true, BLK, P, S, KS>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, p0, s0, np, ns, last, r, g,
                             acc);
     else
-      build_wtile3<0, false>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, p0, s0, np, ns, last, r,
+      build_wtile3<0, false, BLK, P, S, KS>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, p0, s0, np, ns, last, r,
                              g, acc);
     store_wtile(out, nv, blk0, p0, s0, r, g, acc);
   } else {          // shared rows, per-block cols
     d4 acc[BLK][S][P];
     zero_acc(acc);
 #define SIE_W3(L, V) \
-  build_wtile3<L, V>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, s0, p0, ns, np, last, r, g, acc)
+  build_wtile3<L, V, BLK, S, P, KS>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, s0, p0, ns, np, \
+                                    last, r, g, acc)
     if (lay == 1) {
       if (fd.vec) SIE_W3(1, true);
       else SIE_W3(1, false);
@@ -693,6 +738,31 @@ __device__ __forceinline__ double block_sum_256(double v, double* red) {
   return s;
 }
 
+// Wt of a thread's kPer orbit elements: w1[a][b][c] (+ w2[a][b][c], three
+// layouts) + w3[b][a][c], indices clamped into the cube (the caller masks
+// elements past n_v), all loads issued before any is summed.
+template <bool L3, int kPer, typename CubeT>
+__device__ __forceinline__ void epi_load_w(const CubeT* __restrict__ w1,
+                                           const CubeT* __restrict__ w2,
+                                           const CubeT* __restrict__ w3, int nv, int t0, int t1b,
+                                           int t2b, double (&wreg)[kPer]) {
+  constexpr int E = kOrb * kOrb * kOrb;
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const int idx = threadIdx.x + 256 * m;
+    const int s = idx / E, e = idx - s * E;
+    int p0, p1, p2;
+    slot_perm(s, p0, p1, p2);
+    const int a = min(kOrb * pick3(p0, t0, t1b, t2b) + (e >> 6), nv - 1);
+    const int b = min(kOrb * pick3(p1, t0, t1b, t2b) + ((e >> 3) & 7), nv - 1);
+    const int c = min(kOrb * pick3(p2, t0, t1b, t2b) + (e & 7), nv - 1);
+    const int64_t abc = ((int64_t)a * nv + b) * nv + c;
+    double w = (double)gptr(w1)[abc];
+    if (L3) w += (double)gptr(w2)[abc];
+    wreg[m] = w + (double)gptr(w3)[((int64_t)b * nv + a) * nv + c];
+  }
+}
+
 // Per-unit partial sums of Wt R'[Wt + Vt] / D over symmetric orbits of
 // 8 x 8 x 8 virtual blocks (A >= B >= C and their permuted images).
 // Wt[a][b][c] = P1[a][b][c] + P2[b][a][c] from the two-layout builds, or
@@ -750,7 +820,15 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
   for (int64_t o = slot; o < n_orb; o += fd.n_part) {
     int t0, t1b, t2b;
     decode_sorted_triple(o, nb, t0, t1b, t2b);
-    double wreg[kPer];   // Wt of this thread's elements (the same ones in both passes)
+    // Wt of this thread's elements (the same ones in both passes): every cube
+    // load of the orbit is issued before any is used (indices clamped into the
+    // cube, so the loads are unconditional; elements past n_v are masked in
+    // the second loop), then V-tilde is added and Z = Wt + V-tilde goes to LDS
+    double wreg[kPer];
+    if (l3)
+      epi_load_w<true, kPer>(w1, w2, w3, nv, t0, t1b, t2b, wreg);
+    else
+      epi_load_w<false, kPer>(w1, w2, w3, nv, t0, t1b, t2b, wreg);
 #pragma unroll 2
     for (int m = 0; m < kPer; ++m) {
       const int idx = threadIdx.x + 256 * m;
@@ -760,18 +838,15 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
       const int a = kOrb * pick3(p0, t0, t1b, t2b) + (e >> 6);
       const int b = kOrb * pick3(p1, t0, t1b, t2b) + ((e >> 3) & 7);
       const int c = kOrb * pick3(p2, t0, t1b, t2b) + (e & 7);
-      double w = 0.0, z = 0.0;
+      double z = 0.0;
       if (a < nv && b < nv && c < nv) {
-        const int64_t abc = ((int64_t)a * nv + b) * nv + c;
-        w = (double)gptr(w1)[abc];
-        if (l3) w += (double)gptr(w2)[abc];
-        w += (double)gptr(w3)[((int64_t)b * nv + a) * nv + c];
         const double vt = (double)gptr(ov_ij)[(int64_t)a * nonv + b] * (double)gptr(t1k)[c] +
                           (double)gptr(ov_ik)[(int64_t)a * nonv + c] * (double)gptr(t1j)[b] +
                           (double)gptr(ov_jk)[(int64_t)b * nonv + c] * (double)gptr(t1i)[a];
-        z = w + vt;
+        z = wreg[m] + vt;
+      } else {
+        wreg[m] = 0.0;
       }
-      wreg[m] = w;
       sz[s][orb_lds(e >> 6, (e >> 3) & 7, e & 7)] = z;
     }
     __syncthreads();
@@ -814,7 +889,7 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
       const double zbac = sz[orbit_slot(p1, p0, p2)][orb_lds(y, x, zz)];
       const double rz = 4.0 * zabc + zcab + zbca - 2.0 * (zcba + zacb + zbac);
       const double d = eijk - gptr(ev)[a] - gptr(ev)[b] - gptr(ev)[c];
-      acc += wreg[m] * rz / d;
+      acc += wreg[m] * rz * recip(d);
     }
     __syncthreads();
   }

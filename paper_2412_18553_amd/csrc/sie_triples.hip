@@ -308,6 +308,8 @@ sie_status sie_profile_collect(double* ms, int64_t* launches) {
 
 int32_t sie_tile_variants(void) { return sie::kWVariants; }
 
+int32_t sie_tile_variant_of(int32_t n_vir) { return n_vir < 1 ? -1 : tile_variant(n_vir); }
+
 sie_status sie_tile_variant_shape(int32_t variant, int32_t* shape) {
   if (variant < 0 || variant >= sie::kWVariants || !shape)
     return fail(SIE_ERR_INVALID_ARG, "sie_tile_variant_shape: bad variant or NULL output");
@@ -319,6 +321,7 @@ sie_status sie_tile_variant_shape(int32_t variant, int32_t* shape) {
   shape[4] = w.wr;
   shape[5] = w.wc;
   shape[6] = w.lay;
+  shape[7] = w.ks;
   return SIE_OK;
 }
 

@@ -166,17 +166,21 @@ def test_backward_workspace_and_errors(lib):
 def test_tile_table(lib):
     n = lib.sie_tile_variants()
     assert n >= 2
-    shape = (ctypes.c_int32 * 7)()
+    shape = (ctypes.c_int32 * 8)()
     for v in range(n):
         assert lib.sie_tile_variant_shape(v, shape) == _lib.SIE_OK
         assert all(x >= 1 for x in shape)
-        assert shape[6] in (2, 3)
+        assert shape[6] in (2, 3) and shape[7] in (2, 4)
     assert lib.sie_tile_variant_shape(n, shape) == _lib.SIE_ERR_INVALID_ARG
     arr = lambda *x: (ctypes.c_int32 * len(x))(*x)  # noqa: E731
     assert lib.sie_set_tile_table(2, arr(100, 400), arr(1, 0)) == _lib.SIE_OK
     assert lib.sie_set_tile_table(2, arr(400, 100), arr(1, 0)) == _lib.SIE_ERR_INVALID_ARG
     assert lib.sie_set_tile_table(1, arr(100), arr(n)) == _lib.SIE_ERR_INVALID_ARG
     assert lib.sie_set_tile_table(1, None, None) == _lib.SIE_ERR_INVALID_ARG
+    assert lib.sie_set_tile_table(0, None, None) == _lib.SIE_OK
+    assert lib.sie_tile_variant_of(0) == -1
+    assert lib.sie_set_tile_table(2, arr(100, 400), arr(1, 2)) == _lib.SIE_OK
+    assert [lib.sie_tile_variant_of(v) for v in (1, 100, 101, 400, 401)] == [1, 1, 2, 2, 0]
     assert lib.sie_set_tile_table(0, None, None) == _lib.SIE_OK
     # the work-group count of a fragment depends on its variant only through sizing
     keep = []
