@@ -784,6 +784,8 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
   int i, j, k;
   const bool one = unit_triple(it.unit, fd.no, fd.pair, i, j, k);
   __shared__ double sz[6][kOrbSlot];
+  // per orbit, for its three block positions: e_vir, t1[i], t1[j], t1[k]
+  __shared__ double sv[4 * 3 * kOrb];
   __shared__ double red[4];
   double* out = partials + (fd.unit_base + it.unit) * pstride + slot;
   if (i == k) {
@@ -815,11 +817,22 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
 
   constexpr int E = kOrb * kOrb * kOrb;
   constexpr int kPer = 6 * E / 256;       // elements of an orbit per thread
+  const double* V = sv;   // V[(3 q + p) kOrb + x]: vector q at block position p
 
   double acc = 0.0;
   for (int64_t o = slot; o < n_orb; o += fd.n_part) {
     int t0, t1b, t2b;
     decode_sorted_triple(o, nb, t0, t1b, t2b);
+    if (threadIdx.x < 4 * 3 * kOrb) {   // (the previous orbit's last barrier freed sv)
+      const int q = threadIdx.x / (3 * kOrb), p = (threadIdx.x / kOrb) % 3;
+      const int v = min(kOrb * pick3(p, t0, t1b, t2b) + int(threadIdx.x % kOrb), nv - 1);
+      double x;
+      if (q == 0) x = gptr(ev)[v];
+      else if (q == 1) x = (double)gptr(t1i)[v];
+      else if (q == 2) x = (double)gptr(t1j)[v];
+      else x = (double)gptr(t1k)[v];
+      sv[threadIdx.x] = x;
+    }
     // Wt of this thread's elements (the same ones in both passes): every cube
     // load of the orbit is issued before any is used (indices clamped into the
     // cube, so the loads are unconditional; elements past n_v are masked in
@@ -829,20 +842,22 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
       epi_load_w<true, kPer>(w1, w2, w3, nv, t0, t1b, t2b, wreg);
     else
       epi_load_w<false, kPer>(w1, w2, w3, nv, t0, t1b, t2b, wreg);
+    __syncthreads();   // sv filled
 #pragma unroll 2
     for (int m = 0; m < kPer; ++m) {
       const int idx = threadIdx.x + 256 * m;
       const int s = idx / E, e = idx - s * E;
       int p0, p1, p2;
       slot_perm(s, p0, p1, p2);
-      const int a = kOrb * pick3(p0, t0, t1b, t2b) + (e >> 6);
-      const int b = kOrb * pick3(p1, t0, t1b, t2b) + ((e >> 3) & 7);
-      const int c = kOrb * pick3(p2, t0, t1b, t2b) + (e & 7);
+      const int x = e >> 6, y = (e >> 3) & 7, zz = e & 7;
+      const int a = kOrb * pick3(p0, t0, t1b, t2b) + x;
+      const int b = kOrb * pick3(p1, t0, t1b, t2b) + y;
+      const int c = kOrb * pick3(p2, t0, t1b, t2b) + zz;
       double z = 0.0;
       if (a < nv && b < nv && c < nv) {
-        const double vt = (double)gptr(ov_ij)[(int64_t)a * nonv + b] * (double)gptr(t1k)[c] +
-                          (double)gptr(ov_ik)[(int64_t)a * nonv + c] * (double)gptr(t1j)[b] +
-                          (double)gptr(ov_jk)[(int64_t)b * nonv + c] * (double)gptr(t1i)[a];
+        const double vt = (double)gptr(ov_ij)[(int64_t)a * nonv + b] * V[(9 + p2) * kOrb + zz] +
+                          (double)gptr(ov_ik)[(int64_t)a * nonv + c] * V[(6 + p1) * kOrb + y] +
+                          (double)gptr(ov_jk)[(int64_t)b * nonv + c] * V[(3 + p0) * kOrb + x];
         z = wreg[m] + vt;
       } else {
         wreg[m] = 0.0;
@@ -888,7 +903,7 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
       const double zacb = sz[orbit_slot(p0, p2, p1)][orb_lds(x, zz, y)];
       const double zbac = sz[orbit_slot(p1, p0, p2)][orb_lds(y, x, zz)];
       const double rz = 4.0 * zabc + zcab + zbca - 2.0 * (zcba + zacb + zbac);
-      const double d = eijk - gptr(ev)[a] - gptr(ev)[b] - gptr(ev)[c];
+      const double d = eijk - V[p0 * kOrb + x] - V[p1 * kOrb + y] - V[p2 * kOrb + zz];
       acc += wreg[m] * rz * recip(d);
     }
     __syncthreads();
