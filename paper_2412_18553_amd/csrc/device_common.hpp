@@ -8,6 +8,7 @@ namespace sie {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
 typedef uint32_t u4v __attribute__((ext_vector_type(4)));   // 8 bf16 or 16 bytes
 
 // Global-address-space views of generic pointers: loads through them are

@@ -738,28 +738,49 @@ __device__ __forceinline__ double block_sum_256(double v, double* red) {
   return s;
 }
 
-// Wt of a thread's kPer orbit elements: w1[a][b][c] (+ w2[a][b][c], three
-// layouts) + w3[b][a][c], indices clamped into the cube (the caller masks
-// elements past n_v), all loads issued before any is summed.
-template <bool L3, int kPer, typename CubeT>
+// Elements (row, c0) and (row, c0 + 1) of a row-major array with rows of
+// stride `rs` and n columns: one two-element load (PV: n even, so an in-range
+// even c0 has c0 + 1 < n and the pair is aligned), or two loads with each
+// column clamped to n - 1 (callers mask columns past n).
+template <typename T, bool PV>
+__device__ __forceinline__ void ld_pair(const T* p, int64_t row, int64_t rs, int c0, int n,
+                                        double (&v)[2]) {
+  if (PV) {
+    typedef typename std::conditional<sizeof(T) == 8, d2v, f2v>::type V2;
+    const V2 u = *(const SIE_GLOBAL V2*)(gptr(p) + row * rs + min(c0, n - 2));
+    v[0] = (double)u.x;
+    v[1] = (double)u.y;
+  } else {
+    v[0] = (double)gptr(p)[row * rs + min(c0, n - 1)];
+    v[1] = (double)gptr(p)[row * rs + min(c0 + 1, n - 1)];
+  }
+}
+
+// Element mapping of the epilogue: thread t holds, in every slot s of the
+// orbit, the two elements at in-block offsets (t / 32, (t / 4) % 8,
+// 2 (t % 4) + h), h = 0, 1 (adjacent along c).  Wt of those 12 elements:
+// w1[a][b][c] (+ w2[a][b][c], three layouts) + w3[b][a][c], indices clamped
+// into the cube (c to an even start with PV; the caller masks elements past
+// n_v), all loads issued before any is summed.
+template <bool L3, bool PV, typename CubeT>
 __device__ __forceinline__ void epi_load_w(const CubeT* __restrict__ w1,
                                            const CubeT* __restrict__ w2,
                                            const CubeT* __restrict__ w3, int nv, int t0, int t1b,
-                                           int t2b, double (&wreg)[kPer]) {
-  constexpr int E = kOrb * kOrb * kOrb;
+                                           int t2b, double (&wreg)[12]) {
+  const int x = threadIdx.x >> 5, y = (threadIdx.x >> 2) & 7, z0 = 2 * (threadIdx.x & 3);
 #pragma unroll
-  for (int m = 0; m < kPer; ++m) {
-    const int idx = threadIdx.x + 256 * m;
-    const int s = idx / E, e = idx - s * E;
+  for (int s = 0; s < 6; ++s) {
     int p0, p1, p2;
     slot_perm(s, p0, p1, p2);
-    const int a = min(kOrb * pick3(p0, t0, t1b, t2b) + (e >> 6), nv - 1);
-    const int b = min(kOrb * pick3(p1, t0, t1b, t2b) + ((e >> 3) & 7), nv - 1);
-    const int c = min(kOrb * pick3(p2, t0, t1b, t2b) + (e & 7), nv - 1);
-    const int64_t abc = ((int64_t)a * nv + b) * nv + c;
-    double w = (double)gptr(w1)[abc];
-    if (L3) w += (double)gptr(w2)[abc];
-    wreg[m] = w + (double)gptr(w3)[((int64_t)b * nv + a) * nv + c];
+    const int a = min(kOrb * pick3(p0, t0, t1b, t2b) + x, nv - 1);
+    const int b = min(kOrb * pick3(p1, t0, t1b, t2b) + y, nv - 1);
+    const int c0 = kOrb * pick3(p2, t0, t1b, t2b) + z0;
+    double u[2], v[2], w[2];
+    ld_pair<CubeT, PV>(w1, (int64_t)a * nv + b, nv, c0, nv, u);
+    if (L3) ld_pair<CubeT, PV>(w2, (int64_t)a * nv + b, nv, c0, nv, v);
+    ld_pair<CubeT, PV>(w3, (int64_t)b * nv + a, nv, c0, nv, w);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) wreg[2 * s + h] = u[h] + (L3 ? v[h] : 0.0) + w[h];
   }
 }
 
@@ -815,8 +836,6 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
   const InT* t1j = t1 + (int64_t)j * nv;
   const InT* t1k = t1 + (int64_t)k * nv;
 
-  constexpr int E = kOrb * kOrb * kOrb;
-  constexpr int kPer = 6 * E / 256;       // elements of an orbit per thread
   const double* V = sv;   // V[(3 q + p) kOrb + x]: vector q at block position p
 
   double acc = 0.0;
@@ -834,35 +853,48 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
       sv[threadIdx.x] = x;
     }
     // Wt of this thread's elements (the same ones in both passes): every cube
-    // load of the orbit is issued before any is used (indices clamped into the
-    // cube, so the loads are unconditional; elements past n_v are masked in
-    // the second loop), then V-tilde is added and Z = Wt + V-tilde goes to LDS
-    double wreg[kPer];
-    if (l3)
-      epi_load_w<true, kPer>(w1, w2, w3, nv, t0, t1b, t2b, wreg);
-    else
-      epi_load_w<false, kPer>(w1, w2, w3, nv, t0, t1b, t2b, wreg);
+    // load of the orbit is issued before any is used, then V-tilde is added
+    // and Z = Wt + V-tilde goes to LDS
+    double wreg[12];
+    if (fd.epv) {
+      if (l3) epi_load_w<true, true>(w1, w2, w3, nv, t0, t1b, t2b, wreg);
+      else epi_load_w<false, true>(w1, w2, w3, nv, t0, t1b, t2b, wreg);
+    } else {
+      if (l3) epi_load_w<true, false>(w1, w2, w3, nv, t0, t1b, t2b, wreg);
+      else epi_load_w<false, false>(w1, w2, w3, nv, t0, t1b, t2b, wreg);
+    }
     __syncthreads();   // sv filled
+    const int x = threadIdx.x >> 5, y = (threadIdx.x >> 2) & 7, z0 = 2 * (threadIdx.x & 3);
 #pragma unroll 2
-    for (int m = 0; m < kPer; ++m) {
-      const int idx = threadIdx.x + 256 * m;
-      const int s = idx / E, e = idx - s * E;
+    for (int s = 0; s < 6; ++s) {
       int p0, p1, p2;
       slot_perm(s, p0, p1, p2);
-      const int x = e >> 6, y = (e >> 3) & 7, zz = e & 7;
       const int a = kOrb * pick3(p0, t0, t1b, t2b) + x;
       const int b = kOrb * pick3(p1, t0, t1b, t2b) + y;
-      const int c = kOrb * pick3(p2, t0, t1b, t2b) + zz;
-      double z = 0.0;
-      if (a < nv && b < nv && c < nv) {
-        const double vt = (double)gptr(ov_ij)[(int64_t)a * nonv + b] * V[(9 + p2) * kOrb + zz] +
-                          (double)gptr(ov_ik)[(int64_t)a * nonv + c] * V[(6 + p1) * kOrb + y] +
-                          (double)gptr(ov_jk)[(int64_t)b * nonv + c] * V[(3 + p0) * kOrb + x];
-        z = wreg[m] + vt;
+      const int c0 = kOrb * pick3(p2, t0, t1b, t2b) + z0;
+      const int ac = min(a, nv - 1), bc = min(b, nv - 1);
+      double oik[2], ojk[2];
+      const double oij = (double)gptr(ov_ij)[(int64_t)ac * nonv + bc];
+      if (fd.epv) {
+        ld_pair<InT, true>(ov_ik, ac, nonv, c0, nv, oik);
+        ld_pair<InT, true>(ov_jk, bc, nonv, c0, nv, ojk);
       } else {
-        wreg[m] = 0.0;
+        ld_pair<InT, false>(ov_ik, ac, nonv, c0, nv, oik);
+        ld_pair<InT, false>(ov_jk, bc, nonv, c0, nv, ojk);
       }
-      sz[s][orb_lds(e >> 6, (e >> 3) & 7, e & 7)] = z;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int zz = z0 + h;
+        double z = 0.0;
+        if (a < nv && b < nv && zz + kOrb * pick3(p2, t0, t1b, t2b) < nv) {
+          const double vt = oij * V[(9 + p2) * kOrb + zz] + oik[h] * V[(6 + p1) * kOrb + y] +
+                            ojk[h] * V[(3 + p0) * kOrb + x];
+          z = wreg[2 * s + h] + vt;
+        } else {
+          wreg[2 * s + h] = 0.0;
+        }
+        sz[s][orb_lds(x, y, zz)] = z;
+      }
     }
     __syncthreads();
     // a slot whose block triple repeats an earlier slot's is not summed twice
@@ -883,28 +915,29 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
       if (!dup) primary |= 1u << s;
     }
 #pragma unroll 2
-    for (int m = 0; m < kPer; ++m) {
-      const int idx = threadIdx.x + 256 * m;
-      const int s = idx / E, e = idx - s * E;
+    for (int s = 0; s < 6; ++s) {
       if (!((primary >> s) & 1u)) continue;
       int p0, p1, p2;
       slot_perm(s, p0, p1, p2);
-      const int x = e >> 6, y = (e >> 3) & 7, zz = e & 7;
       const int a = kOrb * pick3(p0, t0, t1b, t2b) + x;
       const int b = kOrb * pick3(p1, t0, t1b, t2b) + y;
-      const int c = kOrb * pick3(p2, t0, t1b, t2b) + zz;
-      if (a >= nv || b >= nv || c >= nv) continue;
-      // Z at the five permuted virtual triples, found in the slot holding
-      // the permuted block triple at the permuted in-block offsets
-      const double zabc = sz[s][orb_lds(x, y, zz)];
-      const double zcab = sz[orbit_slot(p2, p0, p1)][orb_lds(zz, x, y)];
-      const double zbca = sz[orbit_slot(p1, p2, p0)][orb_lds(y, zz, x)];
-      const double zcba = sz[orbit_slot(p2, p1, p0)][orb_lds(zz, y, x)];
-      const double zacb = sz[orbit_slot(p0, p2, p1)][orb_lds(x, zz, y)];
-      const double zbac = sz[orbit_slot(p1, p0, p2)][orb_lds(y, x, zz)];
-      const double rz = 4.0 * zabc + zcab + zbca - 2.0 * (zcba + zacb + zbac);
-      const double d = eijk - V[p0 * kOrb + x] - V[p1 * kOrb + y] - V[p2 * kOrb + zz];
-      acc += wreg[m] * rz * recip(d);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int zz = z0 + h;
+        const int c = kOrb * pick3(p2, t0, t1b, t2b) + zz;
+        if (a >= nv || b >= nv || c >= nv) continue;
+        // Z at the five permuted virtual triples, found in the slot holding
+        // the permuted block triple at the permuted in-block offsets
+        const double zabc = sz[s][orb_lds(x, y, zz)];
+        const double zcab = sz[orbit_slot(p2, p0, p1)][orb_lds(zz, x, y)];
+        const double zbca = sz[orbit_slot(p1, p2, p0)][orb_lds(y, zz, x)];
+        const double zcba = sz[orbit_slot(p2, p1, p0)][orb_lds(zz, y, x)];
+        const double zacb = sz[orbit_slot(p0, p2, p1)][orb_lds(x, zz, y)];
+        const double zbac = sz[orbit_slot(p1, p0, p2)][orb_lds(y, x, zz)];
+        const double rz = 4.0 * zabc + zcab + zbca - 2.0 * (zcba + zacb + zbac);
+        const double d = eijk - V[p0 * kOrb + x] - V[p1 * kOrb + y] - V[p2 * kOrb + zz];
+        acc += wreg[2 * s + h] * rz * recip(d);
+      }
     }
     __syncthreads();
   }

@@ -430,6 +430,7 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
     d.Ko = fp.Ko;
     // 16-byte row reads need an even row length and 16-byte aligned bases
     d.vec = (!pl.split && fp.nv % 2 == 0 && aligned(f.t2, 16) && aligned(f.ovvv, 16)) ? 1 : 0;
+    d.epv = (fp.nv % 2 == 0 && aligned(f.ovov, pl.split ? 8 : 16)) ? 1 : 0;
     d.n_part = fp.n_part;
     d.unit_base = unit_base;
     d.half = int64_t(fp.half_bytes / (pl.split ? sizeof(float) : sizeof(double)));

@@ -29,6 +29,8 @@ struct FragDesc {
   int no, nv;
   int Kv, Ko;             // padded contraction lengths of the split copies
   int vec;                // float64: rows may be read 16 bytes at a time
+  int epv;                // epilogue: n_v even and ovov aligned to two elements, so
+                          // pairs of adjacent c are read with one load
   int variant;            // float64: tile shape of the W-tilde build (see wshape)
   int pair;               // 1: pair units (two equal occupied indices) build only the
                           // first layout's cube (unit_triple); 0: both, as the adjoint needs
