@@ -71,7 +71,7 @@ def lay3_of(v):
     """Whether the float64 energy of a fragment with v virtuals uses the
     three-layout build under the installed tile table."""
     import paper_2412_18553_amd as sie
-    return sie.tile_variants()[sie.tile_variant_of(v)][6] == 3
+    return sie.tile_variants()[sie.tile_variant_of(v)][6] >= 3
 
 
 def cpu_baseline(frag, a_values):
@@ -240,7 +240,8 @@ def main():
             result.update(value=round(F / (ms * 1e-3) / 1e12, 3), dtype="f64",
                           config={"workload": desc, "precision": "fp64", "fragments": 1})
             l3 = lay3_of(v)
-            kernel = "k_build_w3_f64" if l3 else "k_build_w_f64"
+            lay = sie.tile_variants()[sie.tile_variant_of(v)][6]
+            kernel = {2: "k_build_w_f64", 3: "k_build_w3_f64"}[lay]
             result["roofline"] = roofline(prof, "w_build", kernel, build_work(o, v, lay3=l3),
                                           args.steps, PEAK_FP64_MFMA_TFLOPS, workload=name)
             result["roofline"]["tile_variant"] = sie.tile_variant_of(v)

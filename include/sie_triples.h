@@ -203,7 +203,7 @@ sie_status sie_profile_collect(double* ms, int64_t* launches);
  * is compiled for sie_tile_variants() tile shapes; sie_tile_variant_shape
  * writes variant v's shape into shape[8] (host): blocks per wave, 16-wide
  * MFMA row tiles and col tiles per wave, work-groups per CU targeted, the
- * work-group's waves along rows and cols (1, 1: waves along blocks), and the
+ * work-group's waves along rows and cols (1, 1: waves along blocks), the
  * number of partial-cube layouts (2, or 3: the terms regrouped so that the
  * per-block operand of every term lies on one MFMA side; the row and col
  * tiles then count the per-block side and the shared side; the gradient

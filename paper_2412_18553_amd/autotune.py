@@ -84,7 +84,9 @@ def write_table(table, results, path=TABLE) -> None:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--nv", default="48,64,80,96,120,160,200,240,320,400")
-    ap.add_argument("--n-occ", type=int, default=16)
+    ap.add_argument("--n-occ", type=int, default=0,
+                    help="occupied orbitals of the timing fragment (0: n_v / 8 within [8, 24], "
+                         "about the virtual-to-occupied ratio of the benchmark fragments)")
     ap.add_argument("--margin", type=float, default=0.01)
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--write", action="store_true")
@@ -94,7 +96,7 @@ def main():
     best, results = [], []
     try:
         for nv in [int(x) for x in args.nv.split(",")]:
-            frag = random_fragment(args.n_occ, nv)
+            frag = random_fragment(args.n_occ or min(24, max(8, nv // 8)), nv)
             times = []
             for v in range(len(shapes)):
                 times.append(time_variant(frag, v, args.reps))

@@ -216,7 +216,23 @@ struct AdjGroup {
   int rec_begin, rec_end;
   int pad;
   int64_t wg_end;      // inclusive prefix sum of work-groups over the launch
+  int64_t part_off;    // summed-block classes: element offset of the partial slice it writes
 };
+
+// Output slice of a summed-block class and its nparts partial slices, at
+// element offsets off0 + q * (slice elements), summed in that order into the
+// gradient by k_adj_part_sum.
+struct AdjSlice {
+  int frag;
+  int a0, a1;
+  int nparts;
+  int64_t off0;
+};
+
+// Partial slices per output slice of the summed-block classes: the slice's
+// contributions are split over this many groups (work-group sets) for
+// parallelism, then summed in a fixed order.
+constexpr int kAdjParts = 4;
 
 struct AdjRec {
   int item;            // index into the round's items
@@ -326,12 +342,16 @@ __device__ __forceinline__ ATerm<CubeT, InT> make_adj(int kind, int g, int i, in
   return t;
 }
 
-// Registers of one K-chunk for one wave: A side (G) for kABlk blocks x kAT
-// row tiles, B side for kABlk blocks (or the shared row) x kAT col tiles.
-template <int BLK>
+// Registers of one K-chunk for one wave: A side (G) for BLK blocks x TRW
+// row tiles, B side for BLK blocks (or the shared row) x TCW col tiles, as
+// loaded; m: the B-side factor per k of the pair (the term's scale, 0 past
+// K), applied when the chunk is consumed so that issuing the next chunk's
+// loads never waits for them (A needs no zeros: B's cancel it).
+template <int BLK, int TRW, int TCW>
 struct AChunk {
-  double a[BLK][kAT][2];
-  double b[BLK][kAT][2];
+  double a[BLK][TRW][2];
+  double b[BLK][TCW][2];
+  double m[2];
 };
 
 // Element at byte offset `off` from a wave-uniform base (32-bit lane
@@ -342,81 +362,83 @@ __device__ __forceinline__ T aload(const void* base, uint32_t off) {
 }
 
 // The lane's k-pair (k, k+1) of one row (byte offset `row` from `base`, K
-// stride ks elements); past nK in bounds and zero (the A side carries no
-// zeroing: B's zeros cancel it).  `vec`: unit stride and 16-byte aligned pairs.
+// stride ks elements), as loaded; k past nK reads nK - 1 (in bounds; the
+// chunk's factor zeroes it).  `vec`: unit stride and 16-byte aligned pairs.
 template <typename T>
 __device__ __forceinline__ void apair(const T* base, uint32_t row, int64_t ks, int k, int nK,
-                                      double s, bool vec, double (&out)[2]) {
+                                      bool vec, double (&out)[2]) {
   if (vec && k + 1 < nK) {
     const uint32_t o = row + uint32_t(k) * uint32_t(sizeof(T));
     if (sizeof(T) == 8) {
       const d2v v = aload<d2v>(base, o);
-      out[0] = s * v.x;
-      out[1] = s * v.y;
+      out[0] = v.x;
+      out[1] = v.y;
     } else {
-      out[0] = s * (double)aload<T>(base, o);
-      out[1] = s * (double)aload<T>(base, o + uint32_t(sizeof(T)));
+      out[0] = (double)aload<T>(base, o);
+      out[1] = (double)aload<T>(base, o + uint32_t(sizeof(T)));
     }
   } else {
     const uint32_t kb = uint32_t(ks * int64_t(sizeof(T)));
     const uint32_t k0 = uint32_t(k < nK ? k : nK - 1);
     const uint32_t k1 = uint32_t(k + 1 < nK ? k + 1 : nK - 1);
-    out[0] = (k < nK ? s : 0.0) * (double)aload<T>(base, row + k0 * kb);
-    out[1] = (k + 1 < nK ? s : 0.0) * (double)aload<T>(base, row + k1 * kb);
+    out[0] = (double)aload<T>(base, row + k0 * kb);
+    out[1] = (double)aload<T>(base, row + k1 * kb);
   }
 }
 
-// Lane rows of one term: clamped A-side rows x_rt and B-side rows x_ct.
-template <int BLK, typename CubeT, typename InT>
+// Lane rows of one term: clamped A-side rows x_rt and B-side rows x_ct;
+// blocks past nblk read block 0 (their results are not stored).
+template <int BLK, int TRW, int TCW, typename CubeT, typename InT>
 __device__ __forceinline__ void adj_load(const ATerm<CubeT, InT>& t, bool reduce, int c, int nK,
-                                         int rbase, int cbase, int nrow, int ncol, int nblk,
-                                         int r, int g, bool vec, AChunk<BLK>& x) {
+                                         int nrow, int ncol, int nblk, int r, int g, bool vec,
+                                         AChunk<BLK, TRW, TCW>& x) {
   const int k = c * kAKc + 2 * g;
   const bool va = vec && t.a_k == 1, vb = vec && t.b_k == 1;
+  x.m[0] = k < nK ? t.scale : 0.0;
+  x.m[1] = k + 1 < nK ? t.scale : 0.0;
 #pragma unroll
-  for (int rt = 0; rt < kAT; ++rt) {
-    const uint32_t xr =
-        uint32_t(min(rbase + 16 * rt + r, nrow - 1) * t.a_x * int64_t(sizeof(CubeT)));
+  for (int rt = 0; rt < TRW; ++rt) {
+    const uint32_t xr = uint32_t(min(16 * rt + r, nrow - 1) * t.a_x * int64_t(sizeof(CubeT)));
 #pragma unroll
-    for (int beta = 0; beta < BLK; ++beta) {
-      const bool ok = beta < nblk;
-      apair(t.a + (ok ? beta : 0) * t.a_b, xr, t.a_k, k, nK, (reduce && !ok) ? 0.0 : 1.0, va,
-            x.a[beta][rt]);
-    }
+    for (int beta = 0; beta < BLK; ++beta)
+      apair(t.a + (beta < nblk ? beta : 0) * t.a_b, xr, t.a_k, k, nK, va, x.a[beta][rt]);
   }
 #pragma unroll
-  for (int ct = 0; ct < kAT; ++ct) {
-    const uint32_t xc =
-        uint32_t(min(cbase + 16 * ct + r, ncol - 1) * t.b_x * int64_t(sizeof(InT)));
+  for (int ct = 0; ct < TCW; ++ct) {
+    const uint32_t xc = uint32_t(min(16 * ct + r, ncol - 1) * t.b_x * int64_t(sizeof(InT)));
     if (reduce) {
 #pragma unroll
       for (int beta = 0; beta < BLK; ++beta)
-        apair(t.b + (beta < nblk ? beta : 0) * t.b_b, xc, t.b_k, k, nK, t.scale, vb,
-              x.b[beta][ct]);
+        apair(t.b + (beta < nblk ? beta : 0) * t.b_b, xc, t.b_k, k, nK, vb, x.b[beta][ct]);
     } else {
-      apair(t.b, xc, t.b_k, k, nK, t.scale, vb, x.b[0][ct]);
+      apair(t.b, xc, t.b_k, k, nK, vb, x.b[0][ct]);
     }
   }
 }
 
 // acc[beta][rt][ct] += A[beta][rt] * B[beta or shared][ct] over the chunk;
 // row / col tiles wholly outside the output (uniform) are skipped.
-template <int BLK>
-__device__ __forceinline__ void adj_mma(const AChunk<BLK>& x, bool reduce, bool r1, bool c1,
-                                        d4 (&acc)[BLK][kAT][kAT]) {
+template <int BLK, int TRW, int TCW>
+__device__ __forceinline__ void adj_mma(const AChunk<BLK, TRW, TCW>& x, bool reduce, int nrow,
+                                        int ncol, d4 (&acc)[BLK][TRW][TCW]) {
 #pragma unroll
-  for (int s = 0; s < 2; ++s)
+  for (int s = 0; s < 2; ++s) {
+    double b[BLK][TCW];
 #pragma unroll
-    for (int rt = 0; rt < kAT; ++rt)
+    for (int beta = 0; beta < (reduce ? BLK : 1); ++beta)
 #pragma unroll
-      for (int ct = 0; ct < kAT; ++ct) {
-        if ((rt == 1 && !r1) || (ct == 1 && !c1)) continue;
+      for (int ct = 0; ct < TCW; ++ct) b[beta][ct] = x.b[beta][ct][s] * x.m[s];
+#pragma unroll
+    for (int rt = 0; rt < TRW; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < TCW; ++ct) {
+        if ((rt > 0 && 16 * rt >= nrow) || (ct > 0 && 16 * ct >= ncol)) continue;
 #pragma unroll
         for (int beta = 0; beta < BLK; ++beta)
-          acc[beta][rt][ct] = mfma16x16x4(x.a[beta][rt][s], reduce ? x.b[beta][ct][s]
-                                                                    : x.b[0][ct][s],
-                                          acc[beta][rt][ct]);
+          acc[beta][rt][ct] =
+              mfma16x16x4(x.a[beta][rt][s], b[reduce ? beta : 0][ct], acc[beta][rt][ct]);
       }
+  }
 }
 
 struct AdjOut {
@@ -449,12 +471,25 @@ __device__ __forceinline__ AdjOut adj_out(const FragDesc& fd, const AdjGroup& gr
   return o;
 }
 
-// Work-group tile of a class: (blocks, rows, cols) per work-group.
+// Wave tile of a class: BLK blocks x TRW x TCW 16-wide MFMA tiles.  The
+// summed-block classes run the summed virtual one block at a time through
+// K (BLK = 1) so that a wave holds a 64 x 64 (t2) or 64 x 32 (ooov) tile.
+template <int CLS>
+struct AdjWave {
+  static constexpr bool kReduce = CLS == kAdjT2vv || CLS == kAdjOoov;
+  static constexpr int BLK = kReduce ? 1 : kABlk;
+  static constexpr int TRW = kReduce ? 4 : kAT;
+  static constexpr int TCW = CLS == kAdjT2vv ? 4 : CLS == kAdjOoov ? 2 : kAT;
+};
+
+// Work-group tile of a class: (blocks, rows, cols) per work-group: 4 waves
+// along the blocks (per-block classes), 2 x 2 waves (t2 from the d-sums) or
+// 4 x 1 (ooov).
 __host__ __device__ inline void adj_tile_shape(int cls, int& tb, int& tr, int& tc) {
   const bool red = cls == kAdjT2vv || cls == kAdjOoov;
   tb = red ? 1 : 4 * kABlk;
-  tr = cls == kAdjT2vv ? 2 * 16 * kAT : cls == kAdjOoov ? 4 * 16 * kAT : 16 * kAT;
-  tc = cls == kAdjT2vv ? 2 * 16 * kAT : 16 * kAT;
+  tr = cls == kAdjT2vv ? 2 * 64 : cls == kAdjOoov ? 4 * 64 : 16 * kAT;
+  tc = cls == kAdjT2vv ? 2 * 64 : cls == kAdjOoov ? 32 : 16 * kAT;
 }
 
 // Work-groups per output slice of a class for a fragment.
@@ -478,13 +513,19 @@ __device__ __forceinline__ int find_group(const AdjGroup* __restrict__ gs, int n
 }
 
 // Grid: the concatenated tiles of the launch's groups.  Block: 256 threads.
-// arena holds per unit G, H and Gt (cube_off, + half, + 2 half).
+// arena holds per unit G, H and Gt (cube_off, + half, + 2 half).  Per-block
+// classes add their tile into the gradient (read-modify-write: a slice's
+// groups run in separate launches of successive rounds only); summed-block
+// classes store their tile of the group's partial slice into parts (at
+// gr.part_off, o.nr x o.nc row-major), summed by k_adj_part_sum.
 template <int CLS, typename CubeT, typename InT>
-__global__ __launch_bounds__(kAThreads, 2) void k_adj_contract(
+__global__ __launch_bounds__(kAThreads, CLS == kAdjT2vv ? 1 : 2) void k_adj_contract(
     const FragDesc* __restrict__ descs, const Item* __restrict__ items,
     const AdjGroup* __restrict__ groups, int n_groups, const AdjRec* __restrict__ recs,
-    const CubeT* __restrict__ arena) {
-  constexpr bool kReduce = CLS == kAdjT2vv || CLS == kAdjOoov;
+    const CubeT* __restrict__ arena, double* __restrict__ parts) {
+  using W = AdjWave<CLS>;
+  constexpr bool kReduce = W::kReduce;
+  constexpr int BLK = W::BLK, TRW = W::TRW, TCW = W::TCW;
   const int gi = find_group(groups, n_groups, blockIdx.x);
   const AdjGroup gr = groups[gi];
   const int64_t start = gi ? groups[gi - 1].wg_end : 0;
@@ -504,30 +545,42 @@ __global__ __launch_bounds__(kAThreads, 2) void k_adj_contract(
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int r = lane & 15, g = lane >> 4;
   // this wave's part of the tile
-  constexpr int BLK = kReduce ? kARB : kABlk;
   const int blk0 = kReduce ? 0 : tb * TB + wave * kABlk;
-  const int row0 = trow * TR + (CLS == kAdjT2vv ? (wave & 1) * 16 * kAT
-                                : CLS == kAdjOoov ? wave * 16 * kAT : 0);
-  const int col0 = tcol * TC + (CLS == kAdjT2vv ? (wave >> 1) * 16 * kAT : 0);
+  const int row0 = trow * TR + (CLS == kAdjT2vv ? (wave & 1) * 16 * TRW
+                                : CLS == kAdjOoov ? wave * 16 * TRW : 0);
+  const int col0 = tcol * TC + (CLS == kAdjT2vv ? (wave >> 1) * 16 * TCW : 0);
   if ((!kReduce && blk0 >= o.nb) || row0 >= o.nr || col0 >= o.nc) return;   // no barriers
-  const int nrow = min(16 * kAT, o.nr - row0), ncol = min(16 * kAT, o.nc - col0);
-  const int nblk_tile = kReduce ? BLK : min(kABlk, o.nb - blk0);
-  const bool r1 = nrow > 16, c1 = ncol > 16;
+  const int nrow = min(16 * TRW, o.nr - row0), ncol = min(16 * TCW, o.nc - col0);
+  const int nblk_tile = kReduce ? 1 : min(kABlk, o.nb - blk0);
   const bool vec = fd.vec != 0;
 
-  d4 acc[BLK][kAT][kAT];
+  d4 acc[BLK][TRW][TCW];
 #pragma unroll
   for (int b = 0; b < BLK; ++b)
 #pragma unroll
-    for (int p = 0; p < kAT; ++p)
+    for (int p = 0; p < TRW; ++p)
 #pragma unroll
-      for (int q = 0; q < kAT; ++q) acc[b][p][q] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int q = 0; q < TCW; ++q) acc[b][p][q] = d4{0.0, 0.0, 0.0, 0.0};
 
   const InT* t2p = static_cast<const InT*>(fd.t2);
   const InT* ovvvp = static_cast<const InT*>(fd.ovvv);
   const InT* ooovp = static_cast<const InT*>(fd.ooov);
   const int nchunk = (nv + kAKc - 1) / kAKc;
 
+  // one K run (a term, or one summed virtual of a summed-block term): two
+  // chunks in flight
+  auto run = [&](const ATerm<CubeT, InT>& tm, int nblk) {
+    AChunk<BLK, TRW, TCW> b0, b1;
+    adj_load(tm, kReduce, 0, nv, nrow, ncol, nblk, r, g, vec, b0);
+    for (int c = 0;; c += 2) {
+      adj_load(tm, kReduce, c + 1, nv, nrow, ncol, nblk, r, g, vec, b1);
+      adj_mma(b0, kReduce, nrow, ncol, acc);
+      if (c + 1 >= nchunk) break;
+      adj_load(tm, kReduce, c + 2, nv, nrow, ncol, nblk, r, g, vec, b0);
+      adj_mma(b1, kReduce, nrow, ncol, acc);
+      if (c + 2 >= nchunk) break;
+    }
+  };
   for (int rec = gr.rec_begin; rec < gr.rec_end; ++rec) {
     const AdjRec rr = recs[rec];
     const Item it = items[rr.item];
@@ -536,36 +589,30 @@ __global__ __launch_bounds__(kAThreads, 2) void k_adj_contract(
     const CubeT* G = arena + it.cube_off;
     const ATerm<CubeT, InT> tm = make_adj<CLS, CubeT, InT>(
         rr.kind, rr.g, i, j, k, no, nv, G, G + 2 * fd.half, t2p, ovvvp, ooovp, blk0, row0, col0);
-    const int nblk = kReduce ? tm.nblk : nblk_tile;
-    AChunk<BLK> b0, b1;
-    adj_load(tm, kReduce, 0, nv, 0, 0, nrow, ncol, nblk, r, g, vec, b0);
-    for (int c = 0;; c += 2) {
-      adj_load(tm, kReduce, c + 1, nv, 0, 0, nrow, ncol, nblk, r, g, vec, b1);
-      adj_mma(b0, kReduce, r1, c1, acc);
-      if (c + 1 >= nchunk) break;
-      adj_load(tm, kReduce, c + 2, nv, 0, 0, nrow, ncol, nblk, r, g, vec, b0);
-      adj_mma(b1, kReduce, r1, c1, acc);
-      if (c + 2 >= nchunk) break;
+    if (kReduce) {
+      for (int kb = 0; kb < tm.nblk; ++kb) {   // the group's summed virtuals, one at a time
+        ATerm<CubeT, InT> t1 = tm;
+        t1.a += kb * tm.a_b;
+        t1.b += kb * tm.b_b;
+        run(t1, 1);
+      }
+    } else {
+      run(tm, nblk_tile);
     }
   }
 
   // acc[beta][rt][ct][v] = out[blk0 + beta][row0 + 16 rt + 4 v + g][col0 + 16 ct + r]
 #pragma unroll
-  for (int rt = 0; rt < kAT; ++rt)
+  for (int rt = 0; rt < TRW; ++rt)
 #pragma unroll
-    for (int ct = 0; ct < kAT; ++ct) {
+    for (int ct = 0; ct < TCW; ++ct) {
       const int col = col0 + 16 * ct + r;
       if (kReduce) {
-        d4 sum = acc[0][rt][ct];
-#pragma unroll
-        for (int beta = 1; beta < BLK; ++beta) sum += acc[beta][rt][ct];
+        SIE_GLOBAL double* pp = gptr_w(parts) + gr.part_off;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = row0 + 16 * rt + 4 * v + g;
-          if (row < o.nr && col < o.nc) {
-            SIE_GLOBAL double* p = gptr_w(o.out) + row * o.orow + col * o.ocol;
-            *p = *p + sum[v];
-          }
+          if (row < o.nr && col < o.nc) pp[int64_t(row) * o.nc + col] = acc[0][rt][ct][v];
         }
       } else {
 #pragma unroll
@@ -582,6 +629,28 @@ __global__ __launch_bounds__(kAThreads, 2) void k_adj_contract(
         }
       }
     }
+}
+
+// gradient slice += sum of its partial slices, in slot order (fixed), for
+// the summed-block classes.  Grid: (element chunks of 256, slices).
+template <int CLS>
+__global__ __launch_bounds__(256) void k_adj_part_sum(const FragDesc* __restrict__ descs,
+                                                      const AdjSlice* __restrict__ slices,
+                                                      const double* __restrict__ parts) {
+  const AdjSlice sl = slices[blockIdx.y];
+  const FragDesc fd = descs[sl.frag];
+  AdjGroup gr{};
+  gr.a0 = sl.a0;
+  gr.a1 = sl.a1;
+  const AdjOut o = adj_out<CLS>(fd, gr);
+  const int64_t n = int64_t(o.nr) * o.nc;
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= n) return;
+  double s = 0.0;
+  for (int q = 0; q < sl.nparts; ++q) s += gptr(parts)[sl.off0 + int64_t(q) * n + e];
+  const int row = int(e / o.nc), col = int(e - int64_t(row) * o.nc);
+  SIE_GLOBAL double* p = gptr_w(o.out) + row * o.orow + col * o.ocol;
+  *p = *p + s;
 }
 
 // ---------------------------------------------------------------------------

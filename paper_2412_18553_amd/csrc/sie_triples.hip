@@ -95,9 +95,10 @@ struct Plan {
   int64_t total_units = 0, total_work = 0;
   int pstride = 0;
   size_t off_desc = 0, off_eps = 0, off_units = 0, off_part = 0, off_efrag = 0, off_items = 0;
-  size_t off_split = 0, off_adj = 0, off_t1 = 0, off_arena = 0;
+  size_t off_split = 0, off_adj = 0, off_t1 = 0, off_parts = 0, off_arena = 0;
   int nv_max = 1;            // largest n_vir (row stride of the t1 partials)
   size_t adj_recs = 0;       // bound on the adjoint records (= groups) of all rounds
+  size_t part_elems = 0;     // bound on the partial-slice elements of a summed-block class
   size_t fixed_bytes = 0;    // everything before the arena
   int cubes = 2;             // cubes per unit in flight (backward: G, H and G transposed)
   bool pair = false;         // pair units build one layout into one cube (energy only)
@@ -114,6 +115,7 @@ size_t adj_recs_per_unit(int nv) {
 }
 
 int tile_variant(int nv);
+bool aligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) % a) == 0; }
 
 Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad = false) {
   Plan p;
@@ -143,7 +145,13 @@ Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad =
     const size_t n_pair = p.pair ? size_t(fp.no) * size_t(fp.no - 1) : 0;
     p.all_arena += pair * (size_t(fp.work_units) - n_pair) +
                    size_t(fp.cubes_pair) * fp.half_bytes * n_pair;
-    if (grad) p.adj_recs += size_t(fp.work_units) * adj_recs_per_unit(fp.nv);
+    if (grad) {
+      p.adj_recs += size_t(fp.work_units) * adj_recs_per_unit(fp.nv);
+      // a round's slices of a summed-block class are distinct occupied pairs
+      // (at most n_o^2 per fragment), each with at most kAdjParts partials
+      const size_t slice = size_t(fp.nv) * size_t(fp.nv > fp.no ? fp.nv : fp.no);
+      p.part_elems += size_t(sie::kAdjParts) * size_t(fp.no) * size_t(fp.no) * slice;
+    }
     p.nv_max = fp.nv > p.nv_max ? fp.nv : p.nv_max;
     p.frags.push_back(fp);
   }
@@ -163,15 +171,17 @@ Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad =
   p.off_split = off;
   off = align_up(off + split_bytes, 256);
   p.off_adj = off;
-  off = align_up(off + (sizeof(sie::AdjRec) + sizeof(sie::AdjGroup)) * p.adj_recs + 256, 256);
+  off = align_up(off + (sizeof(sie::AdjRec) + sizeof(sie::AdjGroup) + sizeof(sie::AdjSlice)) *
+                           p.adj_recs + 512, 256);
   p.off_t1 = off;
   if (grad) off = align_up(off + sizeof(double) * size_t(kT1Batch) * size_t(p.nv_max), 256);
+  p.off_parts = off;
+  if (grad) off = align_up(off + sizeof(double) * p.part_elems, 256);
   p.off_arena = off;
   p.fixed_bytes = off;
   return p;
 }
 
-bool aligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) % a) == 0; }
 
 sie_status check_fragment(const sie_fragment* f, sie_precision prec, const char* who) {
   std::string w(who);
@@ -764,10 +774,20 @@ struct AdjLaunch {
   int n_groups = 0;
   int64_t n_wg = 0;
   int rec_begin = 0, rec_end = 0;   // the class's records in the uploaded record table
+  size_t slice_off = 0;   // summed-block classes: output slices in the slice table
+  int n_slices = 0;
+  int64_t max_slice = 0;  // largest slice (elements): the partial-sum grid
+  int64_t part_elems = 0; // partial-slice elements the class writes
 };
 
+// Output-slice elements of a summed-block class for a fragment.
+int64_t adj_slice_elems(int cls, int no, int nv) {
+  return cls == sie::kAdjT2vv ? int64_t(nv) * nv : int64_t(nv) * no;
+}
+
 void adj_round_lists(const Tables& T, size_t r0, size_t r1, std::vector<sie::AdjGroup>& groups,
-                     std::vector<sie::AdjRec>& recs, AdjLaunch (&launch)[sie::kAdjClasses]) {
+                     std::vector<sie::AdjRec>& recs, std::vector<sie::AdjSlice>& slices,
+                     AdjLaunch (&launch)[sie::kAdjClasses]) {
   for (int cls = 0; cls < sie::kAdjClasses; ++cls) {
     struct Key {
       int frag, a0, a1;
@@ -809,28 +829,47 @@ void adj_round_lists(const Tables& T, size_t r0, size_t r1, std::vector<sie::Adj
     launch[cls].group_off = groups.size();
     launch[cls].n_groups = 0;
     launch[cls].rec_begin = int(recs.size());
-    int64_t wg = 0;
+    launch[cls].slice_off = slices.size();
+    int64_t wg = 0, part_elems = 0;
     for (size_t q = 0; q < list.size();) {
       size_t e = q;
       while (e < list.size() && !(list[q].first < list[e].first) && !(list[e].first < list[q].first))
         ++e;
       const Key& key = list[q].first;
       const sie::FragDesc& d = T.desc[size_t(key.frag)];
-      sie::AdjGroup gr{};
-      gr.frag = key.frag;
-      gr.a0 = key.a0;
-      gr.a1 = key.a1;
-      gr.rec_begin = int(recs.size());
-      for (size_t m = q; m < e; ++m) recs.push_back(list[m].second);
-      gr.rec_end = int(recs.size());
-      wg += sie::adj_tiles(cls, d.no, d.nv);
-      gr.wg_end = wg;
-      groups.push_back(gr);
-      ++launch[cls].n_groups;
+      // summed-block classes: the slice's records split into up to kAdjParts
+      // contiguous ranges, each a group writing its own partial slice
+      const bool red = sie::adj_reduce(cls);
+      const int n = int(e - q);
+      const int np = red ? (n < sie::kAdjParts ? n : sie::kAdjParts) : 1;
+      const int64_t el = red ? adj_slice_elems(cls, d.no, d.nv) : 0;
+      const int64_t off0 = part_elems;
+      if (red) {
+        slices.push_back(sie::AdjSlice{key.frag, key.a0, key.a1, np, off0});
+        part_elems += el * np;
+        launch[cls].max_slice = el > launch[cls].max_slice ? el : launch[cls].max_slice;
+        ++launch[cls].n_slices;
+      }
+      for (int pp = 0; pp < np; ++pp) {
+        const size_t b0 = q + size_t(n) * pp / np, b1 = q + size_t(n) * (pp + 1) / np;
+        sie::AdjGroup gr{};
+        gr.frag = key.frag;
+        gr.a0 = key.a0;
+        gr.a1 = key.a1;
+        gr.part_off = off0 + el * pp;
+        gr.rec_begin = int(recs.size());
+        for (size_t m = b0; m < b1; ++m) recs.push_back(list[m].second);
+        gr.rec_end = int(recs.size());
+        wg += sie::adj_tiles(cls, d.no, d.nv);
+        gr.wg_end = wg;
+        groups.push_back(gr);
+        ++launch[cls].n_groups;
+      }
       q = e;
     }
     launch[cls].n_wg = wg;
     launch[cls].rec_end = int(recs.size());
+    launch[cls].part_elems = part_elems;
   }
 }
 
@@ -838,7 +877,8 @@ void adj_round_lists(const Tables& T, size_t r0, size_t r1, std::vector<sie::Adj
 template <typename CubeT, typename InT>
 void backward_round(const std::array<AdjLaunch, sie::kAdjClasses>& L, hipStream_t s,
                     const sie::FragDesc* d_desc, const sie::Item* ri, int cnt,
-                    const sie::AdjGroup* d_groups, const sie::AdjRec* d_recs, CubeT* arena,
+                    const sie::AdjGroup* d_groups, const sie::AdjRec* d_recs,
+                    const sie::AdjSlice* d_slices, double* d_parts, CubeT* arena,
                     double* d_part, int pstride, const double* grad_e, unsigned n_epi,
                     double* t1_part, int nv_max) {
   {
@@ -851,12 +891,20 @@ void backward_round(const std::array<AdjLaunch, sie::kAdjClasses>& L, hipStream_
     if (l.n_wg)
       hipLaunchKernelGGL(kernel, dim3(unsigned(l.n_wg)), dim3(sie::kAThreads), 0, s, d_desc, ri,
                          d_groups + l.group_off, l.n_groups, d_recs,
-                         static_cast<const CubeT*>(arena));
+                         static_cast<const CubeT*>(arena), d_parts);
+  };
+  auto part_sum = [&](auto kernel, const AdjLaunch& l) {   // after the class's contraction
+    if (l.n_slices)
+      hipLaunchKernelGGL(kernel, dim3(unsigned((l.max_slice + 255) / 256), unsigned(l.n_slices)),
+                         dim3(256), 0, s, d_desc, d_slices + l.slice_off,
+                         static_cast<const double*>(d_parts));
   };
   contract(sie::k_adj_contract<sie::kAdjOvvv, CubeT, InT>, L[sie::kAdjOvvv]);
   contract(sie::k_adj_contract<sie::kAdjT2vv, CubeT, InT>, L[sie::kAdjT2vv]);
+  part_sum(sie::k_adj_part_sum<sie::kAdjT2vv>, L[sie::kAdjT2vv]);
   contract(sie::k_adj_contract<sie::kAdjT2oo, CubeT, InT>, L[sie::kAdjT2oo]);
   contract(sie::k_adj_contract<sie::kAdjOoov, CubeT, InT>, L[sie::kAdjOoov]);
+  part_sum(sie::k_adj_part_sum<sie::kAdjOoov>, L[sie::kAdjOoov]);
   const AdjLaunch& lp = L[sie::kAdjOvov];
   if (lp.n_wg)
     hipLaunchKernelGGL((sie::k_adj_ovov<CubeT, InT>), dim3(unsigned(lp.n_wg)), dim3(256), 0, s,
@@ -913,16 +961,22 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
   const size_t n_rounds = T.round_begin.size() - 1;
   std::vector<sie::AdjGroup> groups;
   std::vector<sie::AdjRec> recs;
+  std::vector<sie::AdjSlice> slices;
   std::vector<std::array<AdjLaunch, sie::kAdjClasses>> launches(n_rounds);
   for (size_t q = 0; q < n_rounds; ++q) {
     AdjLaunch l[sie::kAdjClasses];
-    adj_round_lists(T, T.round_begin[q], T.round_begin[q + 1], groups, recs, l);
-    for (int c = 0; c < sie::kAdjClasses; ++c) launches[q][size_t(c)] = l[c];
+    adj_round_lists(T, T.round_begin[q], T.round_begin[q + 1], groups, recs, slices, l);
+    for (int c = 0; c < sie::kAdjClasses; ++c) {
+      launches[q][size_t(c)] = l[c];
+      if (size_t(l[c].part_elems) > pl.part_elems)
+        return fail(SIE_ERR_HIP, w + ": internal error: partial slices exceed their bound");
+    }
   }
-  if (recs.size() > pl.adj_recs || groups.size() > pl.adj_recs)
+  if (recs.size() > pl.adj_recs || groups.size() > pl.adj_recs || slices.size() > pl.adj_recs)
     return fail(SIE_ERR_HIP, w + ": internal error: contraction lists exceed their bound");
   const size_t off_recs = pl.off_adj;
   const size_t off_groups = align_up(off_recs + sizeof(sie::AdjRec) * pl.adj_recs, 256);
+  const size_t off_slices = align_up(off_groups + sizeof(sie::AdjGroup) * pl.adj_recs, 256);
 
   sie_status st = hip_check(hipMemcpyAsync(dev(pl.off_desc), T.desc.data(),
                                            sizeof(sie::FragDesc) * T.desc.size(),
@@ -941,6 +995,10 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
     st = hip_check(hipMemcpyAsync(dev(off_groups), groups.data(),
                                   sizeof(sie::AdjGroup) * groups.size(), hipMemcpyHostToDevice, s),
                    "upload contraction groups");
+  if (st == SIE_OK && !slices.empty())
+    st = hip_check(hipMemcpyAsync(dev(off_slices), slices.data(),
+                                  sizeof(sie::AdjSlice) * slices.size(), hipMemcpyHostToDevice, s),
+                   "upload contraction slices");
   if (st == SIE_OK) st = hip_check(hipStreamSynchronize(s), "upload tables");
   if (st != SIE_OK) return st;
 
@@ -948,6 +1006,8 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
   const sie::Item* d_items = reinterpret_cast<const sie::Item*>(dev(pl.off_items));
   const sie::AdjRec* d_recs = reinterpret_cast<const sie::AdjRec*>(dev(off_recs));
   const sie::AdjGroup* d_groups = reinterpret_cast<const sie::AdjGroup*>(dev(off_groups));
+  const sie::AdjSlice* d_slices = reinterpret_cast<const sie::AdjSlice*>(dev(off_slices));
+  double* d_parts = reinterpret_cast<double*>(dev(pl.off_parts));
   double* d_units = reinterpret_cast<double*>(dev(pl.off_units));
   double* d_part = reinterpret_cast<double*>(dev(pl.off_part));
   double* d_efrag = e_frag_out ? e_frag_out : reinterpret_cast<double*>(dev(pl.off_efrag));
@@ -993,12 +1053,13 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
         build_round_f64(T, q, s, d_desc, d_items, arena);
     }
     if (pl.split)
-      backward_round<float, float>(launches[q], s, d_desc, ri, cnt, d_groups, d_recs,
-                                   reinterpret_cast<float*>(dev(pl.off_arena)), d_part,
+      backward_round<float, float>(launches[q], s, d_desc, ri, cnt, d_groups, d_recs, d_slices,
+                                   d_parts, reinterpret_cast<float*>(dev(pl.off_arena)), d_part,
                                    pl.pstride, grad_e, unsigned(T.items[r1 - 1].part_end),
                                    t1_part, pl.nv_max);
     else
-      backward_round<double, double>(launches[q], s, d_desc, ri, cnt, d_groups, d_recs, arena,
+      backward_round<double, double>(launches[q], s, d_desc, ri, cnt, d_groups, d_recs, d_slices,
+                                     d_parts, arena,
                                      d_part, pl.pstride, grad_e,
                                      unsigned(T.items[r1 - 1].part_end), t1_part, pl.nv_max);
     st = hip_check(hipGetLastError(), "launch backward kernels");

@@ -68,7 +68,7 @@ def test_gradient_with_three_layout_table():
     """A tile table that selects a three-layout build shape for the energy:
     the gradient rebuilds W-tilde with a two-layout shape and is unchanged."""
     import paper_2412_18553_amd as sie
-    three = [v for v, s in enumerate(sie.tile_variants()) if s[6] == 3]
+    three = [v for v, s in enumerate(sie.tile_variants()) if s[6] >= 3]
     assert three
     f = make_fragment(4, 20, 30, (11, 12))
     _, _, _, ref = energy_gradient(*f.arrays())
