@@ -222,6 +222,21 @@ sie_status sie_tile_variant_shape(int32_t variant, int32_t* shape);
 int32_t sie_tile_variant_of(int32_t n_vir);
 sie_status sie_set_tile_table(int32_t n, const int32_t* nv_max, const int32_t* variant);
 
+/* Tile shapes of the split-precision W-tilde build.  A work-group of shape s
+ * computes 16 TRW rows x 64 TCW cols of one block of one layout, with
+ * (TRW, TCW) = (4, 2), (5, 5), (7, 4), (4, 4) for s = 0, 1, 2, 3.
+ * sie_split_shape_of returns the shape a fragment with n_vir virtuals builds
+ * with (-1 for n_vir < 1): by default the one of least padded tile area,
+ * preferring the larger tile among shapes within 10% of it.
+ * sie_set_split_shape forces shape s for every fragment of later evaluations
+ * (s = -1 restores the default; SIE_ERR_INVALID_ARG outside [-1,
+ * SIE_SPLIT_SHAPES)).  Energies do not depend on the shape beyond rounding of
+ * the contraction order.  Not to be called while another thread runs an
+ * evaluation. */
+#define SIE_SPLIT_SHAPES 4
+int32_t sie_split_shape_of(int32_t n_vir);
+sie_status sie_set_split_shape(int32_t shape);
+
 const char* sie_last_error(void);
 int sie_abi_version(void);
 

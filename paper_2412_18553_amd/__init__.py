@@ -284,6 +284,18 @@ def tile_variant_of(n_vir: int) -> int:
     return int(_lib.load().sie_tile_variant_of(int(n_vir)))
 
 
+def split_shape_of(n_vir: int) -> int:
+    """The tile shape the split-precision build of a fragment with n_vir
+    virtuals uses (see sie_split_shape_of)."""
+    return int(_lib.load().sie_split_shape_of(int(n_vir)))
+
+
+def set_split_shape(shape: int = -1) -> None:
+    """Force split build shape `shape` for all fragments, or restore the
+    automatic choice with -1."""
+    _lib.check(_lib.load().sie_set_split_shape(int(shape)))
+
+
 def set_tile_table(table=None) -> None:
     """Install [(n_vir upper bound, variant), ...] (ascending) for the float64
     build, or the built-in tuned table with None."""

@@ -29,7 +29,7 @@ EXPORTED = ["sie_abi_version", "sie_last_error", "sie_occupied_triples",
             "sie_triples_workspace_size", "sie_triples_energy", "sie_triples_energy_batched",
             "sie_triples_backward_workspace_size", "sie_triples_backward",
             "sie_tile_variants", "sie_tile_variant_shape", "sie_tile_variant_of",
-            "sie_set_tile_table",
+            "sie_set_tile_table", "sie_split_shape_of", "sie_set_split_shape",
             "sie_profile_enable", "sie_profile_collect"]
 PROF_CLASSES = ("w_build", "epilogue", "reduce", "split", "grad")
 
@@ -106,6 +106,10 @@ def load() -> ctypes.CDLL:
     lib.sie_set_tile_table.restype = ctypes.c_int
     lib.sie_set_tile_table.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32)]
+    lib.sie_split_shape_of.restype = ctypes.c_int32
+    lib.sie_split_shape_of.argtypes = [ctypes.c_int32]
+    lib.sie_set_split_shape.restype = ctypes.c_int
+    lib.sie_set_split_shape.argtypes = [ctypes.c_int32]
     lib.sie_profile_enable.restype = None
     lib.sie_profile_enable.argtypes = [ctypes.c_int]
     lib.sie_profile_collect.restype = ctypes.c_int

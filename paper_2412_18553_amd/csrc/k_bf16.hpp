@@ -176,106 +176,161 @@ __device__ __forceinline__ TermS make_term_split(bool l2, int q, const FragDesc&
   return t;
 }
 
-// Per-thread staging registers for one K chunk (kKs = 4 groups): per-block
-// units kBB * kRows * 4 over kThreads threads, one shared unit at most.
-constexpr int kBlUnitsS = (kBB * kRows * (kKs / 8) + kThreads - 1) / kThreads;
+// ---------------------------------------------------------------------------
+// Split build.  A work-group computes, for one unit, one layout and one
+// block, the six terms over a tile of 16 TRW rows x 64 TCW cols; its four
+// waves sit side by side along the cols, wave w owning cols
+// 16 TCW w .. 16 TCW (w + 1) - 1 of the tile.  Each term is
+//   tile[row][col] += sum_K A[row][K] * B[col][K]
+// with A and B two row-major split copies (one of them the per-block
+// operand).  The A rows of a K chunk are read by all four waves, so they are
+// staged through LDS (double-buffered, one barrier per chunk); each wave's B
+// cols are its own and go straight from memory into registers, one chunk
+// ahead.  Per chunk a wave issues 3 TRW TCW MFMAs for 2 TRW LDS reads and
+// 2 TCW loads of 16 bytes per lane.
+// ---------------------------------------------------------------------------
 
-struct StageS {
-  u4v blh[kBlUnitsS], bll[kBlUnitsS];
-  u4v shh, shl;
+// Tile shapes (TRW x TCW MFMA tiles per wave).
+struct SShape {
+  int trw, tcw;
+};
+constexpr int kSShapes = 4;
+__host__ __device__ constexpr SShape sshape(int s) {
+  return s == 1 ? SShape{5, 5} : s == 2 ? SShape{7, 4} : s == 3 ? SShape{4, 4} : SShape{4, 2};
+}
+__host__ __device__ inline int64_t split_tiles(int nv, int s) {
+  const int R = 16 * sshape(s).trw, C = 64 * sshape(s).tcw;
+  return int64_t(nv) * ((nv + R - 1) / R) * ((nv + C - 1) / C);
+}
+// Shape of a fragment with n_v virtuals: the least padded tile area, and
+// among the shapes within 10% of it the one with the largest tile (more
+// operand reuse).
+inline int split_shape_of(int nv) {
+  int64_t best = -1;
+  for (int s = 0; s < kSShapes; ++s) {
+    const int64_t a = split_tiles(nv, s) / nv * 16 * sshape(s).trw * 64 * sshape(s).tcw;
+    best = (best < 0 || a < best) ? a : best;
+  }
+  int pick = 0, area = 0;
+  for (int s = 0; s < kSShapes; ++s) {
+    const int64_t a = split_tiles(nv, s) / nv * 16 * sshape(s).trw * 64 * sshape(s).tcw;
+    const int t = sshape(s).trw * sshape(s).tcw;
+    if (10 * a <= 11 * best && t > area) {
+      pick = s;
+      area = t;
+    }
+  }
+  return pick;
+}
+
+// One term's operands for a work-group: wave-uniform bases at row 0 / col 0
+// of the tile and K group 0, row strides in bytes, K chunks, and the sign
+// bits xor'ed into A (the minus of the occupied sums).
+struct SOp {
+  const char* a;
+  const char* b;
+  uint32_t sa, sb;
+  int nch;
+  uint32_t flip;
 };
 
-__device__ __forceinline__ void stage_load_s(const TermS& t, int c, const TileDims& d, int tid,
-                                             StageS& st) {
-  const int Xb = t.a_is_bl ? kRows : kCols;
-  const int Xs = t.a_is_bl ? kCols : kRows;
-  const int xbmax = (t.a_is_bl ? d.nrow : d.ncol) - 1;
-  const int xsmax = (t.a_is_bl ? d.ncol : d.nrow) - 1;
-  const int nbl = kBB * Xb * 4;
-  const int g0 = c * (kKs / 8);
-  // every thread loads a valid (clamped) unit for every slot; only the stores
-  // of slots past the operand's extent are skipped
-#pragma unroll
-  for (int m = 0; m < kBlUnitsS; ++m) {
-    int u = tid + m * kThreads;
-    u = u < nbl ? u : nbl - 1;
-    const int gq = u & 3, rr = u >> 2;
-    int beta = rr / Xb, x = rr - (rr / Xb) * Xb;
-    beta = beta < d.nblk ? beta : d.nblk - 1;
-    x = x < xbmax ? x : xbmax;
-    const SIE_GLOBAL u4v* p =
-        gptr(t.bl + ((int64_t)beta * t.bl_b + (int64_t)x * t.bl_x + g0 + gq) * 2);
-    st.blh[m] = p[0];
-    st.bll[m] = p[1];
-  }
-  int u = tid;
-  const int nsh = Xs * 4;
-  u = u < nsh ? u : nsh - 1;
-  const int gq = u & 3;
-  int x = u >> 2;
-  x = x < xsmax ? x : xsmax;
-  const SIE_GLOBAL u4v* p = gptr(t.sh + ((int64_t)x * t.sh_x + g0 + gq) * 2);
-  // loaded values are left untouched until stage_store_s (after the chunk's
-  // MFMAs), so the loads stay in flight across them
-  st.shh = p[0];
-  st.shl = p[1];
+__device__ __forceinline__ SOp split_op(bool l2, int q, const FragDesc& f, int i, int j, int k,
+                                        int blk, int row0, int col0) {
+  const TermS t = make_term_split(l2, q, f, i, j, k, blk, row0, col0);
+  SOp o;
+  const char* bl = reinterpret_cast<const char*>(t.bl);
+  const char* sh = reinterpret_cast<const char*>(t.sh);
+  const uint32_t sbl = uint32_t(t.bl_x) * 32u, ssh = uint32_t(t.sh_x) * 32u;
+  o.a = t.a_is_bl ? bl : sh;
+  o.sa = t.a_is_bl ? sbl : ssh;
+  o.b = t.a_is_bl ? sh : bl;
+  o.sb = t.a_is_bl ? ssh : sbl;
+  o.nch = t.nG / (kKs / 8);
+  o.flip = t.neg ? 0x80008000u : 0u;
+  return o;
 }
 
-// LDS: [group in chunk (4)][hi, lo][row] of u4v (8 bf16).
-__device__ __forceinline__ void stage_store_s(const TermS& t, int tid, const StageS& st,
-                                              u4v (*buf)[2][kLdsRows]) {
-  const int Xb = t.a_is_bl ? kRows : kCols;
-  const int Xs = t.a_is_bl ? kCols : kRows;
-  const int nbl = kBB * Xb * 4;
+__device__ __forceinline__ u4v ld_u4(const char* base, uint32_t off) {
+  return *(const SIE_GLOBAL u4v*)(gptr(base) + off);
+}
+
+// Lane offsets of one term: A staging slots and this lane's B cols.
+template <int NA, int TCW>
+struct SLane {
+  uint32_t a[NA];
+  uint32_t b[TCW];
+};
+
+template <int TRW, int TCW, int NA>
+__device__ __forceinline__ void split_lane(const SOp& o, int tid, int wave, int r, int g,
+                                           int xa_max, int xb_max, SLane<NA, TCW>& L) {
+  constexpr int R = 16 * TRW;
 #pragma unroll
-  for (int m = 0; m < kBlUnitsS; ++m) {
-    const int u = tid + m * kThreads;
-    if (u < nbl) {
-      const int gq = u & 3, rr = u >> 2;
-      buf[gq][0][rr] = st.blh[m];
-      buf[gq][1][rr] = st.bll[m];
-    }
+  for (int m = 0; m < NA; ++m) {
+    int u = tid + 256 * m;
+    u = u < 4 * R ? u : 4 * R - 1;
+    const int x = min(u >> 2, xa_max);
+    L.a[m] = uint32_t(x) * o.sa + uint32_t(u & 3) * 32u;
   }
-  const int u = tid;
-  if (u < Xs * 4) {
-    const int gq = u & 3, x = u >> 2;
-    const uint32_t flip = t.neg ? 0x80008000u : 0u;   // sign of the occupied sums
-    buf[gq][0][kShBase + x] = st.shh ^ flip;
-    buf[gq][1][kShBase + x] = st.shl ^ flip;
+#pragma unroll
+  for (int ct = 0; ct < TCW; ++ct) {
+    const int x = min(wave * 16 * TCW + 16 * ct + r, xb_max);
+    L.b[ct] = uint32_t(x) * o.sb + uint32_t(g) * 32u;
   }
 }
 
-__device__ __forceinline__ void mma_chunk_s(bool a_is_bl, const u4v (*buf)[2][kLdsRows], int g,
-                                            int rrow, int rcol, f4 (&acc)[kBB]) {
-  // the three products of each block in turn over all blocks: consecutive
-  // MFMAs never feed each other
-  u4v vh[kBB], vl[kBB];
-  if (a_is_bl) {
-    const u4v sh = buf[g][0][kShBase + rcol], sl = buf[g][1][kShBase + rcol];
+template <int NA, int TCW>
+struct SRegs {
+  u4v ah[NA], al[NA];     // A staging (hi, lo) for the LDS
+  u4v bh[TCW], bl[TCW];   // B fragments (hi, lo)
+};
+
+template <int NA, int TCW>
+__device__ __forceinline__ void split_load(const SOp& o, int c, const SLane<NA, TCW>& L,
+                                           SRegs<NA, TCW>& x) {
+  const char* a = o.a + c * 128;
+  const char* b = o.b + c * 128;
 #pragma unroll
-    for (int beta = 0; beta < kBB; ++beta) {
-      vh[beta] = buf[g][0][beta * kRows + rrow];
-      vl[beta] = buf[g][1][beta * kRows + rrow];
+  for (int m = 0; m < NA; ++m) {
+    x.ah[m] = ld_u4(a, L.a[m]);
+    x.al[m] = ld_u4(a, L.a[m] + 16u);
+  }
+#pragma unroll
+  for (int ct = 0; ct < TCW; ++ct) {
+    x.bh[ct] = ld_u4(b, L.b[ct]);
+    x.bl[ct] = ld_u4(b, L.b[ct] + 16u);
+  }
+}
+
+// LDS chunk: [K group (4)][hi, lo][row] of u4v.
+template <int R, int NA, int TCW>
+__device__ __forceinline__ void split_stage(const SRegs<NA, TCW>& x, uint32_t flip, int tid,
+                                            u4v (*buf)[2][R]) {
+#pragma unroll
+  for (int m = 0; m < NA; ++m) {
+    const int u = tid + 256 * m;
+    if (u < 4 * R) {
+      buf[u & 3][0][u >> 2] = x.ah[m] ^ flip;
+      buf[u & 3][1][u >> 2] = x.al[m] ^ flip;
     }
+  }
+}
+
+// The three products of every tile, ordered so that MFMAs into one
+// accumulator are TCW apart.
+template <int TRW, int TCW>
+__device__ __forceinline__ void split_mma(const u4v (*buf)[2][16 * TRW], int g, int r,
+                                          const u4v (&bh)[TCW], const u4v (&bl)[TCW],
+                                          f4 (&acc)[TRW][TCW]) {
 #pragma unroll
-    for (int beta = 0; beta < kBB; ++beta) acc[beta] = mfma_bf16(vl[beta], sh, acc[beta]);
+  for (int rt = 0; rt < TRW; ++rt) {
+    const u4v ah = buf[g][0][16 * rt + r], al = buf[g][1][16 * rt + r];
 #pragma unroll
-    for (int beta = 0; beta < kBB; ++beta) acc[beta] = mfma_bf16(vh[beta], sl, acc[beta]);
+    for (int ct = 0; ct < TCW; ++ct) acc[rt][ct] = mfma_bf16(al, bh[ct], acc[rt][ct]);
 #pragma unroll
-    for (int beta = 0; beta < kBB; ++beta) acc[beta] = mfma_bf16(vh[beta], sh, acc[beta]);
-  } else {
-    const u4v sh = buf[g][0][kShBase + rrow], sl = buf[g][1][kShBase + rrow];
+    for (int ct = 0; ct < TCW; ++ct) acc[rt][ct] = mfma_bf16(ah, bl[ct], acc[rt][ct]);
 #pragma unroll
-    for (int beta = 0; beta < kBB; ++beta) {
-      vh[beta] = buf[g][0][beta * kCols + rcol];
-      vl[beta] = buf[g][1][beta * kCols + rcol];
-    }
-#pragma unroll
-    for (int beta = 0; beta < kBB; ++beta) acc[beta] = mfma_bf16(sl, vh[beta], acc[beta]);
-#pragma unroll
-    for (int beta = 0; beta < kBB; ++beta) acc[beta] = mfma_bf16(sh, vl[beta], acc[beta]);
-#pragma unroll
-    for (int beta = 0; beta < kBB; ++beta) acc[beta] = mfma_bf16(sh, vh[beta], acc[beta]);
+    for (int ct = 0; ct < TCW; ++ct) acc[rt][ct] = mfma_bf16(ah, bh[ct], acc[rt][ct]);
   }
 }
 
@@ -285,81 +340,103 @@ __device__ __forceinline__ void mma_chunk_s(bool a_is_bl, const u4v (*buf)[2][kL
 #define SIE_BF16_DROW(v, g) (4 * (g) + (v))
 #endif
 
-// Split-precision partial cubes (float32) of one layout for one tile of one
-// unit; same grid, tiles and term order as k_build_w_f64.
-__global__ __launch_bounds__(kThreads, 1) void k_build_w_bf16x3(const FragDesc* __restrict__ descs,
-                                                                const Item* __restrict__ items,
-                                                                int n_items,
-                                                                float* __restrict__ arena) {
+// Split-precision partial cubes (float32): grid = the items' tiles, one
+// layout (pair units) or two per unit, split_tiles(n_v, shape) per layout.
+template <int TRW, int TCW>
+__global__ __launch_bounds__(256, 1) void k_build_w_bf16x3(const FragDesc* __restrict__ descs,
+                                                           const Item* __restrict__ items,
+                                                           int n_items,
+                                                           float* __restrict__ arena) {
+  constexpr int R = 16 * TRW, C = 64 * TCW;
+  constexpr int NA = (4 * R + 255) / 256;
   const int ri = find_item<true>(items, n_items, blockIdx.x);
   const int64_t start = ri ? items[ri - 1].blk_end : 0;
-  const FragDesc fd = descs[items[ri].frag];
+  const Item it = items[ri];
+  const FragDesc fd = descs[it.frag];
   int i, j, k;
-  const bool one = unit_triple(items[ri].unit, fd.no, fd.pair, i, j, k);
+  const bool one = unit_triple(it.unit, fd.no, fd.pair, i, j, k);
   if (i == k) return;
-  const BlockWork w = block_work(fd, items, ri, int64_t(blockIdx.x) - start, one);
   const int nv = fd.nv;
-  const bool l2 = w.l2;
-  const int blk0 = w.blk0, row0 = w.row0, col0 = w.col0;
-  TileDims dims;
-  dims.nblk = min(kBB, nv - blk0);
-  dims.nrow = min(kRows, nv - row0);
-  dims.ncol = min(kCols, nv - col0);
+  const int nrt = (nv + R - 1) / R, nct = (nv + C - 1) / C;
+  const int per = nv * nrt * nct;
+  int t = xcd_tile(int(int64_t(blockIdx.x) - start), one ? per : 2 * per);
+  const bool l2 = t >= per;
+  if (l2) t -= per;
+  const int blk = t / (nrt * nct);
+  t -= blk * nrt * nct;
+  const int tr = t / nct, tc = t - tr * nct;
+  const int row0 = tr * R, col0 = tc * C;
+  const int xa_max = min(R, nv - row0) - 1, xb_max = nv - 1 - col0;
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int r = lane & 15, g = lane >> 4;
-  const int rq = wave % (kRows / 16), ch = wave / (kRows / 16);
-  const int rrow = rq * 16 + r, rcol = ch * 16 + r;
 
-  __shared__ u4v lds[2][kKs / 8][2][kLdsRows];
+  __shared__ u4v lds[2][kKs / 8][2][R];
 
-  f4 acc[kBB];
+  f4 acc[TRW][TCW];
 #pragma unroll
-  for (int q = 0; q < kBB; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int a = 0; a < TRW; ++a)
+#pragma unroll
+    for (int b = 0; b < TCW; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
 
   int q = 0, c = 0;
-  TermS tcur = make_term_split(l2, 0, fd, i, j, k, blk0, row0, col0);
-  StageS st;
-  stage_load_s(tcur, 0, dims, tid, st);
-  stage_store_s(tcur, tid, st, lds[0]);
+  SOp cur = split_op(l2, 0, fd, i, j, k, blk, row0, col0);
+  SLane<NA, TCW> L;
+  split_lane<TRW, TCW, NA>(cur, tid, wave, r, g, xa_max, xb_max, L);
+  SRegs<NA, TCW> x;
+  split_load(cur, 0, L, x);
+  u4v bh[TCW], bl[TCW];
+  split_stage<R>(x, cur.flip, tid, lds[0]);
+#pragma unroll
+  for (int ct = 0; ct < TCW; ++ct) {
+    bh[ct] = x.bh[ct];
+    bl[ct] = x.bl[ct];
+  }
   __syncthreads();
   int buf = 0;
   while (true) {
-    int qn = q, cn = c + 1;
-    TermS tn = tcur;
+    int cn = c + 1;
     bool more = true;
-    if (cn * (kKs / 8) >= tcur.nG) {
+    SOp nxt = cur;
+    if (cn >= cur.nch) {
       if (q == 5) {
         more = false;
       } else {
-        qn = q + 1;
+        ++q;
         cn = 0;
-        tn = make_term_split(l2, qn, fd, i, j, k, blk0, row0, col0);
+        nxt = split_op(l2, q, fd, i, j, k, blk, row0, col0);
+        split_lane<TRW, TCW, NA>(nxt, tid, wave, r, g, xa_max, xb_max, L);
       }
     }
-    if (more) stage_load_s(tn, cn, dims, tid, st);
-    mma_chunk_s(tcur.a_is_bl, lds[buf], g, rrow, rcol, acc);
+    if (more) split_load(nxt, cn, L, x);
+    split_mma<TRW, TCW>(lds[buf], g, r, bh, bl, acc);
     if (!more) break;
-    stage_store_s(tn, tid, st, lds[buf ^ 1]);
+    split_stage<R>(x, nxt.flip, tid, lds[buf ^ 1]);
+#pragma unroll
+    for (int ct = 0; ct < TCW; ++ct) {
+      bh[ct] = x.bh[ct];
+      bl[ct] = x.bl[ct];
+    }
     __syncthreads();
     buf ^= 1;
-    q = qn;
     c = cn;
-    tcur = tn;
+    cur = nxt;
   }
 
-  float* __restrict__ out = arena + w.it.cube_off + (l2 ? fd.half : 0);
-  const int col = col0 + rcol;
+  float* __restrict__ out = arena + it.cube_off + (l2 ? fd.half : 0);
 #pragma unroll
-  for (int beta = 0; beta < kBB; ++beta) {
-    const int blk = blk0 + beta;
+  for (int ct = 0; ct < TCW; ++ct) {
+    const int col = col0 + wave * 16 * TCW + 16 * ct + r;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = row0 + rq * 16 + SIE_BF16_DROW(v, g);
-      if (blk < nv && row < nv && col < nv)
-        gptr_w(out)[((int64_t)blk * nv + row) * nv + col] = acc[beta][v];
-    }
+    for (int rt = 0; rt < TRW; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = row0 + 16 * rt + SIE_BF16_DROW(v, g);
+        if (row < nv && col < nv)
+          gptr_w(out)[((int64_t)blk * nv + row) * nv + col] = acc[rt][ct][v];
+      }
   }
 }
 

@@ -646,61 +646,6 @@ __global__ __launch_bounds__(256, BPC) void k_build_w3_f64(const FragDesc* __res
   }
 }
 
-// ---------------------------------------------------------------------------
-// Tile geometry of the LDS-staged split build (k_bf16.hpp): each work-group
-// computes, for one unit and one of the two register layouts, that layout's
-// six terms over kBB blocks x kRows rows x kCols cols, 8 waves, wave (rq, ch)
-// owning rows 16 rq .. 16 rq + 15 and cols 16 ch .. 16 ch + 15 of every block.
-// ---------------------------------------------------------------------------
-constexpr int kBB = 8;                          // blocks per work-group
-constexpr int kRows = 64;                       // MFMA rows per work-group (A side)
-constexpr int kCols = 32;                       // MFMA cols per work-group (B side)
-constexpr int kThreads = 64 * (kRows / 16) * (kCols / 16);
-constexpr int kLdsRows = kBB * kRows + kRows;   // per-block region + shared region
-constexpr int kShBase = kBB * kRows;            // first LDS row of the shared operand
-
-// Lane's row/col clamps for one tile: blocks, rows and cols inside [0, n_v).
-struct TileDims {
-  int nblk;       // valid blocks in the tile (>= 1)
-  int nrow;       // valid rows (>= 1)
-  int ncol;       // valid cols (>= 1)
-};
-
-// Build tiles of one layout for a fragment of n_v virtuals.
-__host__ __device__ __forceinline__ int64_t build_tiles(int nv) {
-  return int64_t((nv + kBB - 1) / kBB) * ((nv + kRows - 1) / kRows) * ((nv + kCols - 1) / kCols);
-}
-
-// Block -> (item, layout, tile) of a round.  Within an item, blocks that the
-// hardware places on one XCD (same index mod 8) get a contiguous range of
-// tiles, so they share operand rows in that XCD's L2.
-struct BlockWork {
-  Item it;
-  int l2;
-  int blk0, row0, col0;
-};
-
-// `one`: the item is a pair unit, which builds only the first layout.
-__device__ __forceinline__ BlockWork block_work(const FragDesc& fd, const Item* items, int r,
-                                                int64_t local, bool one) {
-  BlockWork w;
-  w.it = items[r];
-  const int64_t T = fd.tiles;
-  int64_t t = xcd_tile(int(local), int(one ? T : 2 * T));
-  w.l2 = t >= T;
-  if (w.l2) t -= T;
-  const int nv = fd.nv;
-  const int nrt = (nv + kRows - 1) / kRows, nct = (nv + kCols - 1) / kCols;
-  const int tb = int(t / (nrt * nct));
-  t -= int64_t(tb) * nrt * nct;
-  const int tr = int(t / nct);
-  const int tcol = int(t - int64_t(tr) * nct);
-  w.blk0 = tb * kBB;
-  w.row0 = tr * kRows;
-  w.col0 = tcol * kCols;
-  return w;
-}
-
 // LDS position of in-block offset (x, y, z) of an 8^3 orbit block, padded so
 // that the six permuted reads of a wave (x fixed, y and z over the lanes)
 // spread over the 16 double-wide banks (at most 5 lanes per bank instead of

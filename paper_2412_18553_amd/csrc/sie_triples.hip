@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <iterator>
 #include <mutex>
 #include <string>
@@ -56,7 +57,7 @@ struct FragPlan {
   size_t split_bytes = 0;    // vS + tS + tT + oT
   size_t half_bytes = 0;     // one partial cube (aligned)
   double unit_cost = 0.0;    // flops per unit (ordering key)
-  int variant = 0;           // float64 build tile shape (sie::wshape)
+  int variant = 0;           // build tile shape (float64: sie::wshape; split: sie::sshape)
   bool lay3 = false;         // three-layout build (float64 energy only)
   int cubes = 2;             // partial cubes of a unit in flight
   int cubes_pair = 1;        // ... of a pair unit (sie::unit_triple)
@@ -115,6 +116,7 @@ size_t adj_recs_per_unit(int nv) {
 }
 
 int tile_variant(int nv);
+int split_shape(int nv);
 bool aligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) % a) == 0; }
 
 Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad = false) {
@@ -131,6 +133,8 @@ Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad =
       fp.variant = tile_variant(fp.nv);
       if (grad && sie::wshape(fp.variant).lay == 3) fp.variant = 0;
       fp.lay3 = sie::wshape(fp.variant).lay == 3;
+    } else {
+      fp.variant = split_shape(fp.nv);
     }
     fp.cubes = grad ? 3 : fp.lay3 ? 3 : 2;
     fp.cubes_pair = grad ? 3 : fp.lay3 ? 2 : 1;
@@ -223,6 +227,12 @@ sie_status check_fragment(const sie_fragment* f, sie_precision prec, const char*
   if (double(esz) * (o * o * v * v + v * v * v + v * v) >= 4294967296.0)
     return fail(SIE_ERR_UNSUPPORTED,
                 w + ": (element size) x (n_occ^2 n_vir^2 + n_vir^3 + n_vir^2) must be below 2^32");
+  // the split build's largest extent: a (K = d) split copy's i-slice, 4 bytes
+  // per padded element
+  const double kv = double(round_up(size_t(f->n_vir), sie::kKs));
+  if (prec == SIE_SPLIT_BF16 && 4.0 * v * (v + 1) * kv >= 4294967296.0)
+    return fail(SIE_ERR_UNSUPPORTED,
+                w + ": split precision needs 4 n_vir (n_vir + 1) round_up(n_vir, 32) below 2^32");
   return SIE_OK;
 }
 
@@ -248,6 +258,14 @@ int tile_variant(int nv) {
   for (const TileEntry& e : g_tiles)
     if (nv <= e.nv_max) return e.variant;
   return 0;
+}
+
+// ---- split build tile shape: by padded area (sie::split_shape_of) unless forced ----
+std::atomic<int> g_split_forced{-1};
+
+int split_shape(int nv) {
+  const int f = g_split_forced.load();
+  return f >= 0 ? f : sie::split_shape_of(nv);
 }
 
 // ---- optional kernel timing ----
@@ -352,6 +370,16 @@ sie_status sie_set_tile_table(int32_t n, const int32_t* nv_max, const int32_t* v
   return SIE_OK;
 }
 
+int32_t sie_split_shape_of(int32_t n_vir) { return n_vir < 1 ? -1 : split_shape(n_vir); }
+
+sie_status sie_set_split_shape(int32_t shape) {
+  if (shape < -1 || shape >= sie::kSShapes)
+    return fail(SIE_ERR_INVALID_ARG, "sie_set_split_shape: shape out of range");
+  g_split_forced.store(shape);
+  return SIE_OK;
+}
+static_assert(SIE_SPLIT_SHAPES == sie::kSShapes, "header and kernels agree on the split shapes");
+
 const char* sie_last_error(void) { return g_err.c_str(); }
 
 int64_t sie_occupied_triples(int32_t n_occ) {
@@ -444,11 +472,12 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
     d.n_part = fp.n_part;
     d.unit_base = unit_base;
     d.half = int64_t(fp.half_bytes / (pl.split ? sizeof(float) : sizeof(double)));
-    // split: tiles per layout (two layouts); float64: work-groups per unit
+    // work-groups of one layout (split) or of one unit (float64)
     d.variant = fp.variant;
     d.pair = pl.pair ? 1 : 0;
     d.lay3 = fp.lay3 ? 1 : 0;
-    d.tiles = pl.split ? sie::build_tiles(fp.nv) : sie::wbuild_tiles(fp.nv, d.variant);
+    d.tiles = pl.split ? sie::split_tiles(fp.nv, d.variant)
+                       : sie::wbuild_tiles(fp.nv, d.variant);
     d.vS = d.tS = d.tT = d.oT = nullptr;
     d.g_t1 = grads ? grads[x].t1 : nullptr;
     d.g_t2 = grads ? grads[x].t2 : nullptr;
@@ -528,17 +557,16 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
     }
     round_begin.push_back(order.size());
   }
-  // float64: the build launches once per tile variant of a round, so group
-  // each round's items by variant (stable) and restart the block prefix sums
-  // at each variant's segment; the epilogue prefix sums run over the round.
+  // the build launches once per tile variant of a round, so group each
+  // round's items by variant (stable) and restart the block prefix sums at
+  // each variant's segment; the epilogue prefix sums run over the round.
   T.segments.clear();
   for (size_t q = 0; q + 1 < round_begin.size(); ++q) {
     const size_t r0 = round_begin[q], r1 = round_begin[q + 1];
-    if (!pl.split)
-      std::stable_sort(items.begin() + r0, items.begin() + r1,
-                       [&](const sie::Item& a, const sie::Item& b) {
-                         return desc[size_t(a.frag)].variant < desc[size_t(b.frag)].variant;
-                       });
+    std::stable_sort(items.begin() + r0, items.begin() + r1,
+                     [&](const sie::Item& a, const sie::Item& b) {
+                       return desc[size_t(a.frag)].variant < desc[size_t(b.frag)].variant;
+                     });
     int64_t blk = 0, part = 0;
     size_t seg0 = r0;
     for (size_t r = r0; r < r1; ++r) {
@@ -634,6 +662,31 @@ void build_round_f64(const Tables& T, size_t q, hipStream_t s, const sie::FragDe
   }
 }
 
+void build_round_split(const Tables& T, size_t q, hipStream_t s, const sie::FragDesc* desc,
+                       const sie::Item* d_items, float* arena) {
+  for (const auto& sg : T.segments) {
+    if (sg.round != q) continue;
+    const dim3 grid(unsigned(T.items[sg.r1 - 1].blk_end));
+    const sie::Item* it = d_items + sg.r0;
+    const int cnt = int(sg.r1 - sg.r0);
+    switch (sg.variant) {
+#define SIE_SPLIT_CASE(S)                                                                  \
+  case S:                                                                                  \
+    hipLaunchKernelGGL((sie::k_build_w_bf16x3<sie::sshape(S).trw, sie::sshape(S).tcw>), grid, \
+                       dim3(256), 0, s, desc, it, cnt, arena);                             \
+    break;
+      SIE_SPLIT_CASE(0)
+      SIE_SPLIT_CASE(1)
+      SIE_SPLIT_CASE(2)
+      SIE_SPLIT_CASE(3)
+#undef SIE_SPLIT_CASE
+      default:
+        break;
+    }
+  }
+}
+static_assert(sie::kSShapes == 4, "one launch case per split shape");
+
 // bf16 hi/lo copies of every fragment's float32 inputs (see k_bf16.hpp).
 sie_status stage_split(const std::vector<sie::FragDesc>& desc, hipStream_t s) {
   ProfScope ps(s, 3);
@@ -720,7 +773,6 @@ sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag
     const size_t r0 = round_begin[q], r1 = round_begin[q + 1];
     if (r1 == r0) continue;
     const int cnt = int(r1 - r0);
-    const unsigned n_blk = unsigned(items[r1 - 1].blk_end);
     const unsigned n_epi = unsigned(items[r1 - 1].part_end);
     const sie::Item* ri = d_items + r0;
     if (!pl.split) {
@@ -738,8 +790,7 @@ sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag
       float* arena = reinterpret_cast<float*>(dev(pl.off_arena));
       {
         ProfScope ps(s, 0);
-        hipLaunchKernelGGL(sie::k_build_w_bf16x3, dim3(n_blk), dim3(sie::kThreads), 0, s, d_desc,
-                           ri, cnt, arena);
+        build_round_split(T, q, s, d_desc, d_items, arena);
       }
       {
         ProfScope ps(s, 1);
@@ -1046,9 +1097,7 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
     {
       ProfScope ps(s, 0);
       if (pl.split)
-        hipLaunchKernelGGL(sie::k_build_w_bf16x3, dim3(unsigned(T.items[r1 - 1].blk_end)),
-                           dim3(sie::kThreads), 0, s, d_desc, ri, cnt,
-                           reinterpret_cast<float*>(dev(pl.off_arena)));
+        build_round_split(T, q, s, d_desc, d_items, reinterpret_cast<float*>(dev(pl.off_arena)));
       else
         build_round_f64(T, q, s, d_desc, d_items, arena);
     }

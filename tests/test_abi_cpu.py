@@ -182,6 +182,18 @@ def test_tile_table(lib):
     assert lib.sie_set_tile_table(2, arr(100, 400), arr(1, 2)) == _lib.SIE_OK
     assert [lib.sie_tile_variant_of(v) for v in (1, 100, 101, 400, 401)] == [1, 1, 2, 2, 0]
     assert lib.sie_set_tile_table(0, None, None) == _lib.SIE_OK
+    # split build shapes: automatic choice, forcing and range checks
+    m = int(re.search(r"#define SIE_SPLIT_SHAPES (\d+)", open(HEADER).read()).group(1))
+    assert lib.sie_split_shape_of(0) == -1
+    assert lib.sie_split_shape_of(320) == 1            # 80 x 320 tiles cover 320 exactly
+    assert lib.sie_split_shape_of(200) == 2            # 112 x 256: least padding at 200
+    assert lib.sie_split_shape_of(64) == 0
+    assert lib.sie_set_split_shape(m) == _lib.SIE_ERR_INVALID_ARG
+    assert lib.sie_set_split_shape(-2) == _lib.SIE_ERR_INVALID_ARG
+    assert lib.sie_set_split_shape(3) == _lib.SIE_OK
+    assert lib.sie_split_shape_of(320) == 3
+    assert lib.sie_set_split_shape(-1) == _lib.SIE_OK
+    assert lib.sie_split_shape_of(320) == 1
     # the work-group count of a fragment depends on its variant only through sizing
     keep = []
     f = frag(keep=keep)

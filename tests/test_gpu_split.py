@@ -71,3 +71,28 @@ def test_split_deterministic():
     e1, t1 = run_split(f)
     e2, t2 = run_split(f)
     assert e1 == e2 and np.array_equal(t1, t2)
+
+
+_EMULATED = {}
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+@pytest.mark.parametrize("o,v,aux,seed", [(4, 33, 40, 11), (3, 97, 60, 12)])
+def test_split_every_tile_shape(shape, o, v, aux, seed):
+    """Each split build shape, forced, against the emulator: tiles that span
+    several row and col tiles with ragged edges (v = 97) and one partial tile
+    (v = 33)."""
+    import paper_2412_18553_amd as sie
+    print(f"case shape={shape} o={o} v={v}", flush=True)
+    f = make_fragment(o, v, aux, (8, seed)).astype(np.float32)
+    sie.set_split_shape(shape)
+    try:
+        e_gpu, tri = run_split(f)
+    finally:
+        sie.set_split_shape(-1)
+    key = (o, v, aux, seed)
+    if key not in _EMULATED:
+        _EMULATED[key] = energy_split_emulated(*f.arrays())
+    e_em = _EMULATED[key]
+    assert abs(e_gpu - e_em) <= 5e-6 * abs(e_em)
+    assert abs(tri.sum() - e_gpu) <= 1e-12 * abs(e_gpu)
