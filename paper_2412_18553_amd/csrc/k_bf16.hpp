@@ -342,8 +342,10 @@ __device__ __forceinline__ void split_mma(const u4v (*buf)[2][16 * TRW], int g, 
 
 // Split-precision partial cubes (float32): grid = the items' tiles, one
 // layout (pair units) or two per unit, split_tiles(n_v, shape) per layout.
+// Two work-groups per CU (at most 256 registers a lane): while one waits at
+// its barrier or on its loads, the other keeps the matrix cores busy.
 template <int TRW, int TCW>
-__global__ __launch_bounds__(256, 1) void k_build_w_bf16x3(const FragDesc* __restrict__ descs,
+__global__ __launch_bounds__(256, 2) void k_build_w_bf16x3(const FragDesc* __restrict__ descs,
                                                            const Item* __restrict__ items,
                                                            int n_items,
                                                            float* __restrict__ arena) {
