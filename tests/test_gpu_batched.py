@@ -84,3 +84,31 @@ def test_batched_split():
         f32 = f.astype(np.float32)
         ref = T.energy_literal_vectorized(*[np.asarray(x, np.float64) for x in f32.arrays()])
         assert abs(e - ref) <= 1e-4 * abs(ref)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split_bf16"])
+def test_batched_workspace_caps_agree(precision):
+    """Workspace caps from the minimum to the full size group the units into
+    different rounds: the per-fragment energies are bitwise the same, also
+    when the same workspace is reused right away."""
+    import paper_2412_18553_amd as sie
+    hf = [make_fragment(o, v, a, (9, 300 + n)) for n, (o, v, a) in enumerate(SHAPES)]
+    frs = [_frag(f, precision) for f in hf]
+    e_full, _ = sie.energy_batched(frs)
+    full = sie.workspace_size(frs)
+    minimal = None
+    for cap in (1 << 20, 4 << 20, 16 << 20, 64 << 20):
+        try:
+            minimal = sie.workspace_size(frs, max_bytes=cap)
+            break
+        except sie.SieError:
+            continue
+    assert minimal is not None and minimal < full
+    caps = sorted({minimal, 2 * minimal, 3 * minimal, 5 * minimal, (minimal + full) // 2})
+    for cap in caps:
+        if cap >= full:
+            continue
+        for _ in range(2):
+            e_cap, _ = sie.energy_batched(frs, max_workspace_bytes=sie.workspace_size(frs, max_bytes=cap))
+            print(f"cap={cap}", flush=True)
+            assert np.array_equal(e_full.cpu().numpy(), e_cap.cpu().numpy())
