@@ -223,8 +223,9 @@ int32_t sie_tile_variant_of(int32_t n_vir);
 sie_status sie_set_tile_table(int32_t n, const int32_t* nv_max, const int32_t* variant);
 
 /* Tile shapes of the split-precision W-tilde build.  A work-group of shape s
- * computes 16 TRW rows x 64 TCW cols of one block of one layout, with
- * (TRW, TCW) = (4, 2), (5, 5), (7, 4), (4, 4) for s = 0, 1, 2, 3.
+ * computes rows x cols of one block of one layout: 64 x 128, 80 x 320,
+ * 112 x 256, 64 x 256 (four waves) and 160 x 320 (eight waves) for
+ * s = 0 .. 4.
  * sie_split_shape_of returns the shape a fragment with n_vir virtuals builds
  * with (-1 for n_vir < 1): by default the one of least padded tile area,
  * preferring the larger tile among shapes within 10% of it.
@@ -233,7 +234,7 @@ sie_status sie_set_tile_table(int32_t n, const int32_t* nv_max, const int32_t* v
  * SIE_SPLIT_SHAPES)).  Energies do not depend on the shape beyond rounding of
  * the contraction order.  Not to be called while another thread runs an
  * evaluation. */
-#define SIE_SPLIT_SHAPES 4
+#define SIE_SPLIT_SHAPES 5
 int32_t sie_split_shape_of(int32_t n_vir);
 sie_status sie_set_split_shape(int32_t shape);
 

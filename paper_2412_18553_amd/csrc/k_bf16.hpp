@@ -191,15 +191,20 @@ __device__ __forceinline__ TermS make_term_split(bool l2, int q, const FragDesc&
 // ---------------------------------------------------------------------------
 
 // Tile shapes (TRW x TCW MFMA tiles per wave).
+// wr = 2: eight waves, two along the rows, and the B cols go through LDS
+// too (k_build_w_bf16x3_l).
 struct SShape {
-  int trw, tcw;
+  int trw, tcw, wr;
 };
-constexpr int kSShapes = 4;
+constexpr int kSShapes = 5;
 __host__ __device__ constexpr SShape sshape(int s) {
-  return s == 1 ? SShape{5, 5} : s == 2 ? SShape{7, 4} : s == 3 ? SShape{4, 4} : SShape{4, 2};
+  return s == 1 ? SShape{5, 5, 1} : s == 2 ? SShape{7, 4, 1} : s == 3 ? SShape{4, 4, 1}
+       : s == 4 ? SShape{5, 5, 2} : SShape{4, 2, 1};
 }
+__host__ __device__ constexpr int split_rows(int s) { return 16 * sshape(s).trw * sshape(s).wr; }
+__host__ __device__ constexpr int split_cols(int s) { return 64 * sshape(s).tcw; }
 __host__ __device__ inline int64_t split_tiles(int nv, int s) {
-  const int R = 16 * sshape(s).trw, C = 64 * sshape(s).tcw;
+  const int R = split_rows(s), C = split_cols(s);
   return int64_t(nv) * ((nv + R - 1) / R) * ((nv + C - 1) / C);
 }
 // Shape of a fragment with n_v virtuals: the least padded tile area, and
@@ -208,13 +213,13 @@ __host__ __device__ inline int64_t split_tiles(int nv, int s) {
 inline int split_shape_of(int nv) {
   int64_t best = -1;
   for (int s = 0; s < kSShapes; ++s) {
-    const int64_t a = split_tiles(nv, s) / nv * 16 * sshape(s).trw * 64 * sshape(s).tcw;
+    const int64_t a = split_tiles(nv, s) / nv * split_rows(s) * split_cols(s);
     best = (best < 0 || a < best) ? a : best;
   }
   int pick = 0, area = 0;
   for (int s = 0; s < kSShapes; ++s) {
-    const int64_t a = split_tiles(nv, s) / nv * 16 * sshape(s).trw * 64 * sshape(s).tcw;
-    const int t = sshape(s).trw * sshape(s).tcw;
+    const int64_t a = split_tiles(nv, s) / nv * split_rows(s) * split_cols(s);
+    const int t = split_rows(s) * split_cols(s);
     if (10 * a <= 11 * best && t > area) {
       pick = s;
       area = t;
@@ -318,13 +323,13 @@ __device__ __forceinline__ void split_stage(const SRegs<NA, TCW>& x, uint32_t fl
 
 // The three products of every tile, ordered so that MFMAs into one
 // accumulator are TCW apart.
-template <int TRW, int TCW>
-__device__ __forceinline__ void split_mma(const u4v (*buf)[2][16 * TRW], int g, int r,
+template <int TRW, int TCW, int NX>
+__device__ __forceinline__ void split_mma(const u4v (*buf)[2][NX], int g, int r, int ra,
                                           const u4v (&bh)[TCW], const u4v (&bl)[TCW],
                                           f4 (&acc)[TRW][TCW]) {
 #pragma unroll
   for (int rt = 0; rt < TRW; ++rt) {
-    const u4v ah = buf[g][0][16 * rt + r], al = buf[g][1][16 * rt + r];
+    const u4v ah = buf[g][0][ra + 16 * rt + r], al = buf[g][1][ra + 16 * rt + r];
 #pragma unroll
     for (int ct = 0; ct < TCW; ++ct) acc[rt][ct] = mfma_bf16(al, bh[ct], acc[rt][ct]);
 #pragma unroll
@@ -413,7 +418,7 @@ __global__ __launch_bounds__(256, 2) void k_build_w_bf16x3(const FragDesc* __res
       }
     }
     if (more) split_load(nxt, cn, L, x);
-    split_mma<TRW, TCW>(lds[buf], g, r, bh, bl, acc);
+    split_mma<TRW, TCW>(lds[buf], g, r, 0, bh, bl, acc);
     if (!more) break;
     split_stage<R>(x, nxt.flip, tid, lds[buf ^ 1]);
 #pragma unroll
@@ -436,6 +441,141 @@ __global__ __launch_bounds__(256, 2) void k_build_w_bf16x3(const FragDesc* __res
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = row0 + 16 * rt + SIE_BF16_DROW(v, g);
+        if (row < nv && col < nv)
+          gptr_w(out)[((int64_t)blk * nv + row) * nv + col] = acc[rt][ct][v];
+      }
+  }
+}
+
+// Eight-wave split build: 32 TRW rows x 64 TCW cols of one block, wave w at
+// rows 16 TRW (w / 4) and cols 16 TCW (w % 4) of the tile.  Both operands of
+// a K chunk are staged through LDS ([K group][hi, lo][A rows, then B cols]):
+// each A row is read by four waves and each B col by two, so a work-group
+// reads (R + C) rows from memory per chunk for R x C outputs.
+template <int TRW, int TCW>
+__global__ __launch_bounds__(512, 1) void k_build_w_bf16x3_l(const FragDesc* __restrict__ descs,
+                                                             const Item* __restrict__ items,
+                                                             int n_items,
+                                                             float* __restrict__ arena) {
+  constexpr int R = 32 * TRW, C = 64 * TCW, X = R + C;
+  constexpr int NU = (4 * X + 511) / 512;        // staging units (32 bytes) per thread
+  const int ri = find_item<true>(items, n_items, blockIdx.x);
+  const int64_t start = ri ? items[ri - 1].blk_end : 0;
+  const Item it = items[ri];
+  const FragDesc fd = descs[it.frag];
+  int i, j, k;
+  const bool one = unit_triple(it.unit, fd.no, fd.pair, i, j, k);
+  if (i == k) return;
+  const int nv = fd.nv;
+  const int nrt = (nv + R - 1) / R, nct = (nv + C - 1) / C;
+  const int per = nv * nrt * nct;
+  int t = xcd_tile(int(int64_t(blockIdx.x) - start), one ? per : 2 * per);
+  const bool l2 = t >= per;
+  if (l2) t -= per;
+  const int blk = t / (nrt * nct);
+  t -= blk * nrt * nct;
+  const int tr = t / nct, tc = t - tr * nct;
+  const int row0 = tr * R, col0 = tc * C;
+  const int xa_max = min(R, nv - row0) - 1, xb_max = min(C, nv - col0) - 1;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r = lane & 15, g = lane >> 4;
+  const int ra = (wave >> 2) * 16 * TRW;          // this wave's first row in the A region
+  const int cb = R + (wave & 3) * 16 * TCW;       // ... first col in the B region
+
+  __shared__ u4v lds[2][kKs / 8][2][X];
+
+  f4 acc[TRW][TCW];
+#pragma unroll
+  for (int a = 0; a < TRW; ++a)
+#pragma unroll
+    for (int b = 0; b < TCW; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+
+  // staging unit u = tid + 512 m: LDS row x = u / 4 (A row x, or B col x - R),
+  // K group u % 4; lane addresses are rebuilt per term
+  const char* src[NU];
+  uint32_t flip_a = 0;
+  auto lanes = [&](const SOp& o) {
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      int u = tid + 512 * m;
+      u = u < 4 * X ? u : 4 * X - 1;
+      const int x = u >> 2;
+      const uint32_t gq = uint32_t(u & 3) * 32u;
+      src[m] = x < R ? o.a + (uint32_t(min(x, xa_max)) * o.sa + gq)
+                     : o.b + (uint32_t(min(x - R, xb_max)) * o.sb + gq);
+    }
+    flip_a = o.flip;
+  };
+  u4v sh[NU], sl[NU];
+  auto load = [&](int c) {
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      const SIE_GLOBAL u4v* p = (const SIE_GLOBAL u4v*)(gptr(src[m] + c * 128));
+      sh[m] = p[0];
+      sl[m] = p[1];
+    }
+  };
+  auto stage = [&](int b) {
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      const int u = tid + 512 * m;
+      if (u < 4 * X) {
+        const uint32_t f = (u >> 2) < R ? flip_a : 0u;
+        lds[b][u & 3][0][u >> 2] = sh[m] ^ f;
+        lds[b][u & 3][1][u >> 2] = sl[m] ^ f;
+      }
+    }
+  };
+
+  int q = 0, c = 0;
+  SOp cur = split_op(l2, 0, fd, i, j, k, blk, row0, col0);
+  lanes(cur);
+  load(0);
+  stage(0);
+  __syncthreads();
+  int buf = 0;
+  while (true) {
+    int cn = c + 1;
+    bool more = true;
+    if (cn >= cur.nch) {
+      if (q == 5) {
+        more = false;
+      } else {
+        ++q;
+        cn = 0;
+        cur = split_op(l2, q, fd, i, j, k, blk, row0, col0);
+        lanes(cur);
+      }
+    }
+    if (more) load(cn);
+    {
+      u4v bh[TCW], bl[TCW];
+#pragma unroll
+      for (int ct = 0; ct < TCW; ++ct) {
+        bh[ct] = lds[buf][g][0][cb + 16 * ct + r];
+        bl[ct] = lds[buf][g][1][cb + 16 * ct + r];
+      }
+      split_mma<TRW, TCW>(lds[buf], g, r, ra, bh, bl, acc);
+    }
+    if (!more) break;
+    stage(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+    c = cn;
+  }
+
+  float* __restrict__ out = arena + it.cube_off + (l2 ? fd.half : 0);
+#pragma unroll
+  for (int ct = 0; ct < TCW; ++ct) {
+    const int col = col0 + (wave & 3) * 16 * TCW + 16 * ct + r;
+#pragma unroll
+    for (int rt = 0; rt < TRW; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = row0 + ra + 16 * rt + SIE_BF16_DROW(v, g);
         if (row < nv && col < nv)
           gptr_w(out)[((int64_t)blk * nv + row) * nv + col] = acc[rt][ct][v];
       }

@@ -680,12 +680,17 @@ void build_round_split(const Tables& T, size_t q, hipStream_t s, const sie::Frag
       SIE_SPLIT_CASE(2)
       SIE_SPLIT_CASE(3)
 #undef SIE_SPLIT_CASE
+      case 4:
+        hipLaunchKernelGGL((sie::k_build_w_bf16x3_l<sie::sshape(4).trw, sie::sshape(4).tcw>),
+                           grid, dim3(512), 0, s, desc, it, cnt, arena);
+        break;
       default:
         break;
     }
   }
 }
-static_assert(sie::kSShapes == 4, "one launch case per split shape");
+static_assert(sie::kSShapes == 5 && sie::sshape(4).wr == 2,
+              "one launch case per split shape");
 
 // bf16 hi/lo copies of every fragment's float32 inputs (see k_bf16.hpp).
 sie_status stage_split(const std::vector<sie::FragDesc>& desc, hipStream_t s) {
