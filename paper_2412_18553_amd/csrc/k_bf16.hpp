@@ -94,8 +94,10 @@ __global__ __launch_bounds__(256) void k_split_bf16(const float* __restrict__ sr
 
 // One term of the split build: element (beta, x, group G) of the per-block
 // operand is the u4v pair at bl + (beta*bl_b + x*bl_x + G) * 2 (hi, then lo);
-// the shared operand likewise with sh, sh_x.  `neg` flips the sign of the
-// shared operand (the minus of the occupied sums); nG = groups of K.
+// the shared operand likewise with sh, sh_x.  `neg`: the term carries the
+// minus of the occupied sums (the build flips the sign bits of its A
+// operand); nG = groups of K; a_is_bl: the per-block operand is the MFMA's A
+// side (rows), else its B side (cols).
 struct TermS {
   const u4v* bl;
   int64_t bl_b, bl_x;
@@ -107,7 +109,7 @@ struct TermS {
 };
 
 // Term q (0..5) of layout `l2`, in the same order and with the same operand
-// roles as make_term (k_fp64.hpp); row strides are those of the split copies.
+// roles as make_wterm (k_fp64.hpp); row strides are those of the split copies.
 __device__ __forceinline__ TermS make_term_split(bool l2, int q, const FragDesc& f, int i,
                                                  int j, int k, int blk0, int row0, int col0) {
   const int64_t nv = f.nv, no = f.no;
@@ -307,6 +309,15 @@ __device__ __forceinline__ void split_load(const SOp& o, int c, const SLane<NA, 
   }
 }
 
+// LDS rows of K group g are stored xor-swizzled, row ^ lds_swz(g) (a
+// permutation inside each aligned block of 16 rows): the four group planes
+// lie a multiple of 256 bytes apart, so without it the staging stores of
+// the four lanes that write one row (one lane per group) meet in the same
+// banks.  With it every 8 (and every 16) consecutive lanes of a store reach
+// distinct 16-byte bank groups, and the MFMA reads (16 lanes of one group,
+// 16 consecutive rows) stay conflict-free.
+__device__ __forceinline__ int lds_swz(int g) { return (0xAC60 >> (4 * g)) & 15; }
+
 // LDS chunk: [K group (4)][hi, lo][row] of u4v.
 template <int R, int NA, int TCW>
 __device__ __forceinline__ void split_stage(const SRegs<NA, TCW>& x, uint32_t flip, int tid,
@@ -315,8 +326,9 @@ __device__ __forceinline__ void split_stage(const SRegs<NA, TCW>& x, uint32_t fl
   for (int m = 0; m < NA; ++m) {
     const int u = tid + 256 * m;
     if (u < 4 * R) {
-      buf[u & 3][0][u >> 2] = x.ah[m] ^ flip;
-      buf[u & 3][1][u >> 2] = x.al[m] ^ flip;
+      const int row = (u >> 2) ^ lds_swz(u & 3);
+      buf[u & 3][0][row] = x.ah[m] ^ flip;
+      buf[u & 3][1][row] = x.al[m] ^ flip;
     }
   }
 }
@@ -418,7 +430,7 @@ __global__ __launch_bounds__(256, 2) void k_build_w_bf16x3(const FragDesc* __res
       }
     }
     if (more) split_load(nxt, cn, L, x);
-    split_mma<TRW, TCW>(lds[buf], g, r, 0, bh, bl, acc);
+    split_mma<TRW, TCW>(lds[buf], g, r ^ lds_swz(g), 0, bh, bl, acc);
     if (!more) break;
     split_stage<R>(x, nxt.flip, tid, lds[buf ^ 1]);
 #pragma unroll
@@ -484,6 +496,7 @@ __global__ __launch_bounds__(512, 1) void k_build_w_bf16x3_l(const FragDesc* __r
   const int r = lane & 15, g = lane >> 4;
   const int ra = (wave >> 2) * 16 * TRW;          // this wave's first row in the A region
   const int cb = R + (wave & 3) * 16 * TCW;       // ... first col in the B region
+  const int rx = r ^ lds_swz(g);                  // swizzled row within a 16-row block
 
   __shared__ u4v lds[2][kKs / 8][2][X];
 
@@ -524,8 +537,9 @@ __global__ __launch_bounds__(512, 1) void k_build_w_bf16x3_l(const FragDesc* __r
       const int u = tid + 512 * m;
       if (u < 4 * X) {
         const uint32_t f = (u >> 2) < R ? flip_a : 0u;
-        lds[b][u & 3][0][u >> 2] = sh[m] ^ f;
-        lds[b][u & 3][1][u >> 2] = sl[m] ^ f;
+        const int row = (u >> 2) ^ lds_swz(u & 3);
+        lds[b][u & 3][0][row] = sh[m] ^ f;
+        lds[b][u & 3][1][row] = sl[m] ^ f;
       }
     }
   };
@@ -555,10 +569,10 @@ __global__ __launch_bounds__(512, 1) void k_build_w_bf16x3_l(const FragDesc* __r
       u4v bh[TCW], bl[TCW];
 #pragma unroll
       for (int ct = 0; ct < TCW; ++ct) {
-        bh[ct] = lds[buf][g][0][cb + 16 * ct + r];
-        bl[ct] = lds[buf][g][1][cb + 16 * ct + r];
+        bh[ct] = lds[buf][g][0][cb + 16 * ct + rx];
+        bl[ct] = lds[buf][g][1][cb + 16 * ct + rx];
       }
-      split_mma<TRW, TCW>(lds[buf], g, r, ra, bh, bl, acc);
+      split_mma<TRW, TCW>(lds[buf], g, rx, ra, bh, bl, acc);
     }
     if (!more) break;
     stage(buf ^ 1);
