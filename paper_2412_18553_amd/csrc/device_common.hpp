@@ -1,6 +1,8 @@
 // Device helpers shared by the (T) kernels (gfx950, wave64).
 #pragma once
 
+#include <cmath>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -51,13 +53,21 @@ __host__ __device__ __forceinline__ int64_t tri(int64_t n) {     // n(n+1)/2
 }
 
 // Linear index u of a sorted triple p >= q >= r (lexicographic in (p, q, r))
-// back to (p, q, r).  `bound` is an upper bound on p.
+// back to (p, q, r).  `bound` is an upper bound on p.  p is the largest value
+// below `bound` with tetra(p) <= u and q the largest value <= p with
+// tri(q) <= u - tetra(p): both start from the real-valued inverse (cube and
+// square root) and are then corrected with exact integer comparisons, so the
+// result does not depend on the rounding of the estimates.
 __host__ __device__ __forceinline__ void decode_sorted_triple(int64_t u, int bound,
                                                      int& p, int& q, int& r) {
-  int pp = 0;
+  int pp = int(cbrt(6.0 * double(u)));
+  pp = pp < 0 ? 0 : (pp > bound - 1 ? bound - 1 : pp);
+  while (pp > 0 && tetra(pp) > u) --pp;
   while (pp + 1 < bound && tetra(pp + 1) <= u) ++pp;
-  int64_t rem = u - tetra(pp);
-  int qq = 0;
+  const int64_t rem = u - tetra(pp);
+  int qq = int(0.5 * (sqrt(8.0 * double(rem) + 1.0) - 1.0));
+  qq = qq < 0 ? 0 : (qq > pp ? pp : qq);
+  while (qq > 0 && tri(qq) > rem) --qq;
   while (qq + 1 <= pp && tri(qq + 1) <= rem) ++qq;
   p = pp;
   q = qq;

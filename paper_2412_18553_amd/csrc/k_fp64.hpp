@@ -843,21 +843,25 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
     }
     __syncthreads();
     // a slot whose block triple repeats an earlier slot's is not summed twice
-    unsigned primary = 0;
+    // (only when two of the sorted block indices are equal)
+    unsigned primary = 63u;
+    if (t0 == t1b || t1b == t2b) {
+      primary = 0;
 #pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      int p0, p1, p2;
-      slot_perm(s, p0, p1, p2);
-      bool dup = false;
+      for (int s = 0; s < 6; ++s) {
+        int p0, p1, p2;
+        slot_perm(s, p0, p1, p2);
+        bool dup = false;
 #pragma unroll
-      for (int s2 = 0; s2 < s; ++s2) {
-        int q0, q1, q2;
-        slot_perm(s2, q0, q1, q2);
-        dup |= pick3(p0, t0, t1b, t2b) == pick3(q0, t0, t1b, t2b) &&
-               pick3(p1, t0, t1b, t2b) == pick3(q1, t0, t1b, t2b) &&
-               pick3(p2, t0, t1b, t2b) == pick3(q2, t0, t1b, t2b);
+        for (int s2 = 0; s2 < s; ++s2) {
+          int q0, q1, q2;
+          slot_perm(s2, q0, q1, q2);
+          dup |= pick3(p0, t0, t1b, t2b) == pick3(q0, t0, t1b, t2b) &&
+                 pick3(p1, t0, t1b, t2b) == pick3(q1, t0, t1b, t2b) &&
+                 pick3(p2, t0, t1b, t2b) == pick3(q2, t0, t1b, t2b);
+        }
+        if (!dup) primary |= 1u << s;
       }
-      if (!dup) primary |= 1u << s;
     }
 #pragma unroll 2
     for (int s = 0; s < 6; ++s) {
