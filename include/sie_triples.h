@@ -224,17 +224,17 @@ sie_status sie_set_tile_table(int32_t n, const int32_t* nv_max, const int32_t* v
 
 /* Tile shapes of the split-precision W-tilde build.  A work-group of shape s
  * computes rows x cols of one block of one layout: 64 x 128, 80 x 320,
- * 112 x 256, 64 x 256 (four waves) and 160 x 320 (eight waves) for
- * s = 0 .. 4.
+ * 112 x 256, 64 x 256 (four waves), 160 x 320 (eight waves) and 160 x 160
+ * (four waves) for s = 0 .. 5.
  * sie_split_shape_of returns the shape a fragment with n_vir virtuals builds
- * with (-1 for n_vir < 1): by default the one of least padded tile area,
- * preferring the larger tile among shapes within 10% of it.
+ * with (-1 for n_vir < 1): by default, among the shapes whose padded tile
+ * area is within 10% of the least, the first in the order 5, 4, 1, 2, 3, 0.
  * sie_set_split_shape forces shape s for every fragment of later evaluations
  * (s = -1 restores the default; SIE_ERR_INVALID_ARG outside [-1,
  * SIE_SPLIT_SHAPES)).  Energies do not depend on the shape beyond rounding of
  * the contraction order.  Not to be called while another thread runs an
  * evaluation. */
-#define SIE_SPLIT_SHAPES 5
+#define SIE_SPLIT_SHAPES 6
 int32_t sie_split_shape_of(int32_t n_vir);
 sie_status sie_set_split_shape(int32_t shape);
 

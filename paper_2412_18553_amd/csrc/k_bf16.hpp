@@ -193,41 +193,37 @@ __device__ __forceinline__ TermS make_term_split(bool l2, int q, const FragDesc&
 // ---------------------------------------------------------------------------
 
 // Tile shapes (TRW x TCW MFMA tiles per wave).
-// wr = 2: eight waves, two along the rows, and the B cols go through LDS
-// too (k_build_w_bf16x3_l).
+// wr x wc waves along rows x cols; wr = 2: the B cols go through LDS too
+// (k_build_w_bf16x3_l).
 struct SShape {
-  int trw, tcw, wr;
+  int trw, tcw, wr, wc;
 };
-constexpr int kSShapes = 5;
+constexpr int kSShapes = 6;
 __host__ __device__ constexpr SShape sshape(int s) {
-  return s == 1 ? SShape{5, 5, 1} : s == 2 ? SShape{7, 4, 1} : s == 3 ? SShape{4, 4, 1}
-       : s == 4 ? SShape{5, 5, 2} : SShape{4, 2, 1};
+  return s == 1 ? SShape{5, 5, 1, 4} : s == 2 ? SShape{7, 4, 1, 4} : s == 3 ? SShape{4, 4, 1, 4}
+       : s == 4 ? SShape{5, 5, 2, 4} : s == 5 ? SShape{5, 5, 2, 2} : SShape{4, 2, 1, 4};
 }
 __host__ __device__ constexpr int split_rows(int s) { return 16 * sshape(s).trw * sshape(s).wr; }
-__host__ __device__ constexpr int split_cols(int s) { return 64 * sshape(s).tcw; }
+__host__ __device__ constexpr int split_cols(int s) { return 16 * sshape(s).tcw * sshape(s).wc; }
 __host__ __device__ inline int64_t split_tiles(int nv, int s) {
   const int R = split_rows(s), C = split_cols(s);
   return int64_t(nv) * ((nv + R - 1) / R) * ((nv + C - 1) / C);
 }
-// Shape of a fragment with n_v virtuals: the least padded tile area, and
-// among the shapes within 10% of it the one with the largest tile (more
-// operand reuse).
+// Shape of a fragment with n_v virtuals: among the shapes whose padded tile
+// area is within 10% of the least, the first in the order of their measured
+// speed at 32/320 (5, 4, 1, 2, 3, 0).
 inline int split_shape_of(int nv) {
   int64_t best = -1;
   for (int s = 0; s < kSShapes; ++s) {
     const int64_t a = split_tiles(nv, s) / nv * split_rows(s) * split_cols(s);
     best = (best < 0 || a < best) ? a : best;
   }
-  int pick = 0, area = 0;
-  for (int s = 0; s < kSShapes; ++s) {
+  constexpr int kOrder[kSShapes] = {5, 4, 1, 2, 3, 0};
+  for (int s : kOrder) {
     const int64_t a = split_tiles(nv, s) / nv * split_rows(s) * split_cols(s);
-    const int t = split_rows(s) * split_cols(s);
-    if (10 * a <= 11 * best && t > area) {
-      pick = s;
-      area = t;
-    }
+    if (10 * a <= 11 * best) return s;
   }
-  return pick;
+  return 0;
 }
 
 // One term's operands for a work-group: wave-uniform bases at row 0 / col 0
@@ -459,18 +455,21 @@ __global__ __launch_bounds__(256, 2) void k_build_w_bf16x3(const FragDesc* __res
   }
 }
 
-// Eight-wave split build: 32 TRW rows x 64 TCW cols of one block, wave w at
-// rows 16 TRW (w / 4) and cols 16 TCW (w % 4) of the tile.  Both operands of
-// a K chunk are staged through LDS ([K group][hi, lo][A rows, then B cols]):
-// each A row is read by four waves and each B col by two, so a work-group
-// reads (R + C) rows from memory per chunk for R x C outputs.
-template <int TRW, int TCW>
-__global__ __launch_bounds__(512, 1) void k_build_w_bf16x3_l(const FragDesc* __restrict__ descs,
-                                                             const Item* __restrict__ items,
-                                                             int n_items,
-                                                             float* __restrict__ arena) {
-  constexpr int R = 32 * TRW, C = 64 * TCW, X = R + C;
-  constexpr int NU = (4 * X + 511) / 512;        // staging units (32 bytes) per thread
+// Split build with 2 x WC waves: 32 TRW rows x 16 TCW WC cols of one block,
+// wave w at rows 16 TRW (w / WC) and cols 16 TCW (w % WC) of the tile.  Both
+// operands of a K chunk are staged through LDS ([K group][hi, lo][A rows,
+// then B cols]): each A row is read by WC waves and each B col by two, so a
+// work-group reads (R + C) rows from memory per chunk for R x C outputs.
+// WC = 4 (eight waves, 160 x 320 at TRW = TCW = 5) fills a CU with one
+// work-group; WC = 2 (four waves, 160 x 160) needs half the LDS, so two
+// work-groups share a CU and one's barrier waits overlap the other's work.
+template <int TRW, int TCW, int WC>
+__global__ __launch_bounds__(128 * WC, WC == 4 ? 1 : 2) void k_build_w_bf16x3_l(
+    const FragDesc* __restrict__ descs, const Item* __restrict__ items, int n_items,
+    float* __restrict__ arena) {
+  constexpr int NT = 128 * WC;                   // threads
+  constexpr int R = 32 * TRW, C = 16 * TCW * WC, X = R + C;
+  constexpr int NU = (4 * X + NT - 1) / NT;      // staging units (32 bytes) per thread
   const int ri = find_item<true>(items, n_items, blockIdx.x);
   const int64_t start = ri ? items[ri - 1].blk_end : 0;
   const Item it = items[ri];
@@ -494,8 +493,8 @@ __global__ __launch_bounds__(512, 1) void k_build_w_bf16x3_l(const FragDesc* __r
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int r = lane & 15, g = lane >> 4;
-  const int ra = (wave >> 2) * 16 * TRW;          // this wave's first row in the A region
-  const int cb = R + (wave & 3) * 16 * TCW;       // ... first col in the B region
+  const int ra = (wave / WC) * 16 * TRW;          // this wave's first row in the A region
+  const int cb = R + (wave % WC) * 16 * TCW;      // ... first col in the B region
   const int rx = r ^ lds_swz(g);                  // swizzled row within a 16-row block
 
   __shared__ u4v lds[2][kKs / 8][2][X];
@@ -506,14 +505,14 @@ __global__ __launch_bounds__(512, 1) void k_build_w_bf16x3_l(const FragDesc* __r
 #pragma unroll
     for (int b = 0; b < TCW; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
 
-  // staging unit u = tid + 512 m: LDS row x = u / 4 (A row x, or B col x - R),
+  // staging unit u = tid + NT m: LDS row x = u / 4 (A row x, or B col x - R),
   // K group u % 4; lane addresses are rebuilt per term
   const char* src[NU];
   uint32_t flip_a = 0;
   auto lanes = [&](const SOp& o) {
 #pragma unroll
     for (int m = 0; m < NU; ++m) {
-      int u = tid + 512 * m;
+      int u = tid + NT * m;
       u = u < 4 * X ? u : 4 * X - 1;
       const int x = u >> 2;
       const uint32_t gq = uint32_t(u & 3) * 32u;
@@ -534,7 +533,7 @@ __global__ __launch_bounds__(512, 1) void k_build_w_bf16x3_l(const FragDesc* __r
   auto stage = [&](int b) {
 #pragma unroll
     for (int m = 0; m < NU; ++m) {
-      const int u = tid + 512 * m;
+      const int u = tid + NT * m;
       if (u < 4 * X) {
         const uint32_t f = (u >> 2) < R ? flip_a : 0u;
         const int row = (u >> 2) ^ lds_swz(u & 3);
@@ -584,7 +583,7 @@ __global__ __launch_bounds__(512, 1) void k_build_w_bf16x3_l(const FragDesc* __r
   float* __restrict__ out = arena + it.cube_off + (l2 ? fd.half : 0);
 #pragma unroll
   for (int ct = 0; ct < TCW; ++ct) {
-    const int col = col0 + (wave & 3) * 16 * TCW + 16 * ct + r;
+    const int col = col0 + (wave % WC) * 16 * TCW + 16 * ct + r;
 #pragma unroll
     for (int rt = 0; rt < TRW; ++rt)
 #pragma unroll

@@ -680,16 +680,22 @@ void build_round_split(const Tables& T, size_t q, hipStream_t s, const sie::Frag
       SIE_SPLIT_CASE(2)
       SIE_SPLIT_CASE(3)
 #undef SIE_SPLIT_CASE
-      case 4:
-        hipLaunchKernelGGL((sie::k_build_w_bf16x3_l<sie::sshape(4).trw, sie::sshape(4).tcw>),
-                           grid, dim3(512), 0, s, desc, it, cnt, arena);
-        break;
+#define SIE_SPLIT_CASE_L(S)                                                                \
+  case S:                                                                                  \
+    hipLaunchKernelGGL((sie::k_build_w_bf16x3_l<sie::sshape(S).trw, sie::sshape(S).tcw,    \
+                                                sie::sshape(S).wc>),                       \
+                       grid, dim3(128 * sie::sshape(S).wc), 0, s, desc, it, cnt, arena);   \
+    break;
+      SIE_SPLIT_CASE_L(4)
+      SIE_SPLIT_CASE_L(5)
+#undef SIE_SPLIT_CASE_L
       default:
         break;
     }
   }
 }
-static_assert(sie::kSShapes == 5 && sie::sshape(4).wr == 2,
+static_assert(sie::kSShapes == 6 && sie::sshape(3).wr == 1 && sie::sshape(4).wr == 2 &&
+                  sie::sshape(5).wr == 2,
               "one launch case per split shape");
 
 // bf16 hi/lo copies of every fragment's float32 inputs (see k_bf16.hpp).

@@ -185,7 +185,8 @@ def test_tile_table(lib):
     # split build shapes: automatic choice, forcing and range checks
     m = int(re.search(r"#define SIE_SPLIT_SHAPES (\d+)", open(HEADER).read()).group(1))
     assert lib.sie_split_shape_of(0) == -1
-    assert lib.sie_split_shape_of(320) == 4            # 160 x 320 tiles cover 320 exactly
+    assert lib.sie_split_shape_of(320) == 5            # 160 x 160 tiles cover 320 exactly
+    assert lib.sie_split_shape_of(160) == 5
     assert lib.sie_split_shape_of(200) == 2            # 112 x 256: least padding at 200
     assert lib.sie_split_shape_of(64) == 0
     assert lib.sie_set_split_shape(m) == _lib.SIE_ERR_INVALID_ARG
@@ -193,7 +194,7 @@ def test_tile_table(lib):
     assert lib.sie_set_split_shape(3) == _lib.SIE_OK
     assert lib.sie_split_shape_of(320) == 3
     assert lib.sie_set_split_shape(-1) == _lib.SIE_OK
-    assert lib.sie_split_shape_of(320) == 4
+    assert lib.sie_split_shape_of(320) == 5
     # the work-group count of a fragment depends on its variant only through sizing
     keep = []
     f = frag(keep=keep)

@@ -76,7 +76,7 @@ def test_split_deterministic():
 _EMULATED = {}
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("o,v,aux,seed", [(4, 33, 40, 11), (3, 97, 60, 12)])
 def test_split_every_tile_shape(shape, o, v, aux, seed):
     """Each split build shape, forced, against the emulator: tiles that span
