@@ -810,7 +810,7 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
     }
     __syncthreads();   // sv filled
     const int x = threadIdx.x >> 5, y = (threadIdx.x >> 2) & 7, z0 = 2 * (threadIdx.x & 3);
-#pragma unroll 2
+#pragma unroll
     for (int s = 0; s < 6; ++s) {
       int p0, p1, p2;
       slot_perm(s, p0, p1, p2);
@@ -863,7 +863,7 @@ __global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ d
         if (!dup) primary |= 1u << s;
       }
     }
-#pragma unroll 2
+#pragma unroll
     for (int s = 0; s < 6; ++s) {
       if (!((primary >> s) & 1u)) continue;
       int p0, p1, p2;
