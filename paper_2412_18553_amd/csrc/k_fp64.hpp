@@ -736,9 +736,10 @@ __device__ __forceinline__ void epi_load_w(const CubeT* __restrict__ w1,
 // (FragDesc::lay3), float64 or float32 cubes; V-tilde from t1 and ovov
 // (float64 or float32 inputs), all arithmetic in float64.  Grid: the concatenated
 // epilogue blocks of the round's items (n_part per item; block p of an item
-// takes orbits p, p + n_part, ...).
+// takes orbits p, p + n_part, ...).  Register bound: five waves a SIMD with
+// float32 cubes (the LDS allows five work-groups a CU), four with float64.
 template <typename CubeT, typename InT>
-__global__ __launch_bounds__(256) void k_epilogue(const FragDesc* __restrict__ descs,
+__global__ __launch_bounds__(256, sizeof(CubeT) == 4 ? 5 : 4) void k_epilogue(const FragDesc* __restrict__ descs,
                                                   const Item* __restrict__ items, int n_items,
                                                   const CubeT* __restrict__ arena,
                                                   double* __restrict__ partials, int pstride) {
