@@ -18,13 +18,13 @@
 #pragma once
 
 #include "k_fp64.hpp"
+#include "shapes.hpp"
 
 namespace sie {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kKs = 32;       // K per bf16 MFMA step (and per LDS chunk)
 
 // D(16x16, f32) += A(16x32) * B(32x16) on the bf16 matrix cores.
 __device__ __forceinline__ f4 mfma_bf16(const u4v& a, const u4v& b, f4 c) {
@@ -191,40 +191,6 @@ __device__ __forceinline__ TermS make_term_split(bool l2, int q, const FragDesc&
 // ahead.  Per chunk a wave issues 3 TRW TCW MFMAs for 2 TRW LDS reads and
 // 2 TCW loads of 16 bytes per lane.
 // ---------------------------------------------------------------------------
-
-// Tile shapes (TRW x TCW MFMA tiles per wave).
-// wr x wc waves along rows x cols; wr = 2: the B cols go through LDS too
-// (k_build_w_bf16x3_l).
-struct SShape {
-  int trw, tcw, wr, wc;
-};
-constexpr int kSShapes = 6;
-__host__ __device__ constexpr SShape sshape(int s) {
-  return s == 1 ? SShape{5, 5, 1, 4} : s == 2 ? SShape{7, 4, 1, 4} : s == 3 ? SShape{4, 4, 1, 4}
-       : s == 4 ? SShape{5, 5, 2, 4} : s == 5 ? SShape{5, 5, 2, 2} : SShape{4, 2, 1, 4};
-}
-__host__ __device__ constexpr int split_rows(int s) { return 16 * sshape(s).trw * sshape(s).wr; }
-__host__ __device__ constexpr int split_cols(int s) { return 16 * sshape(s).tcw * sshape(s).wc; }
-__host__ __device__ inline int64_t split_tiles(int nv, int s) {
-  const int R = split_rows(s), C = split_cols(s);
-  return int64_t(nv) * ((nv + R - 1) / R) * ((nv + C - 1) / C);
-}
-// Shape of a fragment with n_v virtuals: among the shapes whose padded tile
-// area is within 10% of the least, the first in the order of their measured
-// speed at 32/320 (5, 4, 1, 2, 3, 0).
-inline int split_shape_of(int nv) {
-  int64_t best = -1;
-  for (int s = 0; s < kSShapes; ++s) {
-    const int64_t a = split_tiles(nv, s) / nv * split_rows(s) * split_cols(s);
-    best = (best < 0 || a < best) ? a : best;
-  }
-  constexpr int kOrder[kSShapes] = {5, 4, 1, 2, 3, 0};
-  for (int s : kOrder) {
-    const int64_t a = split_tiles(nv, s) / nv * split_rows(s) * split_cols(s);
-    if (10 * a <= 11 * best) return s;
-  }
-  return 0;
-}
 
 // One term's operands for a work-group: wave-uniform bases at row 0 / col 0
 // of the tile and K group 0, row strides in bytes, K chunks, and the sign

@@ -31,11 +31,11 @@
 #pragma once
 
 #include "device_common.hpp"
+#include "shapes.hpp"
 #include "work.hpp"
 
 namespace sie {
 
-constexpr int kOrb = 8;       // virtual block edge of the epilogue orbits
 
 // ---------------------------------------------------------------------------
 // float64 W-tilde build.  A work-group of 4 waves computes, for one unit and
@@ -54,7 +54,6 @@ constexpr int kOrb = 8;       // virtual block edge of the epilogue orbits
 // with X^{abc}_{ijk} = sum_d (ia|bd) t_kj^cd - sum_l (ia|jl) t_lk^bc, (ia|jl)
 // read as ooov[j][l][i][a] and t_ij^ab as t2[i][j][a][b] or its twin.
 // ---------------------------------------------------------------------------
-constexpr int kWWaves = 4;               // waves per work-group
 
 // Element (beta, x, k) of the per-block operand is bl[beta*bl_b + x*bl_x + k*bl_k];
 // element (x, k) of the shared operand is scale * sh[x*sh_x + k*sh_k]; x is
@@ -460,59 +459,6 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
   const int q = n / kXcd, r = n % kXcd;
   const int xcd = bid % kXcd, local = bid / kXcd;
   return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
-}
-
-// Tile shapes of the float64 build: BLK blocks per wave, TR x TC 16-wide
-// MFMA tiles per wave along rows x cols, the occupancy target BPC
-// (work-groups per CU), and how the 4 waves of a work-group tile it: WR x WC
-// waves along rows x cols (then all waves share the BLK blocks), or, with
-// WR = WC = 1, 4 waves along the blocks (4 BLK blocks per work-group).  Waves
-// that share blocks share the per-block operand rows, which the work-group
-// then reads from L2 once for more output columns (or rows).  Shapes with
-// lay = 3 use the three-layout build (k_build_w3_f64), TR and TC then
-// counting tiles of the per-block and of the shared side.  Variant 0 is the
-// default; a tile table (sie_set_tile_table) picks one per fragment by n_v.
-struct WShape {
-  int blk, tr, tc, bpc, wr, wc;
-  int lay;     // 2: two-layout build (k_build_w_f64); 3: k_build_w3_f64 with tr = P
-               // (per-block side tiles) and tc = S (shared side tiles)
-  int ks;      // k-steps per K-chunk: 2 (chunks of 8) or 4 (16: a 128-byte line per row)
-};
-constexpr int kWVariants = 15;
-__host__ __device__ inline WShape wshape(int v) {
-  switch (v) {
-    case 1: return WShape{4, 2, 2, 1, 1, 1, 2, 2};
-    case 2: return WShape{2, 2, 2, 2, 1, 1, 2, 2};
-    case 3: return WShape{8, 1, 1, 2, 1, 1, 2, 2};
-    case 4: return WShape{4, 4, 2, 1, 1, 1, 2, 2};
-    case 5: return WShape{4, 2, 4, 1, 1, 1, 2, 2};
-    case 6: return WShape{4, 2, 2, 2, 2, 2, 2, 2};
-    case 7: return WShape{4, 2, 2, 2, 1, 4, 2, 2};
-    case 8: return WShape{4, 2, 2, 2, 4, 1, 2, 2};
-    case 9: return WShape{1, 1, 13, 2, 1, 1, 3, 2};
-    case 10: return WShape{1, 2, 7, 2, 1, 1, 3, 2};
-    case 11: return WShape{2, 1, 7, 2, 1, 1, 3, 2};
-    case 12: return WShape{1, 1, 10, 2, 1, 1, 3, 2};
-    case 13: return WShape{1, 2, 10, 1, 1, 1, 3, 2};
-    case 14: return WShape{1, 2, 4, 2, 1, 1, 3, 2};
-    default: return WShape{4, 2, 2, 2, 1, 1, 2, 2};
-  }
-}
-
-// Work-group tile (blocks, rows, cols) of a shape.
-__host__ __device__ inline void wtile(const WShape& w, int& bb, int& er, int& ec) {
-  const bool grid = w.wr * w.wc > 1;
-  bb = grid ? w.blk : kWWaves * w.blk;
-  er = 16 * w.tr * (grid ? w.wr : 1);
-  ec = 16 * w.tc * (grid ? w.wc : 1);
-}
-
-// Build work-groups of one layout of one unit for a fragment of n_v
-// virtuals: the work-group tiles of the variant's shape over the cube.
-__host__ __device__ inline int64_t wbuild_tiles(int nv, int variant) {
-  int bb, er, ec;
-  wtile(wshape(variant), bb, er, ec);
-  return int64_t((nv + bb - 1) / bb) * ((nv + er - 1) / er) * ((nv + ec - 1) / ec);
 }
 
 // Partial cube of one layout over one tile of one unit, written to the

@@ -16,10 +16,10 @@
 #include <utility>
 #include <vector>
 
-#include "k_adjoint.hpp"
-#include "k_bf16.hpp"
-#include "k_fp64.hpp"
-#include "k_reduce.hpp"
+#include "adj_plan.hpp"
+#include "launch.hpp"
+#include "shapes.hpp"
+#include "work.hpp"
 
 namespace {
 
@@ -586,79 +586,13 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
   }
 }
 
-void launch_build_f64(int variant, unsigned grid, hipStream_t s, const sie::FragDesc* desc,
-                      const sie::Item* items, int n_items, double* arena) {
-  switch (variant) {
-    case 1:
-      hipLaunchKernelGGL((sie::k_build_w_f64<4, 2, 2, 1>), dim3(grid), dim3(256), 0, s, desc,
-                         items, n_items, arena);
-      break;
-    case 2:
-      hipLaunchKernelGGL((sie::k_build_w_f64<2, 2, 2, 2>), dim3(grid), dim3(256), 0, s, desc,
-                         items, n_items, arena);
-      break;
-    case 3:
-      hipLaunchKernelGGL((sie::k_build_w_f64<8, 1, 1, 2>), dim3(grid), dim3(256), 0, s, desc,
-                         items, n_items, arena);
-      break;
-    case 4:
-      hipLaunchKernelGGL((sie::k_build_w_f64<4, 4, 2, 1>), dim3(grid), dim3(256), 0, s, desc,
-                         items, n_items, arena);
-      break;
-    case 5:
-      hipLaunchKernelGGL((sie::k_build_w_f64<4, 2, 4, 1>), dim3(grid), dim3(256), 0, s, desc,
-                         items, n_items, arena);
-      break;
-    case 6:
-      hipLaunchKernelGGL((sie::k_build_w_f64<4, 2, 2, 2, 2, 2>), dim3(grid), dim3(256), 0, s,
-                         desc, items, n_items, arena);
-      break;
-    case 7:
-      hipLaunchKernelGGL((sie::k_build_w_f64<4, 2, 2, 2, 1, 4>), dim3(grid), dim3(256), 0, s,
-                         desc, items, n_items, arena);
-      break;
-    case 8:
-      hipLaunchKernelGGL((sie::k_build_w_f64<4, 2, 2, 2, 4, 1>), dim3(grid), dim3(256), 0, s,
-                         desc, items, n_items, arena);
-      break;
-    case 9:
-      hipLaunchKernelGGL((sie::k_build_w3_f64<1, 1, 13, 2>), dim3(grid), dim3(256), 0, s, desc,
-                         items, n_items, arena);
-      break;
-    case 10:
-      hipLaunchKernelGGL((sie::k_build_w3_f64<1, 2, 7, 2>), dim3(grid), dim3(256), 0, s, desc,
-                         items, n_items, arena);
-      break;
-    case 11:
-      hipLaunchKernelGGL((sie::k_build_w3_f64<2, 1, 7, 2>), dim3(grid), dim3(256), 0, s, desc,
-                         items, n_items, arena);
-      break;
-    case 12:
-      hipLaunchKernelGGL((sie::k_build_w3_f64<1, 1, 10, 2>), dim3(grid), dim3(256), 0, s, desc,
-                         items, n_items, arena);
-      break;
-    case 13:
-      hipLaunchKernelGGL((sie::k_build_w3_f64<1, 2, 10, 1>), dim3(grid), dim3(256), 0, s, desc,
-                         items, n_items, arena);
-      break;
-    case 14:
-      hipLaunchKernelGGL((sie::k_build_w3_f64<1, 2, 4, 2>), dim3(grid), dim3(256), 0, s, desc,
-                         items, n_items, arena);
-      break;
-    default:
-      hipLaunchKernelGGL((sie::k_build_w_f64<4, 2, 2, 2>), dim3(grid), dim3(256), 0, s, desc,
-                         items, n_items, arena);
-      break;
-  }
-}
-
 // float64 build launches of round q (one per tile variant present).
 void build_round_f64(const Tables& T, size_t q, hipStream_t s, const sie::FragDesc* desc,
                      const sie::Item* d_items, double* arena) {
   for (const auto& sg : T.segments) {
     if (sg.round != q) continue;
-    launch_build_f64(sg.variant, unsigned(T.items[sg.r1 - 1].blk_end), s, desc,
-                     d_items + sg.r0, int(sg.r1 - sg.r0), arena);
+    sie::launch_build_f64(sg.variant, unsigned(T.items[sg.r1 - 1].blk_end), s, desc,
+                          d_items + sg.r0, int(sg.r1 - sg.r0), arena);
   }
 }
 
@@ -666,37 +600,10 @@ void build_round_split(const Tables& T, size_t q, hipStream_t s, const sie::Frag
                        const sie::Item* d_items, float* arena) {
   for (const auto& sg : T.segments) {
     if (sg.round != q) continue;
-    const dim3 grid(unsigned(T.items[sg.r1 - 1].blk_end));
-    const sie::Item* it = d_items + sg.r0;
-    const int cnt = int(sg.r1 - sg.r0);
-    switch (sg.variant) {
-#define SIE_SPLIT_CASE(S)                                                                  \
-  case S:                                                                                  \
-    hipLaunchKernelGGL((sie::k_build_w_bf16x3<sie::sshape(S).trw, sie::sshape(S).tcw>), grid, \
-                       dim3(256), 0, s, desc, it, cnt, arena);                             \
-    break;
-      SIE_SPLIT_CASE(0)
-      SIE_SPLIT_CASE(1)
-      SIE_SPLIT_CASE(2)
-      SIE_SPLIT_CASE(3)
-#undef SIE_SPLIT_CASE
-#define SIE_SPLIT_CASE_L(S)                                                                \
-  case S:                                                                                  \
-    hipLaunchKernelGGL((sie::k_build_w_bf16x3_l<sie::sshape(S).trw, sie::sshape(S).tcw,    \
-                                                sie::sshape(S).wc>),                       \
-                       grid, dim3(128 * sie::sshape(S).wc), 0, s, desc, it, cnt, arena);   \
-    break;
-      SIE_SPLIT_CASE_L(4)
-      SIE_SPLIT_CASE_L(5)
-#undef SIE_SPLIT_CASE_L
-      default:
-        break;
-    }
+    sie::launch_build_split(sg.variant, unsigned(T.items[sg.r1 - 1].blk_end), s, desc,
+                            d_items + sg.r0, int(sg.r1 - sg.r0), arena);
   }
 }
-static_assert(sie::kSShapes == 6 && sie::sshape(3).wr == 1 && sie::sshape(4).wr == 2 &&
-                  sie::sshape(5).wr == 2,
-              "one launch case per split shape");
 
 // bf16 hi/lo copies of every fragment's float32 inputs (see k_bf16.hpp).
 sie_status stage_split(const std::vector<sie::FragDesc>& desc, hipStream_t s) {
@@ -706,9 +613,8 @@ sie_status stage_split(const std::vector<sie::FragDesc>& desc, hipStream_t s) {
     const int64_t total = int64_t(P) * X * Y * (Kpad / 8);
     const int64_t nb = (total + 255) / 256;
     const unsigned grid = unsigned(nb < 65536 ? nb : 65536);
-    hipLaunchKernelGGL(sie::k_split_bf16, dim3(grid), dim3(256), 0, s,
-                       static_cast<const float*>(src), P, X, Y, sp, sx, sy, sk, K, Kpad, kfast,
-                       const_cast<sie::u4v*>(dst));
+    sie::launch_split_bf16(grid, s, static_cast<const float*>(src), P, X, Y, sp, sx, sy, sk, K,
+                           Kpad, kfast, const_cast<sie::u4v*>(dst));
   };
   for (const sie::FragDesc& d : desc) {
     const int no = d.no, nv = d.nv;
@@ -794,8 +700,7 @@ sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag
       }
       {
         ProfScope ps(s, 1);
-        hipLaunchKernelGGL((sie::k_epilogue<double, double>), dim3(n_epi), dim3(256), 0, s,
-                           d_desc, ri, cnt, arena, d_part, pl.pstride);
+        sie::launch_epilogue_f64(n_epi, s, d_desc, ri, cnt, arena, d_part, pl.pstride);
       }
     } else {
       float* arena = reinterpret_cast<float*>(dev(pl.off_arena));
@@ -805,8 +710,7 @@ sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag
       }
       {
         ProfScope ps(s, 1);
-        hipLaunchKernelGGL((sie::k_epilogue<float, float>), dim3(n_epi), dim3(256), 0, s, d_desc,
-                           ri, cnt, arena, d_part, pl.pstride);
+        sie::launch_epilogue_f32(n_epi, s, d_desc, ri, cnt, arena, d_part, pl.pstride);
       }
     }
     st = hip_check(hipGetLastError(), "launch (T) kernels");
@@ -818,12 +722,10 @@ sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag
     ProfScope ps(s, 2);
     int64_t max_units = 1;
     for (const auto& fp : pl.frags) max_units = fp.n_units > max_units ? fp.n_units : max_units;
-    hipLaunchKernelGGL(sie::k_unit_energy, dim3(unsigned((max_units + 255) / 256), unsigned(n)),
-                       dim3(256), 0, s, d_desc, d_part, pl.pstride, d_units);
-    hipLaunchKernelGGL(sie::k_frag_energy, dim3(unsigned(n)), dim3(256), 0, s, d_desc, d_units,
-                       d_efrag);
-    if (e_total)
-      hipLaunchKernelGGL(sie::k_sum_fixed, dim3(1), dim3(256), 0, s, d_efrag, int64_t(n), e_total);
+    sie::launch_unit_energy(dim3(unsigned((max_units + 255) / 256), unsigned(n)), s, d_desc,
+                            d_part, pl.pstride, d_units);
+    sie::launch_frag_energy(unsigned(n), s, d_desc, d_units, d_efrag);
+    if (e_total) sie::launch_sum_fixed(s, d_efrag, int64_t(n), e_total);
   }
   return hip_check(hipGetLastError(), "launch reductions");
 }
@@ -831,16 +733,7 @@ sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag
 
 // Backward contraction lists of one round: for every class, the output slices
 // the round's units touch (sorted), each with its records in item order.
-struct AdjLaunch {
-  size_t group_off = 0;   // first group in the uploaded group table
-  int n_groups = 0;
-  int64_t n_wg = 0;
-  int rec_begin = 0, rec_end = 0;   // the class's records in the uploaded record table
-  size_t slice_off = 0;   // summed-block classes: output slices in the slice table
-  int n_slices = 0;
-  int64_t max_slice = 0;  // largest slice (elements): the partial-sum grid
-  int64_t part_elems = 0; // partial-slice elements the class writes
-};
+using sie::AdjLaunch;
 
 // Output-slice elements of a summed-block class for a fragment.
 int64_t adj_slice_elems(int cls, int no, int nv) {
@@ -936,56 +829,23 @@ void adj_round_lists(const Tables& T, size_t r0, size_t r1, std::vector<sie::Adj
 }
 
 // G / H and the gradient contractions of one backward round.
-template <typename CubeT, typename InT>
-void backward_round(const std::array<AdjLaunch, sie::kAdjClasses>& L, hipStream_t s,
-                    const sie::FragDesc* d_desc, const sie::Item* ri, int cnt,
-                    const sie::AdjGroup* d_groups, const sie::AdjRec* d_recs,
-                    const sie::AdjSlice* d_slices, double* d_parts, CubeT* arena,
-                    double* d_part, int pstride, const double* grad_e, unsigned n_epi,
-                    double* t1_part, int nv_max) {
+void backward_round(bool split, const std::array<AdjLaunch, sie::kAdjClasses>& L, hipStream_t s,
+                    const sie::AdjArgs& a, void* arena, double* d_part, int pstride,
+                    const double* grad_e, unsigned n_epi) {
   {
     ProfScope ps(s, 1);
-    hipLaunchKernelGGL((sie::k_hat<CubeT, InT>), dim3(n_epi), dim3(256), 0, s, d_desc, ri, cnt,
-                       arena, d_part, pstride, grad_e);
+    if (split)
+      sie::launch_hat_f32(n_epi, s, a.desc, a.items, a.n_items, static_cast<float*>(arena),
+                          d_part, pstride, grad_e);
+    else
+      sie::launch_hat_f64(n_epi, s, a.desc, a.items, a.n_items, static_cast<double*>(arena),
+                          d_part, pstride, grad_e);
   }
   ProfScope ps(s, 4);
-  auto contract = [&](auto kernel, const AdjLaunch& l) {
-    if (l.n_wg)
-      hipLaunchKernelGGL(kernel, dim3(unsigned(l.n_wg)), dim3(sie::kAThreads), 0, s, d_desc, ri,
-                         d_groups + l.group_off, l.n_groups, d_recs,
-                         static_cast<const CubeT*>(arena), d_parts);
-  };
-  auto part_sum = [&](auto kernel, const AdjLaunch& l) {   // after the class's contraction
-    if (l.n_slices)
-      hipLaunchKernelGGL(kernel, dim3(unsigned((l.max_slice + 255) / 256), unsigned(l.n_slices)),
-                         dim3(256), 0, s, d_desc, d_slices + l.slice_off,
-                         static_cast<const double*>(d_parts));
-  };
-  contract(sie::k_adj_contract<sie::kAdjOvvv, CubeT, InT>, L[sie::kAdjOvvv]);
-  contract(sie::k_adj_contract<sie::kAdjT2vv, CubeT, InT>, L[sie::kAdjT2vv]);
-  part_sum(sie::k_adj_part_sum<sie::kAdjT2vv>, L[sie::kAdjT2vv]);
-  contract(sie::k_adj_contract<sie::kAdjT2oo, CubeT, InT>, L[sie::kAdjT2oo]);
-  contract(sie::k_adj_contract<sie::kAdjOoov, CubeT, InT>, L[sie::kAdjOoov]);
-  part_sum(sie::k_adj_part_sum<sie::kAdjOoov>, L[sie::kAdjOoov]);
-  const AdjLaunch& lp = L[sie::kAdjOvov];
-  if (lp.n_wg)
-    hipLaunchKernelGGL((sie::k_adj_ovov<CubeT, InT>), dim3(unsigned(lp.n_wg)), dim3(256), 0, s,
-                       d_desc, ri, d_groups + lp.group_off, lp.n_groups, d_recs,
-                       static_cast<const CubeT*>(arena));
-  const AdjLaunch& l1 = L[sie::kAdjT1];
-  if (l1.n_groups) {
-    const int r0 = l1.rec_begin, r1 = l1.rec_end;
-    for (int b0 = r0; b0 < r1; b0 += kT1Batch) {
-      const int b1 = b0 + kT1Batch < r1 ? b0 + kT1Batch : r1;
-      hipLaunchKernelGGL((sie::k_adj_t1_part<CubeT, InT>), dim3(unsigned(b1 - b0)), dim3(256), 0,
-                         s, d_desc, ri, d_recs, b0, static_cast<const CubeT*>(arena), t1_part,
-                         nv_max);
-      hipLaunchKernelGGL(sie::k_adj_t1_sum, dim3(unsigned((nv_max + 255) / 256),
-                                                 unsigned(l1.n_groups)),
-                         dim3(256), 0, s, d_desc, d_groups + l1.group_off, b0, b1, t1_part,
-                         nv_max);
-    }
-  }
+  if (split)
+    sie::launch_adj_f32(L.data(), a, static_cast<const float*>(arena), s);
+  else
+    sie::launch_adj_f64(L.data(), a, static_cast<const double*>(arena), s);
 }
 
 sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const double* grad_e,
@@ -1079,8 +939,7 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
   auto fill = [&](double* ptr, int64_t count) {
     if (!ptr || count <= 0) return;
     const int64_t nb = (count + 255) / 256;
-    hipLaunchKernelGGL(sie::k_fill_zero, dim3(unsigned(nb < 65536 ? nb : 65536)), dim3(256), 0,
-                       s, ptr, count);
+    sie::launch_fill_zero(unsigned(nb < 65536 ? nb : 65536), s, ptr, count);
   };
   {
     ProfScope ps(s, 4);
@@ -1112,16 +971,10 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
       else
         build_round_f64(T, q, s, d_desc, d_items, arena);
     }
-    if (pl.split)
-      backward_round<float, float>(launches[q], s, d_desc, ri, cnt, d_groups, d_recs, d_slices,
-                                   d_parts, reinterpret_cast<float*>(dev(pl.off_arena)), d_part,
-                                   pl.pstride, grad_e, unsigned(T.items[r1 - 1].part_end),
-                                   t1_part, pl.nv_max);
-    else
-      backward_round<double, double>(launches[q], s, d_desc, ri, cnt, d_groups, d_recs, d_slices,
-                                     d_parts, arena,
-                                     d_part, pl.pstride, grad_e,
-                                     unsigned(T.items[r1 - 1].part_end), t1_part, pl.nv_max);
+    sie::AdjArgs aa{d_desc, ri, cnt, d_groups, d_recs, d_slices, d_parts, t1_part, pl.nv_max,
+                    kT1Batch};
+    backward_round(pl.split, launches[q], s, aa, dev(pl.off_arena), d_part, pl.pstride, grad_e,
+                   unsigned(T.items[r1 - 1].part_end));
     st = hip_check(hipGetLastError(), "launch backward kernels");
     if (st != SIE_OK) return st;
   }
@@ -1131,8 +984,7 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
     auto sym = [&](double* ptr, int kind, int no, int nv, int64_t count) {
       if (!ptr) return;
       const int64_t nb = (count + 255) / 256;
-      hipLaunchKernelGGL(sie::k_symmetrize, dim3(unsigned(nb < 65536 ? nb : 65536)), dim3(256),
-                         0, s, ptr, kind, no, nv, count);
+      sie::launch_symmetrize(unsigned(nb < 65536 ? nb : 65536), s, ptr, kind, no, nv, count);
     };
     for (int x = 0; x < n; ++x) {
       const int no = frags[x].n_occ, nv = frags[x].n_vir;
@@ -1147,10 +999,9 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
     ProfScope ps(s, 2);
     int64_t max_units = 1;
     for (const auto& fp : pl.frags) max_units = fp.n_units > max_units ? fp.n_units : max_units;
-    hipLaunchKernelGGL(sie::k_unit_energy, dim3(unsigned((max_units + 255) / 256), unsigned(n)),
-                       dim3(256), 0, s, d_desc, d_part, pl.pstride, d_units);
-    hipLaunchKernelGGL(sie::k_frag_energy, dim3(unsigned(n)), dim3(256), 0, s, d_desc, d_units,
-                       d_efrag);
+    sie::launch_unit_energy(dim3(unsigned((max_units + 255) / 256), unsigned(n)), s, d_desc,
+                            d_part, pl.pstride, d_units);
+    sie::launch_frag_energy(unsigned(n), s, d_desc, d_units, d_efrag);
   }
   return hip_check(hipGetLastError(), "launch gradient symmetrization and reductions");
 }

@@ -1,0 +1,45 @@
+// R/D epilogue, fixed-order reductions, fill and symmetrize (see k_fp64.hpp,
+// k_reduce.hpp, k_adjoint.hpp).
+#include "k_adjoint.hpp"
+#include "k_fp64.hpp"
+#include "k_reduce.hpp"
+#include "launch.hpp"
+
+namespace sie {
+
+void launch_epilogue_f64(unsigned grid, hipStream_t s, const FragDesc* desc, const Item* items,
+                         int n_items, const double* arena, double* partials, int pstride) {
+  hipLaunchKernelGGL((k_epilogue<double, double>), dim3(grid), dim3(256), 0, s, desc, items,
+                     n_items, arena, partials, pstride);
+}
+
+void launch_epilogue_f32(unsigned grid, hipStream_t s, const FragDesc* desc, const Item* items,
+                         int n_items, const float* arena, double* partials, int pstride) {
+  hipLaunchKernelGGL((k_epilogue<float, float>), dim3(grid), dim3(256), 0, s, desc, items,
+                     n_items, arena, partials, pstride);
+}
+
+void launch_unit_energy(dim3 grid, hipStream_t s, const FragDesc* desc, const double* partials,
+                        int pstride, double* e_units) {
+  hipLaunchKernelGGL(k_unit_energy, grid, dim3(256), 0, s, desc, partials, pstride, e_units);
+}
+
+void launch_frag_energy(unsigned grid, hipStream_t s, const FragDesc* desc,
+                        const double* e_units, double* e_frag) {
+  hipLaunchKernelGGL(k_frag_energy, dim3(grid), dim3(256), 0, s, desc, e_units, e_frag);
+}
+
+void launch_sum_fixed(hipStream_t s, const double* x, int64_t n, double* out) {
+  hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, s, x, n, out);
+}
+
+void launch_fill_zero(unsigned grid, hipStream_t s, double* p, int64_t n) {
+  hipLaunchKernelGGL(k_fill_zero<>, dim3(grid), dim3(256), 0, s, p, n);
+}
+
+void launch_symmetrize(unsigned grid, hipStream_t s, double* g, int kind, int no, int nv,
+                       int64_t n) {
+  hipLaunchKernelGGL(k_symmetrize<>, dim3(grid), dim3(256), 0, s, g, kind, no, nv, n);
+}
+
+}  // namespace sie
