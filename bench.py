@@ -1,23 +1,31 @@
 """Throughput of the per-fragment (T) energy on one MI355X.
 
-python bench.py [--steps K] [--warmup W] [--mode fp64|split|batched|backward]
-                [--workload NAME] [--no-cpu]
+python bench.py [--steps K] [--warmup W] [--mode split|fp64|batched|backward|peak]
+                [--workload NAME] [--precision fp64|split_bf16] [--no-cpu] [--no-fp64]
 
-Default (the headline line): a step is one full float64 (T) energy
-evaluation (W-tilde build, R/D epilogue and the reductions) of the
-24-occupied / 200-virtual synthetic fragment, inputs already resident in
-HBM.  Metric: algorithmic TFLOP/s, F = 2 n_o^3 n_v^4 + 2 n_o^4 n_v^3 per
-fragment, divided by the step time.  Prints one JSON line.
+Default (the headline line): a step is one full split-precision (T) energy
+evaluation (bf16 hi/lo staging, W-tilde build, R/D epilogue, reductions) of
+the 32-occupied / 320-virtual synthetic fragment (float32 inputs), inputs
+already resident in HBM.  Metric: algorithmic TFLOP/s, F = 2 n_o^3 n_v^4 +
+2 n_o^4 n_v^3 per fragment, divided by the step time.  The same run also
+times one float64 evaluation of the same fragment (the float32 inputs
+widened) for the split-over-float64 speedup, and reports both energies'
+errors against the stored CPU-oracle value of that fragment, plus the split
+error on its chemically scaled copy (integrals and t2 times 2^-9).  Prints
+one JSON line.
 
-Other modes (same JSON shape): `split` (float32 inputs, bf16 hi/lo products;
-32/320 fragment), `batched` (one evaluation over the 16-fragment batch),
-`backward` (energy gradient of the 16/120 fragment).
+Other modes (same JSON shape): `fp64` (24/200 fragment, float64), `batched`
+(one evaluation over a named batch, batch16 or batch64, --precision),
+`backward` (energy gradient of the 16/120 fragment), `peak` (the matrix-core
+microbenchmark alone).
 """
 
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
+import math
 import os
 import sys
 import time
@@ -25,11 +33,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_MFMA_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
-PEAK_BF16_MFMA_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
+PEAK_FP64_MFMA_TFLOPS = 78.6      # MI355X dense FP64 matrix peak (published)
+PEAK_BF16_MFMA_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak (published)
+CHEM_SCALE = 2.0 ** -9            # integrals and t2 of the chemically scaled copy
 
 DEFAULT_WORKLOAD = {"fp64": "o24v200", "split": "o32v320", "batched": "batch16",
-                    "backward": "o16v120"}
+                    "backward": "o16v120", "peak": None}
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
 def parse():
@@ -37,16 +47,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="fp64", choices=sorted(DEFAULT_WORKLOAD))
+    ap.add_argument("--mode", default="split", choices=sorted(DEFAULT_WORKLOAD))
     ap.add_argument("--workload", default=None)
     ap.add_argument("--precision", default=None, choices=["fp64", "split_bf16"],
                     help="batched mode: precision of the evaluation (default fp64)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="split mode: skip the float64 evaluation of the same fragment")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES device-to-device (a known-size transfer against "
                          "which hardware byte counters are scaled)")
-    ap.add_argument("--cpu-a", default="120,121",
-                    help="outer virtual indices a of the CPU-baseline sample")
     return ap.parse_args()
 
 
@@ -55,47 +65,57 @@ def flops(o, v):
     return 2.0 * o ** 3 * v ** 4 + 2.0 * o ** 4 * v ** 3
 
 
-def build_work(o, v, pair=True, lay3=False):
-    """Flops of the W-tilde build actually launched for one fragment: every
-    occupied triple that is not i = j = k, 12 terms (6 with K = n_v, 6 with
-    K = n_o) in two layouts of six or three layouts of four (`lay3`); a triple
-    with exactly two equal indices (n_o (n_o - 1) of them) builds one of two
-    layouts or two of three in the energy (`pair`), all of them in the gradient."""
-    n_units = o * (o + 1) * (o + 2) // 6
-    n_pair = o * (o - 1) if pair else 0
-    saved = (1.0 / 3.0 if lay3 else 0.5) * n_pair
-    return (n_units - o - saved) * (12.0 * v ** 4 + 12.0 * o * v ** 3)
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
-def lay3_of(v):
-    """Whether the float64 energy of a fragment with v virtuals uses the
-    three-layout build under the installed tile table."""
-    import paper_2412_18553_amd as sie
-    return sie.tile_variants()[sie.tile_variant_of(v)][6] >= 3
+# ---------------------------------------------------------------- peak
+def measured_peak(kind):
+    """TFLOP/s of the in-repo matrix-core microbenchmark (kind 0: float64
+    16x16x4, kind 1: bf16 16x16x32), or None if its library is absent."""
+    path = os.path.join(ROOT, "paper_2412_18553_amd", "libsie_mfma_peak.so")
+    if not os.path.exists(path):
+        return None
+    lib = ctypes.CDLL(path)
+    lib.sie_mfma_peak.restype = ctypes.c_int
+    lib.sie_mfma_peak.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_double)]
+    out = ctypes.c_double(0.0)
+    iters = 20000 if kind == 0 else 40000
+    st = lib.sie_mfma_peak(kind, iters, 8192, ctypes.byref(out))
+    if st != 0:
+        raise RuntimeError(f"sie_mfma_peak failed with {st}")
+    return round(out.value, 2)
 
 
-def cpu_baseline(frag, a_values):
+# ---------------------------------------------------------------- CPU baseline
+def cpu_baseline(host_frag, units):
     """Time the CPU oracle on a bounded sample of the same fragment: the
-    virtual triples (a, b, c) with a in a_values (all b <= a, c <= b)."""
-    import oracle.triples as T
+    occupied-outer oracle (oracle.occupied_triple_parts) on the given
+    occupied triples; the rate is the sample's flops over its time, i.e. an
+    extrapolation of the whole fragment's oracle rate."""
+    import oracle
     try:
         from threadpoolctl import threadpool_info
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
         cores = 1
-    o, v = frag.n_occ, frag.n_vir
-    n_tri = sum((a + 1) * (a + 2) // 2 for a in a_values)
-    work = n_tri * 12.0 * o ** 3 * (v + o)       # per virtual triple: 6 terms, K = n_v and n_o
+    o, v = host_frag.n_occ, host_frag.n_vir
     t0 = time.perf_counter()
-    T.energy_literal_vectorized(*frag.arrays(), a_values=list(a_values))
+    for (i, j, k) in units:
+        oracle.occupied_triple_parts(i, j, k, *host_frag.arrays())
     dt = time.perf_counter() - t0
-    return {"value": work / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": f"oracle.energy_literal_vectorized over the {n_tri} virtual triples "
-                      f"with a in {list(a_values)} of the same {o}/{v} fragment ({dt:.1f} s)",
-            "seconds": dt}
+    # flops of one occupied triple with three distinct indices: 12 n_v^4 + 12 n_o n_v^3
+    work = len(units) * (12.0 * v ** 4 + 12.0 * o * v ** 3)
+    return {"value": round(work / dt / 1e12, 5), "unit": "TFLOP/s", "cores": int(cores),
+            "kind": "oracle", "extrapolated": True,
+            "sample": f"oracle.occupied_triple_parts on occupied triples {list(units)} of the same "
+                      f"{o}/{v} fragment ({dt:.1f} s); rate = sample flops / sample time, "
+                      f"extrapolated to the whole fragment",
+            "seconds": round(dt, 2)}
 
 
+# ---------------------------------------------------------------- helpers
 def sources_sha256():
     """Hash of the kernel sources (csrc/), against which a recorded counter
     measurement is matched: any change to them voids the measurement."""
@@ -133,19 +153,10 @@ def recorded_traffic(kernel, workload):
     return None
 
 
-def log(msg):
-    print(msg, file=sys.stderr, flush=True)
-
-
-def to_device(frag, dtype):
-    import numpy as np
-    import torch
+def frag_of(df, precision):
     import paper_2412_18553_amd as sie
-    dev = torch.device("cuda:0")
-    cast = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev, dtype)  # noqa: E731
-    prec = "fp64" if dtype == torch.float64 else "split_bf16"
-    return sie.Fragment(frag.eps_occ, frag.eps_vir, cast(frag.t1), cast(frag.t2),
-                        cast(frag.ovvv), cast(frag.ooov), cast(frag.ovov), prec)
+    return sie.Fragment(df.eps_occ, df.eps_vir, df.t1, df.t2, df.ovvv, df.ooov, df.ovov,
+                        precision)
 
 
 def timed(step, steps, warmup):
@@ -160,22 +171,29 @@ def timed(step, steps, warmup):
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
-    for _ in range(steps):
+    for s in range(steps):
         step()
     stop.record()
     torch.cuda.synchronize()
     prof = sie.profile_collect()
     sie.profile_enable(False)
+    log(f"# {steps} timed steps done")
     return start.elapsed_time(stop) / steps, prof
 
 
-def roofline(prof, cls, kernel, work_per_step, steps, peak, scale=1.0, bound="mfma",
+def roofline(prof, cls, kernel, work_per_step, steps, peak, *, issued=1.0, measured=None,
              workload=None):
+    """Achieved rate of the dominant kernel class `cls`: algorithmic flops
+    (`work_per_step` x `issued` products per algorithmic product) over the
+    summed launch durations (HIP events on the launch stream)."""
     ms, n = prof[cls]
-    achieved = scale * work_per_step * steps / (ms * 1e-3) / 1e12
-    out = {"bound": bound, "kernel": kernel, "achieved": round(achieved, 3), "peak": peak,
+    achieved = issued * work_per_step * steps / (ms * 1e-3) / 1e12
+    out = {"bound": "mfma", "kernel": kernel, "achieved": round(achieved, 3), "peak": peak,
            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-           "launches": int(n), "avg_launch_ms": round(ms / max(n, 1), 4)}
+           "launches": int(n), "avg_launch_ms": round(ms / max(n, 1), 4),
+           "work": "algorithmic F" + (f" x {issued:g} issued products" if issued != 1 else "")}
+    if measured:
+        out.update(peak_measured=measured, frac_measured=round(achieved / measured, 4))
     rec = recorded_traffic(kernel, workload) if workload else None
     if rec:
         # HBM bytes per launch (counters, copy-calibrated) against the
@@ -184,6 +202,209 @@ def roofline(prof, cls, kernel, work_per_step, steps, peak, scale=1.0, bound="mf
                    algorithmic_bytes=rec["algorithmic_bytes_per_launch"],
                    traffic_source=rec["profile"])
     return out
+
+
+def split_kernel_name(nv):
+    import paper_2412_18553_amd as sie
+    s = sie.split_shape_of(nv)
+    shapes = {0: "k_build_w_bf16x3<4, 2>", 1: "k_build_w_bf16x3<5, 5>",
+              2: "k_build_w_bf16x3<7, 4>", 3: "k_build_w_bf16x3<4, 4>",
+              4: "k_build_w_bf16x3_l<5, 5, 4>", 5: "k_build_w_bf16x3_l<5, 5, 2>"}
+    return shapes[s]
+
+
+def stored_oracle(name):
+    p = os.path.join(GOLDEN, name)
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        return json.load(fh)
+
+
+# ---------------------------------------------------------------- modes
+def run_split(args, result, name):
+    import torch
+    import paper_2412_18553_amd as sie
+    from synth import WORKLOADS
+    from synth.device import workload_fragment_device
+    w = WORKLOADS[name]
+    o, v = w["n_occ"], w["n_vir"]
+    F = flops(o, v)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    df = workload_fragment_device(name, device=dev, dtype=torch.float32)
+    log(f"# workload {name}: float32 inputs built on the GPU in {time.perf_counter() - t0:.1f} s")
+    fr = frag_of(df, "split_bf16")
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    ws = torch.empty(sie.workspace_size(fr), dtype=torch.uint8, device=dev)
+    step = lambda: sie.energy(fr, workspace=ws, out=out)  # noqa: E731
+    ms, prof = timed(step, args.steps, args.warmup)
+    energy = float(out.item())
+    peak_bf16 = measured_peak(1)
+    desc = f"single fragment n_occ={o} n_vir={v} n_aux={w['n_aux']}, float32 inputs"
+    result.update(value=round(F / (ms * 1e-3) / 1e12, 3), dtype="bf16x3/f32",
+                  config={"workload": desc, "precision": "split_bf16", "fragments": 1})
+    rl = roofline(prof, "w_build", split_kernel_name(v), F, args.steps, PEAK_BF16_MFMA_TFLOPS,
+                  issued=3.0, measured=peak_bf16, workload=name)
+    eff = F * args.steps / (prof["w_build"][0] * 1e-3) / 1e12
+    rl.update(effective_achieved=round(eff, 3), effective_frac=round(eff / PEAK_BF16_MFMA_TFLOPS, 4))
+    result["roofline"] = rl
+    result.update(ms_per_step=round(ms, 3), fragments_per_s=round(1000.0 / ms, 4), energy=energy)
+
+    g = stored_oracle(f"{name}_f32_all_units.json")
+    acc = {}
+    if g:
+        acc["oracle_energy"] = g["energy"]
+        acc["split_error_ueh"] = round((energy - g["energy"]) * 1e6, 3)
+        acc["split_error_rel"] = float(f"{(energy - g['energy']) / abs(g['energy']):.3e}")
+    # chemically scaled copy: integrals and t2 times 2^-9 (exact in float32)
+    with torch.no_grad():
+        for x in (df.t2, df.ovvv, df.ooov, df.ovov):
+            x.mul_(CHEM_SCALE)
+    sie.energy(fr, workspace=ws, out=out)
+    e_chem = float(out.item())
+    if g:
+        ref = math.fsum([x * CHEM_SCALE ** 4 for x in g["e_ww_units"]] +
+                        [x * CHEM_SCALE ** 3 for x in g["e_wv_units"]])
+        acc.update(chemical_scale_oracle=ref, chemical_scale_split=e_chem,
+                   chemical_scale_error_ueh=float(f"{(e_chem - ref) * 1e6:.4e}"))
+    with torch.no_grad():
+        for x in (df.t2, df.ovvv, df.ooov, df.ovov):
+            x.mul_(1.0 / CHEM_SCALE)
+    result["accuracy"] = acc
+    log("# split accuracy done")
+
+    if not args.no_fp64:
+        # one float64 evaluation of the same fragment (the float32 inputs widened)
+        del ws
+        d64 = type(df)(df.eps_occ, df.eps_vir, *(x.double() for x in df.arrays()[2:]))
+        fr64 = frag_of(d64, "fp64")
+        ws64 = torch.empty(sie.workspace_size(fr64), dtype=torch.uint8, device=dev)
+        out64 = torch.empty(1, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        sie.profile_enable(True)
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        sie.energy(fr64, workspace=ws64, out=out64)
+        stop.record()
+        torch.cuda.synchronize()
+        p64 = sie.profile_collect()
+        sie.profile_enable(False)
+        ms64 = start.elapsed_time(stop)
+        e64 = float(out64.item())
+        peak64 = measured_peak(0)
+        fp = {"ms": round(ms64, 1), "value": round(F / (ms64 * 1e-3) / 1e12, 3),
+              "speedup_split_over_fp64": round(ms64 / ms, 3), "energy": e64,
+              "build_achieved": round(F / (p64["w_build"][0] * 1e-3) / 1e12, 3),
+              "build_frac": round(F / (p64["w_build"][0] * 1e-3) / 1e12 / PEAK_FP64_MFMA_TFLOPS, 4),
+              "peak_measured": peak64}
+        if g:
+            fp["error_rel"] = float(f"{(e64 - g['energy']) / abs(g['energy']):.3e}")
+        result["fp64_same_fragment"] = fp
+        log("# float64 evaluation done")
+        del ws64, d64, fr64
+    if not args.no_cpu:
+        host = df.host()
+        del df, fr
+        torch.cuda.empty_cache()
+        result["cpu_baseline"] = cpu_baseline(host, [(o - 1, o // 2, 0), (o // 3, o // 4, o // 5)])
+    result["kernel_ms_per_step"] = {k: round(t / args.steps, 3) for k, (t, _) in prof.items()}
+
+
+def run_single(args, result, name, mode):
+    import torch
+    import paper_2412_18553_amd as sie
+    from synth import WORKLOADS
+    from synth.device import workload_fragment_device
+    w = WORKLOADS[name]
+    o, v = w["n_occ"], w["n_vir"]
+    F = flops(o, v)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    df = workload_fragment_device(name, device=dev)
+    log(f"# workload {name}: built on the GPU in {time.perf_counter() - t0:.1f} s")
+    fr = frag_of(df, "fp64")
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    desc = f"single fragment n_occ={o} n_vir={v} n_aux={w['n_aux']}"
+    if mode == "backward":
+        ws = torch.empty(sie.backward_workspace_size(fr), dtype=torch.uint8, device=dev)
+        grads = [{n: torch.empty_like(getattr(fr, n), dtype=torch.float64)
+                  for n in sie.GRAD_NAMES}]
+        step = lambda: sie.backward(fr, grads=grads, e_frag=out, workspace=ws)  # noqa: E731
+    else:
+        ws = torch.empty(sie.workspace_size(fr), dtype=torch.uint8, device=dev)
+        step = lambda: sie.energy(fr, workspace=ws, out=out)  # noqa: E731
+    ms, prof = timed(step, args.steps, args.warmup)
+    energy = float(out.item())
+    peak64 = measured_peak(0)
+    if mode == "fp64":
+        result.update(value=round(F / (ms * 1e-3) / 1e12, 3), dtype="f64",
+                      config={"workload": desc, "precision": "fp64", "fragments": 1})
+        lay = sie.tile_variants()[sie.tile_variant_of(v)][6]
+        kernel = {2: "k_build_w_f64", 3: "k_build_w3_f64"}[lay]
+        result["roofline"] = roofline(prof, "w_build", kernel, F, args.steps,
+                                      PEAK_FP64_MFMA_TFLOPS, measured=peak64, workload=name)
+        result["roofline"]["tile_variant"] = sie.tile_variant_of(v)
+        g = stored_oracle(f"{name}.json")
+        if g:
+            result["accuracy"] = {"oracle_energy": g["energy"],
+                                  "error_rel": float(f"{(energy - g['energy']) / abs(g['energy']):.3e}")}
+    else:
+        # the backward recomputes the build (F) and runs the transposed
+        # contractions of every build term (2F): 3F per step
+        result.update(metric="(T) gradient TFLOP/s (3 x F per step)",
+                      value=round(3.0 * F / (ms * 1e-3) / 1e12, 3), dtype="f64",
+                      config={"workload": desc, "precision": "fp64", "fragments": 1,
+                              "outputs": "dE/d(t1, t2, ovvv, ooov, ovov)"})
+        result["roofline"] = roofline(prof, "grad", "k_adj_contract", 2.0 * F, args.steps,
+                                      PEAK_FP64_MFMA_TFLOPS, measured=peak64, workload=name)
+    result.update(ms_per_step=round(ms, 3), fragments_per_s=round(1000.0 / ms, 4), energy=energy)
+    if mode == "fp64" and not args.no_cpu:
+        host = df.host()
+        del df, fr
+        torch.cuda.empty_cache()
+        result["cpu_baseline"] = cpu_baseline(host, [(o - 1, o // 2, 0)])
+    result["kernel_ms_per_step"] = {k: round(t / args.steps, 3) for k, (t, _) in prof.items()}
+
+
+def run_batched(args, result, name):
+    import torch
+    import paper_2412_18553_amd as sie
+    from synth import batch_shapes
+    from synth.device import make_fragment_device
+    prec = args.precision or "fp64"
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    dev = torch.device("cuda:0")
+    shapes = batch_shapes(name)
+    t0 = time.perf_counter()
+    frs = []
+    for n, (o, v, aux, seed) in enumerate(shapes):
+        frs.append(frag_of(make_fragment_device(o, v, aux, seed, device=dev, dtype=dtype), prec))
+        if n % 8 == 7:
+            log(f"# {n + 1} fragments built")
+    log(f"# workload {name}: {len(frs)} fragments built on the GPU in "
+        f"{time.perf_counter() - t0:.1f} s")
+    ws = torch.empty(sie.workspace_size(frs), dtype=torch.uint8, device=dev)
+    e_frag = torch.empty(len(frs), dtype=torch.float64, device=dev)
+    e_tot = torch.empty(1, dtype=torch.float64, device=dev)
+    step = lambda: sie.energy_batched(frs, workspace=ws, out=e_frag, total=e_tot)  # noqa: E731
+    ms, prof = timed(step, args.steps, args.warmup)
+    F = sum(flops(o, v) for (o, v, _, _) in shapes)
+    result.update(value=round(F / (ms * 1e-3) / 1e12, 3),
+                  dtype="f64" if prec == "fp64" else "bf16x3/f32",
+                  config={"workload": f"{name}: {len(frs)} fragments, n_occ "
+                                      f"{min(s[0] for s in shapes)}..{max(s[0] for s in shapes)}, "
+                                      f"n_vir {min(s[1] for s in shapes)}..{max(s[1] for s in shapes)}",
+                          "precision": prec, "fragments": len(frs)},
+                  ms_per_step=round(ms, 3), fragments_per_s=round(len(frs) * 1000.0 / ms, 4),
+                  energy=float(e_tot.item()))
+    if prec == "fp64":   # the batch mixes the build shapes its fragment sizes select
+        result["roofline"] = roofline(prof, "w_build", "k_build_w_f64 / k_build_w3_f64", F,
+                                      args.steps, PEAK_FP64_MFMA_TFLOPS, measured=measured_peak(0))
+    else:
+        result["roofline"] = roofline(prof, "w_build", "k_build_w_bf16x3*", F, args.steps,
+                                      PEAK_BF16_MFMA_TFLOPS, issued=3.0, measured=measured_peak(1))
+    result["kernel_ms_per_step"] = {k: round(t / args.steps, 3) for k, (t, _) in prof.items()}
 
 
 def main():
@@ -196,12 +417,10 @@ def main():
 
     import torch
 
-    import paper_2412_18553_amd as sie
-    from synth import WORKLOADS, batch_shapes, make_fragment, workload_fragment
-
     mode = args.mode
     name = args.workload or DEFAULT_WORKLOAD[mode]
     dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
     if args.calibrate_copy:
         src = torch.ones(args.calibrate_copy // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -210,89 +429,21 @@ def main():
         torch.cuda.synchronize()
         log(f"# calibration copy: {src.numel() * 8} bytes device to device")
         del src, dst
-    t0 = time.perf_counter()
     result = {"metric": "(T) TFLOP/s", "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
               "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
               "vs_baseline": None, "data": "synthetic"}
-
-    if mode in ("fp64", "split", "backward"):
-        w = WORKLOADS[name]
-        o, v = w["n_occ"], w["n_vir"]
-        frag = workload_fragment(name)
-        dtype = torch.float32 if mode == "split" else torch.float64
-        fr = to_device(frag, dtype)
-        log(f"# workload {name}: generated in {time.perf_counter() - t0:.1f} s")
-        out = torch.empty(1, dtype=torch.float64, device=dev)
-        F = flops(o, v)
-        if mode == "backward":
-            ws = torch.empty(sie.backward_workspace_size(fr), dtype=torch.uint8, device=dev)
-            grads = [{n: torch.empty_like(getattr(fr, n), dtype=torch.float64)
-                      for n in sie.GRAD_NAMES}]
-            step = lambda: sie.backward(fr, grads=grads, e_frag=out, workspace=ws)  # noqa: E731
-        else:
-            ws = torch.empty(sie.workspace_size(fr), dtype=torch.uint8, device=dev)
-            step = lambda: sie.energy(fr, workspace=ws, out=out)  # noqa: E731
-        ms, prof = timed(step, args.steps, args.warmup)
-        energy = float(out.item())
-        bw = build_work(o, v)
-        desc = f"single fragment n_occ={o} n_vir={v} n_aux={w['n_aux']}"
-        if mode == "fp64":
-            result.update(value=round(F / (ms * 1e-3) / 1e12, 3), dtype="f64",
-                          config={"workload": desc, "precision": "fp64", "fragments": 1})
-            l3 = lay3_of(v)
-            lay = sie.tile_variants()[sie.tile_variant_of(v)][6]
-            kernel = {2: "k_build_w_f64", 3: "k_build_w3_f64"}[lay]
-            result["roofline"] = roofline(prof, "w_build", kernel, build_work(o, v, lay3=l3),
-                                          args.steps, PEAK_FP64_MFMA_TFLOPS, workload=name)
-            result["roofline"]["tile_variant"] = sie.tile_variant_of(v)
-        elif mode == "split":
-            result.update(value=round(F / (ms * 1e-3) / 1e12, 3), dtype="bf16x3/f32",
-                          config={"workload": desc + " (float32 inputs)",
-                                  "precision": "split_bf16", "fragments": 1})
-            # three bf16 products (hi*hi + hi*lo + lo*hi) per algorithmic product
-            result["roofline"] = roofline(prof, "w_build", "k_build_w_bf16x3", bw, args.steps,
-                                          PEAK_BF16_MFMA_TFLOPS, scale=3.0)
-        else:
-            # the backward recomputes the build (1x) and runs the transposed
-            # contractions of every build term (2x): 3x the build's work
-            result.update(metric="(T) gradient TFLOP/s (3 x F per step)",
-                          value=round(3.0 * F / (ms * 1e-3) / 1e12, 3), dtype="f64",
-                          config={"workload": desc, "precision": "fp64", "fragments": 1,
-                                  "outputs": "dE/d(t1, t2, ovvv, ooov, ovov)"})
-            result["roofline"] = roofline(prof, "grad", "k_adj_contract",
-                                          2.0 * build_work(o, v, pair=False), args.steps,
-                                          PEAK_FP64_MFMA_TFLOPS)
-        result.update(ms_per_step=round(ms, 3), fragments_per_s=round(1000.0 / ms, 4),
-                      energy=energy)
-        if mode == "fp64" and not args.no_cpu:
-            result["cpu_baseline"] = cpu_baseline(frag, [int(a) for a in args.cpu_a.split(",")])
-    else:   # batched
-        prec = args.precision or "fp64"
-        dtype = torch.float64 if prec == "fp64" else torch.float32
-        shapes = batch_shapes(name)
-        frs = [to_device(make_fragment(o, v, aux, seed), dtype) for (o, v, aux, seed) in shapes]
-        log(f"# workload {name}: {len(frs)} fragments in {time.perf_counter() - t0:.1f} s")
-        ws = torch.empty(sie.workspace_size(frs), dtype=torch.uint8, device=dev)
-        e_frag = torch.empty(len(frs), dtype=torch.float64, device=dev)
-        e_tot = torch.empty(1, dtype=torch.float64, device=dev)
-        step = lambda: sie.energy_batched(frs, workspace=ws, out=e_frag, total=e_tot)  # noqa: E731
-        ms, prof = timed(step, args.steps, args.warmup)
-        F = sum(flops(o, v) for (o, v, _, _) in shapes)
-        bw = sum(build_work(o, v, lay3=(prec == "fp64" and lay3_of(v))) for (o, v, _, _) in shapes)
-        result.update(value=round(F / (ms * 1e-3) / 1e12, 3),
-                      dtype="f64" if prec == "fp64" else "bf16x3/f32",
-                      config={"workload": f"{name}: {len(frs)} fragments, n_occ "
-                                          f"{min(s[0] for s in shapes)}..{max(s[0] for s in shapes)}",
-                              "precision": prec, "fragments": len(frs)},
-                      ms_per_step=round(ms, 3), fragments_per_s=round(len(frs) * 1000.0 / ms, 4),
-                      energy=float(e_tot.item()))
-        if prec == "fp64":   # the batch mixes the build shapes its fragment sizes select
-            result["roofline"] = roofline(prof, "w_build", "k_build_w_f64 / k_build_w3_f64", bw,
-                                          args.steps, PEAK_FP64_MFMA_TFLOPS)
-        else:
-            result["roofline"] = roofline(prof, "w_build", "k_build_w_bf16x3", bw, args.steps,
-                                          PEAK_BF16_MFMA_TFLOPS, scale=3.0)
-    result["kernel_ms_per_step"] = {k: round(t / args.steps, 3) for k, (t, _) in prof.items()}
+    if mode == "peak":
+        p64, p16 = measured_peak(0), measured_peak(1)
+        result.update(metric="matrix-core peak TFLOP/s", value=p64, dtype="f64",
+                      config={"workload": "register-only MFMA chains, 8192 work-groups"},
+                      peaks={"fp64_16x16x4": {"measured": p64, "published": PEAK_FP64_MFMA_TFLOPS},
+                             "bf16_16x16x32": {"measured": p16, "published": PEAK_BF16_MFMA_TFLOPS}})
+    elif mode == "split":
+        run_split(args, result, name)
+    elif mode in ("fp64", "backward"):
+        run_single(args, result, name, mode)
+    else:
+        run_batched(args, result, name)
     print(json.dumps(result), flush=True)
 
 

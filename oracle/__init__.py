@@ -18,6 +18,8 @@ from .triples import (  # noqa: F401
     energy_literal_vectorized,
     energy_dense,
     occupied_triple_energy,
+    occupied_triple_parts,
+    energy_by_occupied_triples,
     occupied_triples,
     triple_weight,
     flops_per_fragment,

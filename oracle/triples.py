@@ -341,3 +341,89 @@ def occupied_triple_energy(i, j, k, eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov):
            - 2.0 * z(k, j, i) - 2.0 * z(i, k, j) - 2.0 * z(j, i, k))
     g = float(np.sum(r_z * p_occ(xo, i, j, k)))
     return 2.0 * triple_weight(i, j, k) * g
+
+
+# ---------------------------------------------------------------------------
+# occupied-outer form: one unordered occupied triple at a time, R moved onto
+# the virtual indices (full-size reference values)
+# ---------------------------------------------------------------------------
+
+def _r_vir(y):
+    """R moved from the occupied to the virtual indices of one occupied
+    triple's cube y[a, b, c]:
+        R'[Y]^{abc} = 4 Y^{abc} + Y^{cab} + Y^{bca} - 2 Y^{cba} - 2 Y^{acb} - 2 Y^{bac}.
+    With Y = Wt or Vt (both unchanged by a simultaneous permutation of the
+    occupied and the virtual indices), Y_{jki}^{abc} = Y_{ijk}^{cab},
+    Y_{kij}^{abc} = Y_{ijk}^{bca}, Y_{kji}^{abc} = Y_{ijk}^{cba},
+    Y_{ikj}^{abc} = Y_{ijk}^{acb} and Y_{jik}^{abc} = Y_{ijk}^{bac}, so
+    R'[Y_{ijk}] equals R[Y]_{ijk} of eq. E_corr_CCSD_T."""
+    return (4.0 * y
+            + np.einsum("cab->abc", y) + np.einsum("bca->abc", y)
+            - 2.0 * np.einsum("cba->abc", y)
+            - 2.0 * np.einsum("acb->abc", y)
+            - 2.0 * np.einsum("bac->abc", y))
+
+
+def occupied_triple_parts(i, j, k, eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov):
+    """(E_WW, E_WV) contributions of the occupied triple {i, j, k} (i >= j >= k)
+    to E_x, C = I, in the occupied-outer form:
+
+        E_unit = 2 A_ijk sum_{abc} Wt^{abc}_{ijk} R'[Wt + Vt]^{abc}_{ijk} / D^{abc}_{ijk},
+
+    with Wt = P[X] and Vt = (1/2) P[U] at the fixed occupied triple (each of
+    the six P-images is the X (or U) of a reordered occupied triple with its
+    virtual axes reordered the same way) and R' the virtual-index form of R
+    (see `_r_vir`).  E_WW keeps Wt in the bracket, E_WV keeps Vt; their sum is
+    what `occupied_triple_energy` gives, which evaluates R over six occupied
+    orderings instead.  Cost: six contractions of 2 n_v^4 flops and a few
+    dozen passes over n_v^3 cubes.
+    """
+    eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov = _check(
+        eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov)
+    if not (i >= j >= k):
+        raise ValueError("need i >= j >= k")
+    v = eps_vir.shape[0]
+
+    def x(p, q, r):
+        """X^{abc}_{pqr} over all a, b, c: array [a, b, c]."""
+        # sum_d (pa|bd) t_rq^{cd}
+        vv = (ovvv[p].reshape(v * v, v) @ t2[r, q].T).reshape(v, v, v)
+        # sum_l (pa|ql) t_lr^{bc}, with (pa|ql) = ooov[q, l, p, a]
+        vv -= np.einsum("la,lbc->abc", ooov[q, :, p, :], t2[:, r], optimize=True)
+        return vv
+
+    # Wt^{abc}_{ijk} = X^{abc}_{ijk} + X^{bca}_{jki} + X^{cab}_{kij}
+    #                + X^{acb}_{ikj} + X^{cba}_{kji} + X^{bac}_{jik}
+    wt = x(i, j, k)
+    wt += np.einsum("bca->abc", x(j, k, i))
+    wt += np.einsum("cab->abc", x(k, i, j))
+    wt += np.einsum("acb->abc", x(i, k, j))
+    wt += np.einsum("cba->abc", x(k, j, i))
+    wt += np.einsum("bac->abc", x(j, i, k))
+    # Vt = (1/2) P[U], U^{abc}_{pqr} = (pa|qb) t_r^c: the six images pair up
+    # into (ia|jb) t_k^c + (ia|kc) t_j^b + (jb|kc) t_i^a
+    vt = (np.einsum("ab,c->abc", ovov[i, :, j, :], t1[k])
+          + np.einsum("ac,b->abc", ovov[i, :, k, :], t1[j])
+          + np.einsum("bc,a->abc", ovov[j, :, k, :], t1[i]))
+    d = (eps_occ[i] + eps_occ[j] + eps_occ[k] - eps_vir[:, None, None]
+         - eps_vir[None, :, None] - eps_vir[None, None, :])
+    w = 2.0 * triple_weight(i, j, k)
+    wd = wt / d
+    e_ww = w * float(np.sum(_r_vir(wt) * wd))
+    e_wv = w * float(np.sum(_r_vir(vt) * wd))
+    return e_ww, e_wv
+
+
+def energy_by_occupied_triples(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov,
+                               return_parts=False):
+    """E_x (C = I) as the compensated sum of `occupied_triple_parts` over all
+    i >= j >= k; with return_parts=True returns (E, E_WW, E_WV)."""
+    o = np.asarray(eps_occ).shape[0]
+    ww, wv = [], []
+    for (i, j, k) in occupied_triples(o):
+        a, b = occupied_triple_parts(i, j, k, eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov)
+        ww.append(a)
+        wv.append(b)
+    e_ww, e_wv = math.fsum(ww), math.fsum(wv)
+    e = math.fsum(ww + wv)
+    return (e, e_ww, e_wv) if return_parts else e

@@ -18,6 +18,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsie_triples.so")
+# matrix-core peak microbenchmark (measurement only), a library of its own
+PEAK_SRC = "mfma_peak.hip"
+PEAK_LIB = os.path.join(HERE, "libsie_mfma_peak.so")
 
 SOURCES = ["sie_triples.hip", "tu_build_f64.hip", "tu_build_f64_l3.hip", "tu_bf16.hip",
            "tu_epilogue.hip", "tu_adj_f64.hip", "tu_adj_f32.hip"]
@@ -47,7 +50,10 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
         cmds.append((obj, [cc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-c",
                            os.path.join(CSRC, src), "-o", obj]))
-    pending = list(cmds)
+    peak_tmp = PEAK_LIB + ".tmp"
+    peak_cmd = (peak_tmp, [cc, *HIPCC_FLAGS, "-shared", os.path.join(CSRC, PEAK_SRC), "-o",
+                           peak_tmp])
+    pending = [peak_cmd] + list(cmds)
     running = []
     failed = []
     while pending or running:
@@ -67,6 +73,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         for cmd, out in failed:
             sys.stderr.write(" ".join(cmd) + "\n" + out)
         raise RuntimeError(f"hipcc failed for {len(failed)} translation unit(s)")
+    os.replace(peak_tmp, PEAK_LIB)
     tmp = LIB + ".tmp"
     link = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *[o for o, _ in cmds], "-o", tmp]
     if verbose:

@@ -126,6 +126,9 @@ WORKLOADS = {
     "o24v200": dict(n_occ=24, n_vir=200, n_aux=672,  stream=1),
     "o32v320": dict(n_occ=32, n_vir=320, n_aux=1056, stream=2),
     "o16v120": dict(n_occ=16, n_vir=120, n_aux=408,  stream=4),
+    # parity case: 337 virtuals span at least two row and two col tiles of
+    # every split build shape, with a ragged edge
+    "o3v337":  dict(n_occ=3,  n_vir=337, n_aux=1020, stream=5),
 }
 
 

@@ -5,7 +5,11 @@
 * the total is the fixed-order sum of the fragment energies;
 * a direct sum of two fragments (no cross integrals or amplitudes) has the
   energy of the two fragments (size extensivity);
-* a workspace cap that forces many rounds changes nothing.
+* a workspace cap that forces many rounds changes nothing;
+* a tile table that gives the fragments of one batch different build
+  shapes (two- and three-layout) changes nothing either: each round then
+  launches the build once per shape over that shape's items, and its
+  epilogue reads two- and three-layout cube sets side by side.
 """
 
 import numpy as np
@@ -112,3 +116,33 @@ def test_batched_workspace_caps_agree(precision):
             e_cap, _ = sie.energy_batched(frs, max_workspace_bytes=sie.workspace_size(frs, max_bytes=cap))
             print(f"cap={cap}", flush=True)
             assert np.array_equal(e_full.cpu().numpy(), e_cap.cpu().numpy())
+
+
+# n_v of SHAPES -> variant: 9, 12 -> 9 (three layouts), 17, 28 -> 0, 33, 40 -> 11
+# (three layouts), 50 -> 6 (wave grid)
+MIXED_TABLE = [(12, 9), (30, 0), (45, 11), (2048, 6)]
+
+
+@pytest.mark.parametrize("cap_rounds", [False, True])
+def test_batched_mixed_tile_variants(cap_rounds):
+    import paper_2412_18553_amd as sie
+    hf = [make_fragment(o, v, a, (9, 400 + n)) for n, (o, v, a) in enumerate(SHAPES)]
+    frs = [_frag(f) for f in hf]
+    try:
+        sie.set_tile_table(MIXED_TABLE)
+        variants = {sie.tile_variant_of(f.n_vir) for f in hf}
+        layouts = {sie.tile_variants()[v][6] for v in variants}
+        assert len(variants) >= 3 and layouts == {2, 3}, (variants, layouts)
+        kw = {}
+        if cap_rounds:   # a cap that forces several rounds, each mixing shapes
+            kw["max_workspace_bytes"] = sie.workspace_size(frs, max_bytes=sie.workspace_size(frs) // 3)
+        e_b, tot = sie.energy_batched(frs, **kw)
+        e_b = e_b.cpu().numpy()
+        singles = np.array([float(sie.energy(fr).item()) for fr in frs])
+    finally:
+        sie.set_tile_table(None)
+    print(f"variants {sorted(variants)}: batched {e_b.tolist()}", flush=True)
+    assert np.array_equal(e_b, singles)
+    for f, e in zip(hf, e_b):
+        ref = T.energy_literal_vectorized(*f.arrays())
+        assert abs(e - ref) <= 1e-10 * max(abs(ref), 1e-300) or (f.n_occ == 1 and e == 0.0)

@@ -79,9 +79,9 @@ _EMULATED = {}
 @pytest.mark.parametrize("shape", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("o,v,aux,seed", [(4, 33, 40, 11), (3, 97, 60, 12)])
 def test_split_every_tile_shape(shape, o, v, aux, seed):
-    """Each split build shape, forced, against the emulator: tiles that span
-    several row and col tiles with ragged edges (v = 97) and one partial tile
-    (v = 33)."""
+    """Each split build shape, forced, against the emulator on one partial
+    tile (v = 33) and on v = 97 (several row tiles for the 64-, 80- and
+    112-row shapes, one partial col tile for all)."""
     import paper_2412_18553_amd as sie
     print(f"case shape={shape} o={o} v={v}", flush=True)
     f = make_fragment(o, v, aux, (8, seed)).astype(np.float32)
@@ -96,3 +96,59 @@ def test_split_every_tile_shape(shape, o, v, aux, seed):
     e_em = _EMULATED[key]
     assert abs(e_gpu - e_em) <= 5e-6 * abs(e_em)
     assert abs(tri.sum() - e_gpu) <= 1e-12 * abs(e_gpu)
+
+
+def test_split_every_tile_shape_multi_tile():
+    """337 virtuals: at least two row tiles and two col tiles of every split
+    shape (64/80/112/160 rows, 128/160/256/320 cols), each with a ragged
+    edge, so every row0 > 0 and col0 > 0 path of both build kernels runs.
+    Every output element accumulates its products in the same order whatever
+    the tile shape, so the per-triple energies of all shapes are bitwise
+    equal; one set is checked against the float64 oracle (stored per
+    occupied triple, float32-rounded inputs)."""
+    import json
+    import os
+    import paper_2412_18553_amd as sie
+    import torch
+    from synth.device import workload_fragment_device
+    gpath = os.path.join(os.path.dirname(__file__), "golden", "o3v337_f32_all_units.json")
+    with open(gpath) as fh:
+        g = json.load(fh)
+    ref = np.array(g["e_ww_units"]) + np.array(g["e_wv_units"])
+    df = workload_fragment_device("o3v337", device="cuda", dtype=torch.float32)
+    frag = sie.Fragment(*df.arrays(), precision="split_bf16")
+    first = None
+    try:
+        for shape in range(6):
+            print(f"case shape={shape} o=3 v=337", flush=True)
+            sie.set_split_shape(shape)
+            tri = torch.empty(frag.n_triples, dtype=torch.float64, device="cuda")
+            sie.energy(frag, triples=tri)
+            tri = tri.cpu().numpy()
+            if first is None:
+                first = tri
+                err = np.abs(tri - ref).max() / np.abs(ref).max()
+                print(f"  worst triple vs oracle: {err:.2e} of the largest", flush=True)
+                assert err <= 2e-5
+            assert np.array_equal(tri, first), shape
+    finally:
+        sie.set_split_shape(-1)
+
+
+def test_split_product_set_on_gpu():
+    """Operands x = h (1 + 2^-9) with h a bfloat16 number: the dropped lo*lo
+    terms are a coherent 2^-18 of every product, so the three-product sum
+    (hi*hi + hi*lo + lo*hi) and the exact value differ by about 2^-17 of
+    E_WW.  The GPU must follow the three-product emulator far closer than
+    that (float32 accumulation only)."""
+    from oracle.split import bf16_rne
+    f = make_fragment(4, 24, 30, (8, 77)).astype(np.float32)
+    g = lambda x: bf16_rne(x) * np.float32(1.0 + 2.0 ** -9)  # noqa: E731
+    f = f.replace(t2=g(f.t2), ovvv=g(f.ovvv), ooov=g(f.ooov))
+    e_gpu, _ = run_split(f)
+    e64, e_em = refs(f)
+    gap = abs(e_em - e64)
+    print(f"gpu={e_gpu!r} emulator={e_em!r} exact={e64!r}: |gpu - emulator| = "
+          f"{abs(e_gpu - e_em) / abs(e_em):.2e}, lo*lo share {gap / abs(e64):.2e}", flush=True)
+    assert gap >= 5e-6 * abs(e64)
+    assert abs(e_gpu - e_em) <= 0.1 * gap

@@ -7,9 +7,11 @@ P3  exact zeros: t2 = 0, one occupied, one virtual, i = j = k, C = 0
 P4  sign: t1 = 0  =>  E <= 0
 P5  polynomial structure in t1, t2 and the (ov|vv), (oo|ov) blocks
 P6  invariance under relabelling occupied or virtual orbitals
+P7  twin invariance: reading the other twin of each symmetric block
 P8  size extensivity for a direct sum of two fragments
 P9  fragment projector: linear, and a complete set sums to C = I
-P10 literal, vectorized, dense, unrestricted and per-occupied-triple forms agree
+P10 literal, vectorized, dense, unrestricted, per-occupied-triple and
+    occupied-outer (R on the virtual indices) forms agree, part by part
 M   planted mistakes in the oracle fail P1 (the pins have teeth)
 """
 
@@ -143,6 +145,50 @@ def test_p6_relabelling():
     assert rel(e_v, e) < 1e-13
 
 
+# ---------------------------------------------------------------- P7
+def _twins(args):
+    """The same inputs read through the other twin of every symmetric block."""
+    eo, ev, t1, t2, ovvv, ooov, ovov = args
+    return (eo, ev, t1, t2.transpose(1, 0, 3, 2), ovvv.transpose(0, 1, 3, 2),
+            ooov.transpose(1, 0, 2, 3), ovov.transpose(2, 3, 0, 1))
+
+
+def test_p7_twin_invariance():
+    """Inputs with the twin symmetries give the same energy through either
+    twin; inputs without them do not (the oracle reads one particular twin,
+    so the invariance is a property of the symmetric inputs, not of the
+    code)."""
+    args = random_symmetric_inputs(3, 5, 71)
+    e = oracle.energy_literal(*args)
+    assert oracle.energy_literal(*_twins(args)) == e
+    rng = np.random.default_rng(72)
+    for pos in (3, 4, 5, 6):      # break one block's symmetry
+        broken = list(args)
+        broken[pos] = args[pos] + 0.3 * rng.normal(size=args[pos].shape)
+        e1 = oracle.energy_literal(*broken)
+        e2 = oracle.energy_literal(*_twins(broken))
+        if pos == 6:
+            assert rel(e1, e2) < 1e-13
+        else:
+            assert rel(e1, e2) > 1e-8, pos
+
+
+# ---------------------------------------------------------------- P5 (power-of-two scale)
+def test_p5_power_of_two_integral_scale_is_exact():
+    """Integrals and t2 scaled by 2^-9 (a chemically scaled copy): Wt scales by
+    2^-18 and Vt by 2^-9, so E = 2^-36 E_WW + 2^-27 E_WV, with every
+    floating-point step scaled exactly; the parts reproduce bitwise."""
+    args = list(random_symmetric_inputs(3, 5, 73))
+    s = 2.0 ** -9
+    sc = list(args)
+    for pos in (3, 4, 5, 6):
+        sc[pos] = args[pos] * s
+    _, ww, wv = oracle.energy_literal(*args, return_parts=True)
+    _, ww_s, wv_s = oracle.energy_literal(*sc, return_parts=True)
+    assert ww_s == ww * s ** 4
+    assert wv_s == wv * s ** 3
+
+
 # ---------------------------------------------------------------- P8
 def direct_sum(fa, fb):
     oa, va = fa[2].shape
@@ -202,6 +248,21 @@ def test_p10_forms_agree(o, v, seed):
     units = [oracle.occupied_triple_energy(i, j, k, *args)
              for (i, j, k) in oracle.occupied_triples(o)]
     assert rel(sum(units), e) < 1e-13
+    _, ww, wv = oracle.energy_literal(*args, return_parts=True)
+    e_o, ww_o, wv_o = oracle.energy_by_occupied_triples(*args, return_parts=True)
+    assert rel(e_o, e) < 1e-13 and rel(ww_o, ww) < 1e-13 and rel(wv_o, wv) < 1e-13
+    for u, (i, j, k) in enumerate(oracle.occupied_triples(o)):
+        a, b = oracle.occupied_triple_parts(i, j, k, *args)
+        assert abs(a + b - units[u]) <= 1e-13 * abs(e)
+
+
+def test_p10_occupied_outer_fragment():
+    """The occupied-outer form on a density-fitted fragment with ragged sizes,
+    part by part against the literal loop."""
+    f = make_fragment(5, 11, 24, (103,))
+    e, ww, wv = T.energy_literal_vectorized(*f.arrays(), return_parts=True)
+    e_o, ww_o, wv_o = oracle.energy_by_occupied_triples(*f.arrays(), return_parts=True)
+    assert rel(e_o, e) < 1e-13 and rel(ww_o, ww) < 1e-13 and rel(wv_o, wv) < 1e-12
 
 
 def test_golden_small_workload():

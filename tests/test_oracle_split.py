@@ -5,7 +5,13 @@
 * hi + lo represents x to 16 significant bits, and lo is exactly zero when x
   is already a bfloat16 number;
 * with operands that are bfloat16 numbers the emulator is the float64 oracle;
-* the split error is small and bounded as the representation predicts.
+* the split error is small and bounded as the representation predicts;
+* the product set is hi*hi + hi*lo + lo*hi: on operands x = h (1 + 2^-9)
+  (h a bfloat16 number, so hi = h and lo = h 2^-9 exactly) every dropped
+  lo*lo term is the same fraction c = 2^-18 / (1 + 2^-9)^2 of its product,
+  Wt scales by (1 - c) exactly and E_split = (1 - c)^2 E_WW + (1 - c) E_WV
+  in closed form; keeping lo*lo (4 products) or dropping hi*lo or lo*hi
+  (2 products) gives a different value.
 """
 
 import numpy as np
@@ -53,3 +59,30 @@ def test_emulator_error_small():
     e64 = T.energy_literal_vectorized(*a64)
     es = energy_split_emulated(*f.arrays())
     assert 0 < abs(es - e64) <= 1e-5 * abs(e64)
+
+
+def _coherent_operands(f):
+    """Every t2, ovvv and ooov entry replaced by h (1 + 2^-9) with h its
+    bfloat16 rounding (exact in float32; hi = h, lo = h 2^-9)."""
+    g = lambda x: bf16_rne(x) * np.float32(1.0 + 2.0 ** -9)  # noqa: E731
+    return f.replace(t2=g(f.t2), ovvv=g(f.ovvv), ooov=g(f.ooov))
+
+
+def test_emulator_product_set_closed_form():
+    f = _coherent_operands(make_fragment(3, 10, 16, (33,)).astype(np.float32))
+    hi, lo = split_bf16(f.ovvv)
+    assert np.array_equal(hi * np.float32(2.0 ** -9), lo)
+    a64 = [np.asarray(x, np.float64) for x in f.arrays()]
+    _, ww, wv = T.energy_literal_vectorized(*a64, return_parts=True)
+    c = 2.0 ** -18 / (1.0 + 2.0 ** -9) ** 2
+    predicted = (1 - c) ** 2 * ww + (1 - c) * wv
+    e3 = energy_split_emulated(*f.arrays())
+    assert abs(e3 - predicted) <= 1e-13 * abs(predicted)
+    # the exact value (four products) and the two-product sums are far off
+    e4 = ww + wv
+    assert abs(e3 - e4) >= 0.5 * 2 * c * abs(ww)
+    t2h, t2l = split_bf16(f.t2)
+    vh, vl = split_bf16(f.ovvv)
+    oh, ol = split_bf16(f.ooov)
+    two = T.energy_literal_vectorized(*a64, x_terms=[(vh, oh, t2h), (vh, oh, t2l)])
+    assert abs(two - e3) >= 100 * abs(e3 - predicted) + 1e-3 * abs(e3)
