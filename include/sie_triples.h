@@ -29,12 +29,22 @@
  * results.
  * Element type of t1, t2 and the ERI blocks: float64 for SIE_FP64, float32 for
  * SIE_SPLIT_BF16.  Energies are always float64.
+ * The orbital energies are host arrays so that every argument check, the
+ * requirement max e_occ < min e_vir (every triples denominator D negative)
+ * included, runs on the host before any device work.
  *
  * Ownership: the caller owns every buffer (inputs, outputs, workspace); the
- * library keeps no device memory between calls and allocates none.  The host
- * arrays (eps_*, the descriptor structs) may be released when the call returns.
+ * library keeps no device memory between calls and allocates none.  It owns a
+ * few page-locked host buffers (allocated on first use, grown as needed, kept
+ * until the process ends) through which it uploads each call's small tables.
+ * The host arrays (eps_*, the descriptor structs) may be released when the
+ * call returns.
  * Streams: `stream` is a hipStream_t (NULL = the default stream); all device
- * work is enqueued on it and the call returns without waiting for it.
+ * work, the table uploads included, is enqueued on it and the call returns
+ * without waiting for the device.  The host waits only when more than four
+ * calls' uploads are still queued, and when the finite check is on (see
+ * sie_set_check_finite).  A workspace must not be used by two calls that may
+ * run at the same time (different streams without ordering between them).
  * Errors: every entry point returns a sie_status; nothing is thrown across
  * the ABI and nothing aborts.  All argument checks run on the host before any
  * HIP call, so a bad argument is reported without touching the device.
@@ -59,6 +69,8 @@ typedef enum {
   SIE_ERR_INVALID_ARG = 1,   /* bad pointer, size, alignment or orbital energies */
   SIE_ERR_UNSUPPORTED = 2,   /* valid request that this build does not implement */
   SIE_ERR_WORKSPACE = 3,     /* workspace missing or smaller than required        */
+  SIE_ERR_NONFINITE = 4,     /* a non-finite orbital energy, or (finite check on)
+                                a NaN or infinity in t1, t2 or an ERI block       */
   SIE_ERR_HIP = 5            /* a HIP runtime call failed; see sie_last_error()   */
 } sie_status;
 
@@ -129,9 +141,8 @@ size_t sie_triples_workspace_size(const sie_fragment* frags, int32_t n,
  *   ws       device workspace of ws_bytes >= sie_triples_workspace_size(frag,
  *            1, p, cap) for some cap; its contents on entry are ignored
  * Deterministic: the same inputs give bitwise the same outputs.  The call
- * waits for work already queued on `stream` while it uploads its small tables
- * (fragment descriptors, orbital energies, work list), then returns before
- * its own kernels finish. */
+ * enqueues the upload of its small tables (fragment descriptors, orbital
+ * energies, work list) and its kernels on `stream` and returns. */
 sie_status sie_triples_energy(const sie_fragment* frag, sie_precision p,
                               double* e_out, double* e_triples,
                               void* ws, size_t ws_bytes, void* stream);
@@ -237,6 +248,15 @@ sie_status sie_set_tile_table(int32_t n, const int32_t* nv_max, const int32_t* v
 #define SIE_SPLIT_SHAPES 6
 int32_t sie_split_shape_of(int32_t n_vir);
 sie_status sie_set_split_shape(int32_t shape);
+
+/* Finite check.  When on, every energy and backward call first scans t1, t2,
+ * ovvv, ooov and ovov of each fragment on the device, waits for the scan, and
+ * returns SIE_ERR_NONFINITE (naming the fragment and the array) before any
+ * (T) kernel runs if one holds a NaN or an infinity; with the check off such
+ * inputs give non-finite outputs.  Default: off, or on when the environment
+ * variable SIE_CHECK_FINITE is set to anything but "0" at the first call.
+ * Orbital energies are always checked on the host.  Process-wide. */
+void sie_set_check_finite(int on);
 
 const char* sie_last_error(void);
 int sie_abi_version(void);

@@ -307,6 +307,12 @@ def set_tile_table(table=None) -> None:
     _lib.check(lib.sie_set_tile_table(n, nv, var))
 
 
+def set_check_finite(on: bool = True) -> None:
+    """Scan the device inputs for NaN / infinity before each evaluation
+    (SieError SIE_ERR_NONFINITE if found; the call then waits for the scan)."""
+    _lib.load().sie_set_check_finite(1 if on else 0)
+
+
 def profile_enable(on: bool = True) -> None:
     """Time every library kernel launch on this thread with HIP events."""
     _lib.load().sie_profile_enable(1 if on else 0)

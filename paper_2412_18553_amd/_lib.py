@@ -16,13 +16,14 @@ SIE_OK = 0
 SIE_ERR_INVALID_ARG = 1
 SIE_ERR_UNSUPPORTED = 2
 SIE_ERR_WORKSPACE = 3
+SIE_ERR_NONFINITE = 4
 SIE_ERR_HIP = 5
 
 SIE_FP64 = 0
 SIE_SPLIT_BF16 = 1
 
 STATUS_NAMES = {0: "SIE_OK", 1: "SIE_ERR_INVALID_ARG", 2: "SIE_ERR_UNSUPPORTED",
-                3: "SIE_ERR_WORKSPACE", 5: "SIE_ERR_HIP"}
+                3: "SIE_ERR_WORKSPACE", 4: "SIE_ERR_NONFINITE", 5: "SIE_ERR_HIP"}
 
 # every symbol include/sie_triples.h declares
 EXPORTED = ["sie_abi_version", "sie_last_error", "sie_occupied_triples",
@@ -30,7 +31,7 @@ EXPORTED = ["sie_abi_version", "sie_last_error", "sie_occupied_triples",
             "sie_triples_backward_workspace_size", "sie_triples_backward",
             "sie_tile_variants", "sie_tile_variant_shape", "sie_tile_variant_of",
             "sie_set_tile_table", "sie_split_shape_of", "sie_set_split_shape",
-            "sie_profile_enable", "sie_profile_collect"]
+            "sie_profile_enable", "sie_profile_collect", "sie_set_check_finite"]
 PROF_CLASSES = ("w_build", "epilogue", "reduce", "split", "grad")
 
 
@@ -112,6 +113,8 @@ def load() -> ctypes.CDLL:
     lib.sie_set_split_shape.argtypes = [ctypes.c_int32]
     lib.sie_profile_enable.restype = None
     lib.sie_profile_enable.argtypes = [ctypes.c_int]
+    lib.sie_set_check_finite.restype = None
+    lib.sie_set_check_finite.argtypes = [ctypes.c_int]
     lib.sie_profile_collect.restype = ctypes.c_int
     lib.sie_profile_collect.argtypes = [ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64)]

@@ -71,4 +71,23 @@ __global__ __launch_bounds__(256) void k_sum_fixed(const double* __restrict__ x,
   if (threadIdx.x == 0) out[0] = buf[0];
 }
 
+// flags[slot] = 1 if any of x[0 .. n) is not finite (NaN or +-inf), else
+// unchanged (zeroed by the caller).  Every finding thread stores the same
+// value, so the stores need no ordering.
+template <typename T>
+__global__ __launch_bounds__(256) void k_nonfinite(const T* __restrict__ x, int64_t n,
+                                                   int* __restrict__ flags, int slot) {
+  bool bad = false;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * blockDim.x)
+    bad |= !__builtin_isfinite(gptr(x)[q]);
+  if (bad) gptr_w(flags)[slot] = 1;
+}
+
+// flags[0 .. n) = 0.
+__global__ __launch_bounds__(256) void k_zero_flags(int* __restrict__ flags, int n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) flags[q] = 0;
+}
+
 }  // namespace sie

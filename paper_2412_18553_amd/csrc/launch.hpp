@@ -49,6 +49,10 @@ void launch_sum_fixed(hipStream_t s, const double* x, int64_t n, double* out);
 void launch_fill_zero(unsigned grid, hipStream_t s, double* p, int64_t n);
 void launch_symmetrize(unsigned grid, hipStream_t s, double* g, int kind, int no, int nv,
                        int64_t n);
+// flags[slot] = 1 if x[0 .. n) holds a non-finite value (float64 or float32
+// elements); launch_zero_flags clears flags[0 .. n) first.
+void launch_zero_flags(hipStream_t s, int* flags, int n);
+void launch_nonfinite(hipStream_t s, const void* x, bool f64, int64_t n, int* flags, int slot);
 
 // ---- adjoint (tu_adj_f64.hip, tu_adj_f32.hip) ----
 // Contraction lists of one class in one backward round (host tables uploaded

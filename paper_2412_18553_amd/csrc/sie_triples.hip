@@ -19,6 +19,7 @@
 #include "adj_plan.hpp"
 #include "launch.hpp"
 #include "shapes.hpp"
+#include "staging.hpp"
 #include "work.hpp"
 
 namespace {
@@ -46,6 +47,24 @@ size_t default_cap() {
 }
 
 size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
+
+// Page-locked staging of the per-call tables (see staging.hpp).
+sie::Staging g_staging;
+
+// Optional scan of the device inputs for non-finite values (SIE_CHECK_FINITE).
+std::atomic<int> g_check_finite{-1};
+
+bool check_finite_on() {
+  int v = g_check_finite.load();
+  if (v < 0) {
+    const char* env = std::getenv("SIE_CHECK_FINITE");
+    v = (env && *env && std::string(env) != "0") ? 1 : 0;
+    int expect = -1;
+    g_check_finite.compare_exchange_strong(expect, v);
+    v = g_check_finite.load();
+  }
+  return v == 1;
+}
 
 // Per-fragment sizes.
 struct FragPlan {
@@ -96,6 +115,7 @@ struct Plan {
   int64_t total_units = 0, total_work = 0;
   int pstride = 0;
   size_t off_desc = 0, off_eps = 0, off_units = 0, off_part = 0, off_efrag = 0, off_items = 0;
+  size_t off_flags = 0;      // non-finite scan flags: 5 per fragment
   size_t off_split = 0, off_adj = 0, off_t1 = 0, off_parts = 0, off_arena = 0;
   int nv_max = 1;            // largest n_vir (row stride of the t1 partials)
   size_t adj_recs = 0;       // bound on the adjoint records (= groups) of all rounds
@@ -170,6 +190,8 @@ Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad =
   off = align_up(off + sizeof(double) * size_t(p.total_units) * size_t(p.pstride), 256);
   p.off_efrag = off;
   off = align_up(off + sizeof(double) * size_t(n), 256);
+  p.off_flags = off;
+  off = align_up(off + sizeof(int) * 5 * size_t(n), 256);
   p.off_items = off;
   off = align_up(off + sizeof(sie::Item) * size_t(p.total_work), 256);
   p.off_split = off;
@@ -207,12 +229,12 @@ sie_status check_fragment(const sie_fragment* f, sie_precision prec, const char*
   double max_occ = -INFINITY, min_vir = INFINITY;
   for (int i = 0; i < f->n_occ; ++i) {
     if (!std::isfinite(f->eps_occ[i]))
-      return fail(SIE_ERR_INVALID_ARG, w + ": eps_occ has a non-finite entry");
+      return fail(SIE_ERR_NONFINITE, w + ": eps_occ has a non-finite entry");
     max_occ = f->eps_occ[i] > max_occ ? f->eps_occ[i] : max_occ;
   }
   for (int a = 0; a < f->n_vir; ++a) {
     if (!std::isfinite(f->eps_vir[a]))
-      return fail(SIE_ERR_INVALID_ARG, w + ": eps_vir has a non-finite entry");
+      return fail(SIE_ERR_NONFINITE, w + ": eps_vir has a non-finite entry");
     min_vir = f->eps_vir[a] < min_vir ? f->eps_vir[a] : min_vir;
   }
   if (!(max_occ < min_vir))
@@ -381,6 +403,8 @@ sie_status sie_set_split_shape(int32_t shape) {
 static_assert(SIE_SPLIT_SHAPES == sie::kSShapes, "header and kernels agree on the split shapes");
 
 const char* sie_last_error(void) { return g_err.c_str(); }
+
+void sie_set_check_finite(int on) { g_check_finite.store(on ? 1 : 0); }
 
 int64_t sie_occupied_triples(int32_t n_occ) {
   return n_occ < 0 ? 0 : sie::tetra(n_occ);
@@ -629,6 +653,34 @@ sie_status stage_split(const std::vector<sie::FragDesc>& desc, hipStream_t s) {
   return hip_check(hipGetLastError(), "launch split staging");
 }
 
+// With the finite check on: scans every fragment's t1, t2, ovvv, ooov and
+// ovov for NaN or infinity, waits for the scan, and reports the first
+// offender.  This is the only path on which a call waits for the device.
+sie_status scan_finite(const sie_fragment* frags, int n, bool f64, int* d_flags, hipStream_t s,
+                       const std::string& w) {
+  static const char* kNames[5] = {"t1", "t2", "ovvv", "ooov", "ovov"};
+  sie::launch_zero_flags(s, d_flags, 5 * n);
+  for (int x = 0; x < n; ++x) {
+    const sie_fragment& f = frags[x];
+    const int64_t o = f.n_occ, v = f.n_vir;
+    const void* ptr[5] = {f.t1, f.t2, f.ovvv, f.ooov, f.ovov};
+    const int64_t cnt[5] = {o * v, o * o * v * v, o * v * v * v, o * o * o * v, o * v * o * v};
+    for (int a = 0; a < 5; ++a) sie::launch_nonfinite(s, ptr[a], f64, cnt[a], d_flags, 5 * x + a);
+  }
+  sie_status st = hip_check(hipGetLastError(), "launch finite scan");
+  if (st != SIE_OK) return st;
+  std::vector<int> h(size_t(5) * size_t(n), 0);
+  st = hip_check(hipMemcpyAsync(h.data(), d_flags, sizeof(int) * h.size(), hipMemcpyDeviceToHost, s),
+                 "read finite scan");
+  if (st == SIE_OK) st = hip_check(hipStreamSynchronize(s), "finite scan");
+  if (st != SIE_OK) return st;
+  for (int q = 0; q < 5 * n; ++q)
+    if (h[size_t(q)])
+      return fail(SIE_ERR_NONFINITE, w + ": fragment " + std::to_string(q / 5) + ": " +
+                                         kNames[q % 5] + " holds a non-finite value");
+  return SIE_OK;
+}
+
 // One evaluation over n fragments (see work.hpp).
 sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag_out,
                double* e_total, double* e_triples, void* ws, size_t ws_bytes, void* stream,
@@ -658,19 +710,25 @@ sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag
   std::vector<sie::Item>& items = T.items;
   std::vector<size_t>& round_begin = T.round_begin;
 
-  // ---- uploads (host tables must outlive the copies: wait for them) ----
-  sie_status st = hip_check(hipMemcpyAsync(dev(pl.off_desc), desc.data(),
-                                           sizeof(sie::FragDesc) * desc.size(),
-                                           hipMemcpyHostToDevice, s), "upload descriptors");
-  if (st == SIE_OK)
-    st = hip_check(hipMemcpyAsync(dev(pl.off_eps), eps.data(), sizeof(double) * eps.size(),
-                                  hipMemcpyHostToDevice, s), "upload orbital energies");
-  if (st == SIE_OK && !items.empty())
-    st = hip_check(hipMemcpyAsync(dev(pl.off_items), items.data(),
-                                  sizeof(sie::Item) * items.size(), hipMemcpyHostToDevice, s),
-                   "upload work items");
-  if (st == SIE_OK) st = hip_check(hipStreamSynchronize(s), "upload tables");
-  if (st != SIE_OK) return st;
+  // ---- uploads: page-locked staging, stream-ordered, no host wait ----
+  sie_status st = SIE_OK;
+  {
+    sie::Staging::Batch up;
+    const size_t bytes = sie::Staging::padded(sizeof(sie::FragDesc) * desc.size()) +
+                         sie::Staging::padded(sizeof(double) * eps.size()) +
+                         sie::Staging::padded(sizeof(sie::Item) * items.size());
+    st = hip_check(g_staging.begin(bytes, up), "stage tables");
+    if (st != SIE_OK) return st;
+    up.add(dev(pl.off_desc), desc.data(), sizeof(sie::FragDesc) * desc.size());
+    up.add(dev(pl.off_eps), eps.data(), sizeof(double) * eps.size());
+    up.add(dev(pl.off_items), items.data(), sizeof(sie::Item) * items.size());
+    st = hip_check(up.commit(s), "upload tables");
+    if (st != SIE_OK) return st;
+  }
+  if (check_finite_on()) {
+    st = scan_finite(frags, n, !pl.split, reinterpret_cast<int*>(dev(pl.off_flags)), s, w);
+    if (st != SIE_OK) return st;
+  }
 
   const sie::FragDesc* d_desc = reinterpret_cast<const sie::FragDesc*>(dev(pl.off_desc));
   const sie::Item* d_items = reinterpret_cast<const sie::Item*>(dev(pl.off_items));
@@ -900,29 +958,30 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
   const size_t off_groups = align_up(off_recs + sizeof(sie::AdjRec) * pl.adj_recs, 256);
   const size_t off_slices = align_up(off_groups + sizeof(sie::AdjGroup) * pl.adj_recs, 256);
 
-  sie_status st = hip_check(hipMemcpyAsync(dev(pl.off_desc), T.desc.data(),
-                                           sizeof(sie::FragDesc) * T.desc.size(),
-                                           hipMemcpyHostToDevice, s), "upload descriptors");
-  if (st == SIE_OK)
-    st = hip_check(hipMemcpyAsync(dev(pl.off_eps), T.eps.data(), sizeof(double) * T.eps.size(),
-                                  hipMemcpyHostToDevice, s), "upload orbital energies");
-  if (st == SIE_OK && !T.items.empty())
-    st = hip_check(hipMemcpyAsync(dev(pl.off_items), T.items.data(),
-                                  sizeof(sie::Item) * T.items.size(), hipMemcpyHostToDevice, s),
-                   "upload work items");
-  if (st == SIE_OK && !recs.empty())
-    st = hip_check(hipMemcpyAsync(dev(off_recs), recs.data(), sizeof(sie::AdjRec) * recs.size(),
-                                  hipMemcpyHostToDevice, s), "upload contraction records");
-  if (st == SIE_OK && !groups.empty())
-    st = hip_check(hipMemcpyAsync(dev(off_groups), groups.data(),
-                                  sizeof(sie::AdjGroup) * groups.size(), hipMemcpyHostToDevice, s),
-                   "upload contraction groups");
-  if (st == SIE_OK && !slices.empty())
-    st = hip_check(hipMemcpyAsync(dev(off_slices), slices.data(),
-                                  sizeof(sie::AdjSlice) * slices.size(), hipMemcpyHostToDevice, s),
-                   "upload contraction slices");
-  if (st == SIE_OK) st = hip_check(hipStreamSynchronize(s), "upload tables");
-  if (st != SIE_OK) return st;
+  sie_status st = SIE_OK;
+  {
+    sie::Staging::Batch up;
+    const size_t bytes = sie::Staging::padded(sizeof(sie::FragDesc) * T.desc.size()) +
+                         sie::Staging::padded(sizeof(double) * T.eps.size()) +
+                         sie::Staging::padded(sizeof(sie::Item) * T.items.size()) +
+                         sie::Staging::padded(sizeof(sie::AdjRec) * recs.size()) +
+                         sie::Staging::padded(sizeof(sie::AdjGroup) * groups.size()) +
+                         sie::Staging::padded(sizeof(sie::AdjSlice) * slices.size());
+    st = hip_check(g_staging.begin(bytes, up), "stage tables");
+    if (st != SIE_OK) return st;
+    up.add(dev(pl.off_desc), T.desc.data(), sizeof(sie::FragDesc) * T.desc.size());
+    up.add(dev(pl.off_eps), T.eps.data(), sizeof(double) * T.eps.size());
+    up.add(dev(pl.off_items), T.items.data(), sizeof(sie::Item) * T.items.size());
+    up.add(dev(off_recs), recs.data(), sizeof(sie::AdjRec) * recs.size());
+    up.add(dev(off_groups), groups.data(), sizeof(sie::AdjGroup) * groups.size());
+    up.add(dev(off_slices), slices.data(), sizeof(sie::AdjSlice) * slices.size());
+    st = hip_check(up.commit(s), "upload tables");
+    if (st != SIE_OK) return st;
+  }
+  if (check_finite_on()) {
+    st = scan_finite(frags, n, !pl.split, reinterpret_cast<int*>(dev(pl.off_flags)), s, w);
+    if (st != SIE_OK) return st;
+  }
 
   const sie::FragDesc* d_desc = reinterpret_cast<const sie::FragDesc*>(dev(pl.off_desc));
   const sie::Item* d_items = reinterpret_cast<const sie::Item*>(dev(pl.off_items));

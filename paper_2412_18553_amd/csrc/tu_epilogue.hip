@@ -42,4 +42,19 @@ void launch_symmetrize(unsigned grid, hipStream_t s, double* g, int kind, int no
   hipLaunchKernelGGL(k_symmetrize<>, dim3(grid), dim3(256), 0, s, g, kind, no, nv, n);
 }
 
+void launch_zero_flags(hipStream_t s, int* flags, int n) {
+  hipLaunchKernelGGL(k_zero_flags, dim3((n + 255) / 256), dim3(256), 0, s, flags, n);
+}
+
+void launch_nonfinite(hipStream_t s, const void* x, bool f64, int64_t n, int* flags, int slot) {
+  const int64_t nb = (n + 255) / 256;
+  const unsigned grid = unsigned(nb < 8192 ? (nb > 0 ? nb : 1) : 8192);
+  if (f64)
+    hipLaunchKernelGGL(k_nonfinite<double>, dim3(grid), dim3(256), 0, s,
+                       static_cast<const double*>(x), n, flags, slot);
+  else
+    hipLaunchKernelGGL(k_nonfinite<float>, dim3(grid), dim3(256), 0, s,
+                       static_cast<const float*>(x), n, flags, slot);
+}
+
 }  // namespace sie

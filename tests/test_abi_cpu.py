@@ -76,7 +76,8 @@ def test_valid_workspace_query(lib):
     (dict(t2=None), _lib.SIE_ERR_INVALID_ARG),
     (dict(ovvv=FAKE + 4), _lib.SIE_ERR_INVALID_ARG),            # misaligned float64
     (dict(eps_occ=[-1.0, 0.5], eps_vir=[0.4, 1.0], o=2, v=2), _lib.SIE_ERR_INVALID_ARG),
-    (dict(eps_occ=[-1.0, float("nan")], o=2), _lib.SIE_ERR_INVALID_ARG),
+    (dict(eps_occ=[-1.0, float("nan")], o=2), _lib.SIE_ERR_NONFINITE),
+    (dict(eps_vir=[0.4, float("inf")], v=2), _lib.SIE_ERR_NONFINITE),
     (dict(frag_proj=FAKE), _lib.SIE_ERR_UNSUPPORTED),
     (dict(o=100, v=700), _lib.SIE_ERR_UNSUPPORTED),             # float64 extent > 2^32 bytes
 ])

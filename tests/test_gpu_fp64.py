@@ -133,3 +133,60 @@ def test_every_tile_variant(o, v, aux, seed):
             assert np.max(np.abs(tri - tri0)) <= RTOL * scale, variant
     finally:
         sie.set_tile_table(None)
+
+
+def test_finite_check():
+    """With the finite check on, a NaN in t2 is reported as
+    SIE_ERR_NONFINITE before any (T) kernel runs; with it off the call
+    computes (a non-finite energy, no fault); clean inputs pass the scan
+    and give the same energy as without it."""
+    import torch
+    import paper_2412_18553_amd as sie
+    from paper_2412_18553_amd import _lib
+    f = make_fragment(4, 20, 30, (7, 31))
+    args = _dev(f)
+    e_ref = float(sie.triples_energy(*args).item())
+    bad = list(args)
+    bad[3] = args[3].clone()
+    bad[3][1, 2, 3, 4] = float("nan")
+    try:
+        sie.set_check_finite(True)
+        assert float(sie.triples_energy(*args).item()) == e_ref
+        with pytest.raises(sie.SieError) as err:
+            sie.triples_energy(*bad)
+        assert err.value.status == _lib.SIE_ERR_NONFINITE and "t2" in str(err.value)
+    finally:
+        sie.set_check_finite(False)
+    assert not np.isfinite(float(sie.triples_energy(*bad).item()))
+    torch.cuda.synchronize()
+
+
+def test_call_returns_before_the_device_finishes():
+    """The energy call enqueues its table uploads and kernels without waiting
+    for work already on the stream: queued behind a long spin kernel, it
+    returns long before the spin ends, and the result is then correct."""
+    import time
+    import torch
+    import paper_2412_18553_amd as sie
+    if not hasattr(torch.cuda, "_sleep"):
+        pytest.skip("no spin kernel in this torch build")
+    f = make_fragment(5, 24, 30, (7, 32))
+    frag = sie.Fragment(*_dev(f))
+    ws = torch.empty(sie.workspace_size(frag), dtype=torch.uint8, device="cuda")
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    e_ref = float(sie.energy(frag, workspace=ws, out=out).item())
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    torch.cuda._sleep(1 << 29)
+    stop.record()
+    t0 = time.perf_counter()
+    sie.energy(frag, workspace=ws, out=out)
+    host_ms = (time.perf_counter() - t0) * 1e3
+    torch.cuda.synchronize()
+    spin_ms = start.elapsed_time(stop)
+    print(f"spin {spin_ms:.1f} ms, energy call returned after {host_ms:.2f} ms", flush=True)
+    if spin_ms < 20.0:
+        pytest.skip("spin kernel too short to tell")
+    assert host_ms < 0.5 * spin_ms
+    assert float(out.item()) == e_ref
