@@ -147,6 +147,29 @@ sie_status sie_triples_energy(const sie_fragment* frag, sie_precision p,
                               double* e_out, double* e_triples,
                               void* ws, size_t ws_bytes, void* stream);
 
+/* E_x of one fragment exactly as sie_triples_energy computes it, for callers
+ * that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): in place of a caller
+ * workspace the call uses a scratch array of SIE_STATIC_SCRATCH_BYTES that
+ * the library holds in each GPU's memory from its load on that GPU until the
+ * process ends, and it allocates nothing (no device, page-locked or torch
+ * memory; its small tables are copied from host memory with pageable copies,
+ * which return once the host data has been consumed).  The caller passes the
+ * inputs and outputs as for sie_triples_energy.
+ *   Limit: the fragment's minimum workspace (sie_triples_workspace_size with
+ *   max_bytes = SIE_STATIC_SCRATCH_BYTES) must fit in the scratch, else the
+ *   call returns SIE_ERR_WORKSPACE and enqueues nothing.  Fragments that fit
+ *   with few triples in flight run in many small rounds.
+ *   Concurrency: every call on one GPU shares that GPU's scratch, which keeps
+ *   the last call's contents (the call needs none of them).  Two calls on one
+ *   GPU that may run at the same time (different streams without ordering,
+ *   or different threads) race on the scratch and give undefined results;
+ *   calls on one stream are ordered and safe.
+ * Results are bitwise equal to sie_triples_energy's for the same inputs. */
+#define SIE_STATIC_SCRATCH_BYTES (256u * 1024u * 1024u)
+sie_status sie_triples_energy_static(const sie_fragment* frag, sie_precision p,
+                                     double* e_out, double* e_triples, void* stream);
+
 /* E_x of each of n fragments and E = sum_x E_x (equation C_f), in one
  * evaluation: the occupied triples of all fragments form one work list,
  * ordered longest first, run in as few launches as the workspace allows.

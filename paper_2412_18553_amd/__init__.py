@@ -135,6 +135,29 @@ def energy(frag: Fragment, *, workspace: torch.Tensor | None = None,
     return out
 
 
+def energy_static(frag: Fragment, *, out: torch.Tensor | None = None,
+                  triples: torch.Tensor | None = None) -> torch.Tensor:
+    """E_x like `energy`, through the entry point that allocates nothing: the
+    library's static device scratch (SIE_STATIC_SCRATCH_BYTES per GPU) serves
+    as the workspace.  `out` and `triples`, when given, are written in place,
+    so a caller that passes both allocates nothing here either."""
+    lib = _lib.load()
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=frag.device)
+    if out.dtype != torch.float64 or not out.is_cuda or out.numel() < 1:
+        raise ValueError("out must be a float64 CUDA tensor")
+    if triples is not None and (triples.dtype != torch.float64 or
+                                triples.numel() != frag.n_triples or
+                                not triples.is_contiguous() or not triples.is_cuda):
+        raise ValueError("triples must be a contiguous float64 CUDA tensor of n_triples entries")
+    stream = torch.cuda.current_stream(frag.device).cuda_stream
+    st = lib.sie_triples_energy_static(ctypes.byref(frag.desc), PRECISIONS[frag.precision],
+                                       out.data_ptr(),
+                                       None if triples is None else triples.data_ptr(), stream)
+    _lib.check(st)
+    return out
+
+
 def energy_batched(frags, *, workspace: torch.Tensor | None = None,
                    out: torch.Tensor | None = None, total: torch.Tensor | None = None,
                    max_workspace_bytes: int = 0):

@@ -22,12 +22,15 @@ SIE_ERR_HIP = 5
 SIE_FP64 = 0
 SIE_SPLIT_BF16 = 1
 
+SIE_STATIC_SCRATCH_BYTES = 256 * 1024 * 1024
+
 STATUS_NAMES = {0: "SIE_OK", 1: "SIE_ERR_INVALID_ARG", 2: "SIE_ERR_UNSUPPORTED",
                 3: "SIE_ERR_WORKSPACE", 4: "SIE_ERR_NONFINITE", 5: "SIE_ERR_HIP"}
 
 # every symbol include/sie_triples.h declares
 EXPORTED = ["sie_abi_version", "sie_last_error", "sie_occupied_triples",
             "sie_triples_workspace_size", "sie_triples_energy", "sie_triples_energy_batched",
+            "sie_triples_energy_static",
             "sie_triples_backward_workspace_size", "sie_triples_backward",
             "sie_tile_variants", "sie_tile_variant_shape", "sie_tile_variant_of",
             "sie_set_tile_table", "sie_split_shape_of", "sie_set_split_shape",
@@ -85,6 +88,9 @@ def load() -> ctypes.CDLL:
     lib.sie_triples_energy.argtypes = [ctypes.POINTER(SieFragment), ctypes.c_int,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_size_t, ctypes.c_void_p]
+    lib.sie_triples_energy_static.restype = ctypes.c_int
+    lib.sie_triples_energy_static.argtypes = [ctypes.POINTER(SieFragment), ctypes.c_int,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.sie_triples_energy_batched.restype = ctypes.c_int
     lib.sie_triples_energy_batched.argtypes = [ctypes.POINTER(SieFragment), ctypes.c_int32,
                                                ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,

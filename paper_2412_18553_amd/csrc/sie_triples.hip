@@ -51,6 +51,38 @@ size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
 // Page-locked staging of the per-call tables (see staging.hpp).
 sie::Staging g_staging;
 
+// Device scratch of sie_triples_energy_static: one copy per GPU, held from the
+// library's load on that GPU until the process ends.  Host code never passes
+// `scratch` itself to a kernel or a copy (in host code the name is only a
+// stand-in); it uses the device address hipGetSymbolAddress returns for the
+// current GPU, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[SIE_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+sie_status fail_hip(hipError_t e, const std::string& what);
+
+sie_status static_scratch(void** out, const std::string& who) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(e, who + ": hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(SIE_ERR_UNSUPPORTED, who + ": device index beyond the library's table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail_hip(e, who + ": hipGetSymbolAddress(scratch)");
+    if (!ptr || (reinterpret_cast<uintptr_t>(ptr) % 256) != 0)
+      return fail(SIE_ERR_HIP, who + ": scratch address is NULL or not 256-byte aligned");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SIE_OK;
+}
+
 // Optional scan of the device inputs for non-finite values (SIE_CHECK_FINITE).
 std::atomic<int> g_check_finite{-1};
 
@@ -261,6 +293,10 @@ sie_status check_fragment(const sie_fragment* f, sie_precision prec, const char*
 sie_status hip_check(hipError_t e, const char* what) {
   if (e == hipSuccess) return SIE_OK;
   return fail(SIE_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+sie_status fail_hip(hipError_t e, const std::string& what) {
+  return fail(SIE_ERR_HIP, what + ": " + hipGetErrorString(e));
 }
 
 // ---- float64 build tile table: (n_v upper bound, variant), ascending ----
@@ -682,9 +718,12 @@ sie_status scan_finite(const sie_fragment* frags, int n, bool f64, int* d_flags,
 }
 
 // One evaluation over n fragments (see work.hpp).
+// With `direct` set the tables are copied straight from the host vectors
+// (pageable copies, which HIP completes before returning) instead of through
+// the page-locked staging ring, so the call allocates nothing anywhere.
 sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag_out,
                double* e_total, double* e_triples, void* ws, size_t ws_bytes, void* stream,
-               const char* who) {
+               const char* who, bool direct = false) {
   const std::string w(who);
   if (!frags || n < 1) return fail(SIE_ERR_INVALID_ARG, w + ": need at least one fragment");
   for (int x = 0; x < n; ++x) {
@@ -712,7 +751,19 @@ sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag
 
   // ---- uploads: page-locked staging, stream-ordered, no host wait ----
   sie_status st = SIE_OK;
-  {
+  if (direct) {
+    const std::pair<size_t, std::pair<const void*, size_t>> parts[3] = {
+        {pl.off_desc, {desc.data(), sizeof(sie::FragDesc) * desc.size()}},
+        {pl.off_eps, {eps.data(), sizeof(double) * eps.size()}},
+        {pl.off_items, {items.data(), sizeof(sie::Item) * items.size()}}};
+    for (const auto& pt : parts) {
+      if (pt.second.second == 0) continue;
+      st = hip_check(hipMemcpyAsync(dev(pt.first), pt.second.first, pt.second.second,
+                                    hipMemcpyHostToDevice, s),
+                     "upload tables");
+      if (st != SIE_OK) return st;
+    }
+  } else {
     sie::Staging::Batch up;
     const size_t bytes = sie::Staging::padded(sizeof(sie::FragDesc) * desc.size()) +
                          sie::Staging::padded(sizeof(double) * eps.size()) +
@@ -1076,6 +1127,29 @@ sie_status sie_triples_energy(const sie_fragment* f, sie_precision p, double* e_
   if (e_triples && !aligned(e_triples, sizeof(double)))
     return fail(SIE_ERR_INVALID_ARG, "sie_triples_energy: e_triples is misaligned");
   return run(f, 1, p, nullptr, e_out, e_triples, ws, ws_bytes, stream, "sie_triples_energy");
+}
+
+sie_status sie_triples_energy_static(const sie_fragment* f, sie_precision p, double* e_out,
+                                     double* e_triples, void* stream) {
+  const char* who = "sie_triples_energy_static";
+  if (!e_out || !aligned(e_out, sizeof(double)))
+    return fail(SIE_ERR_INVALID_ARG, std::string(who) + ": e_out is NULL or misaligned");
+  if (e_triples && !aligned(e_triples, sizeof(double)))
+    return fail(SIE_ERR_INVALID_ARG, std::string(who) + ": e_triples is misaligned");
+  sie_status st = check_fragment(f, p, who);
+  if (st != SIE_OK) return st;
+  const Plan pl = make_plan(f, 1, p);
+  if (pl.fixed_bytes + pl.min_arena > SIE_STATIC_SCRATCH_BYTES)
+    return fail(SIE_ERR_WORKSPACE,
+                std::string(who) + ": the fragment needs " +
+                    std::to_string(pl.fixed_bytes + pl.min_arena) +
+                    " bytes of workspace, more than the static scratch of " +
+                    std::to_string(size_t(SIE_STATIC_SCRATCH_BYTES)) + " bytes");
+  void* ws = nullptr;
+  st = static_scratch(&ws, who);
+  if (st != SIE_OK) return st;
+  return run(f, 1, p, nullptr, e_out, e_triples, ws, SIE_STATIC_SCRATCH_BYTES, stream, who,
+             /*direct=*/true);
 }
 
 sie_status sie_triples_energy_batched(const sie_fragment* frags, int32_t n, sie_precision p,

@@ -200,3 +200,24 @@ def test_tile_table(lib):
     keep = []
     f = frag(keep=keep)
     assert lib.sie_triples_workspace_size(ctypes.byref(f), 1, _lib.SIE_FP64, 0) > 0
+
+
+def test_static_entry_point_rejects_before_any_hip_call(lib):
+    """The allocation-free entry point checks its arguments and the fit of the
+    fragment's minimum workspace in the static scratch on the host, before it
+    looks up the scratch on a device."""
+    keep = []
+    f = frag(keep=keep)
+    static = lambda fr, prec=_lib.SIE_FP64, e_out=FAKE: lib.sie_triples_energy_static(  # noqa: E731
+        ctypes.byref(fr) if fr is not None else None, prec, e_out, None, None)
+    assert static(None) == _lib.SIE_ERR_INVALID_ARG
+    assert static(f, e_out=None) == _lib.SIE_ERR_INVALID_ARG
+    assert static(f, e_out=FAKE + 4) == _lib.SIE_ERR_INVALID_ARG
+    assert static(frag(keep=keep, frag_proj=FAKE)) == _lib.SIE_ERR_UNSUPPORTED
+    # 32 / 320 split needs its bf16 copies (~0.4 GB) in the workspace: too big
+    big = frag(o=32, v=320, keep=keep)
+    assert static(big, prec=_lib.SIE_SPLIT_BF16) == _lib.SIE_ERR_WORKSPACE
+    assert "static scratch" in _lib.last_error()
+    # 24 / 400 float64: one unit's three cubes alone exceed 256 MiB
+    assert static(frag(o=24, v=400, keep=keep)) == _lib.SIE_ERR_WORKSPACE
+    assert _lib.SIE_STATIC_SCRATCH_BYTES == 256 * 1024 * 1024
