@@ -81,7 +81,7 @@ def measured_peak(kind):
     lib.sie_mfma_peak.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                   ctypes.POINTER(ctypes.c_double)]
     out = ctypes.c_double(0.0)
-    iters = 20000 if kind == 0 else 40000
+    iters = 40000 if kind == 0 else 80000
     st = lib.sie_mfma_peak(kind, iters, 8192, ctypes.byref(out))
     if st != 0:
         raise RuntimeError(f"sie_mfma_peak failed with {st}")
@@ -89,11 +89,12 @@ def measured_peak(kind):
 
 
 # ---------------------------------------------------------------- CPU baseline
-def cpu_baseline(host_frag, units):
+def cpu_baseline(host_frag, target_s=15.0):
     """Time the CPU oracle on a bounded sample of the same fragment: the
-    occupied-outer oracle (oracle.occupied_triple_parts) on the given
-    occupied triples; the rate is the sample's flops over its time, i.e. an
-    extrapolation of the whole fragment's oracle rate."""
+    occupied-outer oracle (oracle.occupied_triple_parts) on occupied triples
+    with three distinct indices, taken from a fixed spread until about
+    `target_s` seconds have passed; the rate is the sample's flops over its
+    time, i.e. an extrapolation of the whole fragment's oracle rate."""
     import oracle
     try:
         from threadpoolctl import threadpool_info
@@ -101,15 +102,26 @@ def cpu_baseline(host_frag, units):
     except Exception:  # pragma: no cover
         cores = 1
     o, v = host_frag.n_occ, host_frag.n_vir
+    spread = [(o - 1, o // 2, 0), (o // 3, o // 4, o // 5), (o - 2, o - 3, o - 4),
+              (o // 2, 1, 0), (o - 1, o // 3, o // 6), (2 * o // 3, o // 2, o // 4),
+              (o - 3, 2, 1), (o // 2 + 1, o // 2, o // 2 - 1)]
+    units = []
+    for t in spread:
+        if t[0] > t[1] > t[2] >= 0 and t not in units:
+            units.append(t)
+    done = []
     t0 = time.perf_counter()
     for (i, j, k) in units:
         oracle.occupied_triple_parts(i, j, k, *host_frag.arrays())
+        done.append((i, j, k))
+        if time.perf_counter() - t0 >= target_s:
+            break
     dt = time.perf_counter() - t0
     # flops of one occupied triple with three distinct indices: 12 n_v^4 + 12 n_o n_v^3
-    work = len(units) * (12.0 * v ** 4 + 12.0 * o * v ** 3)
+    work = len(done) * (12.0 * v ** 4 + 12.0 * o * v ** 3)
     return {"value": round(work / dt / 1e12, 5), "unit": "TFLOP/s", "cores": int(cores),
             "kind": "oracle", "extrapolated": True,
-            "sample": f"oracle.occupied_triple_parts on occupied triples {list(units)} of the same "
+            "sample": f"oracle.occupied_triple_parts on occupied triples {done} of the same "
                       f"{o}/{v} fragment ({dt:.1f} s); rate = sample flops / sample time, "
                       f"extrapolated to the whole fragment",
             "seconds": round(dt, 2)}
@@ -307,7 +319,7 @@ def run_split(args, result, name):
         host = df.host()
         del df, fr
         torch.cuda.empty_cache()
-        result["cpu_baseline"] = cpu_baseline(host, [(o - 1, o // 2, 0), (o // 3, o // 4, o // 5)])
+        result["cpu_baseline"] = cpu_baseline(host)
     result["kernel_ms_per_step"] = {k: round(t / args.steps, 3) for k, (t, _) in prof.items()}
 
 
@@ -363,7 +375,7 @@ def run_single(args, result, name, mode):
         host = df.host()
         del df, fr
         torch.cuda.empty_cache()
-        result["cpu_baseline"] = cpu_baseline(host, [(o - 1, o // 2, 0)])
+        result["cpu_baseline"] = cpu_baseline(host)
     result["kernel_ms_per_step"] = {k: round(t / args.steps, 3) for k, (t, _) in prof.items()}
 
 

@@ -62,7 +62,7 @@
 extern "C" {
 #endif
 
-#define SIE_ABI_VERSION 1
+#define SIE_ABI_VERSION 2
 
 typedef enum {
   SIE_OK = 0,
@@ -106,13 +106,19 @@ typedef struct {
 
 /* Gradient outputs of one fragment for sie_triples_backward: device float64
  * arrays with the shapes of the inputs of the same name, or NULL to skip that
- * input's gradient. */
+ * input's gradient.  eps_occ [n_occ] and eps_vir [n_vir] receive the
+ * derivative with respect to the orbital energies (which enter through the
+ * triples denominators D only: the diagonal of the canonical cluster Fock
+ * matrix), device arrays although the orbital energies themselves are host
+ * inputs. */
 typedef struct {
   double* t1;
   double* t2;
   double* ovvv;
   double* ooov;
   double* ovov;
+  double* eps_occ;
+  double* eps_vir;
 } sie_fragment_grad;
 
 /* Number of unordered occupied triples i >= j >= k of a fragment:
@@ -212,6 +218,10 @@ size_t sie_triples_backward_workspace_size(const sie_fragment* frags, int32_t n,
  *            (ia|bc) and (ia|cb), over (jl|ia) and (lj|ia), over (ia|jb) and
  *            (jb|ia)), so the result does not depend on which twin the
  *            kernels read.  Gradient arrays must not overlap the inputs.
+ *            The orbital-energy gradients: dE_x/de_p = sum over the terms of
+ *            dE_x/dD times the number of times p occurs in D (+ for
+ *            occupied, - for virtual indices); they sum to zero over all
+ *            orbitals and satisfy sum_p e_p dE_x/de_p = -E_x.
  *   e_frag   device float64 [n] or NULL: receives E_x
  *   ws       >= sie_triples_backward_workspace_size(frags, n, p, cap) bytes
  * Deterministic (fixed summation order, no atomics); same stream behaviour as

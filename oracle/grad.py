@@ -53,8 +53,9 @@ _TWIN_AXES = {"t2": (1, 0, 3, 2), "ovvv": (0, 1, 3, 2), "ooov": (1, 0, 2, 3),
 
 
 def _orbit_mean(name, x):
-    """Mean of x over the index-symmetry orbit of input `name` (t1 has none)."""
-    if name == "t1":
+    """Mean of x over the index-symmetry orbit of input `name` (t1 and the
+    orbital energies have none)."""
+    if name not in _TWIN_AXES:
         return x
     return 0.5 * (x + x.transpose(_TWIN_AXES[name]))
 
@@ -64,8 +65,11 @@ def _symmetrize(g):
 
 
 def energy_gradient(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, symmetrize=True):
-    """(E, E_WW, E_WV, grads) with grads = {"t1", "t2", "ovvv", "ooov", "ovov"}
-    of dE/d(input) for C = I.  Memory is O(n_o^3 n_v^3)."""
+    """(E, E_WW, E_WV, grads) with grads = {"t1", "t2", "ovvv", "ooov", "ovov",
+    "eps_occ", "eps_vir"} of dE/d(input) for C = I.  The orbital energies enter
+    through the denominators only (the diagonal Fock elements of the canonical
+    cluster orbitals), so dE/d(eps) is the contraction of dE/dD with the index
+    counts of D.  Memory is O(n_o^3 n_v^3)."""
     eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov = _check(
         eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov)
     # forward quantities (same definitions as the energy)
@@ -82,6 +86,14 @@ def energy_gradient(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, symmetrize=True)
     r_v = _R6(vt)
     e_ww = float(np.sum(wt * r_w / d)) / 3.0
     e_wv = float(np.sum(wt * r_v / d)) / 3.0
+    # orbital energies enter through D only: dE/dD = -(1/3) Wt R[Wt + Vt] / D^2
+    # elementwise, and D = e_i + e_j + e_k - e_a - e_b - e_c
+    e_d = -(wt * (r_w + r_v)) / (3.0 * d * d)
+    g_eo = (np.einsum("ijkabc->i", e_d) + np.einsum("ijkabc->j", e_d)
+            + np.einsum("ijkabc->k", e_d))
+    g_ev = -(np.einsum("ijkabc->a", e_d) + np.einsum("ijkabc->b", e_d)
+             + np.einsum("ijkabc->c", e_d))
+    del e_d
     # adjoint cubes
     w_hat = (2.0 * r_w + r_v) / (3.0 * d)
     v_hat = r_w / (3.0 * d)
@@ -93,6 +105,8 @@ def energy_gradient(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, symmetrize=True)
         "ooov": -6.0 * np.einsum("ijkabc,lkbc->jlia", w_hat, t2, optimize=True),
         "ovov": 3.0 * np.einsum("ijkabc,kc->iajb", v_hat, t1, optimize=True),
         "t1": 3.0 * np.einsum("ijkabc,iajb->kc", v_hat, ovov, optimize=True),
+        "eps_occ": g_eo,
+        "eps_vir": g_ev,
     }
     if symmetrize:
         g = _symmetrize(g)

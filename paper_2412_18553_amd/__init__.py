@@ -186,6 +186,17 @@ def energy_batched(frags, *, workspace: torch.Tensor | None = None,
 
 
 GRAD_NAMES = ("t1", "t2", "ovvv", "ooov", "ovov")
+# gradients with respect to the orbital energies (device float64 [n_occ], [n_vir])
+EPS_GRAD_NAMES = ("eps_occ", "eps_vir")
+ALL_GRAD_NAMES = GRAD_NAMES + EPS_GRAD_NAMES
+
+
+def _grad_shape(f, name):
+    if name == "eps_occ":
+        return (f.n_occ,)
+    if name == "eps_vir":
+        return (f.n_vir,)
+    return tuple(getattr(f, name).shape)
 
 
 def backward_workspace_size(frags, max_bytes: int = 0) -> int:
@@ -204,30 +215,34 @@ def backward(frags, *, grad_e: torch.Tensor | None = None, grads=None,
     """Enqueue the gradient of E_x for each fragment on the current stream.
 
     Returns a list (one dict per fragment) of float64 device tensors
-    {name: grad_e[x] * dE_x/d name} for the names in `want`, symmetrized over
-    each input's index-symmetry orbit.  `grads`, if given, is such a list of
-    preallocated tensors to overwrite.  `grad_e`: float64 device tensor [n]
-    or None (ones).  `e_frag`: optional float64 [n] receiving E_x."""
+    {name: grad_e[x] * dE_x/d name} for the names in `want` (any of
+    ALL_GRAD_NAMES), symmetrized over each input's index-symmetry orbit.
+    `grads`, if given, is such a list of preallocated tensors to overwrite.
+    `grad_e`: float64 device tensor [n] or None (ones).  `e_frag`: optional
+    float64 [n] receiving E_x."""
     lib = _lib.load()
     single = isinstance(frags, Fragment)
     frags, arr, prec = _desc_array(frags)
     device = frags[0].device
+    for name in want:
+        if name not in ALL_GRAD_NAMES:
+            raise ValueError(f"unknown gradient {name!r}")
     if grads is None:
-        grads = [{name: torch.empty_like(getattr(f, name), dtype=torch.float64)
+        grads = [{name: torch.empty(_grad_shape(f, name), dtype=torch.float64, device=device)
                   for name in want} for f in frags]
     if len(grads) != len(frags):
         raise ValueError("grads needs one dict per fragment")
     garr = (SieFragmentGrad * len(frags))()
     for x, (f, g) in enumerate(zip(frags, grads)):
-        for name in GRAD_NAMES:
+        for name in ALL_GRAD_NAMES:
             t = g.get(name)
             if t is None:
                 continue
-            ref = getattr(f, name)
+            shape = _grad_shape(f, name)
             if (not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or
-                    t.shape != ref.shape or not t.is_contiguous() or t.device != device):
+                    tuple(t.shape) != shape or not t.is_contiguous() or t.device != device):
                 raise ValueError(f"grads[{x}][{name!r}] must be a contiguous float64 tensor "
-                                 f"of shape {tuple(ref.shape)} on {device}")
+                                 f"of shape {shape} on {device}")
             setattr(garr[x], name, t.data_ptr())
     if grad_e is not None:
         if (grad_e.dtype != torch.float64 or grad_e.numel() != len(frags) or
@@ -252,28 +267,35 @@ def backward(frags, *, grad_e: torch.Tensor | None = None, grads=None,
 
 
 class SieTriples(torch.autograd.Function):
-    """E_x as a differentiable function of (t1, t2, ovvv, ooov, ovov).
+    """E_x as a differentiable function of (eps_occ, eps_vir, t1, t2, ovvv,
+    ooov, ovov).
 
     SieTriples.apply(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov[, precision])
     returns a 0-d float64 tensor; backward calls the library's adjoint and
-    returns the symmetrized gradients cast to each input's dtype.  precision
-    is "fp64" (float64 inputs) or "split_bf16" (float32 inputs)."""
+    returns the symmetrized gradients cast to each input's dtype (and, for
+    orbital energies given as tensors, on their device).  precision is "fp64"
+    (float64 inputs) or "split_bf16" (float32 inputs)."""
 
     @staticmethod
     def forward(ctx, eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, precision="fp64"):
         frag = Fragment(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, precision)
         ctx.frag = frag
+        ctx.eps_like = [x if isinstance(x, torch.Tensor) else None for x in (eps_occ, eps_vir)]
         return energy(frag)[0].clone()
 
     @staticmethod
     def backward(ctx, grad_out):
         frag = ctx.frag
-        want = [name for name, need in zip(GRAD_NAMES, ctx.needs_input_grad[2:7]) if need]
+        want = [name for name, need in zip(ALL_GRAD_NAMES,
+                                           tuple(ctx.needs_input_grad[2:7]) +
+                                           tuple(ctx.needs_input_grad[0:2])) if need]
         if not want:
             return (None,) * 8
         ge = grad_out.detach().reshape(1).to(device=frag.device, dtype=torch.float64).contiguous()
         g = backward(frag, grad_e=ge, want=want)
-        return (None, None) + tuple(
+        eps = tuple(g[name].to(device=like.device, dtype=like.dtype) if name in g else None
+                    for name, like in zip(EPS_GRAD_NAMES, ctx.eps_like))
+        return eps + tuple(
             g[name].to(getattr(frag, name).dtype) if name in g else None
             for name in GRAD_NAMES) + (None,)
 

@@ -54,7 +54,8 @@ class SieFragment(ctypes.Structure):
 
 
 class SieFragmentGrad(ctypes.Structure):
-    _fields_ = [(name, ctypes.c_void_p) for name in ("t1", "t2", "ovvv", "ooov", "ovov")]
+    _fields_ = [(name, ctypes.c_void_p)
+                for name in ("t1", "t2", "ovvv", "ooov", "ovov", "eps_occ", "eps_vir")]
 
 
 class SieError(RuntimeError):

@@ -22,6 +22,8 @@
 // plain read-modify-write sum without atomics and bitwise reproducible.
 #pragma once
 
+#include "sie_triples.h"
+
 #include "device_common.hpp"
 #include "k_fp64.hpp"
 #include "adj_plan.hpp"
@@ -40,12 +42,25 @@ namespace sie {
 // the unit's third cube.  Also
 // writes the unit's energy partials (as k_epilogue).  grad_e[frag] (or 1)
 // scales G and H.
+//
+// Orbital-energy gradient (eo_part non-NULL): the energy depends on the
+// orbital energies only through D, dE_u/dD = -w W R'[Z] / D^2 per element.
+// Per tuple (the six orderings of a virtual triple, which share D; see
+// k_epilogue) q = scale * weight * sum_m Wt_m R'[Z]_m / D^2, so
+//   dL/de_p (occupied) = -sum_u count_p(u) sum_{tuples of u} q,
+//   dL/de_x (virtual)  = +sum_u sum_{tuples of u} count_x(tuple) q.
+// Each work-group writes its share of the first sum to eo_part (layout of
+// `partials`) and its per-virtual sums, accumulated over its orbits in an LDS
+// row, to ev_part[(r pstride + slot) ev_stride + x] (r: item index in the
+// round).  All sums run in fixed orders (wave shuffles, then fixed lanes).
 template <typename CubeT, typename InT>
 __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
                                              const Item* __restrict__ items, int n_items,
                                              CubeT* __restrict__ arena,
                                              double* __restrict__ partials, int pstride,
-                                             const double* __restrict__ grad_e) {
+                                             const double* __restrict__ grad_e,
+                                             double* __restrict__ eo_part,
+                                             double* __restrict__ ev_part, int ev_stride) {
   const int r = find_item<false>(items, n_items, blockIdx.x);
   const int64_t start = r ? items[r - 1].part_end : 0;
   const Item it = items[r];
@@ -56,11 +71,23 @@ __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
   __shared__ double sw[6][kOrbSlot];
   __shared__ double sz[6][kOrbSlot];
   __shared__ double red[4];
+  // orbital-energy gradient: virtual row of this work-group and the
+  // cross-wave partials of one orbit's marginals
+  __shared__ double dv[SIE_MAX_VIR];
+  __shared__ double tp0[2][4], tp1[2][4][kOrb], tp2[2][4][kOrb];
+  const bool want_eps = eo_part != nullptr;
   double* out = partials + (fd.unit_base + it.unit) * pstride + slot;
+  double* ev_row = want_eps ? ev_part + ((int64_t)r * pstride + slot) * ev_stride : nullptr;
   if (i == k) {
     if (threadIdx.x == 0) *out = 0.0;
+    if (want_eps) {
+      if (threadIdx.x == 0) eo_part[(fd.unit_base + it.unit) * pstride + slot] = 0.0;
+      for (int a = threadIdx.x; a < fd.nv; a += 256) ev_row[a] = 0.0;
+    }
     return;
   }
+  if (want_eps)
+    for (int a = threadIdx.x; a < fd.nv; a += 256) dv[a] = 0.0;   // first read after barriers
   const InT* __restrict__ t1 = static_cast<const InT*>(fd.t1);
   const InT* __restrict__ ovov = static_cast<const InT*>(fd.ovov);
   const double* __restrict__ eps = fd.eps;
@@ -82,7 +109,7 @@ __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
   const InT* t1k = t1 + (int64_t)k * nv;
   constexpr int E = kOrb * kOrb * kOrb;
 
-  double acc = 0.0;
+  double acc = 0.0, eacc = 0.0;
   for (int64_t o = slot; o < n_orb; o += fd.n_part) {
     int t0, t1b, t2b;
     decode_sorted_triple(o, nb, t0, t1b, t2b);
@@ -157,11 +184,77 @@ __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
                           2.0 * (sw[s][e_abc] + sw[s_cab][e_cab] + sw[s_bca][e_bca]);
       gptr_w(w3)[pos] = CubeT(scale * (rw_t + rz_t) * id);
     }
+    if (want_eps) {
+      // tuples: threads t and t + 256 take slot-0 offsets e = x*64 + y*8 + z
+      // (x = wave + 4 m, so position 0's marginal is a whole-wave sum)
+      const bool eqAB = t0 == t1b, eqBC = t1b == t2b;
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int e = threadIdx.x + 256 * m;
+        const int ox = e >> 6, oy = (e >> 3) & 7, oz = e & 7;
+        const int a = kOrb * t0 + ox, b = kOrb * t1b + oy, c = kOrb * t2b + oz;
+        double q = 0.0;
+        if (!((eqAB && ox < oy) || (eqBC && oy < oz)) && a < nv && b < nv && c < nv) {
+          const int s0 = orbit_slot(0, 1, 2), e0 = orb_lds(ox, oy, oz);
+          const int s1 = orbit_slot(1, 2, 0), e1 = orb_lds(oy, oz, ox);
+          const int s2 = orbit_slot(2, 0, 1), e2 = orb_lds(oz, ox, oy);
+          const int s3 = orbit_slot(0, 2, 1), e3 = orb_lds(ox, oz, oy);
+          const int s4 = orbit_slot(1, 0, 2), e4 = orb_lds(oy, ox, oz);
+          const int s5 = orbit_slot(2, 1, 0), e5 = orb_lds(oz, oy, ox);
+          const double w0 = sw[s0][e0], w1v = sw[s1][e1], w2v = sw[s2][e2];
+          const double w3v = sw[s3][e3], w4 = sw[s4][e4], w5 = sw[s5][e5];
+          const double z0 = sz[s0][e0], z1 = sz[s1][e1], z2 = sz[s2][e2];
+          const double z3 = sz[s3][e3], z4 = sz[s4][e4], z5 = sz[s5][e5];
+          const double wz = w0 * z0 + w1v * z1 + w2v * z2 + w3v * z3 + w4 * z4 + w5 * z5;
+          const double we = w0 + w1v + w2v, wo = w3v + w4 + w5;
+          const double ze = z0 + z1 + z2, zo = z3 + z4 + z5;
+          const double f = 3.0 * wz - 0.5 * (we + wo) * (ze + zo) + 1.5 * (we - wo) * (ze - zo);
+          const int eq = (a == b) + (b == c) + (a == c);
+          const double wt = eq == 0 ? 1.0 : (eq == 1 ? 0.5 : 1.0 / 6.0);
+          const double id = recip(eijk - gptr(ev)[a] - gptr(ev)[b] - gptr(ev)[c]);
+          q = scale * wt * f * id * id;
+        }
+        eacc += q;
+        double s0v = q, s1v = q, s2v = q;
+        for (int off = 32; off > 0; off >>= 1) s0v += __shfl_xor(s0v, off, 64);   // all lanes
+        for (int off = 1; off < 8; off <<= 1) s1v += __shfl_xor(s1v, off, 64);   // same oy
+        for (int off = 8; off < 64; off <<= 1) s2v += __shfl_xor(s2v, off, 64);  // same oz
+        if (lane == 0) tp0[m][wave] = s0v;
+        if ((lane & 7) == 0) tp1[m][wave][lane >> 3] = s1v;
+        if (lane < 8) tp2[m][wave][lane] = s2v;
+      }
+      __syncthreads();
+      if (threadIdx.x < kOrb) {
+        const int o = threadIdx.x;
+        const double p0 = tp0[o >> 2][o & 3];
+        double p1 = 0.0, p2 = 0.0;
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            p1 += tp1[m][w][o];
+            p2 += tp2[m][w][o];
+          }
+        // one thread per offset adds the three positions in order, so equal
+        // blocks (t0 = t1b or t1b = t2b) add into one entry one after another
+        const int a = kOrb * t0 + o, b = kOrb * t1b + o, c = kOrb * t2b + o;
+        if (a < nv) dv[a] += p0;
+        if (b < nv) dv[b] += p1;
+        if (c < nv) dv[c] += p2;
+      }
+    }
     __syncthreads();
   }
   const double s = block_sum_256(acc, red);
   if (threadIdx.x == 0) *out = s;
+  if (want_eps) {
+    const double se = block_sum_256(eacc, red);
+    if (threadIdx.x == 0) eo_part[(fd.unit_base + it.unit) * pstride + slot] = se;
+    for (int a = threadIdx.x; a < nv; a += 256) ev_row[a] = dv[a];
+  }
 }
+
 
 // ---------------------------------------------------------------------------
 // Contractions of G: output-stationary grouped products on the FP64 matrix

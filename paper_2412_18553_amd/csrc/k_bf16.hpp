@@ -407,6 +407,7 @@ __global__ __launch_bounds__(256, 2) void k_build_w_bf16x3(const FragDesc* __res
   }
 
   float* __restrict__ out = arena + it.cube_off + (l2 ? fd.half : 0);
+  const bool blocked = fd.blocked != 0;
 #pragma unroll
   for (int ct = 0; ct < TCW; ++ct) {
     const int col = col0 + wave * 16 * TCW + 16 * ct + r;
@@ -416,7 +417,7 @@ __global__ __launch_bounds__(256, 2) void k_build_w_bf16x3(const FragDesc* __res
       for (int v = 0; v < 4; ++v) {
         const int row = row0 + 16 * rt + SIE_BF16_DROW(v, g);
         if (row < nv && col < nv)
-          gptr_w(out)[((int64_t)blk * nv + row) * nv + col] = acc[rt][ct][v];
+          gptr_w(out)[cube_at(blocked, nv, blk, row, col)] = acc[rt][ct][v];
       }
   }
 }
@@ -547,6 +548,7 @@ __global__ __launch_bounds__(128 * WC, WC == 4 ? 1 : 2) void k_build_w_bf16x3_l(
   }
 
   float* __restrict__ out = arena + it.cube_off + (l2 ? fd.half : 0);
+  const bool blocked = fd.blocked != 0;
 #pragma unroll
   for (int ct = 0; ct < TCW; ++ct) {
     const int col = col0 + (wave % WC) * 16 * TCW + 16 * ct + r;
@@ -556,7 +558,7 @@ __global__ __launch_bounds__(128 * WC, WC == 4 ? 1 : 2) void k_build_w_bf16x3_l(
       for (int v = 0; v < 4; ++v) {
         const int row = row0 + ra + 16 * rt + SIE_BF16_DROW(v, g);
         if (row < nv && col < nv)
-          gptr_w(out)[((int64_t)blk * nv + row) * nv + col] = acc[rt][ct][v];
+          gptr_w(out)[cube_at(blocked, nv, blk, row, col)] = acc[rt][ct][v];
       }
   }
 }

@@ -412,12 +412,12 @@ __device__ __forceinline__ void build_wtile3(const double* t2, const double* ovv
   }
 }
 
-// Store a wave's accumulators into a cube [block][row][col] of n_v^3: element
-// v of lane (g, r) in acc[beta][rt][ct] holds
-// P[blk0 + beta][row0 + 16 rt + 4 v + g][col0 + 16 ct + r].
+// Store a wave's accumulators into a cube (block, row, col) of edge n_v, in
+// the layout cube_at gives: element v of lane (g, r) in acc[beta][rt][ct]
+// holds P[blk0 + beta][row0 + 16 rt + 4 v + g][col0 + 16 ct + r].
 template <int BLK, int TR, int TC>
-__device__ __forceinline__ void store_wtile(double* __restrict__ out, int nv, int blk0, int row0,
-                                            int col0, int r, int g,
+__device__ __forceinline__ void store_wtile(double* __restrict__ out, bool blocked, int nv,
+                                            int blk0, int row0, int col0, int r, int g,
                                             const d4 (&acc)[BLK][TR][TC]) {
 #pragma unroll
   for (int beta = 0; beta < BLK; ++beta) {
@@ -431,7 +431,7 @@ __device__ __forceinline__ void store_wtile(double* __restrict__ out, int nv, in
         for (int v = 0; v < 4; ++v) {
           const int row = row0 + 16 * rt + 4 * v + g;
           if (blk < nv && row < nv && col < nv)
-            gptr_w(out)[((int64_t)blk * nv + row) * nv + col] = acc[beta][rt][ct][v];
+            gptr_w(out)[cube_at(blocked, nv, blk, row, col)] = acc[beta][rt][ct][v];
         }
       }
   }
@@ -521,7 +521,8 @@ __global__ __launch_bounds__(256, BPC) void k_build_w_f64(const FragDesc* __rest
   }
 #undef SIE_WTILE
 
-  store_wtile(arena + it.cube_off + (l2 ? fd.half : 0), nv, blk0, row0, col0, r, g, acc);
+  store_wtile(arena + it.cube_off + (l2 ? fd.half : 0), fd.blocked != 0, nv, blk0, row0, col0,
+              r, g, acc);
 }
 
 // Three-layout build (build_wtile3): partial cubes A, B, C of one tile of
@@ -573,7 +574,7 @@ __global__ __launch_bounds__(256, BPC) void k_build_w3_f64(const FragDesc* __res
     else
       build_wtile3<0, false, BLK, P, S, KS>(t2, ovvv, ooov, i, j, k, fd.no, nv, blk0, p0, s0, np, ns, last, r,
                              g, acc);
-    store_wtile(out, nv, blk0, p0, s0, r, g, acc);
+    store_wtile(out, fd.blocked != 0, nv, blk0, p0, s0, r, g, acc);
   } else {          // shared rows, per-block cols
     d4 acc[BLK][S][P];
     zero_acc(acc);
@@ -588,7 +589,7 @@ __global__ __launch_bounds__(256, BPC) void k_build_w3_f64(const FragDesc* __res
       else SIE_W3(2, false);
     }
 #undef SIE_W3
-    store_wtile(out, nv, blk0, s0, p0, r, g, acc);
+    store_wtile(out, fd.blocked != 0, nv, blk0, s0, p0, r, g, acc);
   }
 }
 
@@ -649,29 +650,34 @@ __device__ __forceinline__ void ld_pair(const T* p, int64_t row, int64_t rs, int
 
 // Element mapping of the epilogue: thread t holds, in every slot s of the
 // orbit, the two elements at in-block offsets (t / 32, (t / 4) % 8,
-// 2 (t % 4) + h), h = 0, 1 (adjacent along c).  Wt of those 12 elements:
-// w1[a][b][c] (+ w2[a][b][c], three layouts) + w3[b][a][c], indices clamped
-// into the cube (c to an even start with PV; the caller masks elements past
-// n_v), all loads issued before any is summed.
-template <bool L3, bool PV, typename CubeT>
+// 2 (t % 4) + h), h = 0, 1 (adjacent along c), i.e. elements 2t and 2t + 1
+// of the slot's 8^3 block of a blocked cube (cube_at).  Wt of those 12
+// elements: w1[a][b][c] (+ w2[a][b][c], three layouts) + w3[b][a][c]; every
+// block of the padded cube exists, so nothing is clamped (the caller masks
+// elements past n_v); all loads are issued before any is summed.
+template <bool L3, typename CubeT>
 __device__ __forceinline__ void epi_load_w(const CubeT* __restrict__ w1,
                                            const CubeT* __restrict__ w2,
-                                           const CubeT* __restrict__ w3, int nv, int t0, int t1b,
+                                           const CubeT* __restrict__ w3, int nb, int t0, int t1b,
                                            int t2b, double (&wreg)[12]) {
+  typedef typename std::conditional<sizeof(CubeT) == 8, d2v, f2v>::type V2;
+  constexpr int kB = kOrb * kOrb * kOrb;
   const int x = threadIdx.x >> 5, y = (threadIdx.x >> 2) & 7, z0 = 2 * (threadIdx.x & 3);
+  const int in_xy = x * 64 + y * 8 + z0, in_yx = y * 64 + x * 8 + z0;
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
     int p0, p1, p2;
     slot_perm(s, p0, p1, p2);
-    const int a = min(kOrb * pick3(p0, t0, t1b, t2b) + x, nv - 1);
-    const int b = min(kOrb * pick3(p1, t0, t1b, t2b) + y, nv - 1);
-    const int c0 = kOrb * pick3(p2, t0, t1b, t2b) + z0;
-    double u[2], v[2], w[2];
-    ld_pair<CubeT, PV>(w1, (int64_t)a * nv + b, nv, c0, nv, u);
-    if (L3) ld_pair<CubeT, PV>(w2, (int64_t)a * nv + b, nv, c0, nv, v);
-    ld_pair<CubeT, PV>(w3, (int64_t)b * nv + a, nv, c0, nv, w);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) wreg[2 * s + h] = u[h] + (L3 ? v[h] : 0.0) + w[h];
+    const int P0 = pick3(p0, t0, t1b, t2b), P1 = pick3(p1, t0, t1b, t2b);
+    const int P2 = pick3(p2, t0, t1b, t2b);
+    const int64_t o1 = ((int64_t(P0) * nb + P1) * nb + P2) * kB + in_xy;
+    const int64_t o3 = ((int64_t(P1) * nb + P0) * nb + P2) * kB + in_yx;
+    const V2 u = *(const SIE_GLOBAL V2*)(gptr(w1) + o1);
+    V2 v{};
+    if (L3) v = *(const SIE_GLOBAL V2*)(gptr(w2) + o1);
+    const V2 w = *(const SIE_GLOBAL V2*)(gptr(w3) + o3);
+    wreg[2 * s] = (double)u.x + (L3 ? (double)v.x : 0.0) + (double)w.x;
+    wreg[2 * s + 1] = (double)u.y + (L3 ? (double)v.y : 0.0) + (double)w.y;
   }
 }
 
@@ -748,13 +754,8 @@ __global__ __launch_bounds__(256, sizeof(CubeT) == 4 ? 5 : 4) void k_epilogue(co
     // load of the orbit is issued before any is used, then V-tilde is added
     // and Z = Wt + V-tilde goes to LDS
     double wreg[12];
-    if (fd.epv) {
-      if (l3) epi_load_w<true, true>(w1, w2, w3, nv, t0, t1b, t2b, wreg);
-      else epi_load_w<false, true>(w1, w2, w3, nv, t0, t1b, t2b, wreg);
-    } else {
-      if (l3) epi_load_w<true, false>(w1, w2, w3, nv, t0, t1b, t2b, wreg);
-      else epi_load_w<false, false>(w1, w2, w3, nv, t0, t1b, t2b, wreg);
-    }
+    if (l3) epi_load_w<true>(w1, w2, w3, nb, t0, t1b, t2b, wreg);
+    else epi_load_w<false>(w1, w2, w3, nb, t0, t1b, t2b, wreg);
     __syncthreads();   // sv filled
     const int x = threadIdx.x >> 5, y = (threadIdx.x >> 2) & 7, z0 = 2 * (threadIdx.x & 3);
 #pragma unroll

@@ -85,10 +85,18 @@ struct AdjArgs {
 // G and H over the round's partial cubes (and the unit energy partials).
 void launch_hat_f64(unsigned grid, hipStream_t s, const FragDesc* desc, const Item* items,
                     int n_items, double* arena, double* partials, int pstride,
-                    const double* grad_e);
+                    const double* grad_e, double* eo_part, double* ev_part, int ev_stride);
 void launch_hat_f32(unsigned grid, hipStream_t s, const FragDesc* desc, const Item* items,
                     int n_items, float* arena, double* partials, int pstride,
-                    const double* grad_e);
+                    const double* grad_e, double* eo_part, double* ev_part, int ev_stride);
+// Orbital-energy gradient reductions (k_adjoint.hpp): per round, the
+// work-group rows into per-item rows and those into g_ev; after the last
+// round, the per-unit sums and g_eo.
+void launch_eps_vir(hipStream_t s, const FragDesc* desc, const Item* items, int n_items,
+                    int n_frag, const double* ev_part, int pstride, int ev_stride,
+                    double* ev_item);
+void launch_eps_occ(hipStream_t s, const FragDesc* desc, int n_frag, int64_t max_units,
+                    int max_no, const double* eo_part, int pstride, double* eo_units);
 // Every G and H contraction of one round (L: kAdjClasses entries).
 void launch_adj_f64(const AdjLaunch* L, const AdjArgs& a, const double* arena, hipStream_t s);
 void launch_adj_f32(const AdjLaunch* L, const AdjArgs& a, const float* arena, hipStream_t s);

@@ -81,7 +81,10 @@ int sie_mfma_peak(int kind, int iters, int blocks, double* tflops) {
       hipLaunchKernelGGL(k_peak_bf16, dim3(blocks), dim3(256), 0, s, static_cast<float*>(out), it);
   };
   if (err == hipSuccess) {
-    launch(iters / 10 + 1);   // warm-up: clocks up, code loaded
+    // warm-up of the same length as the timed launch: the clocks take tens
+    // of milliseconds of sustained load to settle (a short warm-up measured
+    // 42 TFLOP/s float64 where a long one gives 50)
+    launch(iters);
     err = hipGetLastError();
   }
   if (err == hipSuccess) err = hipEventRecord(e0, s);

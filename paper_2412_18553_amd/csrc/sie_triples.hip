@@ -149,12 +149,16 @@ struct Plan {
   size_t off_desc = 0, off_eps = 0, off_units = 0, off_part = 0, off_efrag = 0, off_items = 0;
   size_t off_flags = 0;      // non-finite scan flags: 5 per fragment
   size_t off_split = 0, off_adj = 0, off_t1 = 0, off_parts = 0, off_arena = 0;
+  // orbital-energy gradient (backward only): occupied partials per (unit,
+  // slot) and per unit; virtual rows per (round item, slot) and per item
+  size_t off_eo = 0, off_eou = 0, off_evp = 0, off_evi = 0;
   int nv_max = 1;            // largest n_vir (row stride of the t1 partials)
   size_t adj_recs = 0;       // bound on the adjoint records (= groups) of all rounds
   size_t part_elems = 0;     // bound on the partial-slice elements of a summed-block class
   size_t fixed_bytes = 0;    // everything before the arena
   int cubes = 2;             // cubes per unit in flight (backward: G, H and G transposed)
   bool pair = false;         // pair units build one layout into one cube (energy only)
+  bool blocked = false;      // 8^3-blocked cubes (energy only; see sie::cube_at)
   size_t min_arena = 0;      // the largest cube set of any fragment
   size_t all_arena = 0;      // every unit's cube set at once
 };
@@ -162,6 +166,9 @@ struct Plan {
 // Records per unit of the backward pass: 6 + 6 per-block terms, 6 + 6 summed
 // terms per block group of kARB virtuals, 3 + 3 H terms.
 constexpr int kT1Batch = 4096;    // t1 records per partial-sum batch (backward)
+// Items per backward round at most: bounds the per-work-group rows of the
+// virtual orbital-energy gradient (items x epilogue slots x n_vir).
+constexpr size_t kGradRoundItems = 256;
 
 size_t adj_recs_per_unit(int nv) {
   return size_t(18) + size_t(12) * size_t((nv + sie::kARB - 1) / sie::kARB);
@@ -175,6 +182,7 @@ Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad =
   Plan p;
   p.cubes = grad ? 3 : 2;
   p.pair = !grad;
+  p.blocked = !grad;
   p.split = prec == SIE_SPLIT_BF16;
   size_t eps_n = 0, split_bytes = 0;
   for (int x = 0; x < n; ++x) {
@@ -188,6 +196,9 @@ Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad =
     } else {
       fp.variant = split_shape(fp.nv);
     }
+    if (p.blocked)   // the blocked cube pads its edge to a multiple of the orbit block
+      fp.half_bytes = align_up((p.split ? sizeof(float) : sizeof(double)) *
+                                   size_t(sie::cube_blocked_elems(fp.nv)), 256);
     fp.cubes = grad ? 3 : fp.lay3 ? 3 : 2;
     fp.cubes_pair = grad ? 3 : fp.lay3 ? 2 : 1;
     p.total_units += fp.n_units;
@@ -235,6 +246,17 @@ Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad =
   if (grad) off = align_up(off + sizeof(double) * size_t(kT1Batch) * size_t(p.nv_max), 256);
   p.off_parts = off;
   if (grad) off = align_up(off + sizeof(double) * p.part_elems, 256);
+  if (grad) {
+    p.off_eo = off;
+    off = align_up(off + sizeof(double) * size_t(p.total_units) * size_t(p.pstride), 256);
+    p.off_eou = off;
+    off = align_up(off + sizeof(double) * size_t(p.total_units), 256);
+    p.off_evp = off;
+    off = align_up(off + sizeof(double) * kGradRoundItems * size_t(p.pstride) *
+                             size_t(p.nv_max), 256);
+    p.off_evi = off;
+    off = align_up(off + sizeof(double) * kGradRoundItems * size_t(p.nv_max), 256);
+  }
   p.off_arena = off;
   p.fixed_bytes = off;
   return p;
@@ -536,6 +558,7 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
     d.variant = fp.variant;
     d.pair = pl.pair ? 1 : 0;
     d.lay3 = fp.lay3 ? 1 : 0;
+    d.blocked = pl.blocked ? 1 : 0;
     d.tiles = pl.split ? sie::split_tiles(fp.nv, d.variant)
                        : sie::wbuild_tiles(fp.nv, d.variant);
     d.vS = d.tS = d.tT = d.oT = nullptr;
@@ -544,6 +567,8 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
     d.g_ovvv = grads ? grads[x].ovvv : nullptr;
     d.g_ooov = grads ? grads[x].ooov : nullptr;
     d.g_ovov = grads ? grads[x].ovov : nullptr;
+    d.g_eo = grads ? grads[x].eps_occ : nullptr;
+    d.g_ev = grads ? grads[x].eps_vir : nullptr;
     if (pl.split) {
       const size_t o = size_t(fp.no), v = size_t(fp.nv);
       d.vS = reinterpret_cast<const sie::u4v*>(dev(split_off));
@@ -599,7 +624,8 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
     for (size_t r = 0; r < order.size(); ++r) {
       const FragPlan& fp = pl.frags[size_t(order[r].frag)];
       const size_t pair = size_t(order[r].one ? fp.cubes_pair : fp.cubes) * fp.half_bytes;
-      if (r == 0 || used + pair > arena_bytes) {
+      const bool full = grads && r > 0 && r - round_begin.back() >= kGradRoundItems;
+      if (r == 0 || used + pair > arena_bytes || full) {
         round_begin.push_back(r);
         used = 0;
         blk = 0;
@@ -938,17 +964,22 @@ void adj_round_lists(const Tables& T, size_t r0, size_t r1, std::vector<sie::Adj
 }
 
 // G / H and the gradient contractions of one backward round.
+// eo_part NULL: no orbital-energy gradient is wanted.
 void backward_round(bool split, const std::array<AdjLaunch, sie::kAdjClasses>& L, hipStream_t s,
                     const sie::AdjArgs& a, void* arena, double* d_part, int pstride,
-                    const double* grad_e, unsigned n_epi) {
+                    const double* grad_e, unsigned n_epi, int n_frag, double* eo_part,
+                    double* ev_part, double* ev_item, int ev_stride) {
   {
     ProfScope ps(s, 1);
     if (split)
       sie::launch_hat_f32(n_epi, s, a.desc, a.items, a.n_items, static_cast<float*>(arena),
-                          d_part, pstride, grad_e);
+                          d_part, pstride, grad_e, eo_part, ev_part, ev_stride);
     else
       sie::launch_hat_f64(n_epi, s, a.desc, a.items, a.n_items, static_cast<double*>(arena),
-                          d_part, pstride, grad_e);
+                          d_part, pstride, grad_e, eo_part, ev_part, ev_stride);
+    if (eo_part)
+      sie::launch_eps_vir(s, a.desc, a.items, a.n_items, n_frag, ev_part, pstride, ev_stride,
+                          ev_item);
   }
   ProfScope ps(s, 4);
   if (split)
@@ -968,7 +999,7 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
     sie_status st = check_fragment(&frags[x], p, who);
     if (st != SIE_OK) return st;
     const sie_fragment_grad& g = grads[x];
-    for (const double* q : {g.t1, g.t2, g.ovvv, g.ooov, g.ovov})
+    for (const double* q : {g.t1, g.t2, g.ovvv, g.ooov, g.ovov, g.eps_occ, g.eps_vir})
       if (q && !aligned(q, sizeof(double)))
         return fail(SIE_ERR_INVALID_ARG, w + ": a gradient array is misaligned");
   }
@@ -1060,8 +1091,14 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
       fill(grads[x].ovvv, o * v * v * v);
       fill(grads[x].ooov, o * o * o * v);
       fill(grads[x].ovov, o * v * o * v);
+      fill(grads[x].eps_vir, v);
     }
   }
+  bool want_eps = false;
+  for (int x = 0; x < n; ++x) want_eps |= grads[x].eps_occ || grads[x].eps_vir;
+  double* eo_part = want_eps ? reinterpret_cast<double*>(dev(pl.off_eo)) : nullptr;
+  double* ev_part = reinterpret_cast<double*>(dev(pl.off_evp));
+  double* ev_item = reinterpret_cast<double*>(dev(pl.off_evi));
   st = hip_check(hipGetLastError(), "launch gradient fill");
   if (st != SIE_OK) return st;
 
@@ -1084,7 +1121,7 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
     sie::AdjArgs aa{d_desc, ri, cnt, d_groups, d_recs, d_slices, d_parts, t1_part, pl.nv_max,
                     kT1Batch};
     backward_round(pl.split, launches[q], s, aa, dev(pl.off_arena), d_part, pl.pstride, grad_e,
-                   unsigned(T.items[r1 - 1].part_end));
+                   unsigned(T.items[r1 - 1].part_end), n, eo_part, ev_part, ev_item, pl.nv_max);
     st = hip_check(hipGetLastError(), "launch backward kernels");
     if (st != SIE_OK) return st;
   }
@@ -1112,6 +1149,12 @@ sie_status run_backward(const sie_fragment* frags, int n, sie_precision p, const
     sie::launch_unit_energy(dim3(unsigned((max_units + 255) / 256), unsigned(n)), s, d_desc,
                             d_part, pl.pstride, d_units);
     sie::launch_frag_energy(unsigned(n), s, d_desc, d_units, d_efrag);
+    if (want_eps) {
+      int max_no = 1;
+      for (const auto& fp : pl.frags) max_no = fp.no > max_no ? fp.no : max_no;
+      sie::launch_eps_occ(s, d_desc, n, max_units, max_no, eo_part, pl.pstride,
+                          reinterpret_cast<double*>(dev(pl.off_eou)));
+    }
   }
   return hip_check(hipGetLastError(), "launch gradient symmetrization and reductions");
 }

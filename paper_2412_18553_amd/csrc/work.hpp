@@ -10,6 +10,7 @@
 #pragma once
 
 #include "device_common.hpp"
+#include "shapes.hpp"
 
 namespace sie {
 
@@ -36,6 +37,8 @@ struct FragDesc {
                           // first layout's cube (unit_triple); 0: both, as the adjoint needs
   int lay3;               // float64 energy: three-layout build (k_build_w3_f64), three
                           // partial cubes per unit (two for a pair unit)
+  int blocked;            // partial cubes in 8^3-blocked order (energy), else row-major
+                          // (the adjoint's cubes); see cube_at
   int n_part;             // epilogue partial slots per unit
   int64_t unit_base;      // first entry of this fragment in the per-unit arrays
   int64_t half;           // elements per partial cube (aligned)
@@ -46,7 +49,31 @@ struct FragDesc {
   double* g_ovvv;
   double* g_ooov;
   double* g_ovov;
+  double* g_eo;           // [no]  orbital-energy gradients (backward only)
+  double* g_ev;           // [nv]
 };
+
+// Element offset of (x, y, z) in a partial cube of edge n_v.  Energy
+// evaluations store their cubes 8^3-blocked: the cube is cut into blocks of
+// kOrb^3 elements (nb = ceil(n_v / kOrb) a side, the last ones padded), each
+// block one contiguous run of 512 elements in (x, y, z) order, the blocks in
+// (x, y, z) order too.  An orbit block of the epilogue is then whole 128-byte
+// lines: with row-major cubes each of its 8-element rows pulled a full line
+// from HBM of which it used a quarter (float32) or a half (float64).  The
+// adjoint keeps row-major cubes ([x][y][z], n_v a side), which its
+// contractions read with unit stride along rows.
+__host__ __device__ __forceinline__ int64_t cube_at(bool blocked, int nv, int x, int y, int z) {
+  if (!blocked) return ((int64_t)x * nv + y) * nv + z;
+  const int nb = (nv + kOrb - 1) / kOrb;
+  const int64_t blk = ((int64_t)(x >> 3) * nb + (y >> 3)) * nb + (z >> 3);
+  return blk * (kOrb * kOrb * kOrb) + ((x & 7) << 6) + ((y & 7) << 3) + (z & 7);
+}
+
+// Elements of one blocked cube (nb^3 blocks of 512).
+__host__ __device__ __forceinline__ int64_t cube_blocked_elems(int nv) {
+  const int64_t nb = (nv + kOrb - 1) / kOrb;
+  return nb * nb * nb * (kOrb * kOrb * kOrb);
+}
 
 struct Item {
   int frag;               // fragment index

@@ -48,7 +48,7 @@ def test_every_declared_symbol_exported(lib):
 
 
 def test_version_and_counts(lib):
-    assert lib.sie_abi_version() == 1
+    assert lib.sie_abi_version() == 2
     assert lib.sie_occupied_triples(24) == 2600
     assert lib.sie_occupied_triples(1) == 1
 
@@ -63,9 +63,11 @@ def test_valid_workspace_query(lib):
     f = frag(keep=keep)
     n = lib.sie_triples_workspace_size(ctypes.byref(f), 1, _lib.SIE_FP64, 0)
     assert n >= 10 ** 3 * 8
-    # a cap forces fewer units per launch but never below one cube
-    small = lib.sie_triples_workspace_size(ctypes.byref(f), 1, _lib.SIE_FP64, 20000)
-    assert 0 < small <= 20000
+    # a cap forces fewer units per launch but never below one unit's cubes
+    # (8^3-blocked: a 10-virtual cube pads to 16^3 elements, 32 KiB in float64)
+    small = lib.sie_triples_workspace_size(ctypes.byref(f), 1, _lib.SIE_FP64, 200000)
+    assert 0 < small <= 200000
+    assert small < n
     assert lib.sie_triples_workspace_size(ctypes.byref(f), 1, _lib.SIE_FP64, 100) == 0
 
 

@@ -13,7 +13,12 @@ G3  Euler identities of the polynomial structure: sum t1 dE/dt1 = E_WV =
 G4  torch float64 automatic differentiation of the plain definition
 G5  single-orbit differences: perturbing one symmetry orbit of an entry moves
     E by |orbit| * (symmetrized gradient entry)
-M   planted mistakes (a flipped sign, a wrong factor) fail G1
+G6  the orbital-energy gradient: Richardson-extrapolated central differences
+    of the spin-orbital energy along random directions of eps_occ and eps_vir;
+    homogeneity (E is of degree -1 in the orbital energies, so
+    sum_p eps_p dE/deps_p = -E); invariance under a common shift of all
+    orbital energies (sum_p dE/deps_p = 0); torch autograd (G4)
+M   planted mistakes (a flipped sign, a wrong factor) fail G1 or G6
 """
 
 import numpy as np
@@ -108,6 +113,8 @@ def test_g4_torch_autograd():
                 + y.permute(0, 2, 1, 3, 5, 4) + y.permute(2, 1, 0, 5, 4, 3)
                 + y.permute(1, 0, 2, 4, 3, 5))
 
+    eo.requires_grad_(True)
+    ev.requires_grad_(True)
     wt, vt = perm_sum(x), 0.5 * perm_sum(u)
     d = (eo[:, None, None, None, None, None] + eo[None, :, None, None, None, None]
          + eo[None, None, :, None, None, None] - ev[None, None, None, :, None, None]
@@ -121,6 +128,10 @@ def test_g4_torch_autograd():
     e.backward()
     for name, leaf in zip(NAMES, leaves):
         ref = symmetrize_direction(name, leaf.grad.numpy())
+        err = np.abs(ref - g[name]).max() / np.abs(ref).max()
+        assert err < 1e-12, (name, err)
+    for name, leaf in (("eps_occ", eo), ("eps_vir", ev)):
+        ref = leaf.grad.numpy()
         err = np.abs(ref - g[name]).max() / np.abs(ref).max()
         assert err < 1e-12, (name, err)
 
@@ -163,3 +174,57 @@ def test_planted_mistakes_fail_g1(mistake):
         bad["t2"] = g0["t2"]
     ok, worst = check_fd(spin_orbital_triples, args, bad, 31, 1e-9)
     assert not ok, worst
+
+
+# ---------------------------------------------------------------- G6
+def eps_fd(energy, args, which, v, h):
+    """Richardson-extrapolated central difference of E along v in eps_occ
+    (which = 0) or eps_vir (which = 1): (4 C(h/2) - C(h)) / 3, error O(h^4)."""
+    def central(step):
+        plus, minus = list(args), list(args)
+        plus[which] = args[which] + step * v
+        minus[which] = args[which] - step * v
+        return (energy(*plus) - energy(*minus)) / (2.0 * step)
+    return (4.0 * central(h / 2) - central(h)) / 3.0
+
+
+@pytest.mark.parametrize("o,v,seed", [(2, 3, 41), (3, 4, 42), (2, 5, 43)])
+def test_g6_eps_fd_of_spin_orbital_energy(o, v, seed):
+    args = random_symmetric_inputs(o, v, seed)
+    _, _, _, g = energy_gradient(*args)
+    rng = np.random.default_rng(seed)
+    for which, name in ((0, "eps_occ"), (1, "eps_vir")):
+        d = rng.normal(size=args[which].shape)
+        fd = eps_fd(spin_orbital_triples, args, which, d, 1e-3)
+        an = float(np.sum(g[name] * d))
+        assert abs(an - fd) < 1e-9 * abs(fd), (name, an, fd)
+
+
+@pytest.mark.parametrize("o,v,naux,seed", [(4, 12, 30, (9, 7)), (5, 20, 60, (9, 8))])
+def test_g6_eps_homogeneity_and_shift(o, v, naux, seed):
+    f = make_fragment(o, v, naux, seed)
+    args = f.arrays()
+    e, _, _, g = energy_gradient(*args)
+    euler = float(np.dot(args[0], g["eps_occ"]) + np.dot(args[1], g["eps_vir"]))
+    assert abs(euler + e) < 1e-12 * abs(e), (euler, e)
+    total = float(g["eps_occ"].sum() + g["eps_vir"].sum())
+    scale = float(np.abs(g["eps_occ"]).sum() + np.abs(g["eps_vir"]).sum())
+    assert abs(total) < 1e-13 * scale, (total, scale)
+    # and against central differences of the literal energy
+    rng = np.random.default_rng(3)
+    d = rng.normal(size=args[1].shape)
+    fd = eps_fd(oracle.energy_literal_vectorized, args, 1, d, 1e-3)
+    assert abs(float(np.sum(g["eps_vir"] * d)) - fd) < 1e-9 * abs(fd)
+
+
+@pytest.mark.parametrize("mistake", ["vir_sign", "occ_count"])
+def test_planted_eps_mistakes_fail_g6(mistake):
+    args = random_symmetric_inputs(3, 4, 44)
+    _, _, _, g = energy_gradient(*args)
+    rng = np.random.default_rng(44)
+    which = 1 if mistake == "vir_sign" else 0
+    name = ("eps_occ", "eps_vir")[which]
+    bad = -g[name] if mistake == "vir_sign" else g[name] / 3.0   # one index of three
+    d = rng.normal(size=args[which].shape)
+    fd = eps_fd(spin_orbital_triples, args, which, d, 1e-3)
+    assert abs(float(np.sum(bad * d)) - fd) > 1e-6 * abs(fd)
