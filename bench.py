@@ -30,6 +30,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -38,7 +40,7 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak (published)
 CHEM_SCALE = 2.0 ** -9            # integrals and t2 of the chemically scaled copy
 
 DEFAULT_WORKLOAD = {"fp64": "o24v200", "split": "o32v320", "batched": "batch16",
-                    "backward": "o16v120", "peak": None}
+                    "backward": "o16v120", "peak": None, "mp2": "mp2_o64v512"}
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
@@ -419,6 +421,62 @@ def run_batched(args, result, name):
     result["kernel_ms_per_step"] = {k: round(t / args.steps, 3) for k, (t, _) in prof.items()}
 
 
+def run_mp2(args, result, name):
+    """MP2 energy and 1-RDM blocks of one cluster from DF factors (the
+    embedding workflow's BNO step).  A step is one sie_mp2 call with the
+    density (amplitudes kept in the workspace).  The energy-only call, which
+    runs the pair kernel alone, is timed separately for its roofline."""
+    import torch
+    import paper_2412_18553_amd as sie
+    from synth import WORKLOADS, mp2_inputs
+    from synth.fragments import SEED_ROOT
+    w = WORKLOADS[name]
+    o, v, na = w["n_occ"], w["n_vir"], w["n_aux"]
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    eo, ev, l = mp2_inputs(o, v, na, (SEED_ROOT, w["stream"], 0))
+    lt = torch.from_numpy(l).to(dev)
+    del l
+    log(f"# workload {name}: factors built in {time.perf_counter() - t0:.1f} s")
+    f_pair = 2.0 * o * o * v * v * na          # (ia|jb) for all ordered pairs
+    f_dens = 2.0 * o * o * v ** 3 + 2.0 * o ** 3 * v * v
+    for _ in range(args.warmup):
+        sie.mp2(eo, ev, lt, want_density=True)
+        torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(args.steps):
+        out = sie.mp2(eo, ev, lt, want_density=True)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / args.steps
+    ws = torch.empty(sie._lib.load().sie_mp2_workspace_size(
+        ctypes.byref(sie._lib.SieMp2Input(o, v, na, eo.ctypes.data, ev.ctypes.data,
+                                          lt.data_ptr())), 0), dtype=torch.uint8, device=dev)
+    sie.mp2(eo, ev, lt, workspace=ws)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        sie.mp2(eo, ev, lt, workspace=ws)
+    stop.record()
+    torch.cuda.synchronize()
+    ms_pair = start.elapsed_time(stop) / args.steps
+    achieved = f_pair / (ms_pair * 1e-3) / 1e12
+    gamma_oo = out["gamma_oo"].cpu().numpy()
+    gamma_vv = out["gamma_vv"].cpu().numpy()
+    result.update(metric="MP2 energy + 1-RDM TFLOP/s", value=round((f_pair + f_dens) / (ms * 1e-3) / 1e12, 3),
+                  dtype="f64",
+                  config={"workload": f"cluster MP2 n_occ={o} n_vir={v} n_aux={na}, DF factors",
+                          "precision": "fp64", "outputs": "E_MP2, gamma_oo, gamma_vv"},
+                  ms_per_step=round(ms, 3), energy=float(out["energy"].item()),
+                  electron_count=float(np.trace(gamma_oo) + np.trace(gamma_vv)),
+                  roofline={"bound": "mfma", "kernel": "k_mp2_pair", "achieved": round(achieved, 3),
+                            "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                            "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4), "traffic": None,
+                            "avg_launch_ms": round(ms_pair, 4),
+                            "work": "algorithmic 2 n_o^2 n_v^2 n_aux (energy-only call)"})
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -454,6 +512,8 @@ def main():
         run_split(args, result, name)
     elif mode in ("fp64", "backward"):
         run_single(args, result, name, mode)
+    elif mode == "mp2":
+        run_mp2(args, result, name)
     else:
         run_batched(args, result, name)
     print(json.dumps(result), flush=True)

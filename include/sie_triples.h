@@ -230,6 +230,48 @@ sie_status sie_triples_backward(const sie_fragment* frags, int32_t n, sie_precis
                                 const double* grad_e, const sie_fragment_grad* grads,
                                 double* e_frag, void* ws, size_t ws_bytes, void* stream);
 
+/* MP2 of one cluster or subspace (the paper's embedding workflow, SI section
+ * "Systematically Improvable Quantum Embedding Workflow"): amplitudes
+ *   t_ij^ab = -(ia|jb) / (e_a + e_b - e_i - e_j),
+ * the energy E = sum_ijab t_ij^ab [2 (ia|jb) - (ib|ja)], and the occupied and
+ * virtual blocks of the MP2 one-particle density matrix
+ *   gamma_ij = 2 delta_ij - 2 sum_k sum_ab t_ik^ab (2 t_jk^ab - t_jk^ba),
+ *   gamma_ab = 2 sum_ij sum_c t_ij^ac (2 t_ij^bc - t_ij^cb)
+ * (the occupied-virtual block is zero), with the integrals from
+ * density-fitting factors, (ia|jb) = sum_P l_ov[i][a][P] l_ov[j][b][P]. */
+typedef struct {
+  int32_t n_occ;             /* 1 <= n_occ <= SIE_MAX_OCC                      */
+  int32_t n_vir;             /* 1 <= n_vir <= SIE_MAX_VIR                      */
+  int32_t n_aux;             /* >= 1                                          */
+  const double* eps_occ;     /* host [n_occ]                                   */
+  const double* eps_vir;     /* host [n_vir], max(eps_occ) < min(eps_vir)      */
+  const double* l_ov;        /* device [n_occ][n_vir][n_aux], float64          */
+} sie_mp2_input;
+
+/* Workspace bytes of sie_mp2 (energy partial sums; with want_density the
+ * amplitudes, unless the caller stores them, and the partial slices of the
+ * density products).  0 for invalid arguments. */
+size_t sie_mp2_workspace_size(const sie_mp2_input* in, int32_t want_density);
+
+/* MP2 energy and, optionally, amplitudes and density blocks.
+ *   e_out     device float64 [1]: E
+ *   t2        device float64 [n_occ][n_occ][n_vir][n_vir] or NULL: t_ij^ab
+ *   gamma_oo  device float64 [n_occ][n_occ] or NULL
+ *   gamma_vv  device float64 [n_vir][n_vir] or NULL
+ *   ws        >= sie_mp2_workspace_size(in, gamma_oo || gamma_vv) bytes
+ *             (a caller that passes t2 may use less: the amplitudes are then
+ *             kept there)
+ * The (ia|jb) products run on the float64 matrix cores, one work-group per
+ * occupied pair i >= j and 64 x 64 virtual tile pair, forming (ia|jb) and
+ * (ib|ja) together so that the energy needs no second pass; the density
+ * blocks are batched products over the stored amplitudes.  Deterministic
+ * (fixed-order sums); the orbital energies are uploaded with pageable copies
+ * that complete before the call returns; everything else is enqueued on
+ * `stream`.  At most 361 occupied orbitals (65535 occupied pairs per
+ * launch), else SIE_ERR_UNSUPPORTED. */
+sie_status sie_mp2(const sie_mp2_input* in, double* e_out, double* t2, double* gamma_oo,
+                   double* gamma_vv, void* ws, size_t ws_bytes, void* stream);
+
 /* Kernel timing (diagnostics).  While enabled on the calling thread, every
  * launch made by the entry points above is bracketed by two HIP events on the
  * launch stream.  sie_profile_collect waits for those events, writes the

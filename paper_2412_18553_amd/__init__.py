@@ -311,6 +311,41 @@ def triples_energy(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, *, precision="fp6
     return (e[0], tri) if return_triples else e[0]
 
 
+def mp2(eps_occ, eps_vir, l_ov: torch.Tensor, *, want_t2: bool = False,
+        want_density: bool = False, workspace: torch.Tensor | None = None):
+    """MP2 energy of one cluster from density-fitting factors l_ov [n_occ][n_vir]
+    [n_aux] (float64 CUDA tensor), enqueued on the current stream.  Returns
+    {"energy": float64 [1]} plus "t2" [o][o][v][v] with want_t2 and
+    "gamma_oo" [o][o], "gamma_vv" [v][v] with want_density (device
+    tensors, no synchronisation); see sie_mp2 in the C header."""
+    lib = _lib.load()
+    eo, ev = _host_f64(eps_occ, "eps_occ"), _host_f64(eps_vir, "eps_vir")
+    o, v = eo.shape[0], ev.shape[0]
+    if (not isinstance(l_ov, torch.Tensor) or not l_ov.is_cuda or l_ov.dtype != torch.float64
+            or l_ov.dim() != 3 or tuple(l_ov.shape[:2]) != (o, v) or not l_ov.is_contiguous()):
+        raise ValueError("l_ov must be a contiguous float64 CUDA tensor [n_occ][n_vir][n_aux]")
+    dev = l_ov.device
+    desc = _lib.SieMp2Input(o, v, int(l_ov.shape[2]), eo.ctypes.data, ev.ctypes.data,
+                            l_ov.data_ptr())
+    out = {"energy": torch.empty(1, dtype=torch.float64, device=dev)}
+    if want_t2:
+        out["t2"] = torch.empty((o, o, v, v), dtype=torch.float64, device=dev)
+    if want_density:
+        out["gamma_oo"] = torch.empty((o, o), dtype=torch.float64, device=dev)
+        out["gamma_vv"] = torch.empty((v, v), dtype=torch.float64, device=dev)
+    if workspace is None:
+        n = lib.sie_mp2_workspace_size(ctypes.byref(desc), 1 if want_density else 0)
+        if n == 0:
+            raise SieError(_lib.SIE_ERR_INVALID_ARG, _lib.last_error())
+        workspace = torch.empty(n, dtype=torch.uint8, device=dev)
+    ptr = lambda k: out[k].data_ptr() if k in out else None  # noqa: E731
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    st = lib.sie_mp2(ctypes.byref(desc), ptr("energy"), ptr("t2"), ptr("gamma_oo"),
+                     ptr("gamma_vv"), workspace.data_ptr(), workspace.numel(), stream)
+    _lib.check(st)
+    return out
+
+
 def tile_variants():
     """Tile shapes of the float64 build: [(blocks/wave, row tiles, col tiles, WGs/CU,
     wave rows, wave cols, layouts, k-steps per chunk)] (see sie_tile_variant_shape)."""

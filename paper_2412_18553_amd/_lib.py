@@ -34,7 +34,8 @@ EXPORTED = ["sie_abi_version", "sie_last_error", "sie_occupied_triples",
             "sie_triples_backward_workspace_size", "sie_triples_backward",
             "sie_tile_variants", "sie_tile_variant_shape", "sie_tile_variant_of",
             "sie_set_tile_table", "sie_split_shape_of", "sie_set_split_shape",
-            "sie_profile_enable", "sie_profile_collect", "sie_set_check_finite"]
+            "sie_profile_enable", "sie_profile_collect", "sie_set_check_finite",
+            "sie_mp2_workspace_size", "sie_mp2"]
 PROF_CLASSES = ("w_build", "epilogue", "reduce", "split", "grad")
 
 
@@ -56,6 +57,12 @@ class SieFragment(ctypes.Structure):
 class SieFragmentGrad(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p)
                 for name in ("t1", "t2", "ovvv", "ooov", "ovov", "eps_occ", "eps_vir")]
+
+
+class SieMp2Input(ctypes.Structure):
+    _fields_ = [("n_occ", ctypes.c_int32), ("n_vir", ctypes.c_int32), ("n_aux", ctypes.c_int32),
+                ("eps_occ", ctypes.c_void_p), ("eps_vir", ctypes.c_void_p),
+                ("l_ov", ctypes.c_void_p)]
 
 
 class SieError(RuntimeError):
@@ -125,6 +132,12 @@ def load() -> ctypes.CDLL:
     lib.sie_profile_collect.restype = ctypes.c_int
     lib.sie_profile_collect.argtypes = [ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64)]
+    lib.sie_mp2_workspace_size.restype = ctypes.c_size_t
+    lib.sie_mp2_workspace_size.argtypes = [ctypes.POINTER(SieMp2Input), ctypes.c_int32]
+    lib.sie_mp2.restype = ctypes.c_int
+    lib.sie_mp2.argtypes = [ctypes.POINTER(SieMp2Input), ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                            ctypes.c_void_p]
     _lib = lib
     return lib
 

@@ -312,6 +312,15 @@ sie_status check_fragment(const sie_fragment* f, sie_precision prec, const char*
   return SIE_OK;
 }
 
+}  // namespace
+
+namespace sie {
+// Error reporting for the other host translation units (sie_mp2.hip).
+sie_status set_error(sie_status s, const std::string& msg) { return fail(s, msg); }
+}  // namespace sie
+
+namespace {
+
 sie_status hip_check(hipError_t e, const char* what) {
   if (e == hipSuccess) return SIE_OK;
   return fail(SIE_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));

@@ -11,5 +11,7 @@ from .fragments import (  # noqa: F401
     make_fragment,
     workload_fragment,
     batch_shapes,
+    ov_factors,
+    mp2_inputs,
     WORKLOADS,
 )

@@ -119,6 +119,35 @@ def make_fragment(n_occ: int, n_vir: int, n_aux: int, seed, *,
                     np.ascontiguousarray(ovov))
 
 
+def ov_factors(n_occ: int, n_vir: int, n_aux: int, seed, *, b_std: float = 0.05,
+               b_scale: float = 1.0) -> np.ndarray:
+    """The occupied-virtual density-fitting factors L[i, a, P] = B^P_{i, a}
+    that `make_fragment` draws for the same arguments (same random stream),
+    so that (ia|jb) = sum_P L[i, a, P] L[j, b, P] is its ovov block up to the
+    rounding of the contraction."""
+    rng = np.random.default_rng(np.random.SeedSequence([int(s) for s in seed]))
+    rng.uniform(-1.5, -0.3, n_occ)
+    rng.uniform(0.1, 3.0, n_vir)
+    n = n_occ + n_vir
+    g = rng.normal(0.0, b_std, size=(n_aux, n, n))
+    # the occupied-virtual block lies in the drawn upper triangle (i < n_occ <= p)
+    out = np.ascontiguousarray(g[:, :n_occ, n_occ:].transpose(1, 2, 0))
+    del g
+    if b_scale != 1.0:
+        out *= b_scale
+    return out
+
+
+def mp2_inputs(n_occ: int, n_vir: int, n_aux: int, seed):
+    """(eps_occ, eps_vir, L[i, a, P]) of one seeded synthetic cluster for the
+    MP2 energy and density: the orbital energies and factors `make_fragment`
+    draws, without the (T) blocks."""
+    rng = np.random.default_rng(np.random.SeedSequence([int(s) for s in seed]))
+    eps_occ = np.sort(rng.uniform(-1.5, -0.3, n_occ))
+    eps_vir = np.sort(rng.uniform(0.1, 3.0, n_vir))
+    return eps_occ, eps_vir, ov_factors(n_occ, n_vir, n_aux, seed)
+
+
 # Named single-fragment workloads: occupied / virtual / auxiliary sizes and the
 # seed stream they draw from.
 WORKLOADS = {
@@ -129,6 +158,8 @@ WORKLOADS = {
     # parity case: 337 virtuals span at least two row and two col tiles of
     # every split build shape, with a ragged edge
     "o3v337":  dict(n_occ=3,  n_vir=337, n_aux=1020, stream=5),
+    # MP2 energy and density of a cluster (factors and orbital energies only)
+    "mp2_o64v512": dict(n_occ=64, n_vir=512, n_aux=1728, stream=6),
 }
 
 

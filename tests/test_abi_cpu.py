@@ -223,3 +223,32 @@ def test_static_entry_point_rejects_before_any_hip_call(lib):
     # 24 / 400 float64: one unit's three cubes alone exceed 256 MiB
     assert static(frag(o=24, v=400, keep=keep)) == _lib.SIE_ERR_WORKSPACE
     assert _lib.SIE_STATIC_SCRATCH_BYTES == 256 * 1024 * 1024
+
+
+def test_mp2_argument_errors(lib):
+    """sie_mp2 checks everything on the host before any HIP call."""
+    eo = np.linspace(-1.0, -0.5, 3)
+    ev = np.linspace(0.2, 1.0, 5)
+    keep = [eo, ev]
+
+    def desc(o=3, v=5, naux=4, e_o=eo, e_v=ev, l=FAKE):
+        keep.extend([e_o, e_v])
+        return _lib.SieMp2Input(o, v, naux, e_o.ctypes.data if e_o is not None else None,
+                                e_v.ctypes.data if e_v is not None else None, l)
+
+    call = lambda d, e_out=FAKE, ws=FAKE, ws_bytes=1 << 30: lib.sie_mp2(  # noqa: E731
+        ctypes.byref(d) if d is not None else None, e_out, None, None, None, ws, ws_bytes, None)
+    assert call(None) == _lib.SIE_ERR_INVALID_ARG
+    assert call(desc(o=0)) == _lib.SIE_ERR_INVALID_ARG
+    assert call(desc(naux=0)) == _lib.SIE_ERR_INVALID_ARG
+    assert call(desc(l=None)) == _lib.SIE_ERR_INVALID_ARG
+    assert call(desc(l=FAKE + 4)) == _lib.SIE_ERR_INVALID_ARG
+    assert call(desc(e_o=np.array([-1.0, 0.5, 0.1]), e_v=ev)) == _lib.SIE_ERR_INVALID_ARG
+    assert call(desc(e_o=np.array([-1.0, np.nan, -0.5]))) == _lib.SIE_ERR_NONFINITE
+    assert call(desc(), e_out=None) == _lib.SIE_ERR_INVALID_ARG
+    assert call(desc(), ws=None) == _lib.SIE_ERR_WORKSPACE
+    assert call(desc(), ws_bytes=16) == _lib.SIE_ERR_WORKSPACE
+    assert lib.sie_mp2_workspace_size(ctypes.byref(desc()), 0) > 0
+    assert lib.sie_mp2_workspace_size(ctypes.byref(desc()), 1) > \
+        lib.sie_mp2_workspace_size(ctypes.byref(desc()), 0)
+    assert lib.sie_mp2_workspace_size(ctypes.byref(desc(o=0)), 0) == 0
