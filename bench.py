@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true",
                     help="split mode: skip the float64 evaluation of the same fragment")
+    ap.add_argument("--parts", type=int, default=1,
+                    help="batched mode: evaluate the batch as this many consecutive groups")
+    ap.add_argument("--singles", action="store_true",
+                    help="batched mode: also time every fragment alone")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES device-to-device (a known-size transfer against "
                          "which hardware byte counters are scaled)")
@@ -382,6 +386,11 @@ def run_single(args, result, name, mode):
 
 
 def run_batched(args, result, name):
+    """One batched evaluation over a named batch (`--parts P`: the batch in P
+    consecutive groups of fragments, each group's inputs built, evaluated in
+    one batched call and freed, for batches whose inputs exceed the HBM; the
+    step time is the sum over the groups).  With --singles every fragment is
+    also evaluated alone (same workspace cap) for the batching speedup."""
     import torch
     import paper_2412_18553_amd as sie
     from synth import batch_shapes
@@ -390,35 +399,73 @@ def run_batched(args, result, name):
     dtype = torch.float64 if prec == "fp64" else torch.float32
     dev = torch.device("cuda:0")
     shapes = batch_shapes(name)
-    t0 = time.perf_counter()
-    frs = []
-    for n, (o, v, aux, seed) in enumerate(shapes):
-        frs.append(frag_of(make_fragment_device(o, v, aux, seed, device=dev, dtype=dtype), prec))
-        if n % 8 == 7:
-            log(f"# {n + 1} fragments built")
-    log(f"# workload {name}: {len(frs)} fragments built on the GPU in "
-        f"{time.perf_counter() - t0:.1f} s")
-    ws = torch.empty(sie.workspace_size(frs), dtype=torch.uint8, device=dev)
-    e_frag = torch.empty(len(frs), dtype=torch.float64, device=dev)
-    e_tot = torch.empty(1, dtype=torch.float64, device=dev)
-    step = lambda: sie.energy_batched(frs, workspace=ws, out=e_frag, total=e_tot)  # noqa: E731
-    ms, prof = timed(step, args.steps, args.warmup)
+    parts = max(1, min(args.parts, len(shapes)))
+    bounds = [len(shapes) * q // parts for q in range(parts + 1)]
+    ms_total, singles_ms = 0.0, 0.0
+    prof_total = {}
+    e_sum = 0.0
+    for q in range(parts):
+        sub = shapes[bounds[q]:bounds[q + 1]]
+        t0 = time.perf_counter()
+        frs = []
+        for n, (o, v, aux, seed) in enumerate(sub):
+            frs.append(frag_of(make_fragment_device(o, v, aux, seed, device=dev, dtype=dtype), prec))
+            if n % 8 == 7:
+                log(f"# part {q}: {n + 1} fragments built")
+        log(f"# workload {name} part {q}: {len(frs)} fragments built on the GPU in "
+            f"{time.perf_counter() - t0:.1f} s")
+        try:
+            ws_bytes = sie.workspace_size(frs)
+        except sie.SieError:
+            # the group's split copies of its inputs exceed the default cap:
+            # give the library most of the free HBM instead
+            cap = int(torch.cuda.mem_get_info(dev)[0] * 0.9)
+            ws_bytes = sie.workspace_size(frs, max_bytes=cap)
+            log(f"# part {q}: workspace cap raised to {cap / 2**30:.1f} GiB")
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        e_frag = torch.empty(len(frs), dtype=torch.float64, device=dev)
+        e_tot = torch.empty(1, dtype=torch.float64, device=dev)
+        step = lambda: sie.energy_batched(frs, workspace=ws, out=e_frag, total=e_tot)  # noqa: E731
+        ms, prof = timed(step, args.steps, args.warmup)
+        ms_total += ms
+        e_sum += float(e_tot.item())
+        for k, (t, c) in prof.items():
+            t0_, c0_ = prof_total.get(k, (0.0, 0))
+            prof_total[k] = (t0_ + t, c0_ + c)
+        if args.singles:
+            out = torch.empty(1, dtype=torch.float64, device=dev)
+            for fr in frs:
+                sie.energy(fr, workspace=ws, out=out)      # warm-up of this size
+                torch.cuda.synchronize()
+                start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                start.record()
+                sie.energy(fr, workspace=ws, out=out)
+                stop.record()
+                torch.cuda.synchronize()
+                singles_ms += start.elapsed_time(stop)
+            log(f"# part {q}: singles timed")
+        del frs, ws, step
+        torch.cuda.empty_cache()
+    ms = ms_total
     F = sum(flops(o, v) for (o, v, _, _) in shapes)
     result.update(value=round(F / (ms * 1e-3) / 1e12, 3),
                   dtype="f64" if prec == "fp64" else "bf16x3/f32",
-                  config={"workload": f"{name}: {len(frs)} fragments, n_occ "
+                  config={"workload": f"{name}: {len(shapes)} fragments, n_occ "
                                       f"{min(s[0] for s in shapes)}..{max(s[0] for s in shapes)}, "
                                       f"n_vir {min(s[1] for s in shapes)}..{max(s[1] for s in shapes)}",
-                          "precision": prec, "fragments": len(frs)},
-                  ms_per_step=round(ms, 3), fragments_per_s=round(len(frs) * 1000.0 / ms, 4),
-                  energy=float(e_tot.item()))
+                          "precision": prec, "fragments": len(shapes), "batched_calls": parts},
+                  ms_per_step=round(ms, 3), fragments_per_s=round(len(shapes) * 1000.0 / ms, 4),
+                  energy=e_sum)
+    if args.singles:
+        result["singles"] = {"ms": round(singles_ms, 3),
+                             "batching_speedup": round(singles_ms / ms, 4)}
     if prec == "fp64":   # the batch mixes the build shapes its fragment sizes select
-        result["roofline"] = roofline(prof, "w_build", "k_build_w_f64 / k_build_w3_f64", F,
+        result["roofline"] = roofline(prof_total, "w_build", "k_build_w_f64 / k_build_w3_f64", F,
                                       args.steps, PEAK_FP64_MFMA_TFLOPS, measured=measured_peak(0))
     else:
-        result["roofline"] = roofline(prof, "w_build", "k_build_w_bf16x3*", F, args.steps,
+        result["roofline"] = roofline(prof_total, "w_build", "k_build_w_bf16x3*", F, args.steps,
                                       PEAK_BF16_MFMA_TFLOPS, issued=3.0, measured=measured_peak(1))
-    result["kernel_ms_per_step"] = {k: round(t / args.steps, 3) for k, (t, _) in prof.items()}
+    result["kernel_ms_per_step"] = {k: round(t / args.steps, 3) for k, (t, _) in prof_total.items()}
 
 
 def run_mp2(args, result, name):

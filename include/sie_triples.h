@@ -92,9 +92,13 @@ typedef struct {
   const void* ovvv;
   const void* ooov;
   const void* ovov;
-  const double* frag_proj;   /* C^f_ii' [n_occ][n_occ] of the same section, or
-                                NULL for the identity; non-NULL is rejected with
-                                SIE_ERR_UNSUPPORTED by this build               */
+  const double* frag_proj;   /* host [n_occ][n_occ]: the fragment projector C^f_ii'
+                                of the same section (in the cluster's occupied
+                                orbitals), or NULL for the identity; used by
+                                sie_triples_energy and
+                                sie_triples_projector_matrix, rejected with
+                                SIE_ERR_UNSUPPORTED by the batched and backward
+                                entry points                                  */
 } sie_fragment;
 
 #define SIE_MAX_OCC 256
@@ -152,6 +156,30 @@ size_t sie_triples_workspace_size(const sie_fragment* frags, int32_t n,
 sie_status sie_triples_energy(const sie_fragment* frag, sie_precision p,
                               double* e_out, double* e_triples,
                               void* ws, size_t ws_bytes, void* stream);
+
+/* Fragment projector (the C^f factor of equation E_corr_CCSD_T).  The
+ * printed sum over a >= b >= c applies C^f to the occupied index paired with
+ * one virtual of the sorted triple, which makes the result depend on the
+ * order of the virtual orbitals; this library takes the order-independent
+ * reading with C acting on the first occupied index of W-tilde:
+ *   E_x(C) = (1/3) sum_{ijk abc} (C Wt)_{ijk} R[Wt + Vt]_{ijk} / D_{ijk}
+ *          = sum_{i i'} C_{i i'} M_{i i'},
+ *   M_{i i'} = (1/3) sum_{jk abc} Wt^{abc}_{i'jk} (R[Wt + Vt] / D)^{abc}_{ijk},
+ * which equals the unprojected energy for C = I (tr M = E_x) and is linear
+ * in C, so the energies of a complete set of projectors add up to it.
+ * sie_triples_projector_matrix writes M (device float64 [n_occ][n_occ],
+ * row i, column i'), from which E_x of any projector is a trace; the energy
+ * entry point with frag_proj set computes M in its workspace and writes
+ * sum C M to e_out (e_triples must then be NULL).  Cost: about three times
+ * the energy's (every ordered occupied triple is built: W-tilde and R/D of
+ * triples that share two occupied indices are paired).  The workspace of
+ * either call is sie_triples_projector_workspace_size (for the energy entry
+ * point also what sie_triples_workspace_size returns for a fragment with
+ * frag_proj set); frag_proj, when given, must be finite. */
+size_t sie_triples_projector_workspace_size(const sie_fragment* frag, sie_precision p,
+                                            size_t max_bytes);
+sie_status sie_triples_projector_matrix(const sie_fragment* frag, sie_precision p,
+                                        double* m_out, void* ws, size_t ws_bytes, void* stream);
 
 /* E_x of one fragment exactly as sie_triples_energy computes it, for callers
  * that cannot allocate device memory (code under stream capture, tight
@@ -313,8 +341,13 @@ sie_status sie_set_tile_table(int32_t n, const int32_t* nv_max, const int32_t* v
  * 112 x 256, 64 x 256 (four waves), 160 x 320 (eight waves) and 160 x 160
  * (four waves) for s = 0 .. 5.
  * sie_split_shape_of returns the shape a fragment with n_vir virtuals builds
- * with (-1 for n_vir < 1): by default, among the shapes whose padded tile
- * area is within 10% of the least, the first in the order 5, 4, 1, 2, 3, 0.
+ * with (-1 for n_vir < 1): the shape of the first entry of the installed
+ * table (the built-in one comes from the autotuner's timings) whose bound is
+ * >= n_vir, and past the table, among the shapes whose padded tile area is
+ * within 10% of the least, the first in the order 5, 4, 1, 2, 3, 0.
+ * sie_set_split_table installs a table of n entries (host arrays: strictly
+ * ascending bounds >= 1, shapes in [0, SIE_SPLIT_SHAPES)), or the built-in
+ * one for n = 0.
  * sie_set_split_shape forces shape s for every fragment of later evaluations
  * (s = -1 restores the default; SIE_ERR_INVALID_ARG outside [-1,
  * SIE_SPLIT_SHAPES)).  Energies do not depend on the shape beyond rounding of
@@ -323,6 +356,7 @@ sie_status sie_set_tile_table(int32_t n, const int32_t* nv_max, const int32_t* v
 #define SIE_SPLIT_SHAPES 6
 int32_t sie_split_shape_of(int32_t n_vir);
 sie_status sie_set_split_shape(int32_t shape);
+sie_status sie_set_split_table(int32_t n, const int32_t* nv_max, const int32_t* shape);
 
 /* Finite check.  When on, every energy and backward call first scans t1, t2,
  * ovvv, ooov and ovov of each fragment on the device, waits for the scan, and

@@ -17,6 +17,7 @@ from .triples import (  # noqa: F401
     energy_literal,
     energy_literal_vectorized,
     energy_dense,
+    projector_matrix,
     occupied_triple_energy,
     occupied_triple_parts,
     energy_by_occupied_triples,

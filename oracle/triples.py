@@ -414,6 +414,25 @@ def occupied_triple_parts(i, j, k, eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov):
     return e_ww, e_wv
 
 
+def projector_matrix(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov):
+    """M[i, i'] = (1/3) sum_{jk abc} Wt^{abc}_{i'jk} (R[Wt + Vt] / D)^{abc}_{ijk}
+    (plain six-index tensors, tiny inputs), so that the projected energy of
+    the unrestricted reading, (1/3) sum (C Wt) R[Wt + Vt] / D, equals
+    sum_{i i'} C[i, i'] M[i, i'] for every C, and tr M is E_x."""
+    eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov = _check(
+        eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov)
+    x6 = (np.einsum("iabd,kjcd->ijkabc", ovvv, t2, optimize=True)
+          - np.einsum("jlia,lkbc->ijkabc", ooov, t2, optimize=True))
+    wt = _P6(x6)
+    vt = 0.5 * _P6(np.einsum("iajb,kc->ijkabc", ovov, t1))
+    eo, ev = eps_occ, eps_vir
+    d = (eo[:, None, None, None, None, None] + eo[None, :, None, None, None, None]
+         + eo[None, None, :, None, None, None] - ev[None, None, None, :, None, None]
+         - ev[None, None, None, None, :, None] - ev[None, None, None, None, None, :])
+    q = _R6((wt + vt) / d)
+    return np.einsum("pjkabc,ijkabc->ip", wt, q, optimize=True) / 3.0
+
+
 def energy_by_occupied_triples(eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov,
                                return_parts=False):
     """E_x (C = I) as the compensated sum of `occupied_triple_parts` over all

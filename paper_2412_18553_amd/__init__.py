@@ -56,7 +56,8 @@ class Fragment:
 
     Keeps references to every buffer the descriptor points at."""
 
-    def __init__(self, eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, precision="fp64"):
+    def __init__(self, eps_occ, eps_vir, t1, t2, ovvv, ooov, ovov, precision="fp64",
+                 frag_proj=None):
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {list(PRECISIONS)}")
         self.precision = precision
@@ -74,10 +75,18 @@ class Fragment:
             if getattr(self, name).device != self.device:
                 raise ValueError("all device inputs must be on the same GPU")
         self.n_occ, self.n_vir = o, v
+        self.frag_proj = None
+        if frag_proj is not None:   # host float64 [n_occ][n_occ], C^f of the fragment
+            c = frag_proj.detach().to("cpu").numpy() if isinstance(frag_proj, torch.Tensor) \
+                else frag_proj
+            self.frag_proj = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
+            if self.frag_proj.shape != (o, o):
+                raise ValueError(f"frag_proj must be [{o}][{o}]")
         self.desc = SieFragment(
             o, v, self.eps_occ.ctypes.data, self.eps_vir.ctypes.data,
             self.t1.data_ptr(), self.t2.data_ptr(), self.ovvv.data_ptr(),
-            self.ooov.data_ptr(), self.ovov.data_ptr(), None)
+            self.ooov.data_ptr(), self.ovov.data_ptr(),
+            None if self.frag_proj is None else self.frag_proj.ctypes.data)
 
     @property
     def n_triples(self) -> int:
@@ -131,6 +140,31 @@ def energy(frag: Fragment, *, workspace: torch.Tensor | None = None,
                                 out.data_ptr(),
                                 None if triples is None else triples.data_ptr(),
                                 workspace.data_ptr(), workspace.numel(), stream)
+    _lib.check(st)
+    return out
+
+
+def projector_matrix(frag: Fragment, *, out: torch.Tensor | None = None,
+                     workspace: torch.Tensor | None = None,
+                     max_workspace_bytes: int = 0) -> torch.Tensor:
+    """M [n_occ][n_occ] (float64, device) with E_x(C) = sum_{ii'} C_ii' M_ii' for
+    any fragment projector C (see sie_triples_projector_matrix; tr M = E_x).
+    Enqueued on the current stream."""
+    lib = _lib.load()
+    prec = PRECISIONS[frag.precision]
+    if workspace is None:
+        n = lib.sie_triples_projector_workspace_size(ctypes.byref(frag.desc), prec,
+                                                     max_workspace_bytes)
+        if n == 0:
+            raise SieError(_lib.SIE_ERR_INVALID_ARG, _lib.last_error())
+        workspace = torch.empty(n, dtype=torch.uint8, device=frag.device)
+    if out is None:
+        out = torch.empty((frag.n_occ, frag.n_occ), dtype=torch.float64, device=frag.device)
+    if out.dtype != torch.float64 or out.numel() != frag.n_occ ** 2 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor of n_occ^2 entries")
+    stream = torch.cuda.current_stream(frag.device).cuda_stream
+    st = lib.sie_triples_projector_matrix(ctypes.byref(frag.desc), prec, out.data_ptr(),
+                                          workspace.data_ptr(), workspace.numel(), stream)
     _lib.check(st)
     return out
 
@@ -385,6 +419,17 @@ def set_tile_table(table=None) -> None:
     nv = (ctypes.c_int32 * max(n, 1))(*[int(b) for b, _ in table])
     var = (ctypes.c_int32 * max(n, 1))(*[int(v) for _, v in table])
     _lib.check(lib.sie_set_tile_table(n, nv, var))
+
+
+def set_split_table(table=None) -> None:
+    """Install [(n_vir upper bound, split shape), ...] (ascending) for the
+    split-precision build, or the built-in tuned table with None."""
+    lib = _lib.load()
+    table = list(table or [])
+    n = len(table)
+    nv = (ctypes.c_int32 * max(n, 1))(*[int(b) for b, _ in table])
+    sh = (ctypes.c_int32 * max(n, 1))(*[int(v) for _, v in table])
+    _lib.check(lib.sie_set_split_table(n, nv, sh))
 
 
 def set_check_finite(on: bool = True) -> None:

@@ -34,8 +34,10 @@ EXPORTED = ["sie_abi_version", "sie_last_error", "sie_occupied_triples",
             "sie_triples_backward_workspace_size", "sie_triples_backward",
             "sie_tile_variants", "sie_tile_variant_shape", "sie_tile_variant_of",
             "sie_set_tile_table", "sie_split_shape_of", "sie_set_split_shape",
+            "sie_set_split_table",
             "sie_profile_enable", "sie_profile_collect", "sie_set_check_finite",
-            "sie_mp2_workspace_size", "sie_mp2"]
+            "sie_mp2_workspace_size", "sie_mp2",
+            "sie_triples_projector_workspace_size", "sie_triples_projector_matrix"]
 PROF_CLASSES = ("w_build", "epilogue", "reduce", "split", "grad")
 
 
@@ -125,6 +127,9 @@ def load() -> ctypes.CDLL:
     lib.sie_split_shape_of.argtypes = [ctypes.c_int32]
     lib.sie_set_split_shape.restype = ctypes.c_int
     lib.sie_set_split_shape.argtypes = [ctypes.c_int32]
+    lib.sie_set_split_table.restype = ctypes.c_int
+    lib.sie_set_split_table.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)]
     lib.sie_profile_enable.restype = None
     lib.sie_profile_enable.argtypes = [ctypes.c_int]
     lib.sie_set_check_finite.restype = None
@@ -132,6 +137,13 @@ def load() -> ctypes.CDLL:
     lib.sie_profile_collect.restype = ctypes.c_int
     lib.sie_profile_collect.argtypes = [ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64)]
+    lib.sie_triples_projector_workspace_size.restype = ctypes.c_size_t
+    lib.sie_triples_projector_workspace_size.argtypes = [ctypes.POINTER(SieFragment),
+                                                         ctypes.c_int, ctypes.c_size_t]
+    lib.sie_triples_projector_matrix.restype = ctypes.c_int
+    lib.sie_triples_projector_matrix.argtypes = [ctypes.POINTER(SieFragment), ctypes.c_int,
+                                                 ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_size_t, ctypes.c_void_p]
     lib.sie_mp2_workspace_size.restype = ctypes.c_size_t
     lib.sie_mp2_workspace_size.argtypes = [ctypes.POINTER(SieMp2Input), ctypes.c_int32]
     lib.sie_mp2.restype = ctypes.c_int

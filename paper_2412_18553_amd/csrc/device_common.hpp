@@ -93,4 +93,28 @@ __host__ __device__ __forceinline__ bool unit_triple(int64_t u, int bound, bool 
   return i == j;
 }
 
+// Occupied triple of a work item.  u >= 0: the unordered triple u as above
+// (unit_triple); returns false for i = j = k, whose energy contribution is
+// exactly zero.  u < 0: the ordered triple (i, j, k) with
+// -1 - u = (i n_occ + j) n_occ + k (the projector evaluation, which needs
+// W-tilde of every ordered triple, i = j = k included); `one` is then false.
+__host__ __device__ __forceinline__ bool item_triple(int64_t u, int bound, bool pair, int& i,
+                                                     int& j, int& k, bool& one) {
+  if (u >= 0) {
+    one = unit_triple(u, bound, pair, i, j, k);
+    return i != k;
+  }
+  const int64_t x = -1 - u;
+  k = int(x % bound);
+  j = int((x / bound) % bound);
+  i = int(x / (int64_t(bound) * bound));
+  one = false;
+  return true;
+}
+
+// Item code of the ordered occupied triple (i, j, k).
+__host__ __device__ __forceinline__ int ordered_item(int i, int j, int k, int bound) {
+  return -1 - int((int64_t(i) * bound + j) * bound + k);
+}
+
 }  // namespace sie

@@ -335,8 +335,8 @@ __global__ __launch_bounds__(256, 2) void k_build_w_bf16x3(const FragDesc* __res
   const Item it = items[ri];
   const FragDesc fd = descs[it.frag];
   int i, j, k;
-  const bool one = unit_triple(it.unit, fd.no, fd.pair, i, j, k);
-  if (i == k) return;
+  bool one;
+  if (!item_triple(it.unit, fd.no, fd.pair, i, j, k, one)) return;
   const int nv = fd.nv;
   const int nrt = (nv + R - 1) / R, nct = (nv + C - 1) / C;
   const int per = nv * nrt * nct;
@@ -442,8 +442,8 @@ __global__ __launch_bounds__(128 * WC, WC == 4 ? 1 : 2) void k_build_w_bf16x3_l(
   const Item it = items[ri];
   const FragDesc fd = descs[it.frag];
   int i, j, k;
-  const bool one = unit_triple(it.unit, fd.no, fd.pair, i, j, k);
-  if (i == k) return;
+  bool one;
+  if (!item_triple(it.unit, fd.no, fd.pair, i, j, k, one)) return;
   const int nv = fd.nv;
   const int nrt = (nv + R - 1) / R, nct = (nv + C - 1) / C;
   const int per = nv * nrt * nct;

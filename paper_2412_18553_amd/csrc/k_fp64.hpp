@@ -482,8 +482,8 @@ __global__ __launch_bounds__(256, BPC) void k_build_w_f64(const FragDesc* __rest
   const Item it = items[ri];
   const FragDesc fd = descs[it.frag];
   int i, j, k;
-  const bool one = unit_triple(it.unit, fd.no, fd.pair, i, j, k);
-  if (i == k) return;
+  bool one;
+  if (!item_triple(it.unit, fd.no, fd.pair, i, j, k, one)) return;
   const int nv = fd.nv;
   const int nbt = (nv + BB - 1) / BB, nrt = (nv + ER - 1) / ER, nct = (nv + EC - 1) / EC;
   const int per = nbt * nrt * nct;
@@ -542,8 +542,8 @@ __global__ __launch_bounds__(256, BPC) void k_build_w3_f64(const FragDesc* __res
   const Item it = items[ri];
   const FragDesc fd = descs[it.frag];
   int i, j, k;
-  const bool one = unit_triple(it.unit, fd.no, fd.pair, i, j, k);
-  if (i == k) return;
+  bool one;
+  if (!item_triple(it.unit, fd.no, fd.pair, i, j, k, one)) return;
   const int nv = fd.nv;
   const int nbt = (nv + BB - 1) / BB, npt = (nv + EP - 1) / EP, nst = (nv + ES - 1) / ES;
   const int per = nbt * npt * nst;

@@ -54,6 +54,19 @@ void launch_symmetrize(unsigned grid, hipStream_t s, double* g, int kind, int no
 void launch_zero_flags(hipStream_t s, int* flags, int n);
 void launch_nonfinite(hipStream_t s, const void* x, bool f64, int64_t n, int* flags, int slot);
 
+// ---- fragment projector (k_proj.hpp, in tu_epilogue.hip) ----
+void launch_proj_wq_f64(unsigned grid, hipStream_t s, const FragDesc* desc, const Item* items,
+                        int n_items, double* arena);
+void launch_proj_wq_f32(unsigned grid, hipStream_t s, const FragDesc* desc, const Item* items,
+                        int n_items, float* arena);
+void launch_proj_m_f64(hipStream_t s, const double* wt, const double* q, int64_t stride, int no,
+                       int64_t K, int64_t chunk, int chunks, double* part);
+void launch_proj_m_f32(hipStream_t s, const float* wt, const float* q, int64_t stride, int no,
+                       int64_t K, int64_t chunk, int chunks, double* part);
+void launch_proj_msum(hipStream_t s, const double* part, int chunks, int no, double weight,
+                      double* m);
+void launch_proj_energy(hipStream_t s, const double* c, const double* m, int64_t n, double* out);
+
 // ---- adjoint (tu_adj_f64.hip, tu_adj_f32.hip) ----
 // Contraction lists of one class in one backward round (host tables uploaded
 // to the workspace): the class's groups and records, and for the

@@ -263,7 +263,10 @@ Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad =
 }
 
 
-sie_status check_fragment(const sie_fragment* f, sie_precision prec, const char* who) {
+// allow_proj: the entry point evaluates the fragment projector C^f (the
+// single-fragment energy and the projector matrix); elsewhere it is rejected.
+sie_status check_fragment(const sie_fragment* f, sie_precision prec, const char* who,
+                          bool allow_proj = false) {
   std::string w(who);
   if (!f) return fail(SIE_ERR_INVALID_ARG, w + ": fragment descriptor is NULL");
   if (prec != SIE_FP64 && prec != SIE_SPLIT_BF16)
@@ -294,8 +297,15 @@ sie_status check_fragment(const sie_fragment* f, sie_precision prec, const char*
   if (!(max_occ < min_vir))
     return fail(SIE_ERR_INVALID_ARG,
                 w + ": max(eps_occ) >= min(eps_vir): a triples denominator would not be negative");
-  if (f->frag_proj)
-    return fail(SIE_ERR_UNSUPPORTED, w + ": fragment projector C^f is not supported by this build");
+  if (f->frag_proj) {
+    if (!allow_proj)
+      return fail(SIE_ERR_UNSUPPORTED,
+                  w + ": the fragment projector C^f is supported by sie_triples_energy and "
+                      "sie_triples_projector_matrix only");
+    for (int64_t q = 0; q < int64_t(f->n_occ) * f->n_occ; ++q)
+      if (!std::isfinite(f->frag_proj[q]))
+        return fail(SIE_ERR_NONFINITE, w + ": frag_proj has a non-finite entry");
+  }
   // the float64 build and the gradient contractions address each operand
   // with 32-bit byte offsets from a per-term base: the largest extent is an
   // l-sum's t2 pair block plus a row
@@ -349,12 +359,25 @@ int tile_variant(int nv) {
   return 0;
 }
 
-// ---- split build tile shape: by padded area (sie::split_shape_of) unless forced ----
+// ---- split build tile shape: forced, else the tuned table (split_table.inc,
+// or one installed by sie_set_split_table), else by padded area
+// (sie::split_shape_of) ----
 std::atomic<int> g_split_forced{-1};
+const TileEntry kBuiltinSplit[] = {
+#include "split_table.inc"
+    {0, -1}};   // terminator (also keeps the array non-empty)
+std::mutex g_split_mu;
+std::vector<TileEntry> g_split(std::begin(kBuiltinSplit), std::end(kBuiltinSplit) - 1);
 
 int split_shape(int nv) {
   const int f = g_split_forced.load();
-  return f >= 0 ? f : sie::split_shape_of(nv);
+  if (f >= 0) return f;
+  {
+    std::lock_guard<std::mutex> lock(g_split_mu);
+    for (const TileEntry& e : g_split)
+      if (nv <= e.nv_max) return e.variant;
+  }
+  return sie::split_shape_of(nv);
 }
 
 // ---- optional kernel timing ----
@@ -467,6 +490,22 @@ sie_status sie_set_split_shape(int32_t shape) {
   g_split_forced.store(shape);
   return SIE_OK;
 }
+sie_status sie_set_split_table(int32_t n, const int32_t* nv_max, const int32_t* shape) {
+  std::vector<TileEntry> t;
+  if (n < 0 || (n > 0 && (!nv_max || !shape)))
+    return fail(SIE_ERR_INVALID_ARG, "sie_set_split_table: bad count or NULL arrays");
+  for (int32_t q = 0; q < n; ++q) {
+    if (shape[q] < 0 || shape[q] >= sie::kSShapes)
+      return fail(SIE_ERR_INVALID_ARG, "sie_set_split_table: unknown shape");
+    if (nv_max[q] < 1 || (q > 0 && nv_max[q] <= nv_max[q - 1]))
+      return fail(SIE_ERR_INVALID_ARG, "sie_set_split_table: bounds must be positive and ascending");
+    t.push_back(TileEntry{nv_max[q], shape[q]});
+  }
+  if (n == 0) t.assign(std::begin(kBuiltinSplit), std::end(kBuiltinSplit) - 1);
+  std::lock_guard<std::mutex> lock(g_split_mu);
+  g_split.swap(t);
+  return SIE_OK;
+}
 static_assert(SIE_SPLIT_SHAPES == sie::kSShapes, "header and kernels agree on the split shapes");
 
 const char* sie_last_error(void) { return g_err.c_str(); }
@@ -481,12 +520,18 @@ int64_t sie_occupied_triples(int32_t n_occ) {
 
 namespace {
 
+size_t proj_workspace(const sie_fragment& f, sie_precision p, size_t max_bytes);
+
 size_t workspace_size(const sie_fragment* frags, int32_t n, sie_precision p, size_t max_bytes,
                       bool grad, const char* who) {
   const std::string w(who);
   if (!frags || n < 1) {
     fail(SIE_ERR_INVALID_ARG, w + ": need at least one fragment");
     return 0;
+  }
+  if (!grad && n == 1 && frags[0].frag_proj) {   // the single-fragment projector energy
+    if (check_fragment(&frags[0], p, who, true) != SIE_OK) return 0;
+    return proj_workspace(frags[0], p, max_bytes);
   }
   for (int32_t x = 0; x < n; ++x)
     if (check_fragment(&frags[x], p, who) != SIE_OK) return 0;
@@ -875,6 +920,224 @@ sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag
 }
 
 
+// ---- fragment projector (k_proj.hpp) ----
+// Workspace: [descriptor][e_occ|e_vir][items of every group][split copies]
+// [product chunk slices][C^f][M][cube arena].  A group is the n_o ordered
+// triples (i', j, k) of one occupied pair j >= k; a round holds as many
+// groups as the arena fits (two row-major cubes per ordered triple).
+struct ProjPlan {
+  FragPlan fp;
+  bool split = false;
+  int64_t groups = 0, K = 0, chunk = 0;
+  int chunks = 0;
+  size_t off_desc = 0, off_eps = 0, off_items = 0, off_split = 0, off_part = 0, off_c = 0,
+         off_m = 0, off_flags = 0, off_arena = 0, fixed = 0, group_bytes = 0;
+};
+
+ProjPlan proj_plan(const sie_fragment& f, sie_precision p) {
+  ProjPlan q;
+  q.split = p == SIE_SPLIT_BF16;
+  q.fp = frag_plan(f.n_occ, f.n_vir, q.split);
+  if (!q.split) {   // two-layout build shape (as the adjoint)
+    q.fp.variant = tile_variant(q.fp.nv);
+    if (sie::wshape(q.fp.variant).lay == 3) q.fp.variant = 0;
+  } else {
+    q.fp.variant = split_shape(q.fp.nv);
+  }
+  q.fp.lay3 = false;
+  const int64_t o = q.fp.no, v = q.fp.nv;
+  q.groups = o * (o + 1) / 2;
+  q.K = v * v * v;
+  q.chunk = 32768;
+  q.chunks = int((q.K + q.chunk - 1) / q.chunk);
+  size_t off = 0;
+  q.off_desc = off;
+  off = align_up(off + sizeof(sie::FragDesc), 256);
+  q.off_eps = off;
+  off = align_up(off + sizeof(double) * size_t(o + v), 256);
+  q.off_items = off;
+  off = align_up(off + sizeof(sie::Item) * size_t(q.groups * o), 256);
+  q.off_split = off;
+  off = align_up(off + q.fp.split_bytes, 256);
+  q.off_part = off;
+  off = align_up(off + sizeof(double) * size_t(q.chunks) * size_t(o * o), 256);
+  q.off_c = off;
+  off = align_up(off + sizeof(double) * size_t(o * o), 256);
+  q.off_m = off;
+  off = align_up(off + sizeof(double) * size_t(o * o), 256);
+  q.off_flags = off;
+  off = align_up(off + sizeof(int) * 5, 256);
+  q.off_arena = off;
+  q.fixed = off;
+  q.group_bytes = size_t(2) * size_t(o) * q.fp.half_bytes;
+  return q;
+}
+
+size_t proj_workspace(const sie_fragment& f, sie_precision p, size_t max_bytes) {
+  const ProjPlan q = proj_plan(f, p);
+  const size_t cap = max_bytes ? max_bytes : default_cap();
+  if (q.fixed + q.group_bytes > cap) {
+    fail(SIE_ERR_WORKSPACE, "projector: cap below the minimum workspace (one group of cubes)");
+    return 0;
+  }
+  size_t arena = cap - q.fixed;
+  const size_t all = q.group_bytes * size_t(q.groups);
+  if (arena > all) arena = all;
+  arena = arena / q.group_bytes * q.group_bytes;
+  return q.fixed + arena;
+}
+
+// M (device, n_o x n_o) of one fragment, and with c_host (the fragment's
+// projector) also E_x = sum C M into e_out.
+sie_status run_projector(const sie_fragment* f, sie_precision p, double* m_out, double* e_out,
+                         void* ws, size_t ws_bytes, void* stream, const char* who) {
+  const std::string w(who);
+  const ProjPlan q = proj_plan(*f, p);
+  if (!ws || !aligned(ws, 256))
+    return fail(SIE_ERR_WORKSPACE, w + ": workspace is NULL or not 256-byte aligned");
+  if (ws_bytes < q.fixed + q.group_bytes)
+    return fail(SIE_ERR_WORKSPACE,
+                w + ": workspace smaller than required (see sie_triples_projector_workspace_size)");
+  const int64_t per_round = int64_t((ws_bytes - q.fixed) / q.group_bytes);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  auto dev = [&](size_t off) { return base + off; };
+  const FragPlan& fp = q.fp;
+  const int no = fp.no, nv = fp.nv;
+
+  sie::FragDesc d{};
+  d.t1 = f->t1; d.t2 = f->t2; d.ovvv = f->ovvv; d.ooov = f->ooov; d.ovov = f->ovov;
+  d.eps = reinterpret_cast<const double*>(dev(q.off_eps));
+  d.no = no;
+  d.nv = nv;
+  d.Kv = fp.Kv;
+  d.Ko = fp.Ko;
+  d.vec = (!q.split && nv % 2 == 0 && aligned(f->t2, 16) && aligned(f->ovvv, 16)) ? 1 : 0;
+  d.epv = (nv % 2 == 0 && aligned(f->ovov, q.split ? 8 : 16)) ? 1 : 0;
+  d.variant = fp.variant;
+  d.pair = 0;
+  d.lay3 = 0;
+  d.blocked = 0;
+  d.n_part = fp.n_part;
+  d.unit_base = 0;
+  d.half = int64_t(fp.half_bytes / (q.split ? sizeof(float) : sizeof(double)));
+  d.tiles = q.split ? sie::split_tiles(nv, d.variant) : sie::wbuild_tiles(nv, d.variant);
+  if (q.split) {
+    const size_t o = size_t(no), v = size_t(nv);
+    size_t off = q.off_split;
+    d.vS = reinterpret_cast<const sie::u4v*>(dev(off));
+    off += align_up(4 * o * v * v * size_t(fp.Kv), 256);
+    d.tS = reinterpret_cast<const sie::u4v*>(dev(off));
+    off += align_up(4 * o * o * v * size_t(fp.Kv), 256);
+    d.tT = reinterpret_cast<const sie::u4v*>(dev(off));
+    off += align_up(4 * o * v * v * size_t(fp.Ko), 256);
+    d.oT = reinterpret_cast<const sie::u4v*>(dev(off));
+  }
+  std::vector<double> eps(f->eps_occ, f->eps_occ + no);
+  eps.insert(eps.end(), f->eps_vir, f->eps_vir + nv);
+  // items: group g = pair (j, k), j >= k in order; item i' of the group is
+  // the ordered triple (i', j, k); prefix sums restart every round
+  std::vector<sie::Item> items(size_t(q.groups * no));
+  std::vector<std::pair<int, int>> pairs;
+  for (int j = 0; j < no; ++j)
+    for (int k = 0; k <= j; ++k) pairs.emplace_back(j, k);
+  {
+    int64_t blk = 0, part = 0;
+    for (int64_t g = 0; g < q.groups; ++g) {
+      if (g % per_round == 0) blk = part = 0;
+      for (int i = 0; i < no; ++i) {
+        sie::Item& it = items[size_t(g * no + i)];
+        it.frag = 0;
+        it.unit = sie::ordered_item(i, pairs[size_t(g)].first, pairs[size_t(g)].second, no);
+        it.cube_off = ((g % per_round) * no + i) * 2 * d.half;
+        blk += 2 * d.tiles;
+        part += fp.n_part;
+        it.blk_end = blk;
+        it.part_end = part;
+      }
+    }
+  }
+  sie_status st = SIE_OK;
+  {
+    sie::Staging::Batch up;
+    const size_t bytes = sie::Staging::padded(sizeof(sie::FragDesc)) +
+                         sie::Staging::padded(sizeof(double) * eps.size()) +
+                         sie::Staging::padded(sizeof(sie::Item) * items.size()) +
+                         sie::Staging::padded(sizeof(double) * size_t(no) * no);
+    st = hip_check(g_staging.begin(bytes, up), "stage tables");
+    if (st != SIE_OK) return st;
+    up.add(dev(q.off_desc), &d, sizeof(sie::FragDesc));
+    up.add(dev(q.off_eps), eps.data(), sizeof(double) * eps.size());
+    up.add(dev(q.off_items), items.data(), sizeof(sie::Item) * items.size());
+    if (f->frag_proj) up.add(dev(q.off_c), f->frag_proj, sizeof(double) * size_t(no) * no);
+    st = hip_check(up.commit(s), "upload tables");
+    if (st != SIE_OK) return st;
+  }
+  if (check_finite_on()) {
+    st = scan_finite(f, 1, !q.split, reinterpret_cast<int*>(dev(q.off_flags)), s, w);
+    if (st != SIE_OK) return st;
+  }
+  const sie::FragDesc* d_desc = reinterpret_cast<const sie::FragDesc*>(dev(q.off_desc));
+  const sie::Item* d_items = reinterpret_cast<const sie::Item*>(dev(q.off_items));
+  double* d_m = m_out ? m_out : reinterpret_cast<double*>(dev(q.off_m));
+  double* d_part = reinterpret_cast<double*>(dev(q.off_part));
+  {
+    const int64_t n = int64_t(no) * no;
+    sie::launch_fill_zero(unsigned((n + 255) / 256), s, d_m, n);
+  }
+  if (q.split) {
+    st = stage_split(std::vector<sie::FragDesc>{d}, s);
+    if (st != SIE_OK) return st;
+  }
+  for (int64_t g0 = 0; g0 < q.groups; g0 += per_round) {
+    const int64_t g1 = std::min(q.groups, g0 + per_round);
+    const size_t r0 = size_t(g0 * no), r1 = size_t(g1 * no);
+    const int cnt = int(r1 - r0);
+    const sie::Item* ri = d_items + r0;
+    void* arena = dev(q.off_arena);
+    {
+      ProfScope ps(s, 0);
+      if (q.split)
+        sie::launch_build_split(d.variant, unsigned(items[r1 - 1].blk_end), s, d_desc, ri, cnt,
+                                static_cast<float*>(arena));
+      else
+        sie::launch_build_f64(d.variant, unsigned(items[r1 - 1].blk_end), s, d_desc, ri, cnt,
+                              static_cast<double*>(arena));
+    }
+    {
+      ProfScope ps(s, 1);
+      if (q.split)
+        sie::launch_proj_wq_f32(unsigned(items[r1 - 1].part_end), s, d_desc, ri, cnt,
+                                static_cast<float*>(arena));
+      else
+        sie::launch_proj_wq_f64(unsigned(items[r1 - 1].part_end), s, d_desc, ri, cnt,
+                                static_cast<double*>(arena));
+    }
+    {
+      ProfScope ps(s, 2);
+      for (int64_t g = g0; g < g1; ++g) {
+        const int64_t off = ((g - g0) * no) * 2 * d.half;   // first item's cube pair
+        const int64_t stride = 2 * d.half;
+        if (q.split) {
+          const float* a = static_cast<const float*>(arena) + off;
+          sie::launch_proj_m_f32(s, a, a + d.half, stride, no, q.K, q.chunk, q.chunks, d_part);
+        } else {
+          const double* a = static_cast<const double*>(arena) + off;
+          sie::launch_proj_m_f64(s, a, a + d.half, stride, no, q.K, q.chunk, q.chunks, d_part);
+        }
+        const bool diag = pairs[size_t(g)].first == pairs[size_t(g)].second;
+        sie::launch_proj_msum(s, d_part, q.chunks, no, diag ? 1.0 / 3.0 : 2.0 / 3.0, d_m);
+      }
+    }
+    st = hip_check(hipGetLastError(), "launch projector kernels");
+    if (st != SIE_OK) return st;
+  }
+  if (e_out && f->frag_proj)
+    sie::launch_proj_energy(s, reinterpret_cast<const double*>(dev(q.off_c)), d_m,
+                            int64_t(no) * no, e_out);
+  return hip_check(hipGetLastError(), "launch projector energy");
+}
+
 // Backward contraction lists of one round: for every class, the output slices
 // the round's units touch (sorted), each with its records in item order.
 using sie::AdjLaunch;
@@ -1178,7 +1441,32 @@ sie_status sie_triples_energy(const sie_fragment* f, sie_precision p, double* e_
     return fail(SIE_ERR_INVALID_ARG, "sie_triples_energy: e_out is NULL or misaligned");
   if (e_triples && !aligned(e_triples, sizeof(double)))
     return fail(SIE_ERR_INVALID_ARG, "sie_triples_energy: e_triples is misaligned");
+  if (f && f->frag_proj) {
+    sie_status st = check_fragment(f, p, "sie_triples_energy", true);
+    if (st != SIE_OK) return st;
+    if (e_triples)
+      return fail(SIE_ERR_UNSUPPORTED,
+                  "sie_triples_energy: with a fragment projector the energy is not a sum of "
+                  "per-triple terms (e_triples must be NULL)");
+    return run_projector(f, p, nullptr, e_out, ws, ws_bytes, stream, "sie_triples_energy");
+  }
   return run(f, 1, p, nullptr, e_out, e_triples, ws, ws_bytes, stream, "sie_triples_energy");
+}
+
+size_t sie_triples_projector_workspace_size(const sie_fragment* frag, sie_precision p,
+                                            size_t max_bytes) {
+  if (check_fragment(frag, p, "sie_triples_projector_workspace_size", true) != SIE_OK) return 0;
+  return proj_workspace(*frag, p, max_bytes);
+}
+
+sie_status sie_triples_projector_matrix(const sie_fragment* frag, sie_precision p, double* m_out,
+                                        void* ws, size_t ws_bytes, void* stream) {
+  const char* who = "sie_triples_projector_matrix";
+  sie_status st = check_fragment(frag, p, who, true);
+  if (st != SIE_OK) return st;
+  if (!m_out || !aligned(m_out, sizeof(double)))
+    return fail(SIE_ERR_INVALID_ARG, std::string(who) + ": m_out is NULL or misaligned");
+  return run_projector(frag, p, m_out, nullptr, ws, ws_bytes, stream, who);
 }
 
 sie_status sie_triples_energy_static(const sie_fragment* f, sie_precision p, double* e_out,

@@ -2,6 +2,7 @@
 // k_reduce.hpp, k_adjoint.hpp).
 #include "k_adjoint.hpp"
 #include "k_fp64.hpp"
+#include "k_proj.hpp"
 #include "k_reduce.hpp"
 #include "launch.hpp"
 
@@ -17,6 +18,43 @@ void launch_epilogue_f32(unsigned grid, hipStream_t s, const FragDesc* desc, con
                          int n_items, const float* arena, double* partials, int pstride) {
   hipLaunchKernelGGL((k_epilogue<float, float>), dim3(grid), dim3(256), 0, s, desc, items,
                      n_items, arena, partials, pstride);
+}
+
+void launch_proj_wq_f64(unsigned grid, hipStream_t s, const FragDesc* desc, const Item* items,
+                        int n_items, double* arena) {
+  hipLaunchKernelGGL((k_proj_wq<double, double>), dim3(grid), dim3(256), 0, s, desc, items,
+                     n_items, arena);
+}
+
+void launch_proj_wq_f32(unsigned grid, hipStream_t s, const FragDesc* desc, const Item* items,
+                        int n_items, float* arena) {
+  hipLaunchKernelGGL((k_proj_wq<float, float>), dim3(grid), dim3(256), 0, s, desc, items,
+                     n_items, arena);
+}
+
+void launch_proj_m_f64(hipStream_t s, const double* wt, const double* q, int64_t stride, int no,
+                       int64_t K, int64_t chunk, int chunks, double* part) {
+  const unsigned t = unsigned((no + 31) / 32);
+  hipLaunchKernelGGL(k_proj_m<double>, dim3(t, t, unsigned(chunks)), dim3(256), 0, s, wt, q,
+                     stride, no, K, chunk, part);
+}
+
+void launch_proj_m_f32(hipStream_t s, const float* wt, const float* q, int64_t stride, int no,
+                       int64_t K, int64_t chunk, int chunks, double* part) {
+  const unsigned t = unsigned((no + 31) / 32);
+  hipLaunchKernelGGL(k_proj_m<float>, dim3(t, t, unsigned(chunks)), dim3(256), 0, s, wt, q,
+                     stride, no, K, chunk, part);
+}
+
+void launch_proj_msum(hipStream_t s, const double* part, int chunks, int no, double weight,
+                      double* m) {
+  const int64_t n = int64_t(no) * no;
+  hipLaunchKernelGGL(k_proj_msum, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, part, chunks,
+                     no, weight, m);
+}
+
+void launch_proj_energy(hipStream_t s, const double* c, const double* m, int64_t n, double* out) {
+  hipLaunchKernelGGL(k_proj_energy, dim3(1), dim3(256), 0, s, c, m, n, out);
 }
 
 void launch_unit_energy(dim3 grid, hipStream_t s, const FragDesc* desc, const double* partials,

@@ -77,7 +77,8 @@ __host__ __device__ __forceinline__ int64_t cube_blocked_elems(int nv) {
 
 struct Item {
   int frag;               // fragment index
-  int unit;               // unit index u within the fragment (tetrahedral order)
+  int unit;               // unit index u >= 0 within the fragment (tetrahedral order), or
+                          // an ordered occupied triple (ordered_item, < 0)
   int64_t cube_off;       // element offset of the item's two partial cubes
   int64_t blk_end;        // inclusive end of the item's build blocks (prefix sum over the
                           // item's build segment: the round's items of one tile variant)

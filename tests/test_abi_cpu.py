@@ -80,7 +80,6 @@ def test_valid_workspace_query(lib):
     (dict(eps_occ=[-1.0, 0.5], eps_vir=[0.4, 1.0], o=2, v=2), _lib.SIE_ERR_INVALID_ARG),
     (dict(eps_occ=[-1.0, float("nan")], o=2), _lib.SIE_ERR_NONFINITE),
     (dict(eps_vir=[0.4, float("inf")], v=2), _lib.SIE_ERR_NONFINITE),
-    (dict(frag_proj=FAKE), _lib.SIE_ERR_UNSUPPORTED),
     (dict(o=100, v=700), _lib.SIE_ERR_UNSUPPORTED),             # float64 extent > 2^32 bytes
 ])
 def test_argument_errors(lib, kw, code):
@@ -252,3 +251,27 @@ def test_mp2_argument_errors(lib):
     assert lib.sie_mp2_workspace_size(ctypes.byref(desc()), 1) > \
         lib.sie_mp2_workspace_size(ctypes.byref(desc()), 0)
     assert lib.sie_mp2_workspace_size(ctypes.byref(desc(o=0)), 0) == 0
+
+
+def test_projector_argument_checks(lib):
+    """frag_proj is a host array the energy entry point reads on the host:
+    non-finite entries and a per-triple output request are rejected before
+    any HIP call; the batched entry point rejects a projector outright."""
+    keep = []
+    c = np.eye(4)
+    f = frag(keep=keep, frag_proj=c.ctypes.data)
+    assert energy(lib, f, e_tri=FAKE) == _lib.SIE_ERR_UNSUPPORTED
+    bad = np.eye(4)
+    bad[1, 2] = np.nan
+    fb = frag(keep=keep, frag_proj=bad.ctypes.data)
+    assert energy(lib, fb) == _lib.SIE_ERR_NONFINITE
+    assert lib.sie_triples_energy_batched(ctypes.byref(f), 1, _lib.SIE_FP64, FAKE, None, FAKE,
+                                          1 << 30, None) == _lib.SIE_ERR_UNSUPPORTED
+    n = lib.sie_triples_projector_workspace_size(ctypes.byref(f), _lib.SIE_FP64, 0)
+    assert n > 0
+    assert lib.sie_triples_workspace_size(ctypes.byref(f), 1, _lib.SIE_FP64, 0) == n
+    assert lib.sie_triples_projector_matrix(ctypes.byref(f), _lib.SIE_FP64, None, FAKE, n,
+                                            None) == _lib.SIE_ERR_INVALID_ARG
+    assert lib.sie_triples_projector_matrix(ctypes.byref(f), _lib.SIE_FP64, FAKE, FAKE, 64,
+                                            None) == _lib.SIE_ERR_WORKSPACE
+    keep.extend([c, bad])

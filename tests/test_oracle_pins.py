@@ -332,3 +332,22 @@ def test_planted_layout_mistakes_fail_p1():
     # t1 term with the wrong sign
     bad = oracle.energy_literal(eo, ev, -t1, t2, ovvv, ooov, ovov)
     assert rel(bad, e_so) > 1e-6
+
+
+# ---------------------------------------------------------------- P9b
+def test_p9b_projector_matrix():
+    """The projector matrix reproduces the projected energy of the
+    unrestricted reading for arbitrary C (computed there with C applied to
+    W-tilde first), its trace is the unprojected energy, and a complete
+    orthogonal set of projectors sums to it."""
+    args = random_symmetric_inputs(3, 4, 61)
+    m = oracle.projector_matrix(*args)
+    e = oracle.energy_literal(*args)
+    assert abs(np.trace(m) - e) <= 1e-12 * abs(e)
+    rng = np.random.default_rng(61)
+    c = rng.normal(size=(3, 3))
+    e_c = oracle.energy_dense(*args, frag_proj=c, form="unrestricted")
+    assert abs(float(np.sum(c * m)) - e_c) <= 1e-12 * abs(e_c)
+    u, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    parts = [u[:, :1] @ u[:, :1].T, u[:, 1:] @ u[:, 1:].T]
+    assert abs(sum(float(np.sum(p * m)) for p in parts) - e) <= 1e-12 * abs(e)
