@@ -68,9 +68,11 @@ struct AdjSlice {
   int64_t off0;
 };
 
-// Partial slices per output slice of the summed-block classes: the slice's
-// contributions are split over this many groups (work-group sets) for
-// parallelism, then summed in a fixed order.
+// Partial slices of the summed-block classes, per fragment and round: at
+// most kAdjParts n_o^2 (the workspace holds that many).  A slice's
+// contributions are split over groups (work-group sets) of about equal
+// length for parallelism, each writing a partial slice, then summed in a
+// fixed order.
 constexpr int kAdjParts = 4;
 
 struct AdjRec {
@@ -81,27 +83,40 @@ struct AdjRec {
 };
 
 // Tiles of the G contractions (4 waves per work-group, operands loaded from
-// L1/L2 straight into registers, two K-chunks of 8 in flight):
-//   per-block classes (ovvv, t2 from the l-sums): wave w owns blocks
-//     4w .. 4w + 3 x 32 rows x 32 cols, the work-group 16 blocks x 32 x 32;
+// L1/L2 straight into registers, two K-chunks of 8 in flight, the chunks of
+// all of a group's records in one continuous stream):
+//   per-block classes: wave w owns blocks 4w .. 4w + 3 of the work-group's
+//     16 blocks, each TRW x TCW 16-wide MFMA tiles: 32 x 32 for ovvv, 32 x 16
+//     for t2 from the l-sums (whose cols are the few occupied);
 //   summed-block classes (t2 from the d-sums, ooov): the first summed
-//     virtual runs in groups of kARB as the block index of both operands,
-//     summed at the end; waves tile 64 x 64 (t2: 2 x 2 waves of 32 x 32) or
-//     128 x 32 (ooov, whose cols are the few occupied: 4 x 1 waves).
+//     virtual runs in groups of kARB as the block index of both operands.
+//     t2: 2 x 2 waves of 64 x 64, each over the whole stream.  ooov (cols:
+//     the few occupied): all four waves compute the same 64 x 16 tile over
+//     every fourth chunk of the stream, and their accumulators are added
+//     through LDS in a fixed order.
 constexpr int kABlk = 4;                 // blocks per wave, per-block classes
 constexpr int kARB = 2;                  // summed-block group (blocks per wave) of the others
-constexpr int kAT = 2;                   // 16-wide MFMA tiles per wave along rows and cols
+constexpr int kAT = 2;                   // 16-wide MFMA tiles per wave along rows and cols (ovvv)
 constexpr int kAKc = 8;                  // K chunk
 constexpr int kAThreads = 256;
 
-// Work-group tile of a class: (blocks, rows, cols) per work-group: 4 waves
-// along the blocks (per-block classes), 2 x 2 waves (t2 from the d-sums) or
-// 4 x 1 (ooov).
+// 16-wide MFMA tiles per wave along rows (trw) and cols (tcw) of a class,
+// and the waves of a work-group along rows (wr) and cols (wc) of the output
+// (per-block classes: 1 x 1, the waves take different blocks; ooov: 1 x 1,
+// the waves take different chunks).
+__host__ __device__ constexpr int adj_trw(int cls) { return cls == kAdjT2vv || cls == kAdjOoov ? 4 : kAT; }
+__host__ __device__ constexpr int adj_tcw(int cls) {
+  return cls == kAdjOvvv ? kAT : cls == kAdjT2vv ? 4 : 1;
+}
+__host__ __device__ constexpr int adj_wr(int cls) { return cls == kAdjT2vv ? 2 : 1; }
+__host__ __device__ constexpr int adj_wc(int cls) { return cls == kAdjT2vv ? 2 : 1; }
+
+// Work-group tile of a class: (blocks, rows, cols) per work-group.
 __host__ __device__ inline void adj_tile_shape(int cls, int& tb, int& tr, int& tc) {
   const bool red = cls == kAdjT2vv || cls == kAdjOoov;
   tb = red ? 1 : 4 * kABlk;
-  tr = cls == kAdjT2vv ? 2 * 64 : cls == kAdjOoov ? 4 * 64 : 16 * kAT;
-  tc = cls == kAdjT2vv ? 2 * 64 : cls == kAdjOoov ? 32 : 16 * kAT;
+  tr = 16 * adj_trw(cls) * adj_wr(cls);
+  tc = 16 * adj_tcw(cls) * adj_wc(cls);
 }
 
 // Work-groups per output slice of a class for a fragment.

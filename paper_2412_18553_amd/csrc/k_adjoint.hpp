@@ -479,13 +479,14 @@ __device__ __forceinline__ AdjOut adj_out(const FragDesc& fd, const AdjGroup& gr
 
 // Wave tile of a class: BLK blocks x TRW x TCW 16-wide MFMA tiles.  The
 // summed-block classes run the summed virtual one block at a time through
-// K (BLK = 1) so that a wave holds a 64 x 64 (t2) or 64 x 32 (ooov) tile.
+// K (BLK = 1).
 template <int CLS>
 struct AdjWave {
   static constexpr bool kReduce = CLS == kAdjT2vv || CLS == kAdjOoov;
+  static constexpr bool kKSplit = CLS == kAdjOoov;   // waves split the stream
   static constexpr int BLK = kReduce ? 1 : kABlk;
-  static constexpr int TRW = kReduce ? 4 : kAT;
-  static constexpr int TCW = CLS == kAdjT2vv ? 4 : CLS == kAdjOoov ? 2 : kAT;
+  static constexpr int TRW = adj_trw(CLS);
+  static constexpr int TCW = adj_tcw(CLS);
 };
 
 __device__ __forceinline__ int find_group(const AdjGroup* __restrict__ gs, int n, int64_t x) {
@@ -496,6 +497,15 @@ __device__ __forceinline__ int find_group(const AdjGroup* __restrict__ gs, int n
   }
   return lo;
 }
+
+// Position in a group's chunk stream: record `rec`, summed virtual `kb` of
+// its block group (summed-block classes; 0 otherwise), K chunk `c`; `tm` is
+// the record's term.
+template <typename CubeT, typename InT>
+struct AdjPos {
+  int rec, kb, c;
+  ATerm<CubeT, InT> tm;
+};
 
 // Grid: the concatenated tiles of the launch's groups.  Block: 256 threads.
 // arena holds per unit G, H and Gt (cube_off, + half, + 2 half).  Per-block
@@ -509,7 +519,7 @@ __global__ __launch_bounds__(kAThreads, CLS == kAdjT2vv ? 1 : 2) void k_adj_cont
     const AdjGroup* __restrict__ groups, int n_groups, const AdjRec* __restrict__ recs,
     const CubeT* __restrict__ arena, double* __restrict__ parts) {
   using W = AdjWave<CLS>;
-  constexpr bool kReduce = W::kReduce;
+  constexpr bool kReduce = W::kReduce, kKSplit = W::kKSplit;
   constexpr int BLK = W::BLK, TRW = W::TRW, TCW = W::TCW;
   const int gi = find_group(groups, n_groups, blockIdx.x);
   const AdjGroup gr = groups[gi];
@@ -529,12 +539,14 @@ __global__ __launch_bounds__(kAThreads, CLS == kAdjT2vv ? 1 : 2) void k_adj_cont
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int r = lane & 15, g = lane >> 4;
-  // this wave's part of the tile
+  // this wave's part of the tile: its own blocks (per-block classes), its
+  // own sub-tile (t2 from the d-sums), or the whole tile and every fourth
+  // chunk (ooov)
   const int blk0 = kReduce ? 0 : tb * TB + wave * kABlk;
-  const int row0 = trow * TR + (CLS == kAdjT2vv ? (wave & 1) * 16 * TRW
-                                : CLS == kAdjOoov ? wave * 16 * TRW : 0);
-  const int col0 = tcol * TC + (CLS == kAdjT2vv ? (wave >> 1) * 16 * TCW : 0);
-  if ((!kReduce && blk0 >= o.nb) || row0 >= o.nr || col0 >= o.nc) return;   // no barriers
+  const int row0 = trow * TR + (adj_wr(CLS) > 1 ? (wave & 1) * 16 * TRW : 0);
+  const int col0 = tcol * TC + (adj_wc(CLS) > 1 ? (wave >> 1) * 16 * TCW : 0);
+  // work-group-uniform where the waves meet at barriers below (ooov)
+  if ((!kReduce && blk0 >= o.nb) || row0 >= o.nr || col0 >= o.nc) return;
   const int nrow = min(16 * TRW, o.nr - row0), ncol = min(16 * TCW, o.nc - col0);
   const int nblk_tile = kReduce ? 1 : min(kABlk, o.nb - blk0);
   const bool vec = fd.vec != 0;
@@ -552,38 +564,99 @@ __global__ __launch_bounds__(kAThreads, CLS == kAdjT2vv ? 1 : 2) void k_adj_cont
   const InT* ooovp = static_cast<const InT*>(fd.ooov);
   const int nchunk = (nv + kAKc - 1) / kAKc;
 
-  // one K run (a term, or one summed virtual of a summed-block term): two
-  // chunks in flight
-  auto run = [&](const ATerm<CubeT, InT>& tm, int nblk) {
-    AChunk<BLK, TRW, TCW> b0, b1;
-    adj_load(tm, kReduce, 0, nv, nrow, ncol, nblk, r, g, vec, b0);
-    for (int c = 0;; c += 2) {
-      adj_load(tm, kReduce, c + 1, nv, nrow, ncol, nblk, r, g, vec, b1);
-      adj_mma(b0, kReduce, nrow, ncol, acc);
-      if (c + 1 >= nchunk) break;
-      adj_load(tm, kReduce, c + 2, nv, nrow, ncol, nblk, r, g, vec, b0);
-      adj_mma(b1, kReduce, nrow, ncol, acc);
-      if (c + 2 >= nchunk) break;
-    }
-  };
-  for (int rec = gr.rec_begin; rec < gr.rec_end; ++rec) {
+  auto term = [&](int rec) {
     const AdjRec rr = recs[rec];
     const Item it = items[rr.item];
     int i, j, k;
     decode_sorted_triple(it.unit, no, i, j, k);
     const CubeT* G = arena + it.cube_off;
-    const ATerm<CubeT, InT> tm = make_adj<CLS, CubeT, InT>(
-        rr.kind, rr.g, i, j, k, no, nv, G, G + 2 * fd.half, t2p, ovvvp, ooovp, blk0, row0, col0);
-    if (kReduce) {
-      for (int kb = 0; kb < tm.nblk; ++kb) {   // the group's summed virtuals, one at a time
-        ATerm<CubeT, InT> t1 = tm;
-        t1.a += kb * tm.a_b;
-        t1.b += kb * tm.b_b;
-        run(t1, 1);
-      }
-    } else {
-      run(tm, nblk_tile);
+    return make_adj<CLS, CubeT, InT>(rr.kind, rr.g, i, j, k, no, nv, G, G + 2 * fd.half, t2p,
+                                     ovvvp, ooovp, blk0, row0, col0);
+  };
+  // advance a position by `step` chunks of the stream
+  auto advance = [&](AdjPos<CubeT, InT>& p, int step) {
+    p.c += step;
+    while (p.c >= nchunk && p.rec < gr.rec_end) {
+      p.c -= nchunk;
+      if (kReduce && ++p.kb < p.tm.nblk) continue;
+      p.kb = 0;
+      if (++p.rec < gr.rec_end) p.tm = term(p.rec);
     }
+  };
+  auto load = [&](const AdjPos<CubeT, InT>& p, AChunk<BLK, TRW, TCW>& x) {
+    if (kReduce) {
+      ATerm<CubeT, InT> t1 = p.tm;
+      t1.a += p.kb * p.tm.a_b;
+      t1.b += p.kb * p.tm.b_b;
+      adj_load(t1, true, p.c, nv, nrow, ncol, 1, r, g, vec, x);
+    } else {
+      adj_load(p.tm, false, p.c, nv, nrow, ncol, nblk_tile, r, g, vec, x);
+    }
+  };
+
+  if (gr.rec_begin < gr.rec_end) {
+    // one stream over the group's records with two chunks in flight
+    AdjPos<CubeT, InT> p;
+    p.rec = gr.rec_begin;
+    p.kb = 0;
+    p.c = 0;
+    p.tm = term(p.rec);
+    const int step = kKSplit ? 4 : 1;
+    if (kKSplit) advance(p, wave);
+    AChunk<BLK, TRW, TCW> b0, b1;
+    bool have = p.rec < gr.rec_end;
+    if (have) load(p, b0);
+    while (have) {
+      advance(p, step);
+      const bool have1 = p.rec < gr.rec_end;
+      if (have1) load(p, b1);
+      adj_mma(b0, kReduce, nrow, ncol, acc);
+      if (!have1) break;
+      advance(p, step);
+      have = p.rec < gr.rec_end;
+      if (have) load(p, b0);
+      adj_mma(b1, kReduce, nrow, ncol, acc);
+    }
+  }
+
+  if (kKSplit) {
+    // (acc0 + acc2) + (acc1 + acc3) through LDS, a fixed order
+    constexpr int NV = kKSplit ? TRW * TCW * 4 : 1;
+    __shared__ double red[2][NV][64];
+    if (wave >= 2) {
+#pragma unroll
+      for (int rt = 0; rt < TRW; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < TCW; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) red[wave - 2][(rt * TCW + ct) * 4 + v][lane] = acc[0][rt][ct][v];
+    }
+    __syncthreads();
+    if (wave < 2) {
+#pragma unroll
+      for (int rt = 0; rt < TRW; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < TCW; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[0][rt][ct][v] += red[wave][(rt * TCW + ct) * 4 + v][lane];
+    }
+    __syncthreads();
+    if (wave == 1) {
+#pragma unroll
+      for (int rt = 0; rt < TRW; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < TCW; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) red[0][(rt * TCW + ct) * 4 + v][lane] = acc[0][rt][ct][v];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int rt = 0; rt < TRW; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < TCW; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[0][rt][ct][v] += red[0][(rt * TCW + ct) * 4 + v][lane];
   }
 
   // acc[beta][rt][ct][v] = out[blk0 + beta][row0 + 16 rt + 4 v + g][col0 + 16 ct + r]

@@ -215,7 +215,7 @@ Plan make_plan(const sie_fragment* frags, int n, sie_precision prec, bool grad =
     if (grad) {
       p.adj_recs += size_t(fp.work_units) * adj_recs_per_unit(fp.nv);
       // a round's slices of a summed-block class are distinct occupied pairs
-      // (at most n_o^2 per fragment), each with at most kAdjParts partials
+      // (at most n_o^2 per fragment), with kAdjParts n_o^2 partials in all
       const size_t slice = size_t(fp.nv) * size_t(fp.nv > fp.no ? fp.nv : fp.no);
       p.part_elems += size_t(sie::kAdjParts) * size_t(fp.no) * size_t(fp.no) * slice;
     }
@@ -1192,6 +1192,28 @@ void adj_round_lists(const Tables& T, size_t r0, size_t r1, std::vector<sie::Adj
     launch[cls].n_groups = 0;
     launch[cls].rec_begin = int(recs.size());
     launch[cls].slice_off = slices.size();
+    const bool red = sie::adj_reduce(cls);
+    // summed-block classes: each slice's records split into contiguous
+    // ranges of at most per_group[frag] records, each a group writing its
+    // own partial slice.  per_group is the fragment's records over its
+    // budget of kAdjParts n_o^2 partial slices less one per slice, so that
+    // the ceilings stay within the budget the workspace holds and the
+    // groups are of about equal length.
+    std::vector<int64_t> per_group;
+    if (red) {
+      std::vector<int64_t> n_rec(T.desc.size(), 0), n_sl(T.desc.size(), 0);
+      for (size_t q = 0; q < list.size(); ++q) {
+        ++n_rec[size_t(list[q].first.frag)];
+        if (q == 0 || list[q - 1].first < list[q].first) ++n_sl[size_t(list[q].first.frag)];
+      }
+      per_group.assign(T.desc.size(), 1);
+      for (size_t f = 0; f < T.desc.size(); ++f) {
+        const int64_t budget =
+            int64_t(sie::kAdjParts) * T.desc[f].no * T.desc[f].no - n_sl[f];
+        const int64_t b = budget > 1 ? budget : 1;
+        per_group[f] = n_rec[f] > 0 ? (n_rec[f] + b - 1) / b : 1;
+      }
+    }
     int64_t wg = 0, part_elems = 0;
     for (size_t q = 0; q < list.size();) {
       size_t e = q;
@@ -1199,11 +1221,9 @@ void adj_round_lists(const Tables& T, size_t r0, size_t r1, std::vector<sie::Adj
         ++e;
       const Key& key = list[q].first;
       const sie::FragDesc& d = T.desc[size_t(key.frag)];
-      // summed-block classes: the slice's records split into up to kAdjParts
-      // contiguous ranges, each a group writing its own partial slice
-      const bool red = sie::adj_reduce(cls);
       const int n = int(e - q);
-      const int np = red ? (n < sie::kAdjParts ? n : sie::kAdjParts) : 1;
+      const int np = red ? int((n + per_group[size_t(key.frag)] - 1) / per_group[size_t(key.frag)])
+                         : 1;
       const int64_t el = red ? adj_slice_elems(cls, d.no, d.nv) : 0;
       const int64_t off0 = part_elems;
       if (red) {
@@ -1228,6 +1248,20 @@ void adj_round_lists(const Tables& T, size_t r0, size_t r1, std::vector<sie::Adj
         ++launch[cls].n_groups;
       }
       q = e;
+    }
+    if (cls <= sie::kAdjOoov) {
+      // longest groups first in the grid (the dispatcher starts them in
+      // order).  A summed-block group keeps its partial slice, and a
+      // per-block slice has one group per launch, so no sum changes.
+      const auto first = groups.begin() + std::ptrdiff_t(launch[cls].group_off);
+      std::stable_sort(first, groups.end(), [](const sie::AdjGroup& a, const sie::AdjGroup& b) {
+        return a.rec_end - a.rec_begin > b.rec_end - b.rec_begin;
+      });
+      wg = 0;
+      for (auto g = first; g != groups.end(); ++g) {
+        wg += sie::adj_tiles(cls, T.desc[size_t(g->frag)].no, T.desc[size_t(g->frag)].nv);
+        g->wg_end = wg;
+      }
     }
     launch[cls].n_wg = wg;
     launch[cls].rec_end = int(recs.size());
