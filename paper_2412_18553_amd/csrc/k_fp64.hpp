@@ -691,7 +691,7 @@ __device__ __forceinline__ void epi_load_w(const CubeT* __restrict__ w1,
 // takes orbits p, p + n_part, ...).  Register bound: five waves a SIMD with
 // float32 cubes (the LDS allows five work-groups a CU), four with float64.
 template <typename CubeT, typename InT>
-__global__ __launch_bounds__(256, sizeof(CubeT) == 4 ? 5 : 4) void k_epilogue(const FragDesc* __restrict__ descs,
+__global__ __launch_bounds__(256, 4) void k_epilogue(const FragDesc* __restrict__ descs,
                                                   const Item* __restrict__ items, int n_items,
                                                   const CubeT* __restrict__ arena,
                                                   double* __restrict__ partials, int pstride) {
@@ -756,32 +756,54 @@ __global__ __launch_bounds__(256, sizeof(CubeT) == 4 ? 5 : 4) void k_epilogue(co
     double wreg[12];
     if (l3) epi_load_w<true>(w1, w2, w3, nb, t0, t1b, t2b, wreg);
     else epi_load_w<false>(w1, w2, w3, nb, t0, t1b, t2b, wreg);
-    __syncthreads();   // sv filled
+    // the (ia|jb), (ia|kc), (jb|kc) elements of the six slots: with float32
+    // inputs issued with the cube loads (held as loaded), so that the orbit
+    // waits on memory once; float64 inputs (twice the registers) load them
+    // after the barrier
+    constexpr bool kEarly = sizeof(InT) == 4;
     const int x = threadIdx.x >> 5, y = (threadIdx.x >> 2) & 7, z0 = 2 * (threadIdx.x & 3);
+    InT rij[6], rik[6][2], rjk[6][2];
+    auto ov_load = [&](int s) {
+      int p0, p1, p2;
+      slot_perm(s, p0, p1, p2);
+      const int ac = min(kOrb * pick3(p0, t0, t1b, t2b) + x, nv - 1);
+      const int bc = min(kOrb * pick3(p1, t0, t1b, t2b) + y, nv - 1);
+      const int c0 = kOrb * pick3(p2, t0, t1b, t2b) + z0;
+      rij[s] = gptr(ov_ij)[(int64_t)ac * nonv + bc];
+      if (fd.epv) {
+        // nv even: an in-range even c0 has c0 + 1 < nv, so the pair is aligned
+        const int cc = min(c0, nv - 2);
+        rik[s][0] = gptr(ov_ik)[(int64_t)ac * nonv + cc];
+        rik[s][1] = gptr(ov_ik)[(int64_t)ac * nonv + cc + 1];
+        rjk[s][0] = gptr(ov_jk)[(int64_t)bc * nonv + cc];
+        rjk[s][1] = gptr(ov_jk)[(int64_t)bc * nonv + cc + 1];
+      } else {
+        rik[s][0] = gptr(ov_ik)[(int64_t)ac * nonv + min(c0, nv - 1)];
+        rik[s][1] = gptr(ov_ik)[(int64_t)ac * nonv + min(c0 + 1, nv - 1)];
+        rjk[s][0] = gptr(ov_jk)[(int64_t)bc * nonv + min(c0, nv - 1)];
+        rjk[s][1] = gptr(ov_jk)[(int64_t)bc * nonv + min(c0 + 1, nv - 1)];
+      }
+    };
+    if (kEarly) {
+#pragma unroll
+      for (int s = 0; s < 6; ++s) ov_load(s);
+    }
+    __syncthreads();   // sv filled
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
       int p0, p1, p2;
       slot_perm(s, p0, p1, p2);
       const int a = kOrb * pick3(p0, t0, t1b, t2b) + x;
       const int b = kOrb * pick3(p1, t0, t1b, t2b) + y;
-      const int c0 = kOrb * pick3(p2, t0, t1b, t2b) + z0;
-      const int ac = min(a, nv - 1), bc = min(b, nv - 1);
-      double oik[2], ojk[2];
-      const double oij = (double)gptr(ov_ij)[(int64_t)ac * nonv + bc];
-      if (fd.epv) {
-        ld_pair<InT, true>(ov_ik, ac, nonv, c0, nv, oik);
-        ld_pair<InT, true>(ov_jk, bc, nonv, c0, nv, ojk);
-      } else {
-        ld_pair<InT, false>(ov_ik, ac, nonv, c0, nv, oik);
-        ld_pair<InT, false>(ov_jk, bc, nonv, c0, nv, ojk);
-      }
+      if (!kEarly) ov_load(s);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int zz = z0 + h;
         double z = 0.0;
         if (a < nv && b < nv && zz + kOrb * pick3(p2, t0, t1b, t2b) < nv) {
-          const double vt = oij * V[(9 + p2) * kOrb + zz] + oik[h] * V[(6 + p1) * kOrb + y] +
-                            ojk[h] * V[(3 + p0) * kOrb + x];
+          const double vt = (double)rij[s] * V[(9 + p2) * kOrb + zz] +
+                            (double)rik[s][h] * V[(6 + p1) * kOrb + y] +
+                            (double)rjk[s][h] * V[(3 + p0) * kOrb + x];
           z = wreg[2 * s + h] + vt;
         } else {
           wreg[2 * s + h] = 0.0;

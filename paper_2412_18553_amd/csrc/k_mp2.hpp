@@ -33,6 +33,10 @@
 namespace sie {
 
 constexpr int kMp2Tile = 64;   // virtual tile edge of k_mp2_pair (2 x 2 waves of 32 x 32)
+// Wave tiles (16-wide MFMA tiles, rows x cols) of the Gram products: gamma_vv
+// (n_v x n_v outputs, K = n_v per batch entry) and gamma_oo (n_o x n_o, few
+// outputs: small tiles keep enough work-groups).
+constexpr int kGramVvM = 4, kGramVvN = 2, kGramOoM = 1, kGramOoN = 1;
 
 // Two consecutive float64 values along the contraction of row `row` at
 // column k0 (k0 even), zero past K; `even`: rows start 16-byte aligned.
@@ -180,41 +184,96 @@ struct GramArgs {
   double* part;
 };
 
-template <bool PAIRT>
+// Wave tile of the Gram products: TM x TN 16-wide MFMA tiles; work-group:
+// 2 x 2 waves, (32 TM) x (32 TN) outputs.  A work-group runs the chunks of
+// its batch range as one stream with two chunks in flight.
+template <bool PAIRT, int TM, int TN>
 __global__ __launch_bounds__(256, 2) void k_mp2_gram(GramArgs ga) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = lane & 15, g = lane >> 4;
-  const int m0 = blockIdx.y * 32 + 16 * (wave >> 1), n0 = blockIdx.x * 32 + 16 * (wave & 1);
-  const int rm = min(m0 + r, ga.M - 1), rn = min(n0 + r, ga.N - 1);
+  const int m0 = blockIdx.y * 32 * TM + 16 * TM * (wave >> 1);
+  const int n0 = blockIdx.x * 32 * TN + 16 * TN * (wave & 1);
+  int rm[TM], rn[TN];
+#pragma unroll
+  for (int t = 0; t < TM; ++t) rm[t] = min(m0 + 16 * t + r, ga.M - 1);
+#pragma unroll
+  for (int t = 0; t < TN; ++t) rn[t] = min(n0 + 16 * t + r, ga.N - 1);
   const bool even = (ga.K % 2) == 0 && (ga.sAm % 2) == 0 && (ga.sB1n % 2) == 0 &&
                     (ga.sB2n % 2) == 0 && (ga.sAq % 2) == 0 && (ga.sB1q % 2) == 0 &&
                     (ga.sB2q % 2) == 0;
   const int q0 = blockIdx.z * ga.per, q1 = min(q0 + ga.per, ga.nq);
-  d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+  d4 acc[TM][TN];
+#pragma unroll
+  for (int u = 0; u < TM; ++u)
+#pragma unroll
+    for (int v = 0; v < TN; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
   const int nch = (ga.K + 7) / 8;
-  for (int q = q0; q < q1; ++q) {
+  struct Chunk {
+    d2v x[TM], y1[TN], y2[TN];
+  };
+  auto load = [&](int q, int c, Chunk& ch) {
     const int q2 = PAIRT ? (q % ga.no) * ga.no + q / ga.no : q;
     const double* pa = ga.a + (int64_t)q * ga.sAq;
     const double* p1 = ga.b1 + (int64_t)q * ga.sB1q;
     const double* p2 = ga.b2 + (int64_t)q2 * ga.sB2q;
-    for (int c = 0; c < nch; ++c) {
-      const int k0 = 8 * c + 2 * g;
-      const d2v x = mp2_ld2(pa, rm, ga.sAm, k0, ga.K, even);
-      const d2v y1 = mp2_ld2(p1, rn, ga.sB1n, k0, ga.K, even);
-      const d2v y2 = mp2_ld2(p2, rn, ga.sB2n, k0, ga.K, even);
-      const double yx = ga.alpha * y1.x + ga.beta * y2.x;
-      const double yy = ga.alpha * y1.y + ga.beta * y2.y;
-      acc = mfma16x16x4(x.x, yx, acc);
-      acc = mfma16x16x4(x.y, yy, acc);
+    const int k0 = 8 * c + 2 * g;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) ch.x[t] = mp2_ld2(pa, rm[t], ga.sAm, k0, ga.K, even);
+#pragma unroll
+    for (int t = 0; t < TN; ++t) {
+      ch.y1[t] = mp2_ld2(p1, rn[t], ga.sB1n, k0, ga.K, even);
+      ch.y2[t] = mp2_ld2(p2, rn[t], ga.sB2n, k0, ga.K, even);
+    }
+  };
+  auto mma = [&](const Chunk& ch) {
+    double yx[TN], yy[TN];
+#pragma unroll
+    for (int t = 0; t < TN; ++t) {
+      yx[t] = ga.alpha * ch.y1[t].x + ga.beta * ch.y2[t].x;
+      yy[t] = ga.alpha * ch.y1[t].y + ga.beta * ch.y2[t].y;
+    }
+#pragma unroll
+    for (int u = 0; u < TM; ++u)
+#pragma unroll
+      for (int v = 0; v < TN; ++v) {
+        acc[u][v] = mfma16x16x4(ch.x[u].x, yx[v], acc[u][v]);
+        acc[u][v] = mfma16x16x4(ch.x[u].y, yy[v], acc[u][v]);
+      }
+  };
+  auto next = [&](int& q, int& c) {
+    if (++c == nch) {
+      c = 0;
+      ++q;
+    }
+  };
+  if (q0 < q1) {
+    int q = q0, c = 0;
+    Chunk b0, b1;
+    load(q, c, b0);
+    for (;;) {
+      next(q, c);
+      const bool h1 = q < q1;
+      if (h1) load(q, c, b1);
+      mma(b0);
+      if (!h1) break;
+      next(q, c);
+      const bool h0 = q < q1;
+      if (h0) load(q, c, b0);
+      mma(b1);
+      if (!h0) break;
     }
   }
   double* out = ga.part + (int64_t)blockIdx.z * ga.M * ga.N;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int m = m0 + 4 * u + g, n = n0 + r;
-    if (m < ga.M && n < ga.N) gptr_w(out)[(int64_t)m * ga.N + n] = acc[u];
-  }
+  for (int u = 0; u < TM; ++u)
+#pragma unroll
+    for (int v = 0; v < TN; ++v)
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int m = m0 + 16 * u + 4 * w + g, n = n0 + 16 * v + r;
+        if (m < ga.M && n < ga.N) gptr_w(out)[(int64_t)m * ga.N + n] = acc[u][v][w];
+      }
 }
 
 // out[m][n] = diag * delta_mn + scale * sum_{s < groups} part[s][m][n], the

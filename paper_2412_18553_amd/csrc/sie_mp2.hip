@@ -38,9 +38,12 @@ Mp2Plan mp2_plan(const sie_mp2_input& in, bool density, bool own_t2) {
     per = int((nq + want - 1) / want);
     g = int((nq + per - 1) / per);
   };
-  const int64_t tv = (v + 31) / 32, to = (o + 31) / 32;
-  groups(o * o, tv * tv, p.g_vv, p.per_vv);
-  groups(o, to * to, p.g_oo, p.per_oo);
+  const int64_t tvm = (v + 32 * sie::kGramVvM - 1) / (32 * sie::kGramVvM);
+  const int64_t tvn = (v + 32 * sie::kGramVvN - 1) / (32 * sie::kGramVvN);
+  const int64_t tom = (o + 32 * sie::kGramOoM - 1) / (32 * sie::kGramOoM);
+  const int64_t ton = (o + 32 * sie::kGramOoN - 1) / (32 * sie::kGramOoN);
+  groups(o * o, tvm * tvn, p.g_vv, p.per_vv);
+  groups(o, tom * ton, p.g_oo, p.per_oo);
   size_t off = 0;
   p.off_eps = off;
   off = align256(off + sizeof(double) * size_t(o + v));
@@ -147,8 +150,10 @@ sie_status sie_mp2(const sie_mp2_input* in, double* e_out, double* t2, double* g
     if (gamma_vv) {
       sie::GramArgs ga{d_t2, d_t2, d_t2, nv2, v, nv2, v, nv2, v, v, v, v, o * o, pl.per_vv, o,
                        2.0, -1.0, d_gram};
-      hipLaunchKernelGGL(sie::k_mp2_gram<true>,
-                         dim3(unsigned((v + 31) / 32), unsigned((v + 31) / 32), unsigned(pl.g_vv)),
+      hipLaunchKernelGGL((sie::k_mp2_gram<true, sie::kGramVvM, sie::kGramVvN>),
+                         dim3(unsigned((v + 32 * sie::kGramVvN - 1) / (32 * sie::kGramVvN)),
+                              unsigned((v + 32 * sie::kGramVvM - 1) / (32 * sie::kGramVvM)),
+                              unsigned(pl.g_vv)),
                          dim3(256), 0, s, ga);
       hipLaunchKernelGGL(sie::k_mp2_gram_sum, dim3(unsigned((nv2 + 255) / 256)), dim3(256), 0, s,
                          d_gram, pl.g_vv, v, v, 2.0, 0.0, gamma_vv);
@@ -157,8 +162,10 @@ sie_status sie_mp2(const sie_mp2_input* in, double* e_out, double* t2, double* g
       const int64_t onv2 = int64_t(o) * nv2;
       sie::GramArgs ga{d_t2, d_t2, d_t2, nv2, onv2, nv2, onv2, onv2, nv2, o, o,
                        int(nv2), o, pl.per_oo, o, 2.0, -1.0, d_gram};
-      hipLaunchKernelGGL(sie::k_mp2_gram<false>,
-                         dim3(unsigned((o + 31) / 32), unsigned((o + 31) / 32), unsigned(pl.g_oo)),
+      hipLaunchKernelGGL((sie::k_mp2_gram<false, sie::kGramOoM, sie::kGramOoN>),
+                         dim3(unsigned((o + 32 * sie::kGramOoN - 1) / (32 * sie::kGramOoN)),
+                              unsigned((o + 32 * sie::kGramOoM - 1) / (32 * sie::kGramOoM)),
+                              unsigned(pl.g_oo)),
                          dim3(256), 0, s, ga);
       hipLaunchKernelGGL(sie::k_mp2_gram_sum, dim3(unsigned((int64_t(o) * o + 255) / 256)),
                          dim3(256), 0, s, d_gram, pl.g_oo, o, o, -2.0, 2.0, gamma_oo);
