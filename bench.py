@@ -1,6 +1,7 @@
 """Throughput of the per-fragment (T) energy on one MI355X.
 
-python bench.py [--steps K] [--warmup W] [--mode split|fp64|batched|backward|peak]
+python bench.py [--steps K] [--warmup W]
+                [--mode split|fp64|batched|backward|projector|mp2|peak]
                 [--workload NAME] [--precision fp64|split_bf16] [--no-cpu] [--no-fp64]
 
 Default (the headline line): a step is one full split-precision (T) energy
@@ -40,7 +41,8 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak (published)
 CHEM_SCALE = 2.0 ** -9            # integrals and t2 of the chemically scaled copy
 
 DEFAULT_WORKLOAD = {"fp64": "o24v200", "split": "o32v320", "batched": "batch16",
-                    "backward": "o16v120", "peak": None, "mp2": "mp2_o64v512"}
+                    "backward": "o16v120", "peak": None, "mp2": "mp2_o64v512",
+                    "projector": "o24v200"}
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
@@ -348,6 +350,8 @@ def run_single(args, result, name, mode):
         ws = torch.empty(sie.backward_workspace_size(fr), dtype=torch.uint8, device=dev)
         grads = [{n: torch.empty_like(getattr(fr, n), dtype=torch.float64)
                   for n in sie.GRAD_NAMES}]
+        grads[0].update({n: torch.empty(len(getattr(fr, n)), dtype=torch.float64, device=dev)
+                         for n in sie.EPS_GRAD_NAMES})
         step = lambda: sie.backward(fr, grads=grads, e_frag=out, workspace=ws)  # noqa: E731
     else:
         ws = torch.empty(sie.workspace_size(fr), dtype=torch.uint8, device=dev)
@@ -373,7 +377,7 @@ def run_single(args, result, name, mode):
         result.update(metric="(T) gradient TFLOP/s (3 x F per step)",
                       value=round(3.0 * F / (ms * 1e-3) / 1e12, 3), dtype="f64",
                       config={"workload": desc, "precision": "fp64", "fragments": 1,
-                              "outputs": "dE/d(t1, t2, ovvv, ooov, ovov)"})
+                              "outputs": "dE/d(t1, t2, ovvv, ooov, ovov, eps_occ, eps_vir)"})
         result["roofline"] = roofline(prof, "grad", "k_adj_contract", 2.0 * F, args.steps,
                                       PEAK_FP64_MFMA_TFLOPS, measured=peak64, workload=name)
     result.update(ms_per_step=round(ms, 3), fragments_per_s=round(1000.0 / ms, 4), energy=energy)
@@ -382,6 +386,50 @@ def run_single(args, result, name, mode):
         del df, fr
         torch.cuda.empty_cache()
         result["cpu_baseline"] = cpu_baseline(host)
+    result["kernel_ms_per_step"] = {k: round(t / args.steps, 3) for k, (t, _) in prof.items()}
+
+
+def run_projector(args, result, name):
+    """The fragment-projector matrix M of a fragment (E_x(C) = sum C M for any
+    C; tr M = E_x), float64, with the unprojected energy of the same
+    fragment timed alongside.  Work: the W-tilde build of every ordered
+    occupied triple (i', j, k), j >= k, plus the n_o x n_o products over the
+    cubes of each pair (j, k)."""
+    import torch
+    import paper_2412_18553_amd as sie
+    from synth import WORKLOADS
+    from synth.device import workload_fragment_device
+    w = WORKLOADS[name]
+    o, v = w["n_occ"], w["n_vir"]
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    df = workload_fragment_device(name, device=dev)
+    log(f"# workload {name}: built on the GPU in {time.perf_counter() - t0:.1f} s")
+    fr = frag_of(df, "fp64")
+    groups = o * (o + 1) // 2
+    build = float(groups * o) * (12.0 * v ** 4 + 12.0 * o * v ** 3)
+    contract = float(groups) * 2.0 * o * o * v ** 3
+    m = torch.empty((o, o), dtype=torch.float64, device=dev)
+    step = lambda: sie.projector_matrix(fr, out=m)  # noqa: E731
+    ms, prof = timed(step, args.steps, args.warmup)
+    tr = float(torch.trace(m).item())
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    ws = torch.empty(sie.workspace_size(fr), dtype=torch.uint8, device=dev)
+    e_step = lambda: sie.energy(fr, workspace=ws, out=out)  # noqa: E731
+    ms_e, _ = timed(e_step, 1, 1)
+    energy = float(out.item())
+    peak64 = measured_peak(0)
+    result.update(metric="projector matrix TFLOP/s (ordered-triple build + M products)",
+                  value=round((build + contract) / (ms * 1e-3) / 1e12, 3), dtype="f64",
+                  config={"workload": f"single fragment n_occ={o} n_vir={v} n_aux={w['n_aux']}",
+                          "precision": "fp64", "fragments": 1, "outputs": "M [n_occ][n_occ]"},
+                  ms_per_step=round(ms, 3), energy_ms=round(ms_e, 3),
+                  cost_over_energy=round(ms / ms_e, 3), trace_m=tr, energy=energy,
+                  trace_rel_err=float(f"{(tr - energy) / abs(energy):.3e}"))
+    # ordered triples are built with a two-layout shape
+    result["roofline"] = roofline(prof, "w_build", "k_build_w_f64", build, args.steps,
+                                  PEAK_FP64_MFMA_TFLOPS, measured=peak64)
+    result["roofline"]["work"] = "ordered-triple build flops"
     result["kernel_ms_per_step"] = {k: round(t / args.steps, 3) for k, (t, _) in prof.items()}
 
 
@@ -561,6 +609,8 @@ def main():
         run_single(args, result, name, mode)
     elif mode == "mp2":
         run_mp2(args, result, name)
+    elif mode == "projector":
+        run_projector(args, result, name)
     else:
         run_batched(args, result, name)
     print(json.dumps(result), flush=True)

@@ -13,11 +13,12 @@
 // ordered triples (i', j, k), i' = 0 .. n_o - 1, of one pair j >= k at a
 // time (a "group"; (i', k, j) is the b <-> c image of (i', j, k), so a group
 // with j > k counts twice): the build kernels write the two partial cubes of
-// every ordered triple (row-major), k_proj_wq replaces them by Wt and Q (R in
-// its virtual form at the fixed ordered triple, as in the energy), and
-// k_proj_m / k_proj_msum form the group's n_o x n_o product of Q and Wt
-// cubes on the float64 matrix cores (split over the cube in chunks, summed in
-// a fixed order) and add it into M.
+// every ordered triple (8^3-blocked, cube_at), k_proj_wq replaces them by Wt
+// and Q (R in its virtual form at the fixed ordered triple, as in the
+// energy; zeros in the padding past n_v), and k_proj_m / k_proj_msum form the
+// group's n_o x n_o product of Q and Wt cubes over every element of the
+// blocked cube on the float64 matrix cores (split in chunks, summed in a
+// fixed order) and add it into M.
 #pragma once
 
 #include "device_common.hpp"
@@ -75,8 +76,8 @@ __global__ __launch_bounds__(256) void k_proj_wq(const FragDesc* __restrict__ de
       const int c = kOrb * pick3(p2, t0, t1b, t2b) + (e & 7);
       double w = 0.0, z = 0.0;
       if (a < nv && b < nv && c < nv) {
-        w = (double)gptr(w1)[((int64_t)a * nv + b) * nv + c] +
-            (double)gptr(w2)[((int64_t)b * nv + a) * nv + c];
+        w = (double)gptr(w1)[cube_at(true, nv, a, b, c)] +
+            (double)gptr(w2)[cube_at(true, nv, b, a, c)];
         const double vt = (double)gptr(ov_ij)[(int64_t)a * nonv + b] * (double)gptr(t1k)[c] +
                           (double)gptr(ov_ik)[(int64_t)a * nonv + c] * (double)gptr(t1j)[b] +
                           (double)gptr(ov_jk)[(int64_t)b * nonv + c] * (double)gptr(t1i)[a];
@@ -111,7 +112,12 @@ __global__ __launch_bounds__(256) void k_proj_wq(const FragDesc* __restrict__ de
       const int a = kOrb * pick3(p0, t0, t1b, t2b) + x;
       const int b = kOrb * pick3(p1, t0, t1b, t2b) + y;
       const int c = kOrb * pick3(p2, t0, t1b, t2b) + zz;
-      if (a >= nv || b >= nv || c >= nv) continue;
+      const int64_t pos = cube_at(true, nv, a, b, c);
+      if (a >= nv || b >= nv || c >= nv) {   // padding: zero in both cubes
+        gptr_w(w1)[pos] = CubeT(0);
+        gptr_w(w2)[pos] = CubeT(0);
+        continue;
+      }
       const double rz = 4.0 * sz[s][orb_lds(x, y, zz)] +
                         sz[orbit_slot(p2, p0, p1)][orb_lds(zz, x, y)] +
                         sz[orbit_slot(p1, p2, p0)][orb_lds(y, zz, x)] -
@@ -119,7 +125,6 @@ __global__ __launch_bounds__(256) void k_proj_wq(const FragDesc* __restrict__ de
                                sz[orbit_slot(p0, p2, p1)][orb_lds(x, zz, y)] +
                                sz[orbit_slot(p1, p0, p2)][orb_lds(y, x, zz)]);
       const double id = recip(eijk - gptr(ev)[a] - gptr(ev)[b] - gptr(ev)[c]);
-      const int64_t pos = ((int64_t)a * nv + b) * nv + c;
       gptr_w(w1)[pos] = CubeT(sw[s][orb_lds(x, y, zz)]);
       gptr_w(w2)[pos] = CubeT(rz * id);
     }
@@ -148,13 +153,27 @@ __global__ __launch_bounds__(256, 2) void k_proj_m(const CubeT* __restrict__ wt,
   d4 acc = d4{0.0, 0.0, 0.0, 0.0};
   // steps of 8 elements, the same trip count for every lane (the matrix
   // instructions run on the whole wave); lane group g takes elements
-  // kb + 2g, kb + 2g + 1, zero past the chunk
+  // kb + 2g, kb + 2g + 1, zero past the chunk.  Chunk starts are even and the
+  // cubes 8-aligned, so with even stride and K a full pair is one 2-element
+  // load (`pair`).
+  const bool pair = (stride % 2) == 0 && (K % 2) == 0 && (chunk % 2) == 0;
+  typedef typename std::conditional<sizeof(CubeT) == 8, d2v, f2v>::type V2;
   for (int64_t kb = k_begin; kb < k_end; kb += 8) {
     const int64_t k0 = kb + 2 * g;
-    const double a0 = k0 < k_end ? (double)gptr(pa)[k0] : 0.0;
-    const double b0 = k0 < k_end ? (double)gptr(pb)[k0] : 0.0;
-    const double a1 = k0 + 1 < k_end ? (double)gptr(pa)[k0 + 1] : 0.0;
-    const double b1 = k0 + 1 < k_end ? (double)gptr(pb)[k0 + 1] : 0.0;
+    double a0, a1, b0, b1;
+    if (pair && k0 + 1 < k_end) {
+      const V2 u = *(const SIE_GLOBAL V2*)(gptr(pa) + k0);
+      const V2 w = *(const SIE_GLOBAL V2*)(gptr(pb) + k0);
+      a0 = (double)u.x;
+      a1 = (double)u.y;
+      b0 = (double)w.x;
+      b1 = (double)w.y;
+    } else {
+      a0 = k0 < k_end ? (double)gptr(pa)[k0] : 0.0;
+      b0 = k0 < k_end ? (double)gptr(pb)[k0] : 0.0;
+      a1 = k0 + 1 < k_end ? (double)gptr(pa)[k0 + 1] : 0.0;
+      b1 = k0 + 1 < k_end ? (double)gptr(pb)[k0 + 1] : 0.0;
+    }
     acc = mfma16x16x4(a0, b0, acc);
     acc = mfma16x16x4(a1, b1, acc);
   }
@@ -166,16 +185,26 @@ __global__ __launch_bounds__(256, 2) void k_proj_m(const CubeT* __restrict__ wt,
   }
 }
 
-// M[m][n] += weight * sum_{z < chunks} part[z][m][n] (chunks in order).
+// M[m][n] += weight * sum_{z < chunks} part[z][m][n]: a work-group takes 16
+// elements, lane q of an element sums chunks q, q + 16, ... in order, and
+// the 16 lane sums are added by a fixed tree.
 __global__ __launch_bounds__(256) void k_proj_msum(const double* __restrict__ part, int chunks,
                                                    int no, double weight,
                                                    double* __restrict__ m_out) {
-  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  __shared__ double buf[16][17];
+  const int e = threadIdx.x >> 4, q = threadIdx.x & 15;
+  const int64_t x = (int64_t)blockIdx.x * 16 + e;
   const int64_t mn = (int64_t)no * no;
-  if (x >= mn) return;
   double s = 0.0;
-  for (int z = 0; z < chunks; ++z) s += part[(int64_t)z * mn + x];
-  m_out[x] += weight * s;
+  if (x < mn)
+    for (int z = q; z < chunks; z += 16) s += part[(int64_t)z * mn + x];
+  buf[e][q] = s;
+  __syncthreads();
+  for (int w = 8; w > 0; w >>= 1) {
+    if (q < w) buf[e][q] += buf[e][q + w];
+    __syncthreads();
+  }
+  if (q == 0 && x < mn) m_out[x] += weight * buf[e][0];
 }
 
 // out[0] = sum_{m, n} c[m][n] M[m][n] in a fixed order (one block).

@@ -945,10 +945,14 @@ ProjPlan proj_plan(const sie_fragment& f, sie_precision p) {
     q.fp.variant = split_shape(q.fp.nv);
   }
   q.fp.lay3 = false;
+  // 8^3-blocked cubes, as the energy's (k_proj_m runs over the padding too,
+  // which k_proj_wq zeroes)
+  q.fp.half_bytes = align_up((q.split ? sizeof(float) : sizeof(double)) *
+                                 size_t(sie::cube_blocked_elems(q.fp.nv)), 256);
   const int64_t o = q.fp.no, v = q.fp.nv;
   q.groups = o * (o + 1) / 2;
-  q.K = v * v * v;
-  q.chunk = 32768;
+  q.K = sie::cube_blocked_elems(q.fp.nv);
+  q.chunk = 8192;   // about a thousand work-groups per product at 200 virtuals
   q.chunks = int((q.K + q.chunk - 1) / q.chunk);
   size_t off = 0;
   q.off_desc = off;
@@ -1017,7 +1021,7 @@ sie_status run_projector(const sie_fragment* f, sie_precision p, double* m_out, 
   d.variant = fp.variant;
   d.pair = 0;
   d.lay3 = 0;
-  d.blocked = 0;
+  d.blocked = 1;
   d.n_part = fp.n_part;
   d.unit_base = 0;
   d.half = int64_t(fp.half_bytes / (q.split ? sizeof(float) : sizeof(double)));

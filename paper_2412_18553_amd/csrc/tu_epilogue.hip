@@ -49,7 +49,7 @@ void launch_proj_m_f32(hipStream_t s, const float* wt, const float* q, int64_t s
 void launch_proj_msum(hipStream_t s, const double* part, int chunks, int no, double weight,
                       double* m) {
   const int64_t n = int64_t(no) * no;
-  hipLaunchKernelGGL(k_proj_msum, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, part, chunks,
+  hipLaunchKernelGGL(k_proj_msum, dim3(unsigned((n + 15) / 16)), dim3(256), 0, s, part, chunks,
                      no, weight, m);
 }
 
