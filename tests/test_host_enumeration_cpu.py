@@ -2,9 +2,13 @@
 (csrc/device_common.hpp), compiled for the host only: the closed-form decode
 of a linear index into a sorted triple p >= q >= r must agree with plain
 lexicographic enumeration, and unit_triple must reorder pair units as the
-pair-unit rule states (p > q = r evaluated as (q, q, p)).  The work tables
-are built on the host with these functions, and the kernels use the same
-code for units and 8^3 orbit blocks."""
+pair-unit rule states (p > q = r evaluated as (q, q, p)); the projector's
+ordered-triple item codes must decode to their triple; the 8^3-blocked cube
+offsets must map the n_v^3 elements one to one into the padded cube.  The
+work tables are built on the host with these functions, and the kernels use
+the same code for units, 8^3 orbit blocks and cube addresses.  The program
+is built with the address and undefined-behaviour sanitizers (host code
+only)."""
 
 import os
 import shutil
@@ -17,7 +21,9 @@ CSRC = os.path.join(ROOT, "paper_2412_18553_amd", "csrc")
 
 PROGRAM = r"""
 #include "device_common.hpp"
+#include "work.hpp"
 #include <cstdio>
+#include <vector>
 int main() {
   long n = 0, bad = 0;
   for (int bound : {1, 2, 3, 7, 24, 41, 130}) {
@@ -39,6 +45,34 @@ int main() {
           bad += (one0 || i != p || j != q || k != r);
         }
   }
+  // ordered occupied triples (the projector's items): code -> triple
+  for (int bound : {1, 3, 24, 41}) {
+    for (int i = 0; i < bound; ++i)
+      for (int j = 0; j < bound; ++j)
+        for (int k = 0; k < bound; ++k) {
+          int a, b, c;
+          bool one = true;
+          const int code = sie::ordered_item(i, j, k, bound);
+          const bool work = sie::item_triple(code, bound, false, a, b, c, one);
+          ++n;
+          bad += (code >= 0 || !work || one || a != i || b != j || c != k);
+        }
+  }
+  // blocked cube offsets: a bijection of the n_v^3 elements into the padded
+  // blocked cube
+  for (int nv : {1, 7, 8, 9, 17, 40}) {
+    const int64_t total = sie::cube_blocked_elems(nv);
+    std::vector<char> seen(size_t(total), 0);
+    for (int x = 0; x < nv; ++x)
+      for (int y = 0; y < nv; ++y)
+        for (int z = 0; z < nv; ++z) {
+          const int64_t o = sie::cube_at(true, nv, x, y, z);
+          ++n;
+          if (o < 0 || o >= total || seen[size_t(o)]) { ++bad; continue; }
+          seen[size_t(o)] = 1;
+          bad += (sie::cube_at(false, nv, x, y, z) != (int64_t(x) * nv + y) * nv + z);
+        }
+  }
   std::printf("%ld %ld\n", n, bad);
   return bad != 0;
 }
@@ -52,10 +86,18 @@ def test_sorted_triple_decode_and_pair_units(tmp_path):
     src = tmp_path / "enum.cpp"
     src.write_text(PROGRAM)
     exe = tmp_path / "enum"
+    # host code only, with the address and undefined-behaviour sanitizers
     res = subprocess.run([hipcc, "-x", "hip", "--offload-host-only", "-O1", "-std=c++17",
+                          "-Xarch_host", "-fsanitize=address",
+                          "-Xarch_host", "-fsanitize=undefined",
+                          "-Xarch_host", "-fno-sanitize-recover=all",
                           "-I", CSRC, "-I", os.path.join(ROOT, "include"), str(src), "-o",
                           str(exe)], capture_output=True, text=True)
     assert res.returncode == 0, res.stderr[-2000:]
-    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120,
+                         env={**os.environ, "ASAN_OPTIONS": "detect_leaks=1"})
+    assert out.returncode == 0, (out.stdout, out.stderr[-2000:])
     n, bad = (int(x) for x in out.stdout.split())
-    assert n == 389700 and bad == 0, out.stdout
+    ordered = 1 + 27 + 24 ** 3 + 41 ** 3
+    cubes = sum(v ** 3 for v in (1, 7, 8, 9, 17, 40))
+    assert n == 389700 + ordered + cubes and bad == 0, out.stdout
