@@ -36,7 +36,7 @@ constexpr int kMp2Tile = 64;   // virtual tile edge of k_mp2_pair (2 x 2 waves o
 // Wave tiles (16-wide MFMA tiles, rows x cols) of the Gram products: gamma_vv
 // (n_v x n_v outputs, K = n_v per batch entry) and gamma_oo (n_o x n_o, few
 // outputs: small tiles keep enough work-groups).
-constexpr int kGramVvM = 4, kGramVvN = 2, kGramOoM = 1, kGramOoN = 1;
+constexpr int kGramVvM = 4, kGramVvN = 2, kGramOoM = 2, kGramOoN = 2;
 
 // Two consecutive float64 values along the contraction of row `row` at
 // column k0 (k0 even), zero past K; `even`: rows start 16-byte aligned.
@@ -174,6 +174,10 @@ __global__ __launch_bounds__(256, 2) void k_mp2_pair(const double* __restrict__ 
 // sums batches q in [s * per, min((s + 1) * per, nq)) in order and writes
 // part[s][m][n].  PAIRT: B2's batch is the transposed occupied pair of q
 // (q = i * no + j -> j * no + i, gamma_vv); else B2 batch offset q * sB2q.
+// Batch entry q of a launch is (entry q / ks, contraction split q % ks):
+// with ks > 1 each entry's contraction of Ktot elements is cut into ks runs
+// of K (the last one shorter), so that products with few outputs and a long
+// contraction (gamma_oo) still give enough work-groups.
 struct GramArgs {
   const double* a;
   const double* b1;
@@ -182,6 +186,8 @@ struct GramArgs {
   int M, N, K, nq, per, no;
   double alpha, beta;
   double* part;
+  int ks;
+  int64_t Ktot;
 };
 
 // Wave tile of the Gram products: TM x TN 16-wide MFMA tiles; work-group:
@@ -199,7 +205,8 @@ __global__ __launch_bounds__(256, 2) void k_mp2_gram(GramArgs ga) {
   for (int t = 0; t < TM; ++t) rm[t] = min(m0 + 16 * t + r, ga.M - 1);
 #pragma unroll
   for (int t = 0; t < TN; ++t) rn[t] = min(n0 + 16 * t + r, ga.N - 1);
-  const bool even = (ga.K % 2) == 0 && (ga.sAm % 2) == 0 && (ga.sB1n % 2) == 0 &&
+  const bool even = (ga.K % 2) == 0 && (ga.Ktot % 2) == 0 && (ga.sAm % 2) == 0 &&
+                    (ga.sB1n % 2) == 0 &&
                     (ga.sB2n % 2) == 0 && (ga.sAq % 2) == 0 && (ga.sB1q % 2) == 0 &&
                     (ga.sB2q % 2) == 0;
   const int q0 = blockIdx.z * ga.per, q1 = min(q0 + ga.per, ga.nq);
@@ -213,17 +220,20 @@ __global__ __launch_bounds__(256, 2) void k_mp2_gram(GramArgs ga) {
     d2v x[TM], y1[TN], y2[TN];
   };
   auto load = [&](int q, int c, Chunk& ch) {
-    const int q2 = PAIRT ? (q % ga.no) * ga.no + q / ga.no : q;
-    const double* pa = ga.a + (int64_t)q * ga.sAq;
-    const double* p1 = ga.b1 + (int64_t)q * ga.sB1q;
-    const double* p2 = ga.b2 + (int64_t)q2 * ga.sB2q;
+    const int qe = q / ga.ks;
+    const int64_t koff = int64_t(q - qe * ga.ks) * ga.K;
+    const int klim = int(min(int64_t(ga.K), ga.Ktot - koff));
+    const int q2 = PAIRT ? (qe % ga.no) * ga.no + qe / ga.no : qe;
+    const double* pa = ga.a + (int64_t)qe * ga.sAq + koff;
+    const double* p1 = ga.b1 + (int64_t)qe * ga.sB1q + koff;
+    const double* p2 = ga.b2 + (int64_t)q2 * ga.sB2q + koff;
     const int k0 = 8 * c + 2 * g;
 #pragma unroll
-    for (int t = 0; t < TM; ++t) ch.x[t] = mp2_ld2(pa, rm[t], ga.sAm, k0, ga.K, even);
+    for (int t = 0; t < TM; ++t) ch.x[t] = mp2_ld2(pa, rm[t], ga.sAm, k0, klim, even);
 #pragma unroll
     for (int t = 0; t < TN; ++t) {
-      ch.y1[t] = mp2_ld2(p1, rn[t], ga.sB1n, k0, ga.K, even);
-      ch.y2[t] = mp2_ld2(p2, rn[t], ga.sB2n, k0, ga.K, even);
+      ch.y1[t] = mp2_ld2(p1, rn[t], ga.sB1n, k0, klim, even);
+      ch.y2[t] = mp2_ld2(p2, rn[t], ga.sB2n, k0, klim, even);
     }
   };
   auto mma = [&](const Chunk& ch) {

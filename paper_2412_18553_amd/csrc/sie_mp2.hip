@@ -23,6 +23,8 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 struct Mp2Plan {
   int64_t pairs = 0, tile_pairs = 0;
   int g_vv = 1, per_vv = 1, g_oo = 1, per_oo = 1;
+  int ks_oo = 1;            // contraction splits of gamma_oo (K = n_v^2 per entry)
+  int64_t kc_oo = 0;        // their length (a multiple of 8)
   size_t off_eps = 0, off_epart = 0, off_t2 = 0, off_gram = 0, bytes = 0;
 };
 
@@ -43,7 +45,17 @@ Mp2Plan mp2_plan(const sie_mp2_input& in, bool density, bool own_t2) {
   const int64_t tom = (o + 32 * sie::kGramOoM - 1) / (32 * sie::kGramOoM);
   const int64_t ton = (o + 32 * sie::kGramOoN - 1) / (32 * sie::kGramOoN);
   groups(o * o, tvm * tvn, p.g_vv, p.per_vv);
-  groups(o, tom * ton, p.g_oo, p.per_oo);
+  // gamma_oo: n_o entries of n_v^2 each; split each contraction so that
+  // entries x splits x tiles reach a few thousand work-groups
+  {
+    const int64_t want = (4096 + tom * ton - 1) / (tom * ton);
+    int64_t ks = (want + o - 1) / o;
+    const int64_t max_ks = (v * v + 7) / 8;
+    ks = ks < 1 ? 1 : (ks > max_ks ? max_ks : ks);
+    p.kc_oo = ((v * v + ks - 1) / ks + 7) / 8 * 8;
+    p.ks_oo = int((v * v + p.kc_oo - 1) / p.kc_oo);
+  }
+  groups(o * int64_t(p.ks_oo), tom * ton, p.g_oo, p.per_oo);
   size_t off = 0;
   p.off_eps = off;
   off = align256(off + sizeof(double) * size_t(o + v));
@@ -149,7 +161,7 @@ sie_status sie_mp2(const sie_mp2_input* in, double* e_out, double* t2, double* g
     const int64_t nv2 = int64_t(v) * v;
     if (gamma_vv) {
       sie::GramArgs ga{d_t2, d_t2, d_t2, nv2, v, nv2, v, nv2, v, v, v, v, o * o, pl.per_vv, o,
-                       2.0, -1.0, d_gram};
+                       2.0, -1.0, d_gram, 1, v};
       hipLaunchKernelGGL((sie::k_mp2_gram<true, sie::kGramVvM, sie::kGramVvN>),
                          dim3(unsigned((v + 32 * sie::kGramVvN - 1) / (32 * sie::kGramVvN)),
                               unsigned((v + 32 * sie::kGramVvM - 1) / (32 * sie::kGramVvM)),
@@ -161,7 +173,8 @@ sie_status sie_mp2(const sie_mp2_input* in, double* e_out, double* t2, double* g
     if (gamma_oo) {
       const int64_t onv2 = int64_t(o) * nv2;
       sie::GramArgs ga{d_t2, d_t2, d_t2, nv2, onv2, nv2, onv2, onv2, nv2, o, o,
-                       int(nv2), o, pl.per_oo, o, 2.0, -1.0, d_gram};
+                       int(pl.kc_oo), o * pl.ks_oo, pl.per_oo, o, 2.0, -1.0, d_gram,
+                       pl.ks_oo, nv2};
       hipLaunchKernelGGL((sie::k_mp2_gram<false, sie::kGramOoM, sie::kGramOoN>),
                          dim3(unsigned((o + 32 * sie::kGramOoN - 1) / (32 * sie::kGramOoN)),
                               unsigned((o + 32 * sie::kGramOoM - 1) / (32 * sie::kGramOoM)),
