@@ -1,7 +1,7 @@
 """Throughput of the per-fragment (T) energy on one MI355X.
 
 python bench.py [--steps K] [--warmup W]
-                [--mode split|fp64|batched|backward|projector|mp2|peak]
+                [--mode split|fp64|batched|backward|projector|df|mp2|peak]
                 [--workload NAME] [--precision fp64|split_bf16] [--no-cpu] [--no-fp64]
 
 Default (the headline line): a step is one full split-precision (T) energy
@@ -42,7 +42,7 @@ CHEM_SCALE = 2.0 ** -9            # integrals and t2 of the chemically scaled co
 
 DEFAULT_WORKLOAD = {"fp64": "o24v200", "split": "o32v320", "batched": "batch16",
                     "backward": "o16v120", "peak": None, "mp2": "mp2_o64v512",
-                    "projector": "o24v200"}
+                    "projector": "o24v200", "df": "o32v320"}
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
@@ -389,6 +389,57 @@ def run_single(args, result, name, mode):
     result["kernel_ms_per_step"] = {k: round(t / args.steps, 3) for k, (t, _) in prof.items()}
 
 
+def run_df(args, result, name):
+    """The split-precision energy of a fragment given its density-fitting
+    factors (sie_triples_energy_df): the library forms (jl|ia), (ia|jb) in
+    float32 and (ia|bc) one occupied slice at a time straight into its bf16
+    hi/lo copies.  Timed like the split line (factors, t1 and t2 resident in
+    HBM); also reports the caller-side input bytes against the integral-block
+    form and the energy against the block form's on the same fragment."""
+    import torch
+    import paper_2412_18553_amd as sie
+    from synth import WORKLOADS
+    from synth.device import workload_df_factors_device, workload_fragment_device
+    w = WORKLOADS[name]
+    o, v = w["n_occ"], w["n_vir"]
+    F = flops(o, v)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    fb = workload_fragment_device(name, device=dev, dtype=torch.float32)
+    b = workload_df_factors_device(name, device=dev)
+    log(f"# workload {name}: factors and float32 inputs built in {time.perf_counter() - t0:.1f} s")
+    block_bytes = sum(x.numel() * 4 for x in (fb.t1, fb.t2, fb.ovvv, fb.ooov, fb.ovov))
+    df_bytes = b.numel() * 8 + (fb.t1.numel() + fb.t2.numel()) * 4
+    fr = frag_of(fb, "split_bf16")
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    ws = torch.empty(sie.workspace_size(fr), dtype=torch.uint8, device=dev)
+    sie.energy(fr, workspace=ws, out=out)
+    e_block = float(out.item())
+    t1, t2 = fb.t1, fb.t2
+    eo, ev = fb.eps_occ, fb.eps_vir
+    del fr, ws, fb
+    torch.cuda.empty_cache()
+    ws = torch.empty(sie.df_workspace_size(eo, ev, t1, t2, b, "split_bf16"), dtype=torch.uint8,
+                     device=dev)
+    step = lambda: sie.energy_df(eo, ev, t1, t2, b, "split_bf16", workspace=ws, out=out)  # noqa: E731
+    ms, prof = timed(step, args.steps, args.warmup)
+    energy = float(out.item())
+    peak_bf16 = measured_peak(1)
+    desc = (f"single fragment n_occ={o} n_vir={v} n_aux={w['n_aux']}, density-fitting "
+            "factors (float64) and float32 amplitudes in")
+    result.update(value=round(F / (ms * 1e-3) / 1e12, 3), dtype="bf16x3/f32",
+                  config={"workload": desc, "precision": "split_bf16", "fragments": 1},
+                  ms_per_step=round(ms, 3), fragments_per_s=round(1000.0 / ms, 4), energy=energy,
+                  energy_block_form=e_block,
+                  df_vs_block_rel=float(f"{(energy - e_block) / abs(e_block):.3e}"),
+                  input_bytes={"density_fitting": df_bytes, "integral_blocks": block_bytes},
+                  forming_and_staging_ms=round(prof["split"][0] / args.steps, 3))
+    rl = roofline(prof, "w_build", split_kernel_name(v), F, args.steps, PEAK_BF16_MFMA_TFLOPS,
+                  issued=3.0, measured=peak_bf16)
+    result["roofline"] = rl
+    result["kernel_ms_per_step"] = {k: round(t / args.steps, 3) for k, (t, _) in prof.items()}
+
+
 def run_projector(args, result, name):
     """The fragment-projector matrix M of a fragment (E_x(C) = sum C M for any
     C; tr M = E_x), float64, with the unprojected energy of the same
@@ -611,6 +662,8 @@ def main():
         run_mp2(args, result, name)
     elif mode == "projector":
         run_projector(args, result, name)
+    elif mode == "df":
+        run_df(args, result, name)
     else:
         run_batched(args, result, name)
     print(json.dumps(result), flush=True)

@@ -258,6 +258,46 @@ sie_status sie_triples_backward(const sie_fragment* frags, int32_t n, sie_precis
                                 const double* grad_e, const sie_fragment_grad* grads,
                                 double* e_frag, void* ws, size_t ws_bytes, void* stream);
 
+/* E_x of one fragment given its density-fitting factors in place of the
+ * integral blocks.  The paper's in-situ (T) section closes on memory: the
+ * method never stores six-index quantities and stays within the CCSD
+ * footprint; of the (T) inputs the (ia|bc) block, n_occ n_vir^3 elements, is
+ * by far the largest.  Here the caller passes the factors b with
+ * (pq|rs) = sum_P b[P][p][q] b[P][r][s], and the library forms (ia|bc),
+ * (jl|ia) and (ia|jb) itself on the float64 matrix cores (fixed summation
+ * order over P, float64).  With SIE_SPLIT_BF16, (ia|bc) is formed one
+ * occupied slice i at a time into a slice buffer, rounded to float32 and
+ * split straight into the bf16 hi/lo copies the build reads, so no float32
+ * (ia|bc) array exists anywhere; (jl|ia) and (ia|jb) are formed in float32
+ * in the workspace.  With SIE_FP64 all three blocks are formed in float64 in
+ * the workspace (the same result as sie_triples_energy on the formed blocks;
+ * no memory is saved).
+ *   frag->b     device float64 [n_aux][n][n], n = n_occ + n_vir, occupied
+ *               orbitals first, symmetric in its last two indices (the
+ *               formed blocks then have the twin symmetries exactly)
+ *   frag->t1, t2  device, as in sie_fragment, float64 (SIE_FP64) or float32
+ *               (SIE_SPLIT_BF16)
+ *   ws          >= sie_triples_df_workspace_size(frag, p, cap) bytes: the
+ *               formed blocks, then what sie_triples_energy needs
+ * The finite check (sie_set_check_finite) scans t1, t2 and b.  Same stream
+ * behaviour, determinism and error rules as sie_triples_energy; the per-
+ * triple output e_triples works as there. */
+typedef struct {
+  int32_t n_occ;             /* 1 <= n_occ <= SIE_MAX_OCC                      */
+  int32_t n_vir;             /* 1 <= n_vir <= SIE_MAX_VIR                      */
+  int32_t n_aux;             /* >= 1                                          */
+  const double* eps_occ;     /* host [n_occ]                                   */
+  const double* eps_vir;     /* host [n_vir]                                   */
+  const void* t1;            /* device [n_occ][n_vir]                          */
+  const void* t2;            /* device [n_occ][n_occ][n_vir][n_vir]            */
+  const double* b;           /* device float64 [n_aux][n][n]                   */
+} sie_fragment_df;
+
+size_t sie_triples_df_workspace_size(const sie_fragment_df* frag, sie_precision p,
+                                     size_t max_bytes);
+sie_status sie_triples_energy_df(const sie_fragment_df* frag, sie_precision p, double* e_out,
+                                 double* e_triples, void* ws, size_t ws_bytes, void* stream);
+
 /* MP2 of one cluster or subspace (the paper's embedding workflow, SI section
  * "Systematically Improvable Quantum Embedding Workflow"): amplitudes
  *   t_ij^ab = -(ia|jb) / (e_a + e_b - e_i - e_j),

@@ -380,6 +380,73 @@ def mp2(eps_occ, eps_vir, l_ov: torch.Tensor, *, want_t2: bool = False,
     return out
 
 
+def _df_desc(eps_occ, eps_vir, t1, t2, b, precision):
+    if precision not in PRECISIONS:
+        raise ValueError(f"precision must be one of {list(PRECISIONS)}")
+    eo, ev = _host_f64(eps_occ, "eps_occ"), _host_f64(eps_vir, "eps_vir")
+    o, v = eo.shape[0], ev.shape[0]
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    for name, x, shape in (("t1", t1, (o, v)), ("t2", t2, (o, o, v, v))):
+        if (not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != dt
+                or tuple(x.shape) != shape or not x.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {dt} CUDA tensor of shape {shape}")
+    n = o + v
+    if (not isinstance(b, torch.Tensor) or not b.is_cuda or b.dtype != torch.float64
+            or b.dim() != 3 or tuple(b.shape[1:]) != (n, n) or not b.is_contiguous()):
+        raise ValueError("b must be a contiguous float64 CUDA tensor [n_aux][n][n]")
+    desc = _lib.SieFragmentDf(o, v, int(b.shape[0]), eo.ctypes.data, ev.ctypes.data,
+                              t1.data_ptr(), t2.data_ptr(), b.data_ptr())
+    return desc, (eo, ev), PRECISIONS[precision]
+
+
+def df_workspace_size(eps_occ, eps_vir, t1, t2, b, precision: str = "fp64",
+                      max_bytes: int = 0) -> int:
+    """Workspace bytes of `energy_df` (see sie_triples_df_workspace_size)."""
+    lib = _lib.load()
+    desc, keep, prec = _df_desc(eps_occ, eps_vir, t1, t2, b, precision)
+    n = lib.sie_triples_df_workspace_size(ctypes.byref(desc), prec, max_bytes)
+    del keep
+    if n == 0:
+        raise SieError(_lib.SIE_ERR_INVALID_ARG, _lib.last_error())
+    return n
+
+
+def energy_df(eps_occ, eps_vir, t1: torch.Tensor, t2: torch.Tensor, b: torch.Tensor,
+              precision: str = "fp64", *, workspace: torch.Tensor | None = None,
+              out: torch.Tensor | None = None, triples: torch.Tensor | None = None,
+              max_workspace_bytes: int = 0) -> torch.Tensor:
+    """E_x of one fragment from its density-fitting factors b [n_aux][n][n]
+    (float64 CUDA tensor, n = n_occ + n_vir, occupied first, symmetric in the
+    last two indices) and amplitudes t1, t2 (float64 for "fp64", float32 for
+    "split_bf16"); the library forms the integral blocks itself (see
+    sie_triples_energy_df).  Enqueued on the current stream; returns a
+    1-element float64 device tensor."""
+    lib = _lib.load()
+    desc, keep, prec = _df_desc(eps_occ, eps_vir, t1, t2, b, precision)
+    dev = b.device
+    o = desc.n_occ
+    if workspace is None:
+        nbytes = lib.sie_triples_df_workspace_size(ctypes.byref(desc), prec, max_workspace_bytes)
+        if nbytes == 0:
+            raise SieError(_lib.SIE_ERR_INVALID_ARG, _lib.last_error())
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    if workspace.dtype != torch.uint8 or not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous uint8 CUDA tensor")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=dev)
+    if triples is not None and (triples.dtype != torch.float64 or
+                                triples.numel() != occupied_triples(o) or
+                                not triples.is_contiguous() or not triples.is_cuda):
+        raise ValueError("triples must be a contiguous float64 CUDA tensor of n_triples entries")
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    st = lib.sie_triples_energy_df(ctypes.byref(desc), prec, out.data_ptr(),
+                                   None if triples is None else triples.data_ptr(),
+                                   workspace.data_ptr(), workspace.numel(), stream)
+    del keep
+    _lib.check(st)
+    return out
+
+
 def tile_variants():
     """Tile shapes of the float64 build: [(blocks/wave, row tiles, col tiles, WGs/CU,
     wave rows, wave cols, layouts, k-steps per chunk)] (see sie_tile_variant_shape)."""

@@ -37,7 +37,8 @@ EXPORTED = ["sie_abi_version", "sie_last_error", "sie_occupied_triples",
             "sie_set_split_table",
             "sie_profile_enable", "sie_profile_collect", "sie_set_check_finite",
             "sie_mp2_workspace_size", "sie_mp2",
-            "sie_triples_projector_workspace_size", "sie_triples_projector_matrix"]
+            "sie_triples_projector_workspace_size", "sie_triples_projector_matrix",
+            "sie_triples_df_workspace_size", "sie_triples_energy_df"]
 PROF_CLASSES = ("w_build", "epilogue", "reduce", "split", "grad")
 
 
@@ -65,6 +66,12 @@ class SieMp2Input(ctypes.Structure):
     _fields_ = [("n_occ", ctypes.c_int32), ("n_vir", ctypes.c_int32), ("n_aux", ctypes.c_int32),
                 ("eps_occ", ctypes.c_void_p), ("eps_vir", ctypes.c_void_p),
                 ("l_ov", ctypes.c_void_p)]
+
+
+class SieFragmentDf(ctypes.Structure):
+    _fields_ = [("n_occ", ctypes.c_int32), ("n_vir", ctypes.c_int32), ("n_aux", ctypes.c_int32),
+                ("eps_occ", ctypes.c_void_p), ("eps_vir", ctypes.c_void_p),
+                ("t1", ctypes.c_void_p), ("t2", ctypes.c_void_p), ("b", ctypes.c_void_p)]
 
 
 class SieError(RuntimeError):
@@ -144,6 +151,13 @@ def load() -> ctypes.CDLL:
     lib.sie_triples_projector_matrix.argtypes = [ctypes.POINTER(SieFragment), ctypes.c_int,
                                                  ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_size_t, ctypes.c_void_p]
+    lib.sie_triples_df_workspace_size.restype = ctypes.c_size_t
+    lib.sie_triples_df_workspace_size.argtypes = [ctypes.POINTER(SieFragmentDf), ctypes.c_int,
+                                                  ctypes.c_size_t]
+    lib.sie_triples_energy_df.restype = ctypes.c_int
+    lib.sie_triples_energy_df.argtypes = [ctypes.POINTER(SieFragmentDf), ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_size_t, ctypes.c_void_p]
     lib.sie_mp2_workspace_size.restype = ctypes.c_size_t
     lib.sie_mp2_workspace_size.argtypes = [ctypes.POINTER(SieMp2Input), ctypes.c_int32]
     lib.sie_mp2.restype = ctypes.c_int

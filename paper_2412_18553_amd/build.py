@@ -23,7 +23,8 @@ PEAK_SRC = "mfma_peak.hip"
 PEAK_LIB = os.path.join(HERE, "libsie_mfma_peak.so")
 
 SOURCES = ["sie_triples.hip", "sie_mp2.hip", "tu_build_f64.hip", "tu_build_f64_l3.hip",
-           "tu_bf16.hip", "tu_epilogue.hip", "tu_adj_f64.hip", "tu_adj_f32.hip"]
+           "tu_bf16.hip", "tu_epilogue.hip", "tu_adj_f64.hip", "tu_adj_f32.hip",
+           "tu_df.hip"]
 
 # Packed-FP32 VALU instructions are disabled for all device code.
 HIPCC_FLAGS = [

@@ -36,6 +36,11 @@ void launch_split_bf16(unsigned grid, hipStream_t s, const float* src, int P, in
                        int64_t sp, int64_t sx, int64_t sy, int64_t sk, int K, int Kpad,
                        bool kfast, u4v* dst);
 
+// ---- integral blocks from density-fitting factors (tu_df.hip) ----
+struct DfArgs;
+void launch_df_form_f64(hipStream_t s, const DfArgs& a, double* out);
+void launch_df_form_f32(hipStream_t s, const DfArgs& a, float* out);
+
 // ---- epilogue and reductions (tu_epilogue.hip) ----
 void launch_epilogue_f64(unsigned grid, hipStream_t s, const FragDesc* desc, const Item* items,
                          int n_items, const double* arena, double* partials, int pstride);

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "adj_plan.hpp"
+#include "k_df.hpp"
 #include "launch.hpp"
 #include "shapes.hpp"
 #include "staging.hpp"
@@ -550,6 +551,73 @@ size_t workspace_size(const sie_fragment* frags, int32_t n, sie_precision p, siz
 
 }  // namespace
 
+namespace {
+
+// ---- density-fitting input (sie_triples_energy_df) ----
+// Workspace: [formed blocks][the energy's workspace for the formed fragment].
+// Formed blocks: float64 ovvv, ooov, ovov (SIE_FP64), or float32 ooov, ovov
+// and one float32 (ia|bc) slice (SIE_SPLIT_BF16).
+struct DfPlan {
+  size_t off_ovvv = 0, off_ooov = 0, off_ovov = 0, off_slice = 0, bytes = 0;
+};
+
+DfPlan df_plan(const sie_fragment_df& f, sie_precision p) {
+  DfPlan q;
+  const size_t o = size_t(f.n_occ), v = size_t(f.n_vir);
+  const size_t esz = p == SIE_FP64 ? sizeof(double) : sizeof(float);
+  size_t off = 0;
+  if (p == SIE_FP64) {
+    q.off_ovvv = off;
+    off = align_up(off + esz * o * v * v * v, 256);
+  }
+  q.off_ooov = off;
+  off = align_up(off + esz * o * o * o * v, 256);
+  q.off_ovov = off;
+  off = align_up(off + esz * o * v * o * v, 256);
+  if (p != SIE_FP64) {
+    q.off_slice = off;
+    off = align_up(off + sizeof(float) * v * v * v, 256);
+  }
+  q.bytes = off;
+  return q;
+}
+
+sie_status check_df(const sie_fragment_df* f, sie_precision p, const std::string& w) {
+  if (!f) return fail(SIE_ERR_INVALID_ARG, w + ": fragment descriptor is NULL");
+  if (p != SIE_FP64 && p != SIE_SPLIT_BF16)
+    return fail(SIE_ERR_INVALID_ARG, w + ": unknown precision");
+  if (f->n_occ < 1 || f->n_occ > SIE_MAX_OCC || f->n_vir < 1 || f->n_vir > SIE_MAX_VIR)
+    return fail(SIE_ERR_INVALID_ARG, w + ": n_occ or n_vir out of range");
+  if (f->n_aux < 1) return fail(SIE_ERR_INVALID_ARG, w + ": n_aux must be >= 1");
+  if (!f->b || !aligned(f->b, sizeof(double)))
+    return fail(SIE_ERR_INVALID_ARG, w + ": b is NULL or not aligned to 8 bytes");
+  const double n = double(f->n_occ) + f->n_vir;
+  if (8.0 * n * n * f->n_aux >= 9.2e18)
+    return fail(SIE_ERR_INVALID_ARG, w + ": b is too large");
+  return SIE_OK;
+}
+
+// The descriptor of the formed fragment: integral blocks in the formed-block
+// region (for the split form ovvv points at the slice buffer; the split
+// staging forms the (ia|bc) copy from the factors instead of reading it).
+sie_fragment df_fragment(const sie_fragment_df& f, sie_precision p, char* region,
+                         const DfPlan& q) {
+  sie_fragment g{};
+  g.n_occ = f.n_occ;
+  g.n_vir = f.n_vir;
+  g.eps_occ = f.eps_occ;
+  g.eps_vir = f.eps_vir;
+  g.t1 = f.t1;
+  g.t2 = f.t2;
+  g.ovvv = region + (p == SIE_FP64 ? q.off_ovvv : q.off_slice);
+  g.ooov = region + q.off_ooov;
+  g.ovov = region + q.off_ovov;
+  g.frag_proj = nullptr;
+  return g;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t sie_triples_workspace_size(const sie_fragment* frags, int32_t n, sie_precision p,
@@ -746,7 +814,64 @@ void build_round_split(const Tables& T, size_t q, hipStream_t s, const sie::Frag
 }
 
 // bf16 hi/lo copies of every fragment's float32 inputs (see k_bf16.hpp).
-sie_status stage_split(const std::vector<sie::FragDesc>& desc, hipStream_t s) {
+// Density-fitting source of a split evaluation (sie_triples_energy_df): the
+// (ia|bc) split copy is formed from the factors one occupied slice at a time
+// through `slice` (n_v^3 float32) instead of from an ovvv array.
+struct DfSource {
+  const double* b = nullptr;
+  int n_aux = 0;
+  float* slice = nullptr;
+};
+
+// The factor maps of the blocks, b [n_aux][n][n] with n = n_o + n_v.
+sie::DfArgs df_args(const double* b, int naux, int no, int nv) {
+  sie::DfArgs a{};
+  a.b = b;
+  a.plane = int64_t(no + nv) * (no + nv);
+  a.naux = naux;
+  return a;
+}
+
+// (ia|bc) of occupied i: rows a, cols (b, c) -> out[a][b][c]
+template <typename OutT>
+void df_ovvv_slice(hipStream_t s, const double* b, int naux, int no, int nv, int i, OutT* out) {
+  const int64_t n = no + nv;
+  sie::DfArgs a = df_args(b, naux, no, nv);
+  a.M = nv;
+  a.N = nv * nv;
+  a.x = sie::DfMap{int64_t(i) * n + no, 1 << 30, 0, 1};
+  a.y = sie::DfMap{int64_t(no) * n + no, nv, n, 1};
+  a.ldc = int64_t(nv) * nv;
+  if (sizeof(OutT) == 8) sie::launch_df_form_f64(s, a, reinterpret_cast<double*>(out));
+  else sie::launch_df_form_f32(s, a, reinterpret_cast<float*>(out));
+}
+
+// (jl|ia) -> out[j][l][i][a] and (ia|jb) -> out[i][a][j][b]
+template <typename OutT>
+void df_ooov_ovov(hipStream_t s, const double* b, int naux, int no, int nv, OutT* ooov,
+                  OutT* ovov) {
+  const int64_t n = no + nv;
+  const sie::DfMap oo{0, no, n, 1}, ov{no, nv, n, 1};
+  sie::DfArgs a = df_args(b, naux, no, nv);
+  a.M = no * no;
+  a.N = no * nv;
+  a.x = oo;
+  a.y = ov;
+  a.ldc = int64_t(no) * nv;
+  sie::DfArgs c = a;
+  c.M = no * nv;
+  c.x = ov;
+  if (sizeof(OutT) == 8) {
+    sie::launch_df_form_f64(s, a, reinterpret_cast<double*>(ooov));
+    sie::launch_df_form_f64(s, c, reinterpret_cast<double*>(ovov));
+  } else {
+    sie::launch_df_form_f32(s, a, reinterpret_cast<float*>(ooov));
+    sie::launch_df_form_f32(s, c, reinterpret_cast<float*>(ovov));
+  }
+}
+
+sie_status stage_split(const std::vector<sie::FragDesc>& desc, hipStream_t s,
+                       const DfSource* df = nullptr) {
   ProfScope ps(s, 3);
   auto split = [&](const void* src, int P, int X, int Y, int64_t sp, int64_t sx, int64_t sy,
                    int64_t sk, int K, int Kpad, bool kfast, const sie::u4v* dst) {
@@ -760,7 +885,15 @@ sie_status stage_split(const std::vector<sie::FragDesc>& desc, hipStream_t s) {
     const int no = d.no, nv = d.nv;
     const int64_t o = no, v = nv;
     // vS[i][a][b][d] <- ovvv, tS[i][j][a][d] <- t2 (K = d contiguous)
-    split(d.ovvv, no, nv, nv, v * v * v, v * v, v, 1, nv, d.Kv, true, d.vS);
+    if (df) {   // one formed (ia|bc) slice at a time
+      for (int i = 0; i < no; ++i) {
+        df_ovvv_slice(s, df->b, df->n_aux, no, nv, i, df->slice);
+        split(df->slice, 1, nv, nv, v * v * v, v * v, v, 1, nv, d.Kv, true,
+              d.vS + int64_t(i) * v * v * (d.Kv / 8) * 2);
+      }
+    } else {
+      split(d.ovvv, no, nv, nv, v * v * v, v * v, v, 1, nv, d.Kv, true, d.vS);
+    }
     split(d.t2, no, no, nv, o * v * v, v * v, v, 1, nv, d.Kv, true, d.tS);
     // tT[p][x][y][l] = t2[p][l][x][y], oT[x][y][v][l] = ooov[x][l][y][v] (K = l)
     split(d.t2, no, nv, nv, o * v * v, v, 1, v * v, no, d.Ko, false, d.tT);
@@ -803,7 +936,7 @@ sie_status scan_finite(const sie_fragment* frags, int n, bool f64, int* d_flags,
 // the page-locked staging ring, so the call allocates nothing anywhere.
 sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag_out,
                double* e_total, double* e_triples, void* ws, size_t ws_bytes, void* stream,
-               const char* who, bool direct = false) {
+               const char* who, bool direct = false, const DfSource* df = nullptr) {
   const std::string w(who);
   if (!frags || n < 1) return fail(SIE_ERR_INVALID_ARG, w + ": need at least one fragment");
   for (int x = 0; x < n; ++x) {
@@ -856,7 +989,7 @@ sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag
     st = hip_check(up.commit(s), "upload tables");
     if (st != SIE_OK) return st;
   }
-  if (check_finite_on()) {
+  if (check_finite_on() && !df) {   // (the density-fitting entry scans its own inputs)
     st = scan_finite(frags, n, !pl.split, reinterpret_cast<int*>(dev(pl.off_flags)), s, w);
     if (st != SIE_OK) return st;
   }
@@ -870,7 +1003,7 @@ sie_status run(const sie_fragment* frags, int n, sie_precision p, double* e_frag
 
   // ---- split staging (split precision) ----
   if (pl.split) {
-    st = stage_split(desc, s);
+    st = stage_split(desc, s, df);
     if (st != SIE_OK) return st;
   }
 
@@ -1545,6 +1678,88 @@ sie_status sie_triples_backward(const sie_fragment* frags, int32_t n, sie_precis
                                 const double* grad_e, const sie_fragment_grad* grads,
                                 double* e_frag, void* ws, size_t ws_bytes, void* stream) {
   return run_backward(frags, n, p, grad_e, grads, e_frag, ws, ws_bytes, stream);
+}
+
+size_t sie_triples_df_workspace_size(const sie_fragment_df* f, sie_precision p,
+                                     size_t max_bytes) {
+  const char* who = "sie_triples_df_workspace_size";
+  if (check_df(f, p, who) != SIE_OK) return 0;
+  const DfPlan q = df_plan(*f, p);
+  // the formed fragment at a stand-in region address (checked, never read)
+  const sie_fragment g = df_fragment(*f, p, reinterpret_cast<char*>(uintptr_t(1) << 20), q);
+  const size_t cap = max_bytes ? max_bytes : default_cap();
+  if (q.bytes >= cap) {
+    fail(SIE_ERR_WORKSPACE, std::string(who) + ": cap below the formed integral blocks");
+    return 0;
+  }
+  const size_t rest = workspace_size(&g, 1, p, cap - q.bytes, false, who);
+  return rest ? q.bytes + rest : 0;
+}
+
+sie_status sie_triples_energy_df(const sie_fragment_df* f, sie_precision p, double* e_out,
+                                 double* e_triples, void* ws, size_t ws_bytes, void* stream) {
+  const char* who = "sie_triples_energy_df";
+  const std::string w(who);
+  sie_status st = check_df(f, p, w);
+  if (st != SIE_OK) return st;
+  if (!e_out || !aligned(e_out, sizeof(double)))
+    return fail(SIE_ERR_INVALID_ARG, w + ": e_out is NULL or misaligned");
+  if (e_triples && !aligned(e_triples, sizeof(double)))
+    return fail(SIE_ERR_INVALID_ARG, w + ": e_triples is misaligned");
+  if (!ws || !aligned(ws, 256))
+    return fail(SIE_ERR_WORKSPACE, w + ": workspace is NULL or not 256-byte aligned");
+  const DfPlan q = df_plan(*f, p);
+  char* region = static_cast<char*>(ws);
+  const sie_fragment g = df_fragment(*f, p, region, q);
+  st = check_fragment(&g, p, who);
+  if (st != SIE_OK) return st;
+  {
+    const Plan pl = make_plan(&g, 1, p);
+    if (ws_bytes < q.bytes || ws_bytes - q.bytes < pl.fixed_bytes + pl.min_arena)
+      return fail(SIE_ERR_WORKSPACE,
+                  w + ": workspace smaller than required (see sie_triples_df_workspace_size)");
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int no = f->n_occ, nv = f->n_vir;
+  if (check_finite_on()) {   // t1, t2 and the factors, before anything is formed
+    int* flags = reinterpret_cast<int*>(region);
+    const int64_t o = no, v = nv, n = o + v;
+    sie::launch_zero_flags(s, flags, 3);
+    sie::launch_nonfinite(s, f->t1, p == SIE_FP64, o * v, flags, 0);
+    sie::launch_nonfinite(s, f->t2, p == SIE_FP64, o * o * v * v, flags, 1);
+    sie::launch_nonfinite(s, f->b, true, int64_t(f->n_aux) * n * n, flags, 2);
+    int h[3] = {0, 0, 0};
+    st = hip_check(hipGetLastError(), "launch finite scan");
+    if (st == SIE_OK)
+      st = hip_check(hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s),
+                     "read finite scan");
+    if (st == SIE_OK) st = hip_check(hipStreamSynchronize(s), "finite scan");
+    if (st != SIE_OK) return st;
+    static const char* kNames[3] = {"t1", "t2", "b"};
+    for (int a = 0; a < 3; ++a)
+      if (h[a]) return fail(SIE_ERR_NONFINITE, w + ": " + kNames[a] + " holds a non-finite value");
+  }
+  {
+    ProfScope ps(s, 3);
+    if (p == SIE_FP64) {
+      double* ovvv = reinterpret_cast<double*>(region + q.off_ovvv);
+      for (int i = 0; i < no; ++i)
+        df_ovvv_slice(s, f->b, f->n_aux, no, nv, i, ovvv + int64_t(i) * nv * nv * nv);
+      df_ooov_ovov(s, f->b, f->n_aux, no, nv, reinterpret_cast<double*>(region + q.off_ooov),
+                   reinterpret_cast<double*>(region + q.off_ovov));
+    } else {
+      df_ooov_ovov(s, f->b, f->n_aux, no, nv, reinterpret_cast<float*>(region + q.off_ooov),
+                   reinterpret_cast<float*>(region + q.off_ovov));
+    }
+  }
+  st = hip_check(hipGetLastError(), "launch integral forming");
+  if (st != SIE_OK) return st;
+  DfSource src;
+  src.b = f->b;
+  src.n_aux = f->n_aux;
+  src.slice = reinterpret_cast<float*>(region + q.off_slice);
+  return run(&g, 1, p, nullptr, e_out, e_triples, region + q.bytes, ws_bytes - q.bytes, stream,
+             who, false, &src);
 }
 
 }  // extern "C"

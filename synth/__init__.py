@@ -12,6 +12,7 @@ from .fragments import (  # noqa: F401
     workload_fragment,
     batch_shapes,
     ov_factors,
+    df_factors,
     mp2_inputs,
     WORKLOADS,
 )

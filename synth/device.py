@@ -107,6 +107,26 @@ def make_fragment_device(n_occ: int, n_vir: int, n_aux: int, seed, *, device,
                           ovvv, cast(ooov), cast(ovov))
 
 
+def df_factors_device(n_occ: int, n_vir: int, n_aux: int, seed, *, device,
+                      b_std: float = 0.05):
+    """The symmetric factors B[P, p, q] (float64, on `device`) that
+    `make_fragment_device` draws for the same arguments."""
+    import torch
+    rng = np.random.default_rng(np.random.SeedSequence([int(s) for s in seed]))
+    rng.uniform(-1.5, -0.3, n_occ)
+    rng.uniform(0.1, 3.0, n_vir)
+    n = n_occ + n_vir
+    g = torch.from_numpy(rng.normal(0.0, b_std, size=(n_aux, n, n))).to(device)
+    return (torch.triu(g) + torch.triu(g, 1).transpose(1, 2)).contiguous()
+
+
+def workload_df_factors_device(name: str, **kw):
+    from .fragments import SEED_ROOT, WORKLOADS
+    w = WORKLOADS[name]
+    return df_factors_device(w["n_occ"], w["n_vir"], w["n_aux"], (SEED_ROOT, w["stream"], 0),
+                             **kw)
+
+
 def workload_fragment_device(name: str, **kw) -> DeviceFragment:
     from .fragments import SEED_ROOT, WORKLOADS
     w = WORKLOADS[name]

@@ -119,6 +119,22 @@ def make_fragment(n_occ: int, n_vir: int, n_aux: int, seed, *,
                     np.ascontiguousarray(ovov))
 
 
+def df_factors(n_occ: int, n_vir: int, n_aux: int, seed, *, b_std: float = 0.05,
+               b_scale: float = 1.0) -> np.ndarray:
+    """The symmetric density-fitting factors B[P, p, q] (occupied orbitals
+    first) that `make_fragment` draws for the same arguments (same random
+    stream): its integral blocks are sum_P B[P, p, q] B[P, r, s]."""
+    rng = np.random.default_rng(np.random.SeedSequence([int(s) for s in seed]))
+    rng.uniform(-1.5, -0.3, n_occ)
+    rng.uniform(0.1, 3.0, n_vir)
+    n = n_occ + n_vir
+    g = rng.normal(0.0, b_std, size=(n_aux, n, n))
+    bfac = np.triu(g) + np.triu(g, 1).transpose(0, 2, 1)
+    if b_scale != 1.0:
+        bfac *= b_scale
+    return np.ascontiguousarray(bfac)
+
+
 def ov_factors(n_occ: int, n_vir: int, n_aux: int, seed, *, b_std: float = 0.05,
                b_scale: float = 1.0) -> np.ndarray:
     """The occupied-virtual density-fitting factors L[i, a, P] = B^P_{i, a}

@@ -275,3 +275,54 @@ def test_projector_argument_checks(lib):
     assert lib.sie_triples_projector_matrix(ctypes.byref(f), _lib.SIE_FP64, FAKE, FAKE, 64,
                                             None) == _lib.SIE_ERR_WORKSPACE
     keep.extend([c, bad])
+
+
+def test_df_argument_checks(lib):
+    """The density-fitting entry point checks its descriptor, the formed
+    fragment (orbital energies, amplitude pointers) and the workspace on the
+    host before any HIP call; its workspace is the formed blocks plus the
+    energy's workspace for them."""
+    o, v, naux = 4, 10, 12
+    eo = np.linspace(-1.0, -0.5, o)
+    ev = np.linspace(0.2, 1.0, v)
+
+    def df(**kw):
+        p = dict(n_occ=o, n_vir=v, n_aux=naux, t1=FAKE, t2=FAKE, b=FAKE, eo=eo, ev=ev)
+        p.update(kw)
+        return _lib.SieFragmentDf(p["n_occ"], p["n_vir"], p["n_aux"], p["eo"].ctypes.data,
+                                  p["ev"].ctypes.data, p["t1"], p["t2"], p["b"])
+
+    def size(d, prec=_lib.SIE_FP64, cap=0):
+        return lib.sie_triples_df_workspace_size(ctypes.byref(d) if d is not None else None,
+                                                 prec, cap)
+
+    def run(d, prec=_lib.SIE_FP64, e_out=FAKE, ws=FAKE, ws_bytes=1 << 30):
+        return lib.sie_triples_energy_df(ctypes.byref(d) if d is not None else None, prec,
+                                         e_out, None, ws, ws_bytes, None)
+
+    good = df()
+    n64, n32 = size(good), size(good, _lib.SIE_SPLIT_BF16)
+    # float64: formed ovvv, ooov, ovov (8 bytes) ahead of the energy workspace
+    f = frag(o, v, keep=[])
+    e64 = lib.sie_triples_workspace_size(ctypes.byref(f), 1, _lib.SIE_FP64, 0)
+    formed = sum((8 * x + 255) // 256 * 256 for x in (o * v ** 3, o ** 3 * v, o * o * v * v))
+    assert n64 == formed + e64
+    assert 0 < n32 < n64 + 8 * o * v ** 3
+    assert size(None) == 0
+    assert size(df(n_aux=0)) == 0
+    assert size(df(b=0)) == 0
+    assert size(df(b=FAKE + 4)) == 0
+    assert size(df(t2=0)) == 0
+    assert size(good, cap=1024) == 0
+    assert run(None) == _lib.SIE_ERR_INVALID_ARG
+    assert run(df(n_aux=0)) == _lib.SIE_ERR_INVALID_ARG
+    assert run(df(b=0)) == _lib.SIE_ERR_INVALID_ARG
+    assert run(good, e_out=None) == _lib.SIE_ERR_INVALID_ARG
+    assert run(good, ws=FAKE + 8) == _lib.SIE_ERR_WORKSPACE
+    assert run(good, ws_bytes=4096) == _lib.SIE_ERR_WORKSPACE
+    assert run(good, 7) == _lib.SIE_ERR_INVALID_ARG
+    bad_eo = np.array([-1.0, -0.5, 0.5, -0.2])
+    assert run(df(eo=bad_eo)) == _lib.SIE_ERR_INVALID_ARG
+    nan_ev = ev.copy()
+    nan_ev[3] = np.nan
+    assert run(df(ev=nan_ev)) == _lib.SIE_ERR_NONFINITE
