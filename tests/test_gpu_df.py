@@ -126,3 +126,13 @@ def test_df_nonfinite_factors():
             _df_energy(f, b)
     finally:
         sie.set_check_finite(False)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split_bf16"])
+def test_df_single_occupied_is_zero(precision):
+    """One occupied orbital: the only occupied triple has i = j = k, whose
+    contribution vanishes identically, so E_x = 0 exactly (the formed blocks
+    and the staging still run)."""
+    f = make_fragment(1, 20, 30, (7, 11))
+    b = df_factors(1, 20, 30, (7, 11))
+    assert _df_energy(f, b, precision) == 0.0

@@ -142,3 +142,15 @@ def test_projector_nonfinite_rejected():
     c[1, 2] = np.nan
     with pytest.raises(sie.SieError, match="non-finite"):
         _e(_frag(f, frag_proj=c))
+
+
+def test_projector_single_occupied():
+    """One occupied orbital: M is 1 x 1 (the i = j = k triple, whose
+    contribution vanishes but for rounding: W-tilde and Z are symmetric in
+    abc, which R' annihilates), and E(C) = C M exactly."""
+    f = make_fragment(1, 20, 30, (7, 1))
+    m = _m(_frag(f))
+    assert m.shape == (1, 1) and np.isfinite(m).all()
+    e_ref = oracle.energy_dense(*f.arrays())
+    assert e_ref == 0.0 or abs(e_ref) < 1e-12
+    assert _e(_frag(f, frag_proj=np.array([[0.7]]))) == 0.7 * float(m[0, 0])
