@@ -603,6 +603,17 @@ __device__ __forceinline__ int orb_lds(int x, int y, int z) {
   return x * kOrbPlane + y * kOrbRow + z;
 }
 
+// In-block offset e = x*64 + y*8 + z of element l (0 <= l < 512, in the
+// order idx = threadIdx.x + 256 h of a 256-thread loop over one slot): thread
+// t takes (t / 32, (t / 4) % 8, 2 (t % 4) + h), the element mapping of the
+// epilogue, with which the permuted LDS reads of a wave spread over the banks
+// (consecutive z across the lanes would put lanes a 72-double row apart into
+// the same banks).
+__device__ __forceinline__ int orb_elem(int l) {
+  const int t = l & 255, h = l >> 8;
+  return ((t >> 5) << 6) | (((t >> 2) & 7) << 3) | ((t & 3) << 1) | h;
+}
+
 // Orbit slots enumerate the position permutations (0,1,2) (0,2,1) (1,0,2)
 // (1,2,0) (2,0,1) (2,1,0) of a block triple.
 __device__ __forceinline__ int orbit_slot(int p, int q, int r) {

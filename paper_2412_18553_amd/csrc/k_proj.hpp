@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void k_proj_wq(const FragDesc* __restrict__ de
     int t0, t1b, t2b;
     decode_sorted_triple(o, nb, t0, t1b, t2b);
     for (int idx = threadIdx.x; idx < 6 * E; idx += 256) {
-      const int s = idx / E, e = idx - s * E;
+      const int s = idx / E, e = orb_elem(idx - s * E);
       int p0, p1, p2;
       slot_perm(s, p0, p1, p2);
       const int a = kOrb * pick3(p0, t0, t1b, t2b) + (e >> 6);
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void k_proj_wq(const FragDesc* __restrict__ de
       if (!dup) primary |= 1u << s;
     }
     for (int idx = threadIdx.x; idx < 6 * E; idx += 256) {
-      const int s = idx / E, e = idx - s * E;
+      const int s = idx / E, e = orb_elem(idx - s * E);
       if (!((primary >> s) & 1u)) continue;
       int p0, p1, p2;
       slot_perm(s, p0, p1, p2);
