@@ -741,19 +741,36 @@ __global__ __launch_bounds__(256) void k_adj_ovov(const FragDesc* __restrict__ d
     int i, j, k;
     decode_sorted_triple(it.unit, no, i, j, k);
     const CubeT* H = arena + it.cube_off + fd.half;
-    if (rr.kind == 0) {          // (y, z) = (a, b): sum_c H[a][b][c] t1[k][c]
-      const SIE_GLOBAL CubeT* h = gptr(H) + y * nv2 + int64_t(z) * nv;
-      const SIE_GLOBAL InT* tv = gptr(t1) + int64_t(k) * nv;
-      for (int c = 0; c < nv; ++c) s += (double)h[c] * (double)tv[c];
-    } else if (rr.kind == 1) {   // (y, z) = (a, c): sum_b H[a][b][c] t1[j][b]
-      const SIE_GLOBAL CubeT* h = gptr(H) + y * nv2 + z;
-      const SIE_GLOBAL InT* tv = gptr(t1) + int64_t(j) * nv;
-      for (int b = 0; b < nv; ++b) s += (double)h[int64_t(b) * nv] * (double)tv[b];
-    } else {                     // (y, z) = (b, c): sum_a H[a][b][c] t1[i][a]
-      const SIE_GLOBAL CubeT* h = gptr(H) + int64_t(y) * nv + z;
-      const SIE_GLOBAL InT* tv = gptr(t1) + int64_t(i) * nv;
-      for (int a = 0; a < nv; ++a) s += (double)h[a * nv2] * (double)tv[a];
+    // (y, z) = (a, b): sum_c H[a][b][c] t1[k][c]; (a, c): sum_b H[a][b][c]
+    // t1[j][b]; (b, c): sum_a H[a][b][c] t1[i][a] -- a dot product of
+    // stride hs with a t1 row, in four interleaved partial sums (more loads
+    // in flight) added in a fixed order
+    const SIE_GLOBAL CubeT* h;
+    const SIE_GLOBAL InT* tv;
+    int64_t hs;
+    if (rr.kind == 0) {
+      h = gptr(H) + y * nv2 + int64_t(z) * nv;
+      tv = gptr(t1) + int64_t(k) * nv;
+      hs = 1;
+    } else if (rr.kind == 1) {
+      h = gptr(H) + y * nv2 + z;
+      tv = gptr(t1) + int64_t(j) * nv;
+      hs = nv;
+    } else {
+      h = gptr(H) + int64_t(y) * nv + z;
+      tv = gptr(t1) + int64_t(i) * nv;
+      hs = nv2;
     }
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+    int u = 0;
+    for (; u + 4 <= nv; u += 4) {
+      p0 += (double)h[int64_t(u) * hs] * (double)tv[u];
+      p1 += (double)h[int64_t(u + 1) * hs] * (double)tv[u + 1];
+      p2 += (double)h[int64_t(u + 2) * hs] * (double)tv[u + 2];
+      p3 += (double)h[int64_t(u + 3) * hs] * (double)tv[u + 3];
+    }
+    for (; u < nv; ++u) p0 += (double)h[int64_t(u) * hs] * (double)tv[u];
+    s += (p0 + p1) + (p2 + p3);
   }
   SIE_GLOBAL double* p = gptr_w(fd.g_ovov) + ((int64_t(gr.a0) * nv + y) * no + gr.a1) * nv + z;
   *p = *p + s;
@@ -802,11 +819,23 @@ __global__ __launch_bounds__(256) void k_adj_t1_part(const FragDesc* __restrict_
     for (int c0 = 0; c0 < nv; c0 += 64) {
       const int c = c0 + lane;
       double s = 0.0;
-      if (c < nv)
-        for (int64_t ab = wave; ab < nv2; ab += 4) {
-          const int aa = int(ab / nv), bb = int(ab - int64_t(aa) * nv);
-          s += (double)H[ab * nv + c] * (double)m[aa * onv + bb];
+      if (c < nv) {   // four interleaved partial sums, added in a fixed order
+        double p[4] = {0.0, 0.0, 0.0, 0.0};
+        int64_t ab = wave;
+        for (; ab + 12 < nv2; ab += 16) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int64_t x = ab + 4 * u;
+            const int aa = int(x / nv), bb = int(x - int64_t(aa) * nv);
+            p[u] += (double)H[x * nv + c] * (double)m[aa * onv + bb];
+          }
         }
+        for (; ab < nv2; ab += 4) {
+          const int aa = int(ab / nv), bb = int(ab - int64_t(aa) * nv);
+          p[0] += (double)H[ab * nv + c] * (double)m[aa * onv + bb];
+        }
+        s = (p[0] + p[1]) + (p[2] + p[3]);
+      }
       red[wave][lane] = s;
       __syncthreads();
       if (wave == 0 && c < nv)
@@ -823,12 +852,19 @@ __global__ __launch_bounds__(256) void k_adj_t1_part(const FragDesc* __restrict_
       for (int c0 = 0; c0 < nv; c0 += 64) {
         const int c = c0 + lane;
         double s = 0.0;
-        if (c < nv)
-          for (int u = 0; u < nv; ++u) {
-            const int64_t h = rr.kind == 1 ? (int64_t(u) * nv + y) * nv + c
-                                           : (int64_t(y) * nv + u) * nv + c;
-            s += (double)H[h] * (double)m[int64_t(u) * onv + c];
+        if (c < nv) {   // four interleaved partial sums, added in a fixed order
+          const int64_t h0 = rr.kind == 1 ? int64_t(y) * nv + c : int64_t(y) * nv2 + c;
+          const int64_t hu = rr.kind == 1 ? nv2 : nv;
+          double p[4] = {0.0, 0.0, 0.0, 0.0};
+          int u = 0;
+          for (; u + 4 <= nv; u += 4) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+              p[w] += (double)H[h0 + int64_t(u + w) * hu] * (double)m[int64_t(u + w) * onv + c];
           }
+          for (; u < nv; ++u) p[0] += (double)H[h0 + int64_t(u) * hu] * (double)m[int64_t(u) * onv + c];
+          s = (p[0] + p[1]) + (p[2] + p[3]);
+        }
         for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
         tot += s;
       }
