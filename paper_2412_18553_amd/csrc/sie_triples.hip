@@ -734,20 +734,65 @@ void make_tables(const sie_fragment* frags, int n, const Plan& pl, char* base,
     return (fp.lay3 ? 3 : 2) - (one ? 1 : 0);
   };
 
-  // rounds: consecutive items whose cube pairs fit in the arena
+  // rounds: consecutive items whose cube pairs fit in the arena.  A first
+  // greedy pass counts the rounds; the cut then aims at equal rounds (bytes
+  // and, for the gradient, items) so that the last round is not a small
+  // remainder, keeping the greedy cut if the balanced one needs more rounds.
   std::vector<sie::Item>& items = T.items;
   std::vector<size_t>& round_begin = T.round_begin;
   items.assign(order.size(), sie::Item{});
   round_begin.clear();
+  auto item_bytes = [&](size_t r) {
+    const FragPlan& fp = pl.frags[size_t(order[r].frag)];
+    return size_t(order[r].one ? fp.cubes_pair : fp.cubes) * fp.half_bytes;
+  };
+  auto count_rounds = [&](size_t cap_bytes, size_t cap_items) {
+    size_t n = 0, used = 0, cnt = 0;
+    for (size_t r = 0; r < order.size(); ++r) {
+      const size_t b = item_bytes(r);
+      if (r == 0 || used + b > cap_bytes || cnt >= cap_items) {
+        ++n;
+        used = 0;
+        cnt = 0;
+      }
+      used += b;
+      ++cnt;
+    }
+    return n;
+  };
+  size_t cap_bytes = arena_bytes;
+  size_t cap_items = grads ? kGradRoundItems : order.size() + 1;
+  {
+    const size_t n_greedy = count_rounds(cap_bytes, cap_items);
+    if (n_greedy > 1) {
+      size_t total = 0;
+      for (size_t r = 0; r < order.size(); ++r) total += item_bytes(r);
+      const size_t tb = (total + n_greedy - 1) / n_greedy;
+      const size_t ti = (order.size() + n_greedy - 1) / n_greedy;
+      size_t bb = tb, bi = ti;
+      // grow the targets until the balanced cut fits in as many rounds
+      for (int tries = 0; tries < 64; ++tries) {
+        const size_t cb = bb < arena_bytes ? bb : arena_bytes;
+        const size_t ci = bi < cap_items ? bi : cap_items;
+        if (count_rounds(cb, ci) <= n_greedy) {
+          cap_bytes = cb;
+          cap_items = ci;
+          break;
+        }
+        bb += (tb + 31) / 32;
+        bi += (ti + 31) / 32;
+      }
+    }
+  }
   {
     size_t used = 0;
     int64_t blk = 0, part = 0;
     const size_t elem = pl.split ? sizeof(float) : sizeof(double);
     for (size_t r = 0; r < order.size(); ++r) {
       const FragPlan& fp = pl.frags[size_t(order[r].frag)];
-      const size_t pair = size_t(order[r].one ? fp.cubes_pair : fp.cubes) * fp.half_bytes;
-      const bool full = grads && r > 0 && r - round_begin.back() >= kGradRoundItems;
-      if (r == 0 || used + pair > arena_bytes || full) {
+      const size_t pair = item_bytes(r);
+      const bool full = r > 0 && r - round_begin.back() >= cap_items;
+      if (r == 0 || used + pair > cap_bytes || full) {
         round_begin.push_back(r);
         used = 0;
         blk = 0;
