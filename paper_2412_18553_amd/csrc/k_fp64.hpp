@@ -659,11 +659,54 @@ __device__ __forceinline__ void ld_pair(const T* p, int64_t row, int64_t rs, int
   }
 }
 
+// Element of type T at byte offset `off` from a base that is the same in
+// every lane of the wave (read from the first lane, so that the load takes
+// the base from scalar registers and only the 32-bit offset per lane).
+// (readfirstlane moves 32 bits: the two halves of the address go separately)
+template <typename T, typename B>
+__device__ __forceinline__ T ld_at(const B* base, uint32_t off) {
+  const uint64_t a = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(a))));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(a >> 32))));
+  const uint64_t b = (uint64_t(hi) << 32) | lo;
+  return *(const SIE_GLOBAL T*)(reinterpret_cast<const SIE_GLOBAL char*>(b) + off);
+}
+
 // Element mapping of the epilogue: thread t holds, in every slot s of the
 // orbit, the two elements at in-block offsets (t / 32, (t / 4) % 8,
 // 2 (t % 4) + h), h = 0, 1 (adjacent along c), i.e. elements 2t and 2t + 1
-// of the slot's 8^3 block of a blocked cube (cube_at).  Wt of those 12
-// elements: w1[a][b][c] (+ w2[a][b][c], three layouts) + w3[b][a][c]; every
+// of the slot's 8^3 block of a blocked cube (cube_at).  The cube pairs of
+// those 12 elements: w1[a][b][c] (u), w2[a][b][c] (v, three layouts),
+// w3[b][a][c] (w), as loaded (the caller sums them once every load of the
+// orbit is in flight); every block of the padded cube exists, so nothing is
+// clamped (the caller masks elements past n_v).
+template <bool L3, typename CubeT, typename V2>
+__device__ __forceinline__ void epi_issue_w(const CubeT* __restrict__ w1,
+                                            const CubeT* __restrict__ w2,
+                                            const CubeT* __restrict__ w3, int nb, int t0,
+                                            int t1b, int t2b, V2 (&u)[6], V2 (&v)[6],
+                                            V2 (&w)[6]) {
+  constexpr int kB = kOrb * kOrb * kOrb;
+  const int x = threadIdx.x >> 5, y = (threadIdx.x >> 2) & 7, z0 = 2 * (threadIdx.x & 3);
+  // wave-uniform block bases, 32-bit lane offsets inside a block
+  const uint32_t in_xy = uint32_t(x * 64 + y * 8 + z0) * sizeof(CubeT);
+  const uint32_t in_yx = uint32_t(y * 64 + x * 8 + z0) * sizeof(CubeT);
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    int p0, p1, p2;
+    slot_perm(s, p0, p1, p2);
+    const int P0 = pick3(p0, t0, t1b, t2b), P1 = pick3(p1, t0, t1b, t2b);
+    const int P2 = pick3(p2, t0, t1b, t2b);
+    const int64_t o1 = ((int64_t(P0) * nb + P1) * nb + P2) * kB;
+    const int64_t o3 = ((int64_t(P1) * nb + P0) * nb + P2) * kB;
+    u[s] = ld_at<V2>(w1 + o1, in_xy);
+    if (L3) v[s] = ld_at<V2>(w2 + o1, in_xy);
+    w[s] = ld_at<V2>(w3 + o3, in_yx);
+  }
+}
+
+// Wt of the same 12 elements, summed as the loads arrive (float64 cubes,
+// whose raw pairs would take twice the registers): w1[a][b][c] (+ w2[a][b][c], three layouts) + w3[b][a][c]; every
 // block of the padded cube exists, so nothing is clamped (the caller masks
 // elements past n_v); all loads are issued before any is summed.
 template <bool L3, typename CubeT>
@@ -692,6 +735,89 @@ __device__ __forceinline__ void epi_load_w(const CubeT* __restrict__ w1,
   }
 }
 
+// Z = Wt + V-tilde of slot s of the orbit (t0, t1b, t2b) at this thread's
+// two elements, to LDS; elements past n_v get Z = 0 and Wt = 0.  rij, rik,
+// rjk: the slot's (ia|jb), (ia|kc), (jb|kc) elements; V: the orbit's vectors.
+template <typename InT>
+__device__ __forceinline__ void epi_z_slot(int s, int t0, int t1b, int t2b, int x, int y, int z0,
+                                           int nv, InT rij, const InT (&rik)[2],
+                                           const InT (&rjk)[2], const double* V,
+                                           double (&wreg)[12], double (*sz)[kOrbSlot]) {
+  int p0, p1, p2;
+  slot_perm(s, p0, p1, p2);
+  const int a = kOrb * pick3(p0, t0, t1b, t2b) + x;
+  const int b = kOrb * pick3(p1, t0, t1b, t2b) + y;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int zz = z0 + h;
+    double z = 0.0;
+    if (a < nv && b < nv && zz + kOrb * pick3(p2, t0, t1b, t2b) < nv) {
+      const double vt = (double)rij * V[(9 + p2) * kOrb + zz] +
+                        (double)rik[h] * V[(6 + p1) * kOrb + y] +
+                        (double)rjk[h] * V[(3 + p0) * kOrb + x];
+      z = wreg[2 * s + h] + vt;
+    } else {
+      wreg[2 * s + h] = 0.0;
+    }
+    sz[s][orb_lds(x, y, zz)] = z;
+  }
+}
+
+// Sum over this thread's elements of the orbit of Wt R'[Z] / D, Z read from
+// the six slots in LDS.  A slot whose block triple repeats an earlier slot's
+// is not summed twice (only when two of the sorted block indices are equal).
+__device__ __forceinline__ double epi_rprime(int t0, int t1b, int t2b, int x, int y, int z0,
+                                             int nv, double eijk, const double* V,
+                                             const double (&wreg)[12],
+                                             const double (*sz)[kOrbSlot]) {
+  unsigned primary = 63u;
+  if (t0 == t1b || t1b == t2b) {
+    primary = 0;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      int p0, p1, p2;
+      slot_perm(s, p0, p1, p2);
+      bool dup = false;
+#pragma unroll
+      for (int s2 = 0; s2 < s; ++s2) {
+        int q0, q1, q2;
+        slot_perm(s2, q0, q1, q2);
+        dup |= pick3(p0, t0, t1b, t2b) == pick3(q0, t0, t1b, t2b) &&
+               pick3(p1, t0, t1b, t2b) == pick3(q1, t0, t1b, t2b) &&
+               pick3(p2, t0, t1b, t2b) == pick3(q2, t0, t1b, t2b);
+      }
+      if (!dup) primary |= 1u << s;
+    }
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    if (!((primary >> s) & 1u)) continue;
+    int p0, p1, p2;
+    slot_perm(s, p0, p1, p2);
+    const int a = kOrb * pick3(p0, t0, t1b, t2b) + x;
+    const int b = kOrb * pick3(p1, t0, t1b, t2b) + y;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int zz = z0 + h;
+      const int c = kOrb * pick3(p2, t0, t1b, t2b) + zz;
+      if (a >= nv || b >= nv || c >= nv) continue;
+      // Z at the five permuted virtual triples, found in the slot holding
+      // the permuted block triple at the permuted in-block offsets
+      const double zabc = sz[s][orb_lds(x, y, zz)];
+      const double zcab = sz[orbit_slot(p2, p0, p1)][orb_lds(zz, x, y)];
+      const double zbca = sz[orbit_slot(p1, p2, p0)][orb_lds(y, zz, x)];
+      const double zcba = sz[orbit_slot(p2, p1, p0)][orb_lds(zz, y, x)];
+      const double zacb = sz[orbit_slot(p0, p2, p1)][orb_lds(x, zz, y)];
+      const double zbac = sz[orbit_slot(p1, p0, p2)][orb_lds(y, x, zz)];
+      const double rz = 4.0 * zabc + zcab + zbca - 2.0 * (zcba + zacb + zbac);
+      const double d = eijk - V[p0 * kOrb + x] - V[p1 * kOrb + y] - V[p2 * kOrb + zz];
+      acc += wreg[2 * s + h] * rz * recip(d);
+    }
+  }
+  return acc;
+}
+
 // Per-unit partial sums of Wt R'[Wt + Vt] / D over symmetric orbits of
 // 8 x 8 x 8 virtual blocks (A >= B >= C and their permuted images).
 // Wt[a][b][c] = P1[a][b][c] + P2[b][a][c] from the two-layout builds, or
@@ -699,8 +825,14 @@ __device__ __forceinline__ void epi_load_w(const CubeT* __restrict__ w1,
 // (FragDesc::lay3), float64 or float32 cubes; V-tilde from t1 and ovov
 // (float64 or float32 inputs), all arithmetic in float64.  Grid: the concatenated
 // epilogue blocks of the round's items (n_part per item; block p of an item
-// takes orbits p, p + n_part, ...).  Register bound: five waves a SIMD with
-// float32 cubes (the LDS allows five work-groups a CU), four with float64.
+// takes orbits p, p + n_part, ...).  At most 128 registers a lane (four
+// waves a SIMD).
+//
+// Each orbit's loads: with float32 cubes and inputs every load is issued
+// before any is used (the V entries, the cube pairs and the (ia|jb), (ia|kc),
+// (jb|kc) elements of the six slots), so that the orbit waits on memory
+// once; with float64 (twice the registers) the cube pairs are summed as they
+// arrive and each slot's ovov elements are loaded just before the slot.
 template <typename CubeT, typename InT>
 __global__ __launch_bounds__(256, 4) void k_epilogue(const FragDesc* __restrict__ descs,
                                                   const Item* __restrict__ items, int n_items,
@@ -717,6 +849,7 @@ __global__ __launch_bounds__(256, 4) void k_epilogue(const FragDesc* __restrict_
   // per orbit, for its three block positions: e_vir, t1[i], t1[j], t1[k]
   __shared__ double sv[4 * 3 * kOrb];
   __shared__ double red[4];
+  __shared__ int sorb[256];   // float32 path: packed orbit block triples
   double* out = partials + (fd.unit_base + it.unit) * pstride + slot;
   if (i == k) {
     if (threadIdx.x == 0) *out = 0.0;
@@ -746,130 +879,129 @@ __global__ __launch_bounds__(256, 4) void k_epilogue(const FragDesc* __restrict_
   const InT* t1k = t1 + (int64_t)k * nv;
 
   const double* V = sv;   // V[(3 q + p) kOrb + x]: vector q at block position p
+  const int x = threadIdx.x >> 5, y = (threadIdx.x >> 2) & 7, z0 = 2 * (threadIdx.x & 3);
+  // V entry of this thread (threads below 3 x 4 x kOrb keep theirs): vector
+  // vq at block position vp
+  const int vq = threadIdx.x / (3 * kOrb), vp = (threadIdx.x / kOrb) % 3;
+
+  // the slot's (ia|jb), (ia|kc), (jb|kc) elements at this thread's elements
+  // (pv: fd.epv, as a constant or not)
+  auto ov_load = [&](auto pv, int s, int t0, int t1b, int t2b, InT& rij, InT (&rik)[2],
+                     InT (&rjk)[2]) {
+    int p0, p1, p2;
+    slot_perm(s, p0, p1, p2);
+    const int ac = min(kOrb * pick3(p0, t0, t1b, t2b) + x, nv - 1);
+    const int bc = min(kOrb * pick3(p1, t0, t1b, t2b) + y, nv - 1);
+    const int c0 = kOrb * pick3(p2, t0, t1b, t2b) + z0;
+    // byte offsets inside one (i, j) slice of ovov, below 2^32 (the host
+    // limits s n_occ^2 n_vir^2)
+    constexpr uint32_t es = sizeof(InT);
+    const uint32_t ra = uint32_t(ac) * uint32_t(nonv), rb = uint32_t(bc) * uint32_t(nonv);
+    rij = ld_at<InT>(ov_ij, (ra + uint32_t(bc)) * es);
+    if (pv) {
+      // nv even and the rows aligned to two elements: an in-range even c0
+      // has c0 + 1 < nv, so the pair is one aligned load
+      typedef typename std::conditional<sizeof(InT) == 8, d2v, f2v>::type IV2;
+      const uint32_t cc = uint32_t(min(c0, nv - 2));
+      const IV2 pk = ld_at<IV2>(ov_ik, (ra + cc) * es);
+      const IV2 pj = ld_at<IV2>(ov_jk, (rb + cc) * es);
+      rik[0] = pk.x;
+      rik[1] = pk.y;
+      rjk[0] = pj.x;
+      rjk[1] = pj.y;
+    } else {
+      const uint32_t c1 = uint32_t(min(c0, nv - 1)), c2 = uint32_t(min(c0 + 1, nv - 1));
+      rik[0] = ld_at<InT>(ov_ik, (ra + c1) * es);
+      rik[1] = ld_at<InT>(ov_ik, (ra + c2) * es);
+      rjk[0] = ld_at<InT>(ov_jk, (rb + c1) * es);
+      rjk[1] = ld_at<InT>(ov_jk, (rb + c2) * es);
+    }
+  };
 
   double acc = 0.0;
-  for (int64_t o = slot; o < n_orb; o += fd.n_part) {
-    int t0, t1b, t2b;
-    decode_sorted_triple(o, nb, t0, t1b, t2b);
-    if (threadIdx.x < 4 * 3 * kOrb) {   // (the previous orbit's last barrier freed sv)
-      const int q = threadIdx.x / (3 * kOrb), p = (threadIdx.x / kOrb) % 3;
-      const int v = min(kOrb * pick3(p, t0, t1b, t2b) + int(threadIdx.x % kOrb), nv - 1);
-      double x;
-      if (q == 0) x = gptr(ev)[v];
-      else if (q == 1) x = (double)gptr(t1i)[v];
-      else if (q == 2) x = (double)gptr(t1j)[v];
-      else x = (double)gptr(t1k)[v];
-      sv[threadIdx.x] = x;
-    }
-    // Wt of this thread's elements (the same ones in both passes): every cube
-    // load of the orbit is issued before any is used, then V-tilde is added
-    // and Z = Wt + V-tilde goes to LDS
-    double wreg[12];
-    if (l3) epi_load_w<true>(w1, w2, w3, nb, t0, t1b, t2b, wreg);
-    else epi_load_w<false>(w1, w2, w3, nb, t0, t1b, t2b, wreg);
-    // the (ia|jb), (ia|kc), (jb|kc) elements of the six slots: with float32
-    // inputs issued with the cube loads (held as loaded), so that the orbit
-    // waits on memory once; float64 inputs (twice the registers) load them
-    // after the barrier
-    constexpr bool kEarly = sizeof(InT) == 4;
-    const int x = threadIdx.x >> 5, y = (threadIdx.x >> 2) & 7, z0 = 2 * (threadIdx.x & 3);
-    InT rij[6], rik[6][2], rjk[6][2];
-    auto ov_load = [&](int s) {
-      int p0, p1, p2;
-      slot_perm(s, p0, p1, p2);
-      const int ac = min(kOrb * pick3(p0, t0, t1b, t2b) + x, nv - 1);
-      const int bc = min(kOrb * pick3(p1, t0, t1b, t2b) + y, nv - 1);
-      const int c0 = kOrb * pick3(p2, t0, t1b, t2b) + z0;
-      rij[s] = gptr(ov_ij)[(int64_t)ac * nonv + bc];
-      if (fd.epv) {
-        // nv even: an in-range even c0 has c0 + 1 < nv, so the pair is aligned
-        const int cc = min(c0, nv - 2);
-        rik[s][0] = gptr(ov_ik)[(int64_t)ac * nonv + cc];
-        rik[s][1] = gptr(ov_ik)[(int64_t)ac * nonv + cc + 1];
-        rjk[s][0] = gptr(ov_jk)[(int64_t)bc * nonv + cc];
-        rjk[s][1] = gptr(ov_jk)[(int64_t)bc * nonv + cc + 1];
-      } else {
-        rik[s][0] = gptr(ov_ik)[(int64_t)ac * nonv + min(c0, nv - 1)];
-        rik[s][1] = gptr(ov_ik)[(int64_t)ac * nonv + min(c0 + 1, nv - 1)];
-        rjk[s][0] = gptr(ov_jk)[(int64_t)bc * nonv + min(c0, nv - 1)];
-        rjk[s][1] = gptr(ov_jk)[(int64_t)bc * nonv + min(c0 + 1, nv - 1)];
+  if constexpr (sizeof(CubeT) == 4 && sizeof(InT) == 4) {
+    // three layouts or two, n_v even with aligned ovov rows or not: constant
+    // in the loop (the loads of all six slots are then free of branches, and
+    // none waits for another)
+    auto orbits = [&](auto l3tag, auto pvtag) {
+      constexpr bool L3 = decltype(l3tag)::value;
+      // this work-group's orbits slot + m n_part, decoded 256 at a time by
+      // the threads in parallel into sorb (three 10-bit block indices;
+      // n_v <= 2048 gives at most 256 blocks), then read as wave-uniform
+      // values
+      const int64_t n_mine = (n_orb - slot + fd.n_part - 1) / fd.n_part;
+      for (int64_t m0 = 0; m0 < n_mine; m0 += 256) {
+        if (m0 + threadIdx.x < n_mine) {
+          int a, b, c;
+          decode_sorted_triple(slot + (m0 + threadIdx.x) * fd.n_part, nb, a, b, c);
+          sorb[threadIdx.x] = a | (b << 10) | (c << 20);
+        }
+        __syncthreads();
+        const int cnt = int(n_mine - m0 < 256 ? n_mine - m0 : 256);
+        for (int m = 0; m < cnt; ++m) {
+          const int pk = __builtin_amdgcn_readfirstlane(sorb[m]);
+          const int t0 = pk & 1023, t1b = (pk >> 10) & 1023, t2b = pk >> 20;
+          // both candidate V loads are in bounds for every thread
+          const int vv = min(kOrb * pick3(vp, t0, t1b, t2b) + int(threadIdx.x % kOrb), nv - 1);
+          const double ve = gptr(ev)[vv];
+          const InT vt = gptr(vq == 1 ? t1i : (vq == 2 ? t1j : t1k))[vv];
+          f2v cu[6], cv[6], cw[6];
+          epi_issue_w<L3>(w1, w2, w3, nb, t0, t1b, t2b, cu, cv, cw);
+          InT rij[6], rik[6][2], rjk[6][2];
+#pragma unroll
+          for (int s = 0; s < 6; ++s) ov_load(pvtag, s, t0, t1b, t2b, rij[s], rik[s], rjk[s]);
+          double wreg[12];
+#pragma unroll
+          for (int s = 0; s < 6; ++s) {
+            wreg[2 * s] = (double)cu[s].x + (L3 ? (double)cv[s].x : 0.0) + (double)cw[s].x;
+            wreg[2 * s + 1] = (double)cu[s].y + (L3 ? (double)cv[s].y : 0.0) + (double)cw[s].y;
+          }
+          // (the previous orbit's last barrier freed sv)
+          if (threadIdx.x < 4 * 3 * kOrb) sv[threadIdx.x] = vq == 0 ? ve : (double)vt;
+          __syncthreads();   // sv filled
+#pragma unroll
+          for (int s = 0; s < 6; ++s)
+            epi_z_slot(s, t0, t1b, t2b, x, y, z0, nv, rij[s], rik[s], rjk[s], V, wreg, sz);
+          __syncthreads();
+          acc += epi_rprime(t0, t1b, t2b, x, y, z0, nv, eijk, V, wreg, sz);
+          __syncthreads();   // (also orders this chunk's reads of sorb before the next chunk's writes)
+        }
       }
     };
-    if (kEarly) {
-#pragma unroll
-      for (int s = 0; s < 6; ++s) ov_load(s);
+    if (l3) {
+      if (fd.epv) orbits(std::true_type{}, std::true_type{});
+      else orbits(std::true_type{}, std::false_type{});
+    } else {
+      if (fd.epv) orbits(std::false_type{}, std::true_type{});
+      else orbits(std::false_type{}, std::false_type{});
     }
-    __syncthreads();   // sv filled
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      int p0, p1, p2;
-      slot_perm(s, p0, p1, p2);
-      const int a = kOrb * pick3(p0, t0, t1b, t2b) + x;
-      const int b = kOrb * pick3(p1, t0, t1b, t2b) + y;
-      if (!kEarly) ov_load(s);
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int zz = z0 + h;
-        double z = 0.0;
-        if (a < nv && b < nv && zz + kOrb * pick3(p2, t0, t1b, t2b) < nv) {
-          const double vt = (double)rij[s] * V[(9 + p2) * kOrb + zz] +
-                            (double)rik[s][h] * V[(6 + p1) * kOrb + y] +
-                            (double)rjk[s][h] * V[(3 + p0) * kOrb + x];
-          z = wreg[2 * s + h] + vt;
-        } else {
-          wreg[2 * s + h] = 0.0;
-        }
-        sz[s][orb_lds(x, y, zz)] = z;
+  } else {
+    for (int64_t o = slot; o < n_orb; o += fd.n_part) {
+      int t0, t1b, t2b;
+      decode_sorted_triple(o, nb, t0, t1b, t2b);
+      if (threadIdx.x < 4 * 3 * kOrb) {   // (the previous orbit's last barrier freed sv)
+        const int v = min(kOrb * pick3(vp, t0, t1b, t2b) + int(threadIdx.x % kOrb), nv - 1);
+        double xv;
+        if (vq == 0) xv = gptr(ev)[v];
+        else if (vq == 1) xv = (double)gptr(t1i)[v];
+        else if (vq == 2) xv = (double)gptr(t1j)[v];
+        else xv = (double)gptr(t1k)[v];
+        sv[threadIdx.x] = xv;
       }
-    }
-    __syncthreads();
-    // a slot whose block triple repeats an earlier slot's is not summed twice
-    // (only when two of the sorted block indices are equal)
-    unsigned primary = 63u;
-    if (t0 == t1b || t1b == t2b) {
-      primary = 0;
+      double wreg[12];
+      if (l3) epi_load_w<true>(w1, w2, w3, nb, t0, t1b, t2b, wreg);
+      else epi_load_w<false>(w1, w2, w3, nb, t0, t1b, t2b, wreg);
+      __syncthreads();   // sv filled
 #pragma unroll
       for (int s = 0; s < 6; ++s) {
-        int p0, p1, p2;
-        slot_perm(s, p0, p1, p2);
-        bool dup = false;
-#pragma unroll
-        for (int s2 = 0; s2 < s; ++s2) {
-          int q0, q1, q2;
-          slot_perm(s2, q0, q1, q2);
-          dup |= pick3(p0, t0, t1b, t2b) == pick3(q0, t0, t1b, t2b) &&
-                 pick3(p1, t0, t1b, t2b) == pick3(q1, t0, t1b, t2b) &&
-                 pick3(p2, t0, t1b, t2b) == pick3(q2, t0, t1b, t2b);
-        }
-        if (!dup) primary |= 1u << s;
+        InT rij, rik[2], rjk[2];
+        ov_load(fd.epv != 0, s, t0, t1b, t2b, rij, rik, rjk);
+        epi_z_slot(s, t0, t1b, t2b, x, y, z0, nv, rij, rik, rjk, V, wreg, sz);
       }
+      __syncthreads();
+      acc += epi_rprime(t0, t1b, t2b, x, y, z0, nv, eijk, V, wreg, sz);
+      __syncthreads();
     }
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      if (!((primary >> s) & 1u)) continue;
-      int p0, p1, p2;
-      slot_perm(s, p0, p1, p2);
-      const int a = kOrb * pick3(p0, t0, t1b, t2b) + x;
-      const int b = kOrb * pick3(p1, t0, t1b, t2b) + y;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int zz = z0 + h;
-        const int c = kOrb * pick3(p2, t0, t1b, t2b) + zz;
-        if (a >= nv || b >= nv || c >= nv) continue;
-        // Z at the five permuted virtual triples, found in the slot holding
-        // the permuted block triple at the permuted in-block offsets
-        const double zabc = sz[s][orb_lds(x, y, zz)];
-        const double zcab = sz[orbit_slot(p2, p0, p1)][orb_lds(zz, x, y)];
-        const double zbca = sz[orbit_slot(p1, p2, p0)][orb_lds(y, zz, x)];
-        const double zcba = sz[orbit_slot(p2, p1, p0)][orb_lds(zz, y, x)];
-        const double zacb = sz[orbit_slot(p0, p2, p1)][orb_lds(x, zz, y)];
-        const double zbac = sz[orbit_slot(p1, p0, p2)][orb_lds(y, x, zz)];
-        const double rz = 4.0 * zabc + zcab + zbca - 2.0 * (zcba + zacb + zbac);
-        const double d = eijk - V[p0 * kOrb + x] - V[p1 * kOrb + y] - V[p2 * kOrb + zz];
-        acc += wreg[2 * s + h] * rz * recip(d);
-      }
-    }
-    __syncthreads();
   }
   const double s = block_sum_256(acc, red);
   if (threadIdx.x == 0) *out = s;
