@@ -818,6 +818,82 @@ __device__ __forceinline__ double epi_rprime(int t0, int t1b, int t2b, int x, in
   return acc;
 }
 
+// Energy of this thread's virtual triples (a, b, c_h), h = 0, 1, of an orbit
+// with all six orderings of each (float32 inputs): Wt of the orderings from
+// the six slots in LDS (the first from wreg), V-tilde of each ordering from
+// the ovov elements o_pq (slices (i,j), (i,k), (j,k)) and the orbit's t1
+// vectors in V, Z = Wt + V-tilde.  With the cyclic orderings (abc, bca, cab)
+// as even and the others as odd, R'[Z] of an even ordering is
+// 3 Z + S_e - 2 S_o (S_e, S_o: the sums of Z over the even and the odd
+// orderings), and of an odd one 3 Z + S_o - 2 S_e, so the six terms of
+// Wt R'[Z] / D (one D for all six) add up to
+//   (3 sum Wt Z + (S_e - 2 S_o) W_e + (S_o - 2 S_e) W_o) / D.
+// Orbits with equal block indices repeat slots: there only triples with
+// a >= b (first two blocks equal) or b >= c (last two) count, those with a
+// repeated index at half weight (their six orderings hold each triple
+// twice), and a = b = c not at all (R' annihilates it).
+template <typename InT>
+__device__ __forceinline__ double epi_triple_orbits(
+    int t0, int t1b, int t2b, int x, int y, int z0, int ar, int br, int c0, int nv, double eijk,
+    const double* V, const double (&wreg)[12], const double (*sz)[kOrbSlot],
+    const InT (&o_ab)[3], const InT (&o_ba)[3], const InT (&o_ac)[3][2],
+    const InT (&o_bc)[3][2], const InT (&o_ca)[3][2], const InT (&o_cb)[3][2]) {
+  const bool e01 = t0 == t1b, e12 = t1b == t2b;
+  // V[(3 q + p) kOrb + o]: e_vir (q = 0), t1[i], t1[j], t1[k] at block position p
+  const double ea = V[x], eb = V[kOrb + y];
+  const double ia = V[3 * kOrb + x], ib = V[4 * kOrb + y];
+  const double ja = V[6 * kOrb + x], jb = V[7 * kOrb + y];
+  const double ka = V[9 * kOrb + x], kb = V[10 * kOrb + y];
+  // q = 0: (i|j), 1: (i|k), 2: (j|k)
+  const double ij_ab = o_ab[0], ik_ab = o_ab[1], jk_ab = o_ab[2];
+  const double ij_ba = o_ba[0], ik_ba = o_ba[1], jk_ba = o_ba[2];
+  double acc = 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int zz = z0 + h;
+    const double ec = V[2 * kOrb + zz];
+    const double ic = V[5 * kOrb + zz], jc = V[8 * kOrb + zz], kc = V[11 * kOrb + zz];
+    const double ij_ac = o_ac[0][h], ik_ac = o_ac[1][h], jk_ac = o_ac[2][h];
+    const double ij_bc = o_bc[0][h], ik_bc = o_bc[1][h], jk_bc = o_bc[2][h];
+    const double ij_ca = o_ca[0][h], ik_ca = o_ca[1][h], jk_ca = o_ca[2][h];
+    const double ij_cb = o_cb[0][h], ik_cb = o_cb[1][h], jk_cb = o_cb[2][h];
+    // Wt of the orderings abc, bca, cab (even) and acb, bac, cba (odd)
+    const double w_abc = wreg[h];
+    const double w_bca = sz[3][orb_lds(y, zz, x)];
+    const double w_cab = sz[4][orb_lds(zz, x, y)];
+    const double w_acb = sz[1][orb_lds(x, zz, y)];
+    const double w_bac = sz[2][orb_lds(y, x, zz)];
+    const double w_cba = sz[5][orb_lds(zz, y, x)];
+    // V-tilde(pqr) = (ip|jq) t1[k][r] + (ip|kr) t1[j][q] + (jq|kr) t1[i][p]
+    const double z_abc = w_abc + (ij_ab * kc + ik_ac * jb + jk_bc * ia);
+    const double z_bca = w_bca + (ij_bc * ka + ik_ba * jc + jk_ca * ib);
+    const double z_cab = w_cab + (ij_ca * kb + ik_cb * ja + jk_ab * ic);
+    const double z_acb = w_acb + (ij_ac * kb + ik_ab * jc + jk_cb * ia);
+    const double z_bac = w_bac + (ij_ba * kc + ik_bc * ja + jk_ac * ib);
+    const double z_cba = w_cba + (ij_cb * ka + ik_ca * jb + jk_ba * ic);
+    const double se = (z_abc + z_bca) + z_cab, so = (z_acb + z_bac) + z_cba;
+    const double we = (w_abc + w_bca) + w_cab, wo = (w_acb + w_bac) + w_cba;
+    const double swz = w_abc * z_abc + w_bca * z_bca + w_cab * z_cab + w_acb * z_acb +
+                       w_bac * z_bac + w_cba * z_cba;
+    const double num = 3.0 * swz + (se - 2.0 * so) * we + (so - 2.0 * se) * wo;
+    const int cr = c0 + h;
+    // which triples of a degenerate orbit count, and at what weight (in-block
+    // offsets x, y, zz)
+    double wgt = 1.0;
+    if (e01 && e12) {
+      wgt = (x > y && y > zz) ? 1.0 : ((x >= y && y >= zz && !(x == y && y == zz)) ? 0.5 : 0.0);
+    } else if (e01) {
+      wgt = x > y ? 1.0 : (x == y ? 0.5 : 0.0);
+    } else if (e12) {
+      wgt = y > zz ? 1.0 : (y == zz ? 0.5 : 0.0);
+    }
+    const double d = eijk - ea - eb - ec;
+    const double term = wgt * num * recip(d);
+    acc += (ar < nv && br < nv && cr < nv && wgt != 0.0) ? term : 0.0;
+  }
+  return acc;
+}
+
 // Per-unit partial sums of Wt R'[Wt + Vt] / D over symmetric orbits of
 // 8 x 8 x 8 virtual blocks (A >= B >= C and their permuted images).
 // Wt[a][b][c] = P1[a][b][c] + P2[b][a][c] from the two-layout builds, or
@@ -947,23 +1023,62 @@ __global__ __launch_bounds__(256, 4) void k_epilogue(const FragDesc* __restrict_
           const InT vt = gptr(vq == 1 ? t1i : (vq == 2 ? t1j : t1k))[vv];
           f2v cu[6], cv[6], cw[6];
           epi_issue_w<L3>(w1, w2, w3, nb, t0, t1b, t2b, cu, cv, cw);
-          InT rij[6], rik[6][2], rjk[6][2];
+          // This thread's virtual triples (a, b, c_h) of the first slot,
+          // c_h = c0 + h, and the ovov elements of all six orderings of each:
+          // (p|q) for the ordered pairs of {a, b, c_h} in the (i, j), (i, k)
+          // and (j, k) slices (indices clamped in range; results past n_v are
+          // not used).
+          const int ar = kOrb * t0 + x, br = kOrb * t1b + y, c0 = kOrb * t2b + z0;
+          const uint32_t ua = uint32_t(min(ar, nv - 1)), ub = uint32_t(min(br, nv - 1));
+          const uint32_t nov = uint32_t(nonv);
+          constexpr uint32_t es = sizeof(InT);
+          const InT* const sl[3] = {ov_ij, ov_ik, ov_jk};
+          InT o_ab[3], o_ba[3], o_ac[3][2], o_bc[3][2], o_ca[3][2], o_cb[3][2];
 #pragma unroll
-          for (int s = 0; s < 6; ++s) ov_load(pvtag, s, t0, t1b, t2b, rij[s], rik[s], rjk[s]);
+          for (int q = 0; q < 3; ++q) {
+            o_ab[q] = ld_at<InT>(sl[q], (ua * nov + ub) * es);
+            o_ba[q] = ld_at<InT>(sl[q], (ub * nov + ua) * es);
+            if (decltype(pvtag)::value) {
+              // n_v even, rows aligned to two elements: (c0, c0 + 1) in range
+              // is one aligned pair
+              const uint32_t cc = uint32_t(min(c0, nv - 2));
+              const f2v pa = ld_at<f2v>(sl[q], (ua * nov + cc) * es);
+              const f2v pb = ld_at<f2v>(sl[q], (ub * nov + cc) * es);
+              o_ac[q][0] = pa.x;
+              o_ac[q][1] = pa.y;
+              o_bc[q][0] = pb.x;
+              o_bc[q][1] = pb.y;
+            } else {
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const uint32_t uc = uint32_t(min(c0 + h, nv - 1));
+                o_ac[q][h] = ld_at<InT>(sl[q], (ua * nov + uc) * es);
+                o_bc[q][h] = ld_at<InT>(sl[q], (ub * nov + uc) * es);
+              }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const uint32_t uc = uint32_t(min(c0 + h, nv - 1));
+              o_ca[q][h] = ld_at<InT>(sl[q], (uc * nov + ua) * es);
+              o_cb[q][h] = ld_at<InT>(sl[q], (uc * nov + ub) * es);
+            }
+          }
           double wreg[12];
 #pragma unroll
           for (int s = 0; s < 6; ++s) {
             wreg[2 * s] = (double)cu[s].x + (L3 ? (double)cv[s].x : 0.0) + (double)cw[s].x;
             wreg[2 * s + 1] = (double)cu[s].y + (L3 ? (double)cv[s].y : 0.0) + (double)cw[s].y;
           }
-          // (the previous orbit's last barrier freed sv)
+          // (the previous orbit's last barrier freed sv and sz)
           if (threadIdx.x < 4 * 3 * kOrb) sv[threadIdx.x] = vq == 0 ? ve : (double)vt;
-          __syncthreads();   // sv filled
 #pragma unroll
-          for (int s = 0; s < 6; ++s)
-            epi_z_slot(s, t0, t1b, t2b, x, y, z0, nv, rij[s], rik[s], rjk[s], V, wreg, sz);
-          __syncthreads();
-          acc += epi_rprime(t0, t1b, t2b, x, y, z0, nv, eijk, V, wreg, sz);
+          for (int s = 0; s < 6; ++s) {
+            sz[s][orb_lds(x, y, z0)] = wreg[2 * s];
+            sz[s][orb_lds(x, y, z0 + 1)] = wreg[2 * s + 1];
+          }
+          __syncthreads();   // Wt of the orbit and its vectors in LDS
+          acc += epi_triple_orbits(t0, t1b, t2b, x, y, z0, ar, br, c0, nv, eijk, V, wreg, sz,
+                                   o_ab, o_ba, o_ac, o_bc, o_ca, o_cb);
           __syncthreads();   // (also orders this chunk's reads of sorb before the next chunk's writes)
         }
       }
