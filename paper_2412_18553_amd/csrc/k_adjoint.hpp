@@ -54,7 +54,7 @@ namespace sie {
 // row, to ev_part[(r pstride + slot) ev_stride + x] (r: item index in the
 // round).  All sums run in fixed orders (wave shuffles, then fixed lanes).
 template <typename CubeT, typename InT>
-__global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
+__global__ __launch_bounds__(256, 2) void k_hat(const FragDesc* __restrict__ descs,
                                              const Item* __restrict__ items, int n_items,
                                              CubeT* __restrict__ arena,
                                              double* __restrict__ partials, int pstride,
@@ -71,6 +71,7 @@ __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
   __shared__ double sw[6][kOrbSlot];
   __shared__ double sz[6][kOrbSlot];
   __shared__ double red[4];
+  __shared__ double se[3 * kOrb];   // e_vir at the orbit's three blocks
   // orbital-energy gradient: virtual row of this work-group and the
   // cross-wave partials of one orbit's marginals
   __shared__ double dv[SIE_MAX_VIR];
@@ -113,24 +114,57 @@ __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
   for (int64_t o = slot; o < n_orb; o += fd.n_part) {
     int t0, t1b, t2b;
     decode_sorted_triple(o, nb, t0, t1b, t2b);
-    for (int idx = threadIdx.x; idx < 6 * E; idx += 256) {
-      const int s = idx / E, e = orb_elem(idx - s * E);
-      int p0, p1, p2;
-      slot_perm(s, p0, p1, p2);
-      const int a = kOrb * pick3(p0, t0, t1b, t2b) + (e >> 6);
-      const int b = kOrb * pick3(p1, t0, t1b, t2b) + ((e >> 3) & 7);
-      const int c = kOrb * pick3(p2, t0, t1b, t2b) + (e & 7);
-      double w = 0.0, z = 0.0;
-      if (a < nv && b < nv && c < nv) {
-        w = (double)gptr(w1)[((int64_t)a * nv + b) * nv + c] +
-            (double)gptr(w2)[((int64_t)b * nv + a) * nv + c];
-        const double vt = (double)gptr(ov_ij)[(int64_t)a * nonv + b] * (double)gptr(t1k)[c] +
-                          (double)gptr(ov_ik)[(int64_t)a * nonv + c] * (double)gptr(t1j)[b] +
-                          (double)gptr(ov_jk)[(int64_t)b * nonv + c] * (double)gptr(t1i)[a];
-        z = w + vt;
+    // Wt and Z of the orbit's 6 x 512 elements, 12 per thread, in batches
+    // (all 12 with float32 values, 6 with float64: registers): every load
+    // of a batch (indices clamped in range, results past n_v masked) is
+    // issued before any is used
+    // (the previous orbit's last barrier freed se)
+    if (threadIdx.x < 3 * kOrb)
+      se[threadIdx.x] = gptr(ev)[min(kOrb * pick3(threadIdx.x / kOrb, t0, t1b, t2b) +
+                                         int(threadIdx.x % kOrb), nv - 1)];
+    constexpr int kPer = 6 * E / 256;
+    constexpr int kBatch = sizeof(CubeT) == 4 && sizeof(InT) == 4 ? kPer : kPer / 2;
+#pragma unroll
+    for (int m0 = 0; m0 < kPer; m0 += kBatch) {
+      CubeT lw1[kBatch], lw2[kBatch];
+      InT lij[kBatch], lik[kBatch], ljk[kBatch], lti[kBatch], ltj[kBatch], ltk[kBatch];
+#pragma unroll
+      for (int m = 0; m < kBatch; ++m) {
+        const int idx = threadIdx.x + 256 * (m0 + m);
+        const int s = idx / E, e = orb_elem(idx - s * E);
+        int p0, p1, p2;
+        slot_perm(s, p0, p1, p2);
+        const int64_t a = min(kOrb * pick3(p0, t0, t1b, t2b) + (e >> 6), nv - 1);
+        const int64_t b = min(kOrb * pick3(p1, t0, t1b, t2b) + ((e >> 3) & 7), nv - 1);
+        const int64_t c = min(kOrb * pick3(p2, t0, t1b, t2b) + (e & 7), nv - 1);
+        lw1[m] = gptr(w1)[(a * nv + b) * nv + c];
+        lw2[m] = gptr(w2)[(b * nv + a) * nv + c];
+        lij[m] = gptr(ov_ij)[a * nonv + b];
+        lik[m] = gptr(ov_ik)[a * nonv + c];
+        ljk[m] = gptr(ov_jk)[b * nonv + c];
+        lti[m] = gptr(t1i)[a];
+        ltj[m] = gptr(t1j)[b];
+        ltk[m] = gptr(t1k)[c];
       }
-      sw[s][orb_lds(e >> 6, (e >> 3) & 7, e & 7)] = w;
-      sz[s][orb_lds(e >> 6, (e >> 3) & 7, e & 7)] = z;
+#pragma unroll
+      for (int m = 0; m < kBatch; ++m) {
+        const int idx = threadIdx.x + 256 * (m0 + m);
+        const int s = idx / E, e = orb_elem(idx - s * E);
+        int p0, p1, p2;
+        slot_perm(s, p0, p1, p2);
+        const int a = kOrb * pick3(p0, t0, t1b, t2b) + (e >> 6);
+        const int b = kOrb * pick3(p1, t0, t1b, t2b) + ((e >> 3) & 7);
+        const int c = kOrb * pick3(p2, t0, t1b, t2b) + (e & 7);
+        double w = 0.0, z = 0.0;
+        if (a < nv && b < nv && c < nv) {
+          w = (double)lw1[m] + (double)lw2[m];
+          const double vt = (double)lij[m] * (double)ltk[m] + (double)lik[m] * (double)ltj[m] +
+                            (double)ljk[m] * (double)lti[m];
+          z = w + vt;
+        }
+        sw[s][orb_lds(e >> 6, (e >> 3) & 7, e & 7)] = w;
+        sz[s][orb_lds(e >> 6, (e >> 3) & 7, e & 7)] = z;
+      }
     }
     __syncthreads();
     unsigned primary = 0;
@@ -169,7 +203,8 @@ __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
                         2.0 * (sz[s_cba][e_cba] + sz[s_acb][e_acb] + sz[s_bac][e_bac]);
       const double rw = 4.0 * sw[s][e_abc] + sw[s_cab][e_cab] + sw[s_bca][e_bca] -
                         2.0 * (sw[s_cba][e_cba] + sw[s_acb][e_acb] + sw[s_bac][e_bac]);
-      const double id = recip(eijk - gptr(ev)[a] - gptr(ev)[b] - gptr(ev)[c]);   // 1 / D
+      const double id =
+          recip(eijk - se[p0 * kOrb + x] - se[p1 * kOrb + y] - se[p2 * kOrb + zz]);   // 1 / D
       acc += sw[s][e_abc] * rz * id;
       const int64_t pos = ((int64_t)a * nv + b) * nv + c;
       gptr_w(w1)[pos] = CubeT(scale * (rw + rz) * id);
@@ -212,7 +247,7 @@ __global__ __launch_bounds__(256) void k_hat(const FragDesc* __restrict__ descs,
           const double f = 3.0 * wz - 0.5 * (we + wo) * (ze + zo) + 1.5 * (we - wo) * (ze - zo);
           const int eq = (a == b) + (b == c) + (a == c);
           const double wt = eq == 0 ? 1.0 : (eq == 1 ? 0.5 : 1.0 / 6.0);
-          const double id = recip(eijk - gptr(ev)[a] - gptr(ev)[b] - gptr(ev)[c]);
+          const double id = recip(eijk - se[ox] - se[kOrb + oy] - se[2 * kOrb + oz]);
           q = scale * wt * f * id * id;
         }
         eacc += q;
