@@ -676,16 +676,14 @@ __device__ __forceinline__ T ld_at(const B* base, uint32_t off) {
 // orbit, the two elements at in-block offsets (t / 32, (t / 4) % 8,
 // 2 (t % 4) + h), h = 0, 1 (adjacent along c), i.e. elements 2t and 2t + 1
 // of the slot's 8^3 block of a blocked cube (cube_at).  The cube pairs of
-// those 12 elements: w1[a][b][c] (u), w2[a][b][c] (v, three layouts),
-// w3[b][a][c] (w), as loaded (the caller sums them once every load of the
-// orbit is in flight); every block of the padded cube exists, so nothing is
-// clamped (the caller masks elements past n_v).
-template <bool L3, typename CubeT, typename V2>
+// those 12 elements from two-layout cubes: w1[a][b][c] (u) and w3[b][a][c]
+// (w), as loaded (the caller sums them once every load of the orbit is in
+// flight); every block of the padded cube exists, so nothing is clamped (the
+// caller masks elements past n_v).
+template <typename CubeT, typename V2>
 __device__ __forceinline__ void epi_issue_w(const CubeT* __restrict__ w1,
-                                            const CubeT* __restrict__ w2,
                                             const CubeT* __restrict__ w3, int nb, int t0,
-                                            int t1b, int t2b, V2 (&u)[6], V2 (&v)[6],
-                                            V2 (&w)[6]) {
+                                            int t1b, int t2b, V2 (&u)[6], V2 (&w)[6]) {
   constexpr int kB = kOrb * kOrb * kOrb;
   const int x = threadIdx.x >> 5, y = (threadIdx.x >> 2) & 7, z0 = 2 * (threadIdx.x & 3);
   // wave-uniform block bases, 32-bit lane offsets inside a block
@@ -700,7 +698,6 @@ __device__ __forceinline__ void epi_issue_w(const CubeT* __restrict__ w1,
     const int64_t o1 = ((int64_t(P0) * nb + P1) * nb + P2) * kB;
     const int64_t o3 = ((int64_t(P1) * nb + P0) * nb + P2) * kB;
     u[s] = ld_at<V2>(w1 + o1, in_xy);
-    if (L3) v[s] = ld_at<V2>(w2 + o1, in_xy);
     w[s] = ld_at<V2>(w3 + o3, in_yx);
   }
 }
@@ -904,11 +901,14 @@ __device__ __forceinline__ double epi_triple_orbits(
 // takes orbits p, p + n_part, ...).  At most 128 registers a lane (four
 // waves a SIMD).
 //
-// Each orbit's loads: with float32 cubes and inputs every load is issued
-// before any is used (the V entries, the cube pairs and the (ia|jb), (ia|kc),
-// (jb|kc) elements of the six slots), so that the orbit waits on memory
-// once; with float64 (twice the registers) the cube pairs are summed as they
-// arrive and each slot's ovov elements are loaded just before the slot.
+// Float32 cubes and inputs (the split form, whose build writes two layouts):
+// every load of an orbit is issued before any is used (the V entries, the
+// cube pairs and the ovov elements of each thread's triples), so that the
+// orbit waits on memory once; Wt goes to LDS and each thread sums its
+// triples with all six orderings (epi_triple_orbits).  Float64 (twice the
+// registers): the cube pairs are summed as they arrive, each slot's ovov
+// elements are loaded just before the slot, Z goes to LDS and every element
+// is summed by the thread that holds it (epi_z_slot, epi_rprime).
 template <typename CubeT, typename InT>
 __global__ __launch_bounds__(256, 4) void k_epilogue(const FragDesc* __restrict__ descs,
                                                   const Item* __restrict__ items, int n_items,
@@ -921,7 +921,7 @@ __global__ __launch_bounds__(256, 4) void k_epilogue(const FragDesc* __restrict_
   const int slot = int(int64_t(blockIdx.x) - start);
   int i, j, k;
   const bool one = unit_triple(it.unit, fd.no, fd.pair, i, j, k);
-  __shared__ double sz[6][kOrbSlot];
+  __shared__ double sz[6][kOrbSlot];   // the six slots' Wt (float32) or Z (float64)
   // per orbit, for its three block positions: e_vir, t1[i], t1[j], t1[k]
   __shared__ double sv[4 * 3 * kOrb];
   __shared__ double red[4];
@@ -996,11 +996,9 @@ __global__ __launch_bounds__(256, 4) void k_epilogue(const FragDesc* __restrict_
 
   double acc = 0.0;
   if constexpr (sizeof(CubeT) == 4 && sizeof(InT) == 4) {
-    // three layouts or two, n_v even with aligned ovov rows or not: constant
-    // in the loop (the loads of all six slots are then free of branches, and
-    // none waits for another)
-    auto orbits = [&](auto l3tag, auto pvtag) {
-      constexpr bool L3 = decltype(l3tag)::value;
+    // n_v even with aligned ovov rows or not: a constant in the loop (the
+    // loads are then free of branches, and none waits for another)
+    auto orbits = [&](auto pvtag) {
       // this work-group's orbits slot + m n_part, decoded 256 at a time by
       // the threads in parallel into sorb (three 10-bit block indices;
       // n_v <= 2048 gives at most 256 blocks), then read as wave-uniform
@@ -1021,8 +1019,8 @@ __global__ __launch_bounds__(256, 4) void k_epilogue(const FragDesc* __restrict_
           const int vv = min(kOrb * pick3(vp, t0, t1b, t2b) + int(threadIdx.x % kOrb), nv - 1);
           const double ve = gptr(ev)[vv];
           const InT vt = gptr(vq == 1 ? t1i : (vq == 2 ? t1j : t1k))[vv];
-          f2v cu[6], cv[6], cw[6];
-          epi_issue_w<L3>(w1, w2, w3, nb, t0, t1b, t2b, cu, cv, cw);
+          f2v cu[6], cw[6];
+          epi_issue_w(w1, w3, nb, t0, t1b, t2b, cu, cw);
           // This thread's virtual triples (a, b, c_h) of the first slot,
           // c_h = c0 + h, and the ovov elements of all six orderings of each:
           // (p|q) for the ordered pairs of {a, b, c_h} in the (i, j), (i, k)
@@ -1066,8 +1064,8 @@ __global__ __launch_bounds__(256, 4) void k_epilogue(const FragDesc* __restrict_
           double wreg[12];
 #pragma unroll
           for (int s = 0; s < 6; ++s) {
-            wreg[2 * s] = (double)cu[s].x + (L3 ? (double)cv[s].x : 0.0) + (double)cw[s].x;
-            wreg[2 * s + 1] = (double)cu[s].y + (L3 ? (double)cv[s].y : 0.0) + (double)cw[s].y;
+            wreg[2 * s] = (double)cu[s].x + (double)cw[s].x;
+            wreg[2 * s + 1] = (double)cu[s].y + (double)cw[s].y;
           }
           // (the previous orbit's last barrier freed sv and sz)
           if (threadIdx.x < 4 * 3 * kOrb) sv[threadIdx.x] = vq == 0 ? ve : (double)vt;
@@ -1083,13 +1081,8 @@ __global__ __launch_bounds__(256, 4) void k_epilogue(const FragDesc* __restrict_
         }
       }
     };
-    if (l3) {
-      if (fd.epv) orbits(std::true_type{}, std::true_type{});
-      else orbits(std::true_type{}, std::false_type{});
-    } else {
-      if (fd.epv) orbits(std::false_type{}, std::true_type{});
-      else orbits(std::false_type{}, std::false_type{});
-    }
+    if (fd.epv) orbits(std::true_type{});
+    else orbits(std::false_type{});
   } else {
     for (int64_t o = slot; o < n_orb; o += fd.n_part) {
       int t0, t1b, t2b;
