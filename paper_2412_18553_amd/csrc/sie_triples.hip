@@ -34,6 +34,7 @@ sie_status fail(sie_status s, const std::string& msg) {
 
 constexpr size_t kDefaultCap = size_t(16) << 30;  // 16 GiB of the 288 GB of HBM
 constexpr int kMaxPartials = 256;                  // epilogue blocks per unit
+constexpr int kMinOrbits = 16;                     // orbits per epilogue block, where there are enough
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -123,7 +124,10 @@ FragPlan frag_plan(int no, int nv, bool split) {
   p.work_units = p.n_units - no;
   const int64_t nb = (nv + sie::kOrb - 1) / sie::kOrb;
   const int64_t n_orb = sie::tetra(nb);
-  p.n_part = int(n_orb < kMaxPartials ? n_orb : kMaxPartials);
+  // each epilogue block takes at least kMinOrbits orbits (its set-up is paid
+  // once per block), up to kMaxPartials blocks per unit
+  const int64_t parts = (n_orb + kMinOrbits - 1) / kMinOrbits;
+  p.n_part = int(parts < kMaxPartials ? parts : kMaxPartials);
   const size_t o = size_t(no), v = size_t(nv);
   if (split) {
     p.Kv = int(round_up(v, sie::kKs));
