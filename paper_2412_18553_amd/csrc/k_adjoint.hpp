@@ -122,29 +122,66 @@ __global__ __launch_bounds__(256, 2) void k_hat(const FragDesc* __restrict__ des
     if (threadIdx.x < 3 * kOrb)
       se[threadIdx.x] = gptr(ev)[min(kOrb * pick3(threadIdx.x / kOrb, t0, t1b, t2b) +
                                          int(threadIdx.x % kOrb), nv - 1)];
+    typedef typename std::conditional<sizeof(CubeT) == 8, d2v, f2v>::type CV2;
+    typedef typename std::conditional<sizeof(InT) == 8, d2v, f2v>::type IV2;
+    const bool even_nv = (nv & 1) == 0;
     constexpr int kPer = 6 * E / 256;
     constexpr int kBatch = sizeof(CubeT) == 4 && sizeof(InT) == 4 ? kPer : kPer / 2;
 #pragma unroll
     for (int m0 = 0; m0 < kPer; m0 += kBatch) {
       CubeT lw1[kBatch], lw2[kBatch];
       InT lij[kBatch], lik[kBatch], ljk[kBatch], lti[kBatch], ltj[kBatch], ltk[kBatch];
+      // elements 2q and 2q + 1 of a batch are this thread's (x, y, z0) and
+      // (x, y, z0 + 1) of one slot, adjacent along c: with n_v even their
+      // cube values are one two-element load each (an in-range even c0 has
+      // c0 + 1 < n_v), and so are (ia|kc), (jb|kc) with aligned ovov rows
 #pragma unroll
-      for (int m = 0; m < kBatch; ++m) {
+      for (int q = 0; q < kBatch / 2; ++q) {
+        const int m = 2 * q;
         const int idx = threadIdx.x + 256 * (m0 + m);
         const int s = idx / E, e = orb_elem(idx - s * E);
         int p0, p1, p2;
         slot_perm(s, p0, p1, p2);
         const int64_t a = min(kOrb * pick3(p0, t0, t1b, t2b) + (e >> 6), nv - 1);
         const int64_t b = min(kOrb * pick3(p1, t0, t1b, t2b) + ((e >> 3) & 7), nv - 1);
-        const int64_t c = min(kOrb * pick3(p2, t0, t1b, t2b) + (e & 7), nv - 1);
-        lw1[m] = gptr(w1)[(a * nv + b) * nv + c];
-        lw2[m] = gptr(w2)[(b * nv + a) * nv + c];
-        lij[m] = gptr(ov_ij)[a * nonv + b];
-        lik[m] = gptr(ov_ik)[a * nonv + c];
-        ljk[m] = gptr(ov_jk)[b * nonv + c];
-        lti[m] = gptr(t1i)[a];
-        ltj[m] = gptr(t1j)[b];
-        ltk[m] = gptr(t1k)[c];
+        const int cr = kOrb * pick3(p2, t0, t1b, t2b) + (e & 7);   // even
+        lij[m] = lij[m + 1] = gptr(ov_ij)[a * nonv + b];
+        lti[m] = lti[m + 1] = gptr(t1i)[a];
+        ltj[m] = ltj[m + 1] = gptr(t1j)[b];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) ltk[m + h] = gptr(t1k)[min(cr + h, nv - 1)];
+        if (even_nv) {
+          const int64_t c = min(cr, nv - 2);
+          const CV2 u = *(const SIE_GLOBAL CV2*)(gptr(w1) + (a * nv + b) * nv + c);
+          const CV2 v = *(const SIE_GLOBAL CV2*)(gptr(w2) + (b * nv + a) * nv + c);
+          lw1[m] = u.x;
+          lw1[m + 1] = u.y;
+          lw2[m] = v.x;
+          lw2[m + 1] = v.y;
+        } else {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int64_t c = min(cr + h, nv - 1);
+            lw1[m + h] = gptr(w1)[(a * nv + b) * nv + c];
+            lw2[m + h] = gptr(w2)[(b * nv + a) * nv + c];
+          }
+        }
+        if (fd.epv) {
+          const int64_t c = min(cr, nv - 2);
+          const IV2 u = *(const SIE_GLOBAL IV2*)(gptr(ov_ik) + a * nonv + c);
+          const IV2 v = *(const SIE_GLOBAL IV2*)(gptr(ov_jk) + b * nonv + c);
+          lik[m] = u.x;
+          lik[m + 1] = u.y;
+          ljk[m] = v.x;
+          ljk[m + 1] = v.y;
+        } else {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int64_t c = min(cr + h, nv - 1);
+            lik[m + h] = gptr(ov_ik)[a * nonv + c];
+            ljk[m + h] = gptr(ov_jk)[b * nonv + c];
+          }
+        }
       }
 #pragma unroll
       for (int m = 0; m < kBatch; ++m) {
@@ -183,41 +220,65 @@ __global__ __launch_bounds__(256, 2) void k_hat(const FragDesc* __restrict__ des
       }
       if (!dup) primary |= 1u << s;
     }
-    for (int idx = threadIdx.x; idx < 6 * E; idx += 256) {
-      const int s = idx / E, e = orb_elem(idx - s * E);
+    // G, H and Gt of this thread's two elements (x, y, z0 + h), h = 0, 1, of
+    // each slot (the elements of iterations 2s and 2s + 1 of the loads
+    // above), adjacent along c: with n_v even each cube takes one
+    // two-element store
+    const int x = threadIdx.x >> 5, y = (threadIdx.x >> 2) & 7, z0 = 2 * (threadIdx.x & 3);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
       if (!((primary >> s) & 1u)) continue;
       int p0, p1, p2;
       slot_perm(s, p0, p1, p2);
-      const int x = e >> 6, y = (e >> 3) & 7, zz = e & 7;
       const int a = kOrb * pick3(p0, t0, t1b, t2b) + x;
       const int b = kOrb * pick3(p1, t0, t1b, t2b) + y;
-      const int c = kOrb * pick3(p2, t0, t1b, t2b) + zz;
-      if (a >= nv || b >= nv || c >= nv) continue;
-      const int e_abc = orb_lds(x, y, zz);
-      const int e_cab = orb_lds(zz, x, y), s_cab = orbit_slot(p2, p0, p1);
-      const int e_bca = orb_lds(y, zz, x), s_bca = orbit_slot(p1, p2, p0);
-      const int e_cba = orb_lds(zz, y, x), s_cba = orbit_slot(p2, p1, p0);
-      const int e_acb = orb_lds(x, zz, y), s_acb = orbit_slot(p0, p2, p1);
-      const int e_bac = orb_lds(y, x, zz), s_bac = orbit_slot(p1, p0, p2);
-      const double rz = 4.0 * sz[s][e_abc] + sz[s_cab][e_cab] + sz[s_bca][e_bca] -
-                        2.0 * (sz[s_cba][e_cba] + sz[s_acb][e_acb] + sz[s_bac][e_bac]);
-      const double rw = 4.0 * sw[s][e_abc] + sw[s_cab][e_cab] + sw[s_bca][e_bca] -
-                        2.0 * (sw[s_cba][e_cba] + sw[s_acb][e_acb] + sw[s_bac][e_bac]);
-      const double id =
-          recip(eijk - se[p0 * kOrb + x] - se[p1 * kOrb + y] - se[p2 * kOrb + zz]);   // 1 / D
-      acc += sw[s][e_abc] * rz * id;
-      const int64_t pos = ((int64_t)a * nv + b) * nv + c;
-      gptr_w(w1)[pos] = CubeT(scale * (rw + rz) * id);
-      gptr_w(w2)[pos] = CubeT(scale * rw * id);
-      // G at (c, b, a), stored at this thread's (a, b, c) of the transposed
-      // cube (contiguous across the wave); R' at (c, b, a) combines the same
-      // six permuted values with the roles of (abc, cba), (cab, acb) and
-      // (bca, bac) exchanged.
-      const double rz_t = 4.0 * sz[s_cba][e_cba] + sz[s_acb][e_acb] + sz[s_bac][e_bac] -
-                          2.0 * (sz[s][e_abc] + sz[s_cab][e_cab] + sz[s_bca][e_bca]);
-      const double rw_t = 4.0 * sw[s_cba][e_cba] + sw[s_acb][e_acb] + sw[s_bac][e_bac] -
-                          2.0 * (sw[s][e_abc] + sw[s_cab][e_cab] + sw[s_bca][e_bca]);
-      gptr_w(w3)[pos] = CubeT(scale * (rw_t + rz_t) * id);
+      const int c0 = kOrb * pick3(p2, t0, t1b, t2b) + z0;
+      if (a >= nv || b >= nv || c0 >= nv) continue;
+      const int s_cab = orbit_slot(p2, p0, p1), s_bca = orbit_slot(p1, p2, p0);
+      const int s_cba = orbit_slot(p2, p1, p0), s_acb = orbit_slot(p0, p2, p1);
+      const int s_bac = orbit_slot(p1, p0, p2);
+      CubeT vg[2], vh[2], vt[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int zz = z0 + h;
+        const int e_abc = orb_lds(x, y, zz);
+        const int e_cab = orb_lds(zz, x, y), e_bca = orb_lds(y, zz, x);
+        const int e_cba = orb_lds(zz, y, x), e_acb = orb_lds(x, zz, y);
+        const int e_bac = orb_lds(y, x, zz);
+        const double rz = 4.0 * sz[s][e_abc] + sz[s_cab][e_cab] + sz[s_bca][e_bca] -
+                          2.0 * (sz[s_cba][e_cba] + sz[s_acb][e_acb] + sz[s_bac][e_bac]);
+        const double rw = 4.0 * sw[s][e_abc] + sw[s_cab][e_cab] + sw[s_bca][e_bca] -
+                          2.0 * (sw[s_cba][e_cba] + sw[s_acb][e_acb] + sw[s_bac][e_bac]);
+        const double id =
+            recip(eijk - se[p0 * kOrb + x] - se[p1 * kOrb + y] - se[p2 * kOrb + zz]);   // 1 / D
+        if (c0 + h < nv) acc += sw[s][e_abc] * rz * id;
+        vg[h] = CubeT(scale * (rw + rz) * id);
+        vh[h] = CubeT(scale * rw * id);
+        // G at (c, b, a), stored at this thread's (a, b, c) of the transposed
+        // cube (contiguous across the wave); R' at (c, b, a) combines the same
+        // six permuted values with the roles of (abc, cba), (cab, acb) and
+        // (bca, bac) exchanged.
+        const double rz_t = 4.0 * sz[s_cba][e_cba] + sz[s_acb][e_acb] + sz[s_bac][e_bac] -
+                            2.0 * (sz[s][e_abc] + sz[s_cab][e_cab] + sz[s_bca][e_bca]);
+        const double rw_t = 4.0 * sw[s_cba][e_cba] + sw[s_acb][e_acb] + sw[s_bac][e_bac] -
+                            2.0 * (sw[s][e_abc] + sw[s_cab][e_cab] + sw[s_bca][e_bca]);
+        vt[h] = CubeT(scale * (rw_t + rz_t) * id);
+      }
+      const int64_t pos = ((int64_t)a * nv + b) * nv + c0;
+      if (even_nv) {
+        *(SIE_GLOBAL CV2*)(gptr_w(w1) + pos) = CV2{vg[0], vg[1]};
+        *(SIE_GLOBAL CV2*)(gptr_w(w2) + pos) = CV2{vh[0], vh[1]};
+        *(SIE_GLOBAL CV2*)(gptr_w(w3) + pos) = CV2{vt[0], vt[1]};
+      } else {
+        gptr_w(w1)[pos] = vg[0];
+        gptr_w(w2)[pos] = vh[0];
+        gptr_w(w3)[pos] = vt[0];
+        if (c0 + 1 < nv) {
+          gptr_w(w1)[pos + 1] = vg[1];
+          gptr_w(w2)[pos + 1] = vh[1];
+          gptr_w(w3)[pos + 1] = vt[1];
+        }
+      }
     }
     if (want_eps) {
       // tuples: threads t and t + 256 take slot-0 offsets e = x*64 + y*8 + z
