@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256, 2) void k_hat(const FragDesc* __restrict__ des
   __shared__ double sw[6][kOrbSlot];
   __shared__ double sz[6][kOrbSlot];
   __shared__ double red[4];
-  __shared__ double se[3 * kOrb];   // e_vir at the orbit's three blocks
+  __shared__ double sev[3 * kOrb];   // e_vir at the orbit's three blocks
   // orbital-energy gradient: virtual row of this work-group and the
   // cross-wave partials of one orbit's marginals
   __shared__ double dv[SIE_MAX_VIR];
@@ -118,9 +118,9 @@ __global__ __launch_bounds__(256, 2) void k_hat(const FragDesc* __restrict__ des
     // (all 12 with float32 values, 6 with float64: registers): every load
     // of a batch (indices clamped in range, results past n_v masked) is
     // issued before any is used
-    // (the previous orbit's last barrier freed se)
+    // (the previous orbit's last barrier freed sev)
     if (threadIdx.x < 3 * kOrb)
-      se[threadIdx.x] = gptr(ev)[min(kOrb * pick3(threadIdx.x / kOrb, t0, t1b, t2b) +
+      sev[threadIdx.x] = gptr(ev)[min(kOrb * pick3(threadIdx.x / kOrb, t0, t1b, t2b) +
                                          int(threadIdx.x % kOrb), nv - 1)];
     typedef typename std::conditional<sizeof(CubeT) == 8, d2v, f2v>::type CV2;
     typedef typename std::conditional<sizeof(InT) == 8, d2v, f2v>::type IV2;
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256, 2) void k_hat(const FragDesc* __restrict__ des
         const double rw = 4.0 * sw[s][e_abc] + sw[s_cab][e_cab] + sw[s_bca][e_bca] -
                           2.0 * (sw[s_cba][e_cba] + sw[s_acb][e_acb] + sw[s_bac][e_bac]);
         const double id =
-            recip(eijk - se[p0 * kOrb + x] - se[p1 * kOrb + y] - se[p2 * kOrb + zz]);   // 1 / D
+            recip(eijk - sev[p0 * kOrb + x] - sev[p1 * kOrb + y] - sev[p2 * kOrb + zz]);   // 1 / D
         if (c0 + h < nv) acc += sw[s][e_abc] * rz * id;
         vg[h] = CubeT(scale * (rw + rz) * id);
         vh[h] = CubeT(scale * rw * id);
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(256, 2) void k_hat(const FragDesc* __restrict__ des
           const double f = 3.0 * wz - 0.5 * (we + wo) * (ze + zo) + 1.5 * (we - wo) * (ze - zo);
           const int eq = (a == b) + (b == c) + (a == c);
           const double wt = eq == 0 ? 1.0 : (eq == 1 ? 0.5 : 1.0 / 6.0);
-          const double id = recip(eijk - se[ox] - se[kOrb + oy] - se[2 * kOrb + oz]);
+          const double id = recip(eijk - sev[ox] - sev[kOrb + oy] - sev[2 * kOrb + oz]);
           q = scale * wt * f * id * id;
         }
         eacc += q;
@@ -859,6 +859,19 @@ __global__ __launch_bounds__(256) void k_adj_ovov(const FragDesc* __restrict__ d
     }
     double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
     int u = 0;
+    if (hs == 1 && (nv & 1) == 0) {
+      // kind 0, rows of even length: the row starts at an even element, so
+      // (u, u + 1) is one two-element load (same products, same sums)
+      typedef typename std::conditional<sizeof(CubeT) == 8, d2v, f2v>::type CV2;
+      for (; u + 4 <= nv; u += 4) {
+        const CV2 h01 = *(const SIE_GLOBAL CV2*)(h + u);
+        const CV2 h23 = *(const SIE_GLOBAL CV2*)(h + u + 2);
+        p0 += (double)h01.x * (double)tv[u];
+        p1 += (double)h01.y * (double)tv[u + 1];
+        p2 += (double)h23.x * (double)tv[u + 2];
+        p3 += (double)h23.y * (double)tv[u + 3];
+      }
+    }
     for (; u + 4 <= nv; u += 4) {
       p0 += (double)h[int64_t(u) * hs] * (double)tv[u];
       p1 += (double)h[int64_t(u + 1) * hs] * (double)tv[u + 1];
@@ -918,17 +931,28 @@ __global__ __launch_bounds__(256) void k_adj_t1_part(const FragDesc* __restrict_
       if (c < nv) {   // four interleaved partial sums, added in a fixed order
         double p[4] = {0.0, 0.0, 0.0, 0.0};
         int64_t ab = wave;
+        // (a, b) of ab = a nv + b, stepped along with ab (no division per term)
+        int aa = wave / nv, bb = wave - aa * nv;
+        auto step = [&](int d, int& a2, int& b2) {
+          a2 = aa;
+          b2 = bb + d;
+          while (b2 >= nv) {
+            b2 -= nv;
+            ++a2;
+          }
+        };
         for (; ab + 12 < nv2; ab += 16) {
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const int64_t x = ab + 4 * u;
-            const int aa = int(x / nv), bb = int(x - int64_t(aa) * nv);
-            p[u] += (double)H[x * nv + c] * (double)m[aa * onv + bb];
+            int a2, b2;
+            step(4 * u, a2, b2);
+            p[u] += (double)H[(ab + 4 * u) * nv + c] * (double)m[int64_t(a2) * onv + b2];
           }
+          step(16, aa, bb);
         }
         for (; ab < nv2; ab += 4) {
-          const int aa = int(ab / nv), bb = int(ab - int64_t(aa) * nv);
-          p[0] += (double)H[ab * nv + c] * (double)m[aa * onv + bb];
+          p[0] += (double)H[ab * nv + c] * (double)m[int64_t(aa) * onv + bb];
+          step(4, aa, bb);
         }
         s = (p[0] + p[1]) + (p[2] + p[3]);
       }
