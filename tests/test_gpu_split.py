@@ -152,3 +152,35 @@ def test_split_product_set_on_gpu():
           f"{abs(e_gpu - e_em) / abs(e_em):.2e}, lo*lo share {gap / abs(e64):.2e}", flush=True)
     assert gap >= 5e-6 * abs(e64)
     assert abs(e_gpu - e_em) <= 0.1 * gap
+
+
+def test_split_orbit_table_second_chunk():
+    """584 virtuals: 73 orbit blocks, 67525 orbits a unit and 264 for each of
+    the unit's 256 epilogue work-groups, so the float32 epilogue decodes its
+    orbit table in two chunks of 256.  The split energy is checked against
+    the float64 path on the same float32-rounded inputs (whose epilogue does
+    not use the table): every occupied triple within 2e-5 of the largest,
+    the energy within 2e-6 relative."""
+    import torch
+    import paper_2412_18553_amd as sie
+    from synth.device import make_fragment_device
+    print("case o=2 v=584 aux=300", flush=True)
+    df = make_fragment_device(2, 584, 300, (8, 584), device="cuda", dtype=torch.float32)
+
+    def run(frag):
+        tri = torch.empty(frag.n_triples, dtype=torch.float64, device="cuda")
+        e = sie.energy(frag, triples=tri)
+        torch.cuda.synchronize()
+        return float(e.item()), tri.cpu().numpy()
+
+    e_s, tri_s = run(sie.Fragment(*df.arrays(), precision="split_bf16"))
+    d64 = [x.double() for x in df.arrays()[2:]]
+    e_d, tri_d = run(sie.Fragment(df.eps_occ, df.eps_vir, *d64, precision="fp64"))
+    del d64
+    scale = np.abs(tri_d).max()
+    err = np.abs(tri_s - tri_d).max() / scale
+    print(f"split {e_s!r} float64 {e_d!r}: rel {abs(e_s - e_d) / abs(e_d):.2e}, "
+          f"max triple error {err:.2e} of the largest", flush=True)
+    assert scale > 0.0
+    assert err <= 2e-5
+    assert abs(e_s - e_d) <= 2e-6 * abs(e_d)
