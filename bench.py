@@ -340,12 +340,20 @@ def run_single(args, result, name, mode):
     o, v = w["n_occ"], w["n_vir"]
     F = flops(o, v)
     dev = torch.device("cuda:0")
+    # the gradient in either precision (split: float32 inputs, the bf16 hi/lo
+    # rebuild, FP64 contractions); the fp64 line is the float64 energy only
+    prec = args.precision or "fp64"
+    if mode == "fp64" and prec != "fp64":
+        raise SystemExit("--mode fp64 times the float64 energy; use --mode split for split_bf16")
     t0 = time.perf_counter()
-    df = workload_fragment_device(name, device=dev)
+    df = workload_fragment_device(
+        name, device=dev, dtype=torch.float32 if prec == "split_bf16" else torch.float64)
     log(f"# workload {name}: built on the GPU in {time.perf_counter() - t0:.1f} s")
-    fr = frag_of(df, "fp64")
+    fr = frag_of(df, prec)
     out = torch.empty(1, dtype=torch.float64, device=dev)
     desc = f"single fragment n_occ={o} n_vir={v} n_aux={w['n_aux']}"
+    if prec == "split_bf16":
+        desc += ", float32 inputs"
     if mode == "backward":
         ws = torch.empty(sie.backward_workspace_size(fr), dtype=torch.uint8, device=dev)
         grads = [{n: torch.empty_like(getattr(fr, n), dtype=torch.float64)
@@ -375,11 +383,14 @@ def run_single(args, result, name, mode):
         # the backward recomputes the build (F) and runs the transposed
         # contractions of every build term (2F): 3F per step
         result.update(metric="(T) gradient TFLOP/s (3 x F per step)",
-                      value=round(3.0 * F / (ms * 1e-3) / 1e12, 3), dtype="f64",
-                      config={"workload": desc, "precision": "fp64", "fragments": 1,
+                      value=round(3.0 * F / (ms * 1e-3) / 1e12, 3),
+                      dtype="f64" if prec == "fp64" else "bf16x3/f32 rebuild, f64 contractions",
+                      config={"workload": desc, "precision": prec, "fragments": 1,
                               "outputs": "dE/d(t1, t2, ovvv, ooov, ovov, eps_occ, eps_vir)"})
+        # (counter traffic is recorded for the float64 gradient only)
         result["roofline"] = roofline(prof, "grad", "k_adj_contract", 2.0 * F, args.steps,
-                                      PEAK_FP64_MFMA_TFLOPS, measured=peak64, workload=name)
+                                      PEAK_FP64_MFMA_TFLOPS, measured=peak64,
+                                      workload=name if prec == "fp64" else None)
     result.update(ms_per_step=round(ms, 3), fragments_per_s=round(1000.0 / ms, 4), energy=energy)
     if mode == "fp64" and not args.no_cpu:
         host = df.host()
