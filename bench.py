@@ -343,8 +343,6 @@ def run_single(args, result, name, mode):
     # the gradient in either precision (split: float32 inputs, the bf16 hi/lo
     # rebuild, FP64 contractions); the fp64 line is the float64 energy only
     prec = args.precision or "fp64"
-    if mode == "fp64" and prec != "fp64":
-        raise SystemExit("--mode fp64 times the float64 energy; use --mode split for split_bf16")
     t0 = time.perf_counter()
     df = workload_fragment_device(
         name, device=dev, dtype=torch.float32 if prec == "split_bf16" else torch.float64)
@@ -639,6 +637,15 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the (T) path here is single-GPU "
               "(fragments would shard across GPUs as independent work; not built).",
+              file=sys.stderr)
+        sys.exit(2)
+    # modes with one precision refuse another one (batched and backward take
+    # either)
+    fixed = {"split": "split_bf16", "df": "split_bf16", "fp64": "fp64", "projector": "fp64",
+             "mp2": "fp64"}
+    if args.precision and args.mode in fixed and args.precision != fixed[args.mode]:
+        print(f"--mode {args.mode} runs in {fixed[args.mode]} only; --precision "
+              f"{args.precision} applies to --mode batched and --mode backward",
               file=sys.stderr)
         sys.exit(2)
 

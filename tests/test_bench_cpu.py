@@ -64,3 +64,13 @@ def test_sources_hash_covers_every_kernel_source():
     assert any(n.endswith(".hip") for n in names) and any(n.endswith(".hpp") for n in names)
     h = bench.sources_sha256()
     assert len(h) == 64 and h == bench.sources_sha256()
+
+
+@pytest.mark.parametrize("mode,prec", [("fp64", "split_bf16"), ("split", "fp64"),
+                                       ("projector", "split_bf16"), ("df", "fp64")])
+def test_fixed_precision_modes_refuse_another(mode, prec):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--mode", mode,
+                        "--precision", prec], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert f"--mode {mode} runs in" in r.stderr
+    assert r.stdout == ""
